@@ -1,0 +1,264 @@
+"""FP64 CPU oracle of the HOTRG coarse-graining step and its reverse-mode adjoint.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links this file;
+only the test suite, the smoke check and the CPU-baseline leg of the benchmark do.  It shares
+no code with the HIP implementation: it is plain NumPy (einsum over BLAS, LAPACK ``eigh``),
+written from the paper so that each step can be checked by eye.
+
+What is computed (paper, Supplemental Material B and E):
+
+* Forward.  The HOTRG step (equation labelled ``HOTRGstep`` in SM B and the figure beside it)
+  merges an upper tensor T_{x1 x1' y j} and a lower tensor T_{x2 x2' j y'} along their shared
+  vertical bond j and compresses the doubled horizontal legs with one isometry w on each side:
+      T'_{a b y y'} = sum T_{x1 x1' y j} T_{x2 x2' j y'} w_{x1 x2 a} w_{x1' x2' b}.
+  w is taken from a local higher-order SVD of the pair (SM B, sentence after ``HOTRGstep``):
+  its columns are the leading eigenvectors of the Gram matrix of the (x1, x2) unfolding of the
+  pair, G = M M^T, which factorises as G_{(a c),(b d)} = sum_{jk} A_{a b j k} B_{c d j k} with
+  A_{abjk} = sum_{x,y} T_{a x y j} T_{b x y k} and B_{abjk} = sum_{x,y} T_{a x j y} T_{b x k y}.
+  The direction alternates every step (main text, Fig. 1(a): renormalise along both axes), the
+  tensor is rescaled each step and the logs of the scales are accumulated, and after n steps the
+  single tensor's periodic self-trace closes the network (main text, scheme (a): 2^n sites).
+* Backward.  The SRG environment recursion (SM B, equation ``SRG``) is the chain rule (SM E,
+  equations ``Eeq``, ``Teq``, ``Unify``; SM C, equation ``BP``): the environment of the upper copy
+  is the incoming environment contracted with the lower copy and both isometries, and likewise
+  for the lower copy; the two copies' contributions add.  Beyond the paper (which keeps w fixed),
+  w is differentiated through the eigensolve with the symmetric-eigenvector perturbation formula,
+  with 1/(l_j - l_i) broadened to d/(d^2 + eps), d = l_j - l_i.
+
+Readings where the paper is silent (each is also listed in the design notes):
+  * internal index order T[l][r][u][d] (the paper's T_{x x' y y'}); inputs arrive as [l][u][r][d];
+  * the isometry comes from the left (x1, x2) unfolding; chi' = min(chi, X^2), no threshold;
+  * the Gram is symmetrised and divided by its trace before the eigensolve (spectrum in [0, 1]);
+  * the per-step scale is the Frobenius norm; in the adjoint it is held constant, which is exact
+    because everything downstream of it is log-homogeneous in the rescaled tensor;
+  * each step doubles the number of sites, so step k's log-scale carries weight 2^-k and the final
+    trace 2^-n (N = 2^n sites);
+  * the first step merges a vertical pair (the paper's figure), later steps alternate by the
+    permutation (u, d, l, r) of the previous step's output.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+DEFAULT_BROADENING = 1e-12
+
+
+def _es(spec, *ops):
+    return np.einsum(spec, *ops, optimize=True)
+
+
+@dataclass
+class StepRecord:
+    """What the forward pass keeps of step k for the adjoint and for diagnostics."""
+    T: np.ndarray        # normalised input of the step, [l][r][u][d]
+    c: float             # Frobenius norm of the unnormalised output
+    U: np.ndarray        # all eigenvectors of the normalised Gram, columns sorted descending
+    lam: np.ndarray      # eigenvalues of the normalised Gram, descending
+    trace_G: float       # trace of the symmetrised Gram
+    G_hat: np.ndarray    # symmetrised, trace-normalised Gram
+    A: np.ndarray        # half-environment A[a][b][j][k]
+    B: np.ndarray        # half-environment B[a][b][j][k]
+    chi_kept: int        # chi' = min(chi, X^2)
+    P: np.ndarray | None = None
+    Q: np.ndarray | None = None
+
+
+@dataclass
+class ForwardResult:
+    lnZ_per_site: float
+    steps: list
+    c0: float
+    final_T: np.ndarray
+    final_trace: float
+
+
+def to_internal(T0_lurd: np.ndarray) -> np.ndarray:
+    """[l][u][r][d] -> [l][r][u][d]."""
+    return np.ascontiguousarray(np.transpose(T0_lurd, (0, 2, 1, 3)))
+
+
+def half_environments(T: np.ndarray):
+    """A[a,b,j,k] = sum_{x,y} T[a,x,y,j] T[b,x,y,k];  B[a,b,j,k] = sum_{x,y} T[a,x,j,y] T[b,x,k,y].
+
+    A pairs two upper copies over their right and up legs (free: left legs a, b and the shared
+    vertical legs j, k); B pairs two lower copies over their right and down legs.
+    """
+    A = _es("axyj,bxyk->abjk", T, T)
+    B = _es("axjy,bxky->abjk", T, T)
+    return A, B
+
+
+def gram(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """G[(a,c),(b,d)] = sum_{j,k} A[a,b,j,k] B[c,d,j,k]: Gram of the (x1, x2) unfolding."""
+    X = A.shape[0]
+    G4 = _es("abjk,cdjk->acbd", A, B)
+    return G4.reshape(X * X, X * X)
+
+
+def isometry(G: np.ndarray, chi: int):
+    """Symmetrise, normalise by the trace, full eigendecomposition sorted by descending eigenvalue."""
+    Gs = 0.5 * (G + G.T)
+    t = float(np.trace(Gs))
+    if not (t > 0.0 and math.isfinite(t)):
+        raise FloatingPointError("Gram trace is not positive and finite")
+    G_hat = Gs / t
+    lam, U = np.linalg.eigh(G_hat)
+    order = np.argsort(lam)[::-1]
+    lam, U = lam[order], U[:, order]
+    chi_kept = min(chi, G.shape[0])
+    return G_hat, t, lam, U, chi_kept
+
+
+def project(T: np.ndarray, w: np.ndarray):
+    """The HOTRG step with isometry w[x1][x2][a] on both sides, in three pairwise contractions.
+
+    P[i,y,j,b,a] = sum_x1 T[x1,i,y,j] w[x1,b,a]          (upper copy, left isometry)
+    Q[i,y,a,m,z] = sum_{b,j} P[i,y,j,b,a] T[b,m,j,z]      (lower copy joined over x2 and j)
+    T'[a,c,y,z]  = sum_{i,m} Q[i,y,a,m,z] w[i,m,c]        (right isometry)
+    """
+    P = _es("xiyj,xba->iyjba", T, w)
+    Q = _es("iyjba,bmjz->iyamz", P, T)
+    Tn = _es("iyamz,imc->acyz", Q, w)
+    return P, Q, Tn
+
+
+def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = False) -> ForwardResult:
+    """ln Z / N of the periodic 2^n-site network built from T0 with chi-truncated HOTRG steps."""
+    T0 = np.asarray(T0_lurd, dtype=np.float64)
+    if T0.ndim != 4 or len(set(T0.shape)) != 1:
+        raise ValueError("T0 must be a D x D x D x D tensor")
+    if chi < 1 or n_steps < 1:
+        raise ValueError("chi and n_steps must be positive")
+    if not np.all(np.isfinite(T0)):
+        raise FloatingPointError("T0 has non-finite entries")
+    T = to_internal(T0)
+    c0 = float(np.linalg.norm(T))
+    if not c0 > 0.0:
+        raise FloatingPointError("T0 is zero")
+    T = T / c0
+    L = math.log(c0)
+    steps = []
+    for k in range(1, n_steps + 1):
+        if k > 1:
+            T = np.ascontiguousarray(np.transpose(T, (2, 3, 0, 1)))
+        X = T.shape[0]
+        A, B = half_environments(T)
+        G_hat, t, lam, U, chi_kept = isometry(gram(A, B), chi)
+        w = U[:, :chi_kept].reshape(X, X, chi_kept)
+        P, Q, Tn = project(T, w)
+        c = float(np.linalg.norm(Tn))
+        if not (c > 0.0 and math.isfinite(c)):
+            raise FloatingPointError(f"step {k}: output norm is not positive and finite")
+        steps.append(StepRecord(T=T, c=c, U=U, lam=lam, trace_G=t, G_hat=G_hat, A=A, B=B,
+                                chi_kept=chi_kept, P=P if keep_PQ else None,
+                                Q=Q if keep_PQ else None))
+        T = Tn / c
+        L += math.ldexp(math.log(c), -k)
+    tr = float(_es("xxyy->", T))
+    if not (tr > 0.0 and math.isfinite(tr)):
+        raise FloatingPointError("final trace is not positive and finite")
+    L += math.ldexp(math.log(tr), -n_steps)
+    return ForwardResult(lnZ_per_site=L, steps=steps, c0=c0, final_T=T, final_trace=tr)
+
+
+def broadened_inverse_gap(lam: np.ndarray, eps: float) -> np.ndarray:
+    """F[i,j] = d / (d^2 + eps) with d = lam[j] - lam[i]; F[i,i] = 0."""
+    d = lam[None, :] - lam[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = d / (d * d + eps)
+    np.fill_diagonal(F, 0.0)
+    return F
+
+
+def eig_adjoint(U: np.ndarray, lam: np.ndarray, chi_kept: int, Ubar_kept: np.ndarray,
+                eps: float) -> np.ndarray:
+    """Gradient with respect to the symmetric matrix whose eigenvectors are U, given the gradient
+    with respect to its leading chi_kept eigenvectors.
+
+    First-order perturbation of eigenvector j of a symmetric matrix: du_j = sum_{i != j} u_i
+    (u_i^T dG u_j) / (l_j - l_i).  Its transpose, restricted to symmetric dG, is
+    G_bar = U [F o (Om - Om^T) / 2] U^T with Om = U^T U_bar and F the (broadened) inverse gaps.
+    U_bar has zero columns for the discarded eigenvectors.
+    """
+    n = U.shape[0]
+    Ubar = np.zeros((n, n))
+    Ubar[:, :chi_kept] = Ubar_kept
+    Om = U.T @ Ubar
+    S = broadened_inverse_gap(lam, eps) * (Om - Om.T) * 0.5
+    return U @ S @ U.T
+
+
+def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
+    """Gradient with respect to the step's input T, given the gradient w.r.t. its unnormalised output."""
+    T = rec.T
+    X = T.shape[0]
+    chi_kept = rec.chi_kept
+    w = rec.U[:, :chi_kept].reshape(X, X, chi_kept)
+    if rec.P is not None:
+        P, Q = rec.P, rec.Q
+    else:
+        P, Q, _ = project(T, w)
+    # right isometry:  T'[a,c,y,z] = sum Q[i,y,a,m,z] w[i,m,c]
+    Q_bar = _es("acyz,imc->iyamz", Tn_bar, w)
+    w_bar_R = _es("acyz,iyamz->imc", Tn_bar, Q)
+    # lower copy:  Q[i,y,a,m,z] = sum P[i,y,j,b,a] T[b,m,j,z]
+    P_bar = _es("iyamz,bmjz->iyjba", Q_bar, T)
+    T_bar_lower = _es("iyjba,iyamz->bmjz", P, Q_bar)
+    # upper copy and left isometry:  P[i,y,j,b,a] = sum T[x,i,y,j] w[x,b,a]
+    T_bar_upper = _es("iyjba,xba->xiyj", P_bar, w)
+    w_bar_L = _es("xiyj,iyjba->xba", T, P_bar)
+    # the isometry is the leading eigenvectors of G_hat = sym(G) / tr G
+    Ubar_kept = (w_bar_L + w_bar_R).reshape(X * X, chi_kept)
+    Ghat_bar = eig_adjoint(rec.U, rec.lam, chi_kept, Ubar_kept, eps)
+    t = rec.trace_G
+    Gs_bar = Ghat_bar / t - (np.sum(Ghat_bar * rec.G_hat) / t) * np.eye(X * X)
+    G_bar = 0.5 * (Gs_bar + Gs_bar.T)
+    G4_bar = G_bar.reshape(X, X, X, X)          # [a][c][b][d]
+    A_bar = _es("acbd,cdjk->abjk", G4_bar, rec.B)
+    B_bar = _es("acbd,abjk->cdjk", G4_bar, rec.A)
+    # A[a,b,j,k] = sum T[a,x,y,j] T[b,x,y,k]  (both factors are the same tensor)
+    T_bar_A = _es("abjk,bxyk->axyj", A_bar, T) + _es("abjk,axyj->bxyk", A_bar, T)
+    # B[a,b,j,k] = sum T[a,x,j,y] T[b,x,k,y]
+    T_bar_B = _es("abjk,bxky->axjy", B_bar, T) + _es("abjk,axjy->bxky", B_bar, T)
+    return T_bar_upper + T_bar_lower + T_bar_A + T_bar_B
+
+
+def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_BROADENING) -> np.ndarray:
+    """d(gbar * lnZ/N)/dT0 in the input layout [l][u][r][d]."""
+    n = len(fwd.steps)
+    D = fwd.final_T.shape
+    # final self-trace: L += 2^-n ln sum_{x,y} T[x,x,y,y]
+    T_bar = np.zeros(D)
+    idx_x = np.arange(D[0])
+    idx_y = np.arange(D[2])
+    T_bar[idx_x[:, None], idx_x[:, None], idx_y[None, :], idx_y[None, :]] = (
+        gbar * math.ldexp(1.0, -n) / fwd.final_trace)
+    for k in range(n, 0, -1):
+        rec = fwd.steps[k - 1]
+        # output was divided by c_k; c_k itself is held constant (exact, see module notes)
+        T_in_bar = step_adjoint(rec, T_bar / rec.c, eps)
+        T_bar = np.transpose(T_in_bar, (2, 3, 0, 1)) if k > 1 else T_in_bar
+    T_bar = T_bar / fwd.c0
+    return np.ascontiguousarray(np.transpose(T_bar, (0, 2, 1, 3)))
+
+
+def lnZ_and_grad(T0_lurd: np.ndarray, chi: int, n_steps: int, eps: float = DEFAULT_BROADENING):
+    fwd = hotrg_forward(T0_lurd, chi, n_steps)
+    return fwd.lnZ_per_site, hotrg_backward(fwd, 1.0, eps), fwd
+
+
+def step_invariants(fwd: ForwardResult):
+    """Gauge-invariant per-step quantities: scale c_k, kept count, truncated weight, cut gap."""
+    out = []
+    for rec in fwd.steps:
+        lam = rec.lam
+        kept = rec.chi_kept
+        tw = float(np.sum(lam[kept:])) if kept < lam.size else 0.0
+        gap = float(lam[kept - 1] - lam[kept]) if kept < lam.size else float("inf")
+        out.append({"c": rec.c, "chi_kept": kept, "trunc_weight": tw, "cut_gap": gap,
+                    "lam_kept": lam[:kept].copy()})
+    return out
