@@ -1,0 +1,156 @@
+/*
+ * dtrg.h - C ABI of the HOTRG coarse-graining step and its reverse-mode adjoint on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv:1912.02780, Supplemental Material B and E):
+ *   Z = periodic trace of a square network of identical rank-4 tensors T0 (SM A, first eq.).
+ *   Each HOTRG step (SM B, eq. HOTRGstep and its figure) joins two copies of the current tensor
+ *   along a vertical bond and compresses each doubled horizontal leg with an isometry w made of
+ *   the leading chi' = min(chi, X^2) eigenvectors of the pair's (x1, x2)-unfolding Gram matrix
+ *   (SM B, local HOSVD).  The direction alternates, the tensor is rescaled by its Frobenius norm
+ *   every step, and after n steps (2^n sites) the periodic self-trace closes the network (main
+ *   text, scheme (a)).  The result is ln Z / N, N = 2^n.
+ *   The backward pass is the SRG environment recursion (SM B, eq. SRG), i.e. the chain rule
+ *   (SM E, eqs. Eeq, Teq, Unify), extended through the eigensolver: the leading-eigenvector
+ *   derivative uses the inverse gaps 1/(l_j - l_i) broadened to d / (d^2 + eps).
+ *
+ * Index order.  T0 is passed as T0[l][u][r][d] (left, up, right, down), row-major, D^4 doubles.
+ * The same layout is used for the gradient T0bar.
+ *
+ * Memory.  Every pointer whose name ends in _dev is a device pointer (hipMalloc'd or from
+ * PyTorch's allocator) on the current HIP device; every pointer ending in _host is host memory.
+ * The caller owns T0_dev, T0bar_dev and the stream.  A plan owns its checkpoints and workspaces
+ * (device memory allocated with hipMalloc at plan creation, released by dtrg_plan_destroy).
+ *
+ * Errors.  Every entry point returns a dtrg_status; nothing throws or aborts across the ABI.
+ * dtrg_last_error() returns a thread-local message describing the last failure on the calling
+ * thread (valid until the next call on that thread).  If dtrg_hotrg_forward fails, *plan_out is
+ * set to NULL and nothing is leaked.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the legacy default stream).  All device work of a
+ * call is enqueued on it; entry points that return host values synchronise that stream.  One
+ * plan must not be used from two threads at once.
+ */
+#ifndef DTRG_H
+#define DTRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DTRG_OK = 0,
+    DTRG_EINVAL = 1,   /* invalid argument: sizes, NULL pointers, non-finite T0 */
+    DTRG_ENOMEM = 2,   /* device allocation failed */
+    DTRG_EHIP = 3,     /* a HIP runtime call failed */
+    DTRG_ENOCONV = 4,  /* the truncated eigensolver did not reach its tolerance */
+    DTRG_ENONPOS = 5,  /* a norm or the final trace is not positive and finite */
+    DTRG_ESTATE = 6    /* call out of order (e.g. backward on a plan whose forward failed) */
+} dtrg_status;
+
+/* Arithmetic of the O(chi^7) and O(chi^6) contractions.  The eigensolver, its adjoint, all
+ * norms and the log accumulation are always FP64. */
+typedef enum {
+    DTRG_FP64 = 0,     /* FP64 operands, FP64 MFMA */
+    DTRG_FP32 = 1,     /* FP32 operands, FP32 MFMA, FP32 accumulation */
+    DTRG_BF16X3 = 2    /* FP32 operands split as hi + lo in bf16; hi*hi + hi*lo + lo*hi on bf16
+                          MFMA with FP32 accumulation */
+} dtrg_precision;
+
+typedef struct {
+    int contract;             /* dtrg_precision; default DTRG_FP64 */
+    int gram_fp64;            /* 1: half-environments and Gram in FP64 whatever `contract` is
+                                 (default 1) */
+    double eig_broadening;    /* eps in d / (d^2 + eps), on the trace-normalised spectrum;
+                                 default 1e-12 */
+    int max_subspace_iters;   /* cap on block subspace iterations per step; default 60 */
+    double subspace_tol;      /* residual |G v - theta v| on the trace-normalised Gram at which
+                                 the kept Ritz vectors count as converged; default 1e-15.  If the
+                                 residual stops decreasing above it, the step is accepted when the
+                                 residual is below 1e-12 and fails with DTRG_ENOCONV otherwise. */
+    int block_size;           /* subspace block b (>= chi'); 0 = automatic (min(96, 2 chi')) */
+    int keep_projections;     /* 1: keep every step's chi^5 intermediates for the backward instead
+                                 of recomputing them (more memory, fewer flops); default 0 */
+} dtrg_options;
+
+/* Per-step diagnostics, all gauge invariant. */
+typedef struct {
+    int X;                    /* horizontal bond dimension entering the step */
+    int Y;                    /* vertical bond dimension entering the step */
+    int chi_kept;             /* chi' = min(chi, X^2) */
+    int full_eig;             /* 1 if the whole spectrum was computed (X^2 <= block limit) */
+    int iters;                /* subspace iterations used (0 for a full eigensolve) */
+    double c;                 /* Frobenius norm of the unnormalised step output */
+    double trace_G;           /* trace of the symmetrised Gram */
+    double lam_last_kept;     /* smallest kept eigenvalue of the normalised Gram */
+    double lam_first_dropped; /* largest discarded eigenvalue (or Ritz value) */
+    double resid;             /* largest kept residual |G v - theta v| */
+    int cheb_degree;          /* degree of the complement expansion in the last backward */
+} dtrg_step_info;
+
+typedef struct dtrg_plan dtrg_plan;
+
+/* Fill *opt with the defaults documented above. */
+void dtrg_default_options(dtrg_options* opt);
+
+/*
+ * Forward pass: ln Z / N for the 2^n_steps-site periodic network of T0.
+ *   T0_dev        device, D^4 doubles, [l][u][r][d]; read only; all entries finite, not all 0.
+ *   D             bond dimension of T0, 1 <= D <= 64.
+ *   chi           truncation bond dimension, 1 <= chi <= 80.
+ *   n_steps       number of single-direction HOTRG steps, 1 <= n_steps <= 62.
+ *   opt           options or NULL for the defaults.
+ *   stream        hipStream_t or NULL.
+ *   plan_out      receives a plan holding one checkpoint per step (needed by the backward).
+ *   lnZ_per_site_host  receives ln Z / N.
+ * Synchronises `stream`.  DTRG_EINVAL for bad sizes / NULL pointers / non-finite T0,
+ * DTRG_ENONPOS if T0 is zero or a scale or the final trace is not positive, DTRG_ENOCONV if the
+ * eigensolver stalls above 1e-12, DTRG_ENOMEM / DTRG_EHIP on runtime failures.
+ */
+dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps,
+                               const dtrg_options* opt, void* stream, dtrg_plan** plan_out,
+                               double* lnZ_per_site_host);
+
+/*
+ * Backward pass: T0bar = gbar * d(lnZ/N)/dT0, written to T0bar_dev (device, D^4 doubles,
+ * [l][u][r][d]).  If dT0_dev (device, D^4 doubles, same layout) is not NULL, also writes
+ * <T0bar, dT0> to *dlnZ_dir_host (with dT0 = dT0/dbeta this is gbar * d(lnZ/N)/dbeta).
+ * May be called any number of times on a plan whose forward succeeded.  Synchronises `stream`.
+ */
+dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
+                                const double* dT0_dev, double* dlnZ_dir_host, void* stream);
+
+/* Diagnostics of step k (1 <= k <= n_steps) of a plan whose forward succeeded. */
+dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* info);
+
+/* Device bytes held by the plan (checkpoints + workspaces). */
+size_t dtrg_plan_device_bytes(const dtrg_plan* plan);
+
+/* Release a plan (NULL is allowed). */
+void dtrg_plan_destroy(dtrg_plan* plan);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* dtrg_last_error(void);
+
+/*
+ * Diagnostic: one plain contraction with the library's MFMA kernel,
+ *   C[r * ldc + c] = alpha * sum_k A(r, k) B(c, k) + beta * C[r * ldc + c],  r < M, c < N,
+ * with A(r, k) = A_dev[r * lda + k] (a_kmajor = 0) or A_dev[k * lda + r] (a_kmajor = 1) and
+ * B(c, k) = B_dev[c * ldb + k] (b_kmajor = 0) or B_dev[k * ldb + c] (b_kmajor = 1).
+ * precision DTRG_FP64: A, B, C are double.  DTRG_FP32 / DTRG_BF16X3: A, B are float and C is
+ * double if out_f64 else float.  Device pointers; enqueued on `stream`, not synchronised.
+ */
+dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
+                          const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,
+                          int out_f64, double alpha, double beta, void* stream);
+
+/* Library version string. */
+const char* dtrg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTRG_H */

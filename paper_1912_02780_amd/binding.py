@@ -1,0 +1,197 @@
+"""ctypes binding of ``libdtrg.so`` (the C ABI in include/dtrg.h), with the same entry-point names.
+
+Argument marshalling only: every step of the HOTRG forward and backward runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  If the library has not
+been built, importing this module raises (there is no fallback implementation).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdtrg.so")
+
+DTRG_OK, DTRG_EINVAL, DTRG_ENOMEM, DTRG_EHIP, DTRG_ENOCONV, DTRG_ENONPOS, DTRG_ESTATE = range(7)
+STATUS_NAMES = {0: "DTRG_OK", 1: "DTRG_EINVAL", 2: "DTRG_ENOMEM", 3: "DTRG_EHIP", 4: "DTRG_ENOCONV",
+                5: "DTRG_ENONPOS", 6: "DTRG_ESTATE"}
+DTRG_FP64, DTRG_FP32, DTRG_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3}
+
+EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_hotrg_backward", "dtrg_plan_step_info",
+            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_version", "dtrg_contract"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
+                ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
+                ("keep_projections", c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("X", c_int), ("Y", c_int), ("chi_kept", c_int), ("full_eig", c_int), ("iters", c_int),
+                ("c", c_double), ("trace_G", c_double), ("lam_last_kept", c_double),
+                ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class DtrgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1912_02780_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.dtrg_default_options.argtypes = [POINTER(Options)]
+    lib.dtrg_default_options.restype = None
+    lib.dtrg_hotrg_forward.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(Options), c_void_p,
+                                       POINTER(c_void_p), POINTER(c_double)]
+    lib.dtrg_hotrg_forward.restype = c_int
+    lib.dtrg_hotrg_backward.argtypes = [c_void_p, c_double, c_void_p, c_void_p, POINTER(c_double), c_void_p]
+    lib.dtrg_hotrg_backward.restype = c_int
+    lib.dtrg_plan_step_info.argtypes = [c_void_p, c_int, POINTER(StepInfo)]
+    lib.dtrg_plan_step_info.restype = c_int
+    lib.dtrg_plan_device_bytes.argtypes = [c_void_p]
+    lib.dtrg_plan_device_bytes.restype = c_size_t
+    lib.dtrg_plan_destroy.argtypes = [c_void_p]
+    lib.dtrg_plan_destroy.restype = None
+    lib.dtrg_last_error.argtypes = []
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    lib.dtrg_version.argtypes = []
+    lib.dtrg_version.restype = ctypes.c_char_p
+    lib.dtrg_contract.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_longlong, c_int, c_void_p, c_longlong,
+                                  c_int, c_void_p, c_longlong, c_int, c_double, c_double, c_void_p]
+    lib.dtrg_contract.restype = c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != DTRG_OK:
+        raise DtrgError(status, lib.dtrg_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def default_options(**overrides) -> Options:
+    o = Options()
+    lib.dtrg_default_options(byref(o))
+    for k, v in overrides.items():
+        if k == "contract" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t
+
+
+class Plan:
+    """Owns a dtrg_plan (the forward checkpoints); released with the object."""
+
+    def __init__(self, handle: int, D: int, n_steps: int, device):
+        self._h = c_void_p(handle)
+        self.D = D
+        self.n_steps = n_steps
+        self.device = device
+
+    def step_info(self, k: int) -> dict:
+        info = StepInfo()
+        _check(lib.dtrg_plan_step_info(self._h, k, byref(info)))
+        return info.as_dict()
+
+    def device_bytes(self) -> int:
+        return int(lib.dtrg_plan_device_bytes(self._h))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.dtrg_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dtrg_hotrg_forward(T0: torch.Tensor, chi: int, n_steps: int, options: Options | None = None, stream=None):
+    """Returns (plan, lnZ_per_site).  T0: [l][u][r][d] float64 CUDA tensor."""
+    T0 = _dev_f64(T0, "T0")
+    if T0.dim() != 4 or len(set(T0.shape)) != 1:
+        raise ValueError("T0 must be D x D x D x D")
+    D = int(T0.shape[0])
+    h = c_void_p()
+    out = c_double()
+    with torch.cuda.device(T0.device):
+        _check(lib.dtrg_hotrg_forward(c_void_p(T0.data_ptr()), D, int(chi), int(n_steps),
+                                      byref(options) if options is not None else None, _stream(stream),
+                                      byref(h), byref(out)))
+    return Plan(h.value, D, n_steps, T0.device), out.value
+
+
+def dtrg_hotrg_backward(plan: Plan, gbar: float = 1.0, dT0: torch.Tensor | None = None, stream=None):
+    """Returns (T0bar, <T0bar, dT0> or None)."""
+    D = plan.D
+    T0bar = torch.empty((D, D, D, D), dtype=torch.float64, device=plan.device)
+    dptr = None
+    if dT0 is not None:
+        dT0 = _dev_f64(dT0, "dT0")
+        if tuple(dT0.shape) != (D, D, D, D):
+            raise ValueError("dT0 must have the shape of T0")
+        dptr = c_void_p(dT0.data_ptr())
+    val = c_double()
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_hotrg_backward(plan._h, float(gbar), c_void_p(T0bar.data_ptr()), dptr,
+                                       byref(val) if dT0 is not None else None, _stream(stream)))
+    return T0bar, (val.value if dT0 is not None else None)
+
+
+def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, a_kmajor=False, b_kmajor=False,
+                  alpha=1.0, beta=0.0, stream=None):
+    """C = alpha * A' B'^T + beta * C with A' = A or A.T (a_kmajor), B' = B or B.T (b_kmajor)."""
+    prec = PRECISIONS[precision]
+    if a_kmajor:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    N = B.shape[1] if b_kmajor else B.shape[0]
+    for t in (A, B, C):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise TypeError("operands must be contiguous CUDA tensors")
+    in_dt = torch.float64 if prec == DTRG_FP64 else torch.float32
+    if A.dtype != in_dt or B.dtype != in_dt:
+        raise TypeError("operand dtype does not match the precision")
+    out_f64 = C.dtype == torch.float64
+    if prec == DTRG_FP64 and not out_f64:
+        raise TypeError("fp64 contraction writes float64")
+    if tuple(C.shape) != (M, N):
+        raise ValueError("C has the wrong shape")
+    _check(lib.dtrg_contract(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
+                             c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()), N,
+                             int(out_f64), float(alpha), float(beta), _stream(stream)))
+    return C
+
+
+def version() -> str:
+    return lib.dtrg_version().decode()

@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI: the built library loads and exports every function the header
+declares, and argument validation that happens before any device work returns the documented
+status codes (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dtrg.h")
+LIB = os.path.join(ROOT, "paper_1912_02780_amd", "libdtrg.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(dtrg_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libdtrg.so not built (run python -m paper_1912_02780_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dtrg_hotrg_forward", "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_destroy",
+                     "dtrg_last_error", "dtrg_default_options"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    src = open(os.path.join(ROOT, "paper_1912_02780_amd", "binding.py")).read()
+    m = re.search(r"EXPORTED = \[(.*?)\]", src, flags=re.S)
+    exported = sorted(re.findall(r'"(dtrg_[a-z0-9_]+)"', m.group(1)))
+    assert exported == declared_functions()
+
+
+def test_argument_validation_without_device_work():
+    lib = _lib()
+    lib.dtrg_hotrg_forward.restype = ctypes.c_int
+    lib.dtrg_hotrg_backward.restype = ctypes.c_int
+    lib.dtrg_plan_step_info.restype = ctypes.c_int
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    plan = ctypes.c_void_p()
+    out = ctypes.c_double()
+    # NULL T0 -> DTRG_EINVAL (1), plan set to NULL
+    st = lib.dtrg_hotrg_forward(None, 2, 4, 3, None, None, ctypes.byref(plan), ctypes.byref(out))
+    assert st == 1 and plan.value is None
+    assert b"NULL" in lib.dtrg_last_error()
+    # chi out of range with a non-NULL (never dereferenced) pointer
+    st = lib.dtrg_hotrg_forward(ctypes.c_void_p(8), 2, 0, 3, None, None, ctypes.byref(plan), ctypes.byref(out))
+    assert st == 1
+    st = lib.dtrg_hotrg_forward(ctypes.c_void_p(8), 2, 4, 0, None, None, ctypes.byref(plan), ctypes.byref(out))
+    assert st == 1
+    # backward / step info on a NULL plan
+    assert lib.dtrg_hotrg_backward(None, ctypes.c_double(1.0), ctypes.c_void_p(8), None, None, None) == 1
+    assert lib.dtrg_plan_step_info(None, 1, None) == 1
+    lib.dtrg_plan_destroy(None)
+
+
+def test_default_options():
+    lib = _lib()
+
+    class Options(ctypes.Structure):
+        _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
+                    ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
+                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int)]
+
+    o = Options()
+    lib.dtrg_default_options(ctypes.byref(o))
+    assert o.contract == 0 and o.eig_broadening == 1e-12 and o.max_subspace_iters == 60

@@ -1,0 +1,220 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle and exact references.
+
+Tolerances (FP64 path):
+  * ln Z / N within 1e-10 relative of the oracle (observed: ~1e-16);
+  * d(lnZ/N)/dbeta within 1e-10 relative;
+  * the full gradient T0bar within max(1e-10, 10 s) normwise relative, where s is the oracle's
+    own rounding sensitivity: the relative change of its T0bar when every Gram matrix is perturbed
+    by a relative 2^-52 (recorded in the golden files).  Where the truncation cuts through nearly
+    degenerate eigenvalues (gaps far below sqrt(eps)) the broadened inverse gap d / (d^2 + eps)
+    turns rounding-level eigenvalue differences into T0bar differences of order u / gap in any
+    FP64 implementation, the oracle included, so parity cannot be finer than s;
+  * per-step scales c_k within 1e-11 + lam_K (lam_K the smallest kept eigenvalue of the normalised
+    Gram: swapping nearly degenerate vectors across the cut moves c_k by at most that weight).
+Exact references (enumeration, brute force) within a few ulps of the value.
+"""
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_02780_amd import binding
+    return binding
+
+
+def _gpu(B, T0, chi, n, dT0=None, **opt):
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(np.ascontiguousarray(T0)).to(dev)
+    d = torch.from_numpy(np.ascontiguousarray(dT0)).to(dev) if dT0 is not None else None
+    options = B.default_options(**opt) if opt else None
+    plan, lnZ = B.dtrg_hotrg_forward(t, chi, n, options)
+    g, ddir = B.dtrg_hotrg_backward(plan, 1.0, d)
+    return lnZ, g.cpu().numpy(), ddir, plan
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+# ---------------------------------------------------------------------------------------------
+# exact references
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta", [0.30, 0.40, 0.4406868, 0.50])
+def test_gpu_enumeration_4x4(B, beta):
+    import exact_ising as E
+    from paper_1912_02780_amd import inputs as I
+    _say(f"[gpu] 4x4 torus beta={beta} chi=16 n=4")
+    lnZ, g, d, _ = _gpu(B, I.ising_T0(beta), 16, 4, I.ising_dT0_dbeta(beta))
+    L_ex, dL_ex = E.torus_lnZ_per_site(4, beta)
+    assert abs(lnZ - L_ex) < 1e-14
+    assert abs(d - dL_ex) < 1e-13 * abs(dL_ex)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_gpu_bruteforce_2x2(B, seed):
+    import exact_ising as E
+    _say(f"[gpu] 2x2 brute force seed={seed}")
+    T0 = np.random.default_rng(seed).random((4, 4, 4, 4))
+    Z, dZ = E.bruteforce_2x2(T0)
+    lnZ, g, _, _ = _gpu(B, T0, 16, 2)
+    assert abs(lnZ - math.log(Z) / 4) < 1e-14
+    assert _rel(g, dZ / Z / 4) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------------
+# against the oracle, inline (small sizes; several tiles and ragged edges)
+# ---------------------------------------------------------------------------------------------
+
+SMALL = [
+    # name, input, chi, n, options
+    ("ising_b0.40_chi8_n20", ("ising", 0.40), 8, 20, {}),
+    ("ising_bc_chi16_n20", ("ising", 0.4406868), 16, 20, {}),
+    ("ising_b0.30_chi16_n16", ("ising", 0.30), 16, 16, {}),
+    ("ising_b0.50_chi12_n14", ("ising", 0.50), 12, 14, {}),
+    ("random_d4_seed0_chi16_n12", ("d4", 0), 16, 12, {}),
+    ("random_d3_seed2_chi9_n7", ("raw3", 2), 9, 7, {}),
+    ("random_d5_seed3_chi13_n6", ("raw5", 3), 13, 6, {}),
+    ("ising_bc_chi20_n10_block48", ("ising", 0.4406868), 20, 10, {"block_size": 48}),
+]
+
+
+def _input(spec):
+    from paper_1912_02780_amd import inputs as I
+    kind, p = spec
+    if kind == "ising":
+        return I.ising_T0(p), I.ising_dT0_dbeta(p)
+    if kind == "d4":
+        return I.random_d4_T0(p), None
+    D = int(kind[3:])
+    return np.random.default_rng(p).random((D, D, D, D)) + 0.1, None
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_gpu_vs_oracle_small(B, case):
+    from oracle import hotrg as O
+    name, spec, chi, n, opt = case
+    T0, dT0 = _input(spec)
+    _say(f"[gpu] small parity {name}")
+    lnZ, g, d, plan = _gpu(B, T0, chi, n, dT0, **opt)
+    Lo, go, fwd = O.lnZ_and_grad(T0, chi, n)
+    assert abs(lnZ / Lo - 1) < 1e-12, (lnZ, Lo)
+    assert _rel(g, go) < 1e-10, _rel(g, go)
+    if dT0 is not None:
+        do = float(np.sum(go * dT0))
+        assert abs(d / do - 1) < 1e-10, (d, do)
+    # gauge-invariant per-step quantities
+    for k, rec in enumerate(fwd.steps, start=1):
+        info = plan.step_info(k)
+        assert info["chi_kept"] == rec.chi_kept
+        assert abs(info["c"] / rec.c - 1) < 1e-11 + rec.lam[rec.chi_kept - 1]
+        assert abs(info["trace_G"] / rec.trace_G - 1) < 1e-11 + rec.lam[rec.chi_kept - 1]
+
+
+def test_gpu_euler_identity(B):
+    from paper_1912_02780_amd import inputs as I
+    _say("[gpu] euler identity")
+    T0 = I.ising_T0(0.42)
+    _, g, _, _ = _gpu(B, T0, 12, 16)
+    assert abs(float(np.sum(g * T0)) - 1.0) < 1e-12
+
+
+def test_gpu_repeatable(B):
+    from paper_1912_02780_amd import inputs as I
+    _say("[gpu] bitwise repeatability")
+    T0 = I.random_d4_T0(1)
+    a = _gpu(B, T0, 16, 8)
+    b = _gpu(B, T0, 16, 8)
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------------------------
+# full-size workloads against oracle-written goldens
+# ---------------------------------------------------------------------------------------------
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden {name} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+FULL = ["ising_b0.4406868_chi24_n24", "ising_b0.30_chi32_n30", "ising_b0.4406868_chi32_n30",
+        "ising_b0.50_chi32_n30", "random_d4_seed0_chi48_n24"]
+
+
+@pytest.mark.parametrize("name", FULL)
+def test_gpu_vs_golden_fp64(B, name):
+    from paper_1912_02780_amd import inputs as I
+    gd = _golden(name)
+    if gd["input"] == "ising":
+        T0, dT0 = I.ising_T0(gd["param"]), I.ising_dT0_dbeta(gd["param"])
+    else:
+        T0, dT0 = I.random_d4_T0(int(gd["param"])), None
+    _say(f"[gpu] golden parity {name}")
+    lnZ, g, d, plan = _gpu(B, T0, gd["chi"], gd["n_steps"], dT0)
+    go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
+    tol_g = max(1e-10, 10.0 * gd["rounding_sensitivity_T0bar"])
+    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.3e}  T0bar rel {_rel(g, go):.3e} (tol {tol_g:.1e})"
+         + (f"  dbeta rel {abs(d / gd['dlnZ_dbeta'] - 1):.3e}" if dT0 is not None else ""))
+    assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-10
+    if dT0 is not None:
+        assert abs(d / gd["dlnZ_dbeta"] - 1) < 1e-10
+    assert _rel(g, go) < tol_g
+    for k in range(1, gd["n_steps"] + 1):
+        assert abs(plan.step_info(k)["c"] / gd["c"][k - 1] - 1) < 1e-11 + gd["lam_last_kept"][k - 1]
+
+
+# ---------------------------------------------------------------------------------------------
+# error paths (host-checked; nothing faults)
+# ---------------------------------------------------------------------------------------------
+
+def test_gpu_error_paths(B):
+    dev = torch.device("cuda:0")
+    _say("[gpu] error paths")
+    T = torch.ones((2, 2, 2, 2), dtype=torch.float64, device=dev)
+    bad = T.clone()
+    bad[0, 0, 0, 0] = float("nan")
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_hotrg_forward(bad, 4, 3)
+    assert e.value.status == B.DTRG_EINVAL
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_hotrg_forward(torch.zeros_like(T), 4, 3)
+    assert e.value.status == B.DTRG_ENONPOS
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_hotrg_forward(T, 0, 3)
+    assert e.value.status == B.DTRG_EINVAL
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_hotrg_forward(T, 4, 3, B.default_options(contract="bf16x3", max_subspace_iters=0))
+    assert e.value.status == B.DTRG_EINVAL
+    # a network with Z < 0: after one step (two sites on a torus) Z = tr(M^2) with
+    # M[u][d] = sum_x T0[x][u][x][d]; M = [[0, 1], [-1, 0]] gives Z = -2
+    neg = torch.zeros_like(T)
+    neg[0, 0, 0, 1] = 1.0
+    neg[0, 1, 0, 0] = -1.0
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_hotrg_forward(neg, 4, 1)
+    assert e.value.status == B.DTRG_ENONPOS
