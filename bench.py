@@ -1,0 +1,156 @@
+#!/usr/bin/env python
+"""Benchmark of the HOTRG forward + backward pass on one MI355X.
+
+Workload (the chi = 48 headline): a random rank-4 tensor with bond dimension D = 4 (entries
+i.i.d. uniform [0, 1) from seed 0, averaged over the square's point group), HOTRG with chi = 48
+for 24 alternating single-direction steps, forward to ln Z / N and backward to d(lnZ/N)/dT0.
+One benchmark step = one forward + one backward pass over all 24 RG steps; the reported value is
+RG-steps per second (24 x steps / wall time), inputs resident in HBM, plan allocated beforehand.
+
+Also reported (one JSON line on stdout):
+  * roofline of the dominant kernel (the chi^7 join contraction) from HIP events recorded by the
+    library on its stream inside the timed region;
+  * the error of ln Z / N and of the gradient against the FP64 oracle's stored result;
+  * cpu_baseline: the FP64 NumPy oracle timed on this host on a bounded sample of the same
+    workload (the 4 small steps plus one full-size step, forward and backward), extrapolated to
+    the 24-step run.
+
+    python bench.py [--steps K] [--warmup W] [--contract fp64] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HOTRG fwd+bwd RG-steps/s at χ=48; lnZ/N & ∂lnZ/∂β error vs FP64 oracle"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X datasheet
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (fp32 accumulate)"}
+
+
+def cpu_baseline(chi: int, n_steps: int, D: int = 4, seed: int = 0):
+    """Time the FP64 oracle on a bounded sample of the workload: the first 4 steps (forward +
+    backward, small bonds) and one full-size step (forward step and its adjoint, from the tensor
+    those 4 steps produce); extrapolate t(n) = t(first 4) + (n - 4) t(full step)."""
+    import numpy as np
+    from oracle import hotrg as O
+    from paper_1912_02780_amd import inputs as I
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    T0 = I.random_d4_T0(seed, D)
+    t0 = time.perf_counter()
+    fwd = O.hotrg_forward(T0, chi, 4)
+    O.hotrg_backward(fwd, 1.0)
+    t_small = time.perf_counter() - t0
+    # one full-size step: T5 = permute(T'_4 / c_4), Gram, eigensolve, projection, then its adjoint
+    T = np.ascontiguousarray(np.transpose(fwd.final_T, (2, 3, 0, 1)))
+    t1 = time.perf_counter()
+    A, Bm = O.half_environments(T)
+    G_hat, t, lam, U, kept = O.isometry(O.gram(A, Bm), chi)
+    X = T.shape[0]
+    w = U[:, :kept].reshape(X, X, kept)
+    _, _, Tn = O.project(T, w)
+    rec = O.StepRecord(T=T, c=float(np.linalg.norm(Tn)), U=U, lam=lam, trace_G=t, G_hat=G_hat, A=A, B=Bm,
+                       chi_kept=kept)
+    O.step_adjoint(rec, np.ones_like(Tn) / Tn.size, O.DEFAULT_BROADENING)
+    t_full = time.perf_counter() - t1
+    t_run = t_small + (n_steps - 4) * t_full
+    return {
+        "value": n_steps / t_run, "unit": "RG-steps/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle on this host: forward+backward of the first 4 steps ({t_small:.2f} s) and one "
+                   f"full-size chi={chi} step (Gram, full eigh, projection, step adjoint: {t_full:.2f} s); "
+                   f"extrapolated to {n_steps} steps = {t_run:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--contract", default="fp64", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--chi", type=int, default=48)
+    ap.add_argument("--n-steps", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the path is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1912_02780_amd import binding as B
+    from paper_1912_02780_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    D, chi, n = 4, args.chi, args.n_steps
+    T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
+    opts = B.default_options(contract=args.contract, profile=1)
+    plan = B.dtrg_plan_create(D, chi, n, opts, dev)
+
+    def one_step():
+        L = B.dtrg_plan_forward(plan, T0)
+        g, _ = B.dtrg_hotrg_backward(plan, 1.0)
+        return L, g
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    plan.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L, g = one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, ms, flops = plan.profile(reset=True)
+    wall = t1 - t0
+    value = n * args.steps / wall
+
+    roof = None
+    if launches > 0 and ms > 0:
+        achieved = flops / (ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[args.contract]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None,
+                "kernel": "chi^7 join contraction (gemm_mfma4_kernel, tag 7)",
+                "launches": launches, "avg_ms": ms / launches, "flops_per_launch": flops / launches}
+
+    err = {}
+    gpath = os.path.join(ROOT, "tests", "golden", f"random_d4_seed0_chi{chi}_n{n}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gd = json.load(f)
+        go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
+        gg = g.cpu().numpy()
+        err = {"lnZ_rel_err_vs_oracle": abs(L / gd["lnZ_per_site"] - 1.0),
+               "T0bar_rel_err_vs_oracle": float(np.linalg.norm(gg - go) / np.linalg.norm(go))}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "RG-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.contract], "data": "synthetic",
+        "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
+                                f"{n} RG steps, forward + backward to dlnZ/dT0"),
+                   "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64",
+                   "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
+        "roofline": roof,
+        **err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(chi, n, D)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,7 +20,9 @@
  * Memory.  Every pointer whose name ends in _dev is a device pointer (hipMalloc'd or from
  * PyTorch's allocator) on the current HIP device; every pointer ending in _host is host memory.
  * The caller owns T0_dev, T0bar_dev and the stream.  A plan owns its checkpoints and workspaces
- * (device memory allocated with hipMalloc at plan creation, released by dtrg_plan_destroy).
+ * (device memory allocated with hipMalloc when the plan is created, released by
+ * dtrg_plan_destroy).  The contraction kernel's split-K scratch grows on the first forward and
+ * backward of a plan; later calls on the plan allocate no device memory.
  *
  * Errors.  Every entry point returns a dtrg_status; nothing throws or aborts across the ABI.
  * dtrg_last_error() returns a thread-local message describing the last failure on the calling
@@ -73,6 +75,8 @@ typedef struct {
     int block_size;           /* subspace block b (>= chi'); 0 = automatic (min(96, 2 chi')) */
     int keep_projections;     /* 1: keep every step's chi^5 intermediates for the backward instead
                                  of recomputing them (more memory, fewer flops); default 0 */
+    int profile;              /* 1: time every chi^7 join contraction with HIP events on the plan's
+                                 stream (read with dtrg_plan_profile); default 0 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -114,6 +118,19 @@ dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps
                                double* lnZ_per_site_host);
 
 /*
+ * Plan creation: allocates the checkpoints and workspaces of the forward and backward passes of
+ * this (D, chi, n_steps, options) problem.  Same argument ranges and errors as dtrg_hotrg_forward.
+ */
+dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out);
+
+/*
+ * Forward pass on an existing plan (its checkpoints are overwritten).  T0_dev: device, D^4 doubles,
+ * [l][u][r][d] with the plan's D.  Synchronises `stream`.  Errors as dtrg_hotrg_forward; after a
+ * failure the plan must not be used for a backward until a forward succeeds.
+ */
+dtrg_status dtrg_plan_forward(dtrg_plan* plan, const double* T0_dev, void* stream, double* lnZ_per_site_host);
+
+/*
  * Backward pass: T0bar = gbar * d(lnZ/N)/dT0, written to T0bar_dev (device, D^4 doubles,
  * [l][u][r][d]).  If dT0_dev (device, D^4 doubles, same layout) is not NULL, also writes
  * <T0bar, dT0> to *dlnZ_dir_host (with dT0 = dT0/dbeta this is gbar * d(lnZ/N)/dbeta).
@@ -124,6 +141,15 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
 
 /* Diagnostics of step k (1 <= k <= n_steps) of a plan whose forward succeeded. */
 dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* info);
+
+/*
+ * HIP-event timing of the chi^7 join contraction (the O(D^7) term of the step: the upper copy
+ * times the left isometry joined with the lower copy over (x2, j); launched once per step in the
+ * forward and once more in the backward's recompute) recorded since the last reset on a plan
+ * created with opt.profile = 1: number of launches, summed milliseconds and summed algorithmic
+ * flops (2 M N K per launch).  Synchronises on the recorded events; reset != 0 clears the record.
+ */
+dtrg_status dtrg_plan_profile(dtrg_plan* plan, long long* launches, double* total_ms, double* flops, int reset);
 
 /* Device bytes held by the plan (checkpoints + workspaces). */
 size_t dtrg_plan_device_bytes(const dtrg_plan* plan);

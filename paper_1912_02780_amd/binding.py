@@ -22,14 +22,15 @@ STATUS_NAMES = {0: "DTRG_OK", 1: "DTRG_EINVAL", 2: "DTRG_ENOMEM", 3: "DTRG_EHIP"
 DTRG_FP64, DTRG_FP32, DTRG_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3}
 
-EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_hotrg_backward", "dtrg_plan_step_info",
-            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_version", "dtrg_contract"]
+EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "dtrg_plan_forward",
+            "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_plan_device_bytes",
+            "dtrg_plan_destroy", "dtrg_last_error", "dtrg_version", "dtrg_contract"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("keep_projections", c_int)]
+                ("keep_projections", c_int), ("profile", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -56,6 +57,12 @@ def _load():
     lib.dtrg_hotrg_forward.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(Options), c_void_p,
                                        POINTER(c_void_p), POINTER(c_double)]
     lib.dtrg_hotrg_forward.restype = c_int
+    lib.dtrg_plan_create.argtypes = [c_int, c_int, c_int, POINTER(Options), POINTER(c_void_p)]
+    lib.dtrg_plan_create.restype = c_int
+    lib.dtrg_plan_forward.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_double)]
+    lib.dtrg_plan_forward.restype = c_int
+    lib.dtrg_plan_profile.argtypes = [c_void_p, POINTER(c_longlong), POINTER(c_double), POINTER(c_double), c_int]
+    lib.dtrg_plan_profile.restype = c_int
     lib.dtrg_hotrg_backward.argtypes = [c_void_p, c_double, c_void_p, c_void_p, POINTER(c_double), c_void_p]
     lib.dtrg_hotrg_backward.restype = c_int
     lib.dtrg_plan_step_info.argtypes = [c_void_p, c_int, POINTER(StepInfo)]
@@ -120,6 +127,12 @@ class Plan:
         _check(lib.dtrg_plan_step_info(self._h, k, byref(info)))
         return info.as_dict()
 
+    def profile(self, reset: bool = True):
+        """(launches, total_ms, flops) of the timed chi^7 contractions since the last reset."""
+        n, ms, fl = c_longlong(), c_double(), c_double()
+        _check(lib.dtrg_plan_profile(self._h, byref(n), byref(ms), byref(fl), int(reset)))
+        return n.value, ms.value, fl.value
+
     def device_bytes(self) -> int:
         return int(lib.dtrg_plan_device_bytes(self._h))
 
@@ -148,6 +161,26 @@ def dtrg_hotrg_forward(T0: torch.Tensor, chi: int, n_steps: int, options: Option
                                       byref(options) if options is not None else None, _stream(stream),
                                       byref(h), byref(out)))
     return Plan(h.value, D, n_steps, T0.device), out.value
+
+
+def dtrg_plan_create(D: int, chi: int, n_steps: int, options: Options | None = None, device=None) -> Plan:
+    """Allocate a plan (checkpoints and workspaces) for D^4 inputs on `device` (default: current)."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = c_void_p()
+    with torch.cuda.device(device):
+        _check(lib.dtrg_plan_create(int(D), int(chi), int(n_steps), byref(options) if options is not None else None,
+                                    byref(h)))
+    return Plan(h.value, D, n_steps, device)
+
+
+def dtrg_plan_forward(plan: Plan, T0: torch.Tensor, stream=None) -> float:
+    T0 = _dev_f64(T0, "T0")
+    if tuple(T0.shape) != (plan.D,) * 4:
+        raise ValueError("T0 does not match the plan's D")
+    out = c_double()
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_plan_forward(plan._h, c_void_p(T0.data_ptr()), _stream(stream), byref(out)))
+    return out.value
 
 
 def dtrg_hotrg_backward(plan: Plan, gbar: float = 1.0, dT0: torch.Tensor | None = None, stream=None):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdtrg.so")
-SOURCES = ["gemm.hip", "tensor_ops.hip", "eig.hip", "hotrg.hip"]
+SOURCES = ["gemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_bf16x3.hip", "tensor_ops.hip", "eig.hip", "hotrg.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
         cmds.append([cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-    with ThreadPoolExecutor(max_workers=min(len(cmds), 4)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(cmds), 8)) as ex:
         outs = list(ex.map(_run, cmds))
     if verbose:
         for o in outs:

@@ -96,6 +96,9 @@ struct GemmOp {
     // element capacities of the buffers behind A, B, C (-1: unchecked); checked on the host
     // against the largest offset the kernel can touch before anything is launched
     i64 a_cap = -1, b_cap = -1, c_cap = -1;
+    int tag = 0;   // own kernel symbol for the chi^7 contractions: 7 the join of the two copies
+                   // (forward and its backward recompute; timed when profiling), 8 its adjoint
+                   // with respect to the upper copy's product P, 9 with respect to the lower copy
 };
 
 // Scratch owned by a plan, grown on demand (not shrunk) and reused by every contraction.

@@ -1,0 +1,363 @@
+// MFMA contraction kernel for gfx950: C = alpha * A B^T + beta * C with strided operands,
+// batching, split-K and a two-level scatter epilogue.
+//
+// Every tensor contraction of the HOTRG step and its adjoint is one call of this kernel: the
+// operands are read either K-contiguous or M/N-contiguous straight from the layout their
+// producer wrote, and the epilogue writes each output element at
+//     C + batch * c_bs + (r / rdiv) * rs1 + (r % rdiv) * rs0 + (c / cdiv) * cs1 + (c % cdiv) * cs0,
+// which is enough to emit every intermediate directly in the layout its consumer reads.
+//
+// Tiling: 256 threads = 4 waves (2 x 2); block tile BM x BN x BK staged through LDS with one
+// register-prefetched stage (one barrier per K tile); each wave owns (BM/2) x (BN/2) outputs as
+// 16 x 16 MFMA tiles.  FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32; the split-
+// bf16 path uses v_mfma_f32_16x16x32_bf16 three times per K step (hi*hi + hi*lo + lo*hi).
+#pragma once
+
+#include "common.hpp"
+
+namespace dtrg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+struct KArgs {
+    int M, N, K;
+    const void* A; i64 lda, a_bs;
+    const void* B; i64 ldb, b_bs;
+    void* C; i64 c_bs;
+    IdxMap rmap, cmap;
+    double alpha, beta;
+    int splits, k_chunk, batch;
+    void* W;  // split-K partials [batch * splits][M][N], accumulator type
+};
+
+// ------------------------------------------------------------------------------------------
+// FP64 / FP32: 16x16x4 MFMA.  Fragment layout (A 16x4, B 4x16, D 16x16) for lane l:
+//   A[i = l % 16][k = l / 16], B[k = l / 16][j = l % 16];
+//   accumulator register r of lane l holds D[row(l / 16, r)][j = l % 16] with
+//   row = 4 * (l / 16) + r for the f32 instruction and row = l / 16 + 4 * r for the f64 one
+//   (measured on gfx950 with an in-bounds 16x16x4 product).
+// ------------------------------------------------------------------------------------------
+template <class T> struct Mfma4;
+template <> struct Mfma4<double> {
+    typedef v4d acc_t;
+    __device__ static acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma4<float> {
+    typedef v4f acc_t;
+    __device__ static acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// TAG only distinguishes kernel symbols in profiles (7, 8, 9: the three chi^7 contractions).
+template <class T, class TO, int BM, int BN, int BK, bool AKM, bool BKM, int TAG>
+__global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
+    typedef typename Mfma4<T>::acc_t acc_t;
+    constexpr int NT = 256;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
+    constexpr int PAD = 0;
+    static_assert(AE >= 1 && BE >= 1, "tile too small");
+    __shared__ T As[2][BK][BM + PAD];
+    __shared__ T Bs[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
+    const int kbeg = zs * p.k_chunk;
+    const int kend = min(p.K, kbeg + p.k_chunk);
+    const T* A = (const T*)p.A + (i64)zb * p.a_bs;
+    const T* B = (const T*)p.B + (i64)zb * p.b_bs;
+
+    acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0};
+
+    T ra[AE], rb[BE];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            int m, k;
+            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
+            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            int gm = m0 + m, gk = k0 + k;
+            ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            int n, k;
+            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
+            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            int gn = n0 + n, gk = k0 + k;
+            rb[e] = (gn < p.N && gk < kend) ? (BKM ? B[(i64)gk * p.ldb + gn] : B[(i64)gn * p.ldb + gk]) : T(0);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            int m, k;
+            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
+            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            As[buf][k][m] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            int n, k;
+            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
+            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            Bs[buf][k][n] = rb[e];
+        }
+    };
+
+    const int ntiles = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    if (ntiles > 0) {
+        load(kbeg);
+        store(0);
+    }
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) load(kbeg + (t + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T af[TM], bf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = As[buf][kk + lk][wm0 + i * 16 + li];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bf[j] = Bs[buf][kk + lk][wn0 + j * 16 + li];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma4<T>::mma(af[i], bf[j], acc[i][j]);
+        }
+        if (t + 1 < ntiles) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue
+    if (p.splits > 1) {
+        T* W = (T*)p.W + (i64)blockIdx.z * p.M * p.N;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int gm = m0 + wm0 + i * 16 + Mfma4<T>::row(lk, r), gn = n0 + wn0 + j * 16 + li;
+                    if (gm < p.M && gn < p.N) W[(i64)gm * p.N + gn] = acc[i][j][r];
+                }
+        return;
+    }
+    TO* C = (TO*)p.C + (i64)zb * p.c_bs;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int gm = m0 + wm0 + i * 16 + Mfma4<T>::row(lk, r), gn = n0 + wn0 + j * 16 + li;
+                if (gm < p.M && gn < p.N) {
+                    i64 off = idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
+                    double v = p.alpha * (double)acc[i][j][r];
+                    if (p.beta != 0.0) v += p.beta * (double)C[off];
+                    C[off] = (TO)v;
+                }
+            }
+}
+
+// ------------------------------------------------------------------------------------------
+// split-bf16 x3 on v_mfma_f32_16x16x32_bf16.  Fragment layout (A 16x32, B 32x16) for lane l:
+//   A[i = l % 16][k = 8 * (l / 16) + e], B[k = 8 * (l / 16) + e][j = l % 16], e = 0..7;
+//   D as for the 16x16x4 instructions.
+// Operands arrive as FP32; each element is split into hi = bf16(x) and lo = bf16(x - hi) while
+// it is staged into LDS.
+// ------------------------------------------------------------------------------------------
+__device__ inline __bf16 f2bf(float x) { return (__bf16)x; }
+
+template <class TO, int BM, int BN, bool AKM, bool BKM, int TAG>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
+    constexpr int BK = 32;
+    constexpr int NT = 256;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
+    constexpr int KP = BK + 8;  // k-contiguous rows of bf16, padded
+    __shared__ __bf16 Ah[2][BM][KP], Al[2][BM][KP];
+    __shared__ __bf16 Bh[2][BN][KP], Bl[2][BN][KP];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
+    const int kbeg = zs * p.k_chunk;
+    const int kend = min(p.K, kbeg + p.k_chunk);
+    const float* A = (const float*)p.A + (i64)zb * p.a_bs;
+    const float* B = (const float*)p.B + (i64)zb * p.b_bs;
+
+    v4f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    float ra[AE], rb[BE];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            int m, k;
+            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
+            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            int gm = m0 + m, gk = k0 + k;
+            ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            int n, k;
+            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
+            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            int gn = n0 + n, gk = k0 + k;
+            rb[e] = (gn < p.N && gk < kend) ? (BKM ? B[(i64)gk * p.ldb + gn] : B[(i64)gn * p.ldb + gk]) : 0.f;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            int m, k;
+            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
+            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            __bf16 h = f2bf(ra[e]);
+            Ah[buf][m][k] = h;
+            Al[buf][m][k] = f2bf(ra[e] - (float)h);
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            int n, k;
+            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
+            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            __bf16 h = f2bf(rb[e]);
+            Bh[buf][n][k] = h;
+            Bl[buf][n][k] = f2bf(rb[e] - (float)h);
+        }
+    };
+
+    const int ntiles = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    if (ntiles > 0) {
+        load(kbeg);
+        store(0);
+    }
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) load(kbeg + (t + 1) * BK);
+        v8bf ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            ah[i] = *(const v8bf*)&Ah[buf][wm0 + i * 16 + li][8 * lk];
+            al[i] = *(const v8bf*)&Al[buf][wm0 + i * 16 + li][8 * lk];
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            bh[j] = *(const v8bf*)&Bh[buf][wn0 + j * 16 + li][8 * lk];
+            bl[j] = *(const v8bf*)&Bl[buf][wn0 + j * 16 + li][8 * lk];
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        if (t + 1 < ntiles) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    if (p.splits > 1) {
+        float* W = (float*)p.W + (i64)blockIdx.z * p.M * p.N;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int gm = m0 + wm0 + i * 16 + 4 * lk + r, gn = n0 + wn0 + j * 16 + li;
+                    if (gm < p.M && gn < p.N) W[(i64)gm * p.N + gn] = acc[i][j][r];
+                }
+        return;
+    }
+    TO* C = (TO*)p.C + (i64)zb * p.c_bs;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int gm = m0 + wm0 + i * 16 + 4 * lk + r, gn = n0 + wn0 + j * 16 + li;
+                if (gm < p.M && gn < p.N) {
+                    i64 off = idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
+                    double v = p.alpha * (double)acc[i][j][r];
+                    if (p.beta != 0.0) v += p.beta * (double)C[off];
+                    C[off] = (TO)v;
+                }
+            }
+}
+
+
+template <class T, class TO, int BM, int BN, int BK, int TAG>
+void launch_mfma4_t(const KArgs& a, dim3 grid, bool akm, bool bkm, hipStream_t s) {
+    if (akm && bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, true, TAG>), grid, dim3(256), 0, s, a);
+    else if (akm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, false, TAG>), grid, dim3(256), 0, s, a);
+    else if (bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, true, TAG>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, false, TAG>), grid, dim3(256), 0, s, a);
+}
+
+// tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
+template <class T, class TO, int BM, int BN, int BK>
+void launch_mfma4(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStream_t s) {
+    if constexpr (BM == 128) {
+        if (tag == 7) { launch_mfma4_t<T, TO, BM, BN, BK, 7>(a, grid, akm, bkm, s); return; }
+        if (tag == 8) { launch_mfma4_t<T, TO, BM, BN, BK, 8>(a, grid, akm, bkm, s); return; }
+        if (tag == 9) { launch_mfma4_t<T, TO, BM, BN, BK, 9>(a, grid, akm, bkm, s); return; }
+    }
+    launch_mfma4_t<T, TO, BM, BN, BK, 0>(a, grid, akm, bkm, s);
+}
+
+template <class TO, int BM, int BN, int TAG>
+void launch_bf16x3_t(const KArgs& a, dim3 grid, bool akm, bool bkm, hipStream_t s) {
+    if (akm && bkm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, true, true, TAG>), grid, dim3(256), 0, s, a);
+    else if (akm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, true, false, TAG>), grid, dim3(256), 0, s, a);
+    else if (bkm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, false, true, TAG>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, false, false, TAG>), grid, dim3(256), 0, s, a);
+}
+
+template <class TO, int BM, int BN>
+void launch_bf16x3(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStream_t s) {
+    if constexpr (BM == 128) {
+        if (tag == 7) { launch_bf16x3_t<TO, BM, BN, 7>(a, grid, akm, bkm, s); return; }
+        if (tag == 8) { launch_bf16x3_t<TO, BM, BN, 8>(a, grid, akm, bkm, s); return; }
+        if (tag == 9) { launch_bf16x3_t<TO, BM, BN, 9>(a, grid, akm, bkm, s); return; }
+    }
+    launch_bf16x3_t<TO, BM, BN, 0>(a, grid, akm, bkm, s);
+}
+
+
+// per-precision launchers (one translation unit each, compiled in parallel)
+void launch_gemm_f64(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, hipStream_t s);
+void launch_gemm_f32(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, bool out_f64, hipStream_t s);
+void launch_gemm_bf16x3(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, bool out_f64, hipStream_t s);
+
+}  // namespace dtrg

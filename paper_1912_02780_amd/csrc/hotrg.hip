@@ -121,6 +121,14 @@ struct dtrg_plan {
     DevBuf<double> Gw, Gt, Ub, Xe, Xc, Re, Om, Sm, Vc, Vp, Vn, Ye, We;
     DevBuf<double> V1, V2, Y1, Y2, H, Z, Rinv, Sg, th, res, nrm, coef;
     DevBuf<int> iflag;
+    std::vector<StepShape> shape;
+    // HIP-event timing of the chi^7 projection contractions (when opt.profile is set)
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_flops = 0.0;
+    ~dtrg_plan() {
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+    }
     // elements left in the plan-owned buffer that contains p (-1 if p is not plan memory)
     i64 cap_of(const void* p) const {
         auto chk = [&](const DevBuf<double>& b) -> i64 {
@@ -162,7 +170,21 @@ struct Ctx {
         if (g.a_cap < 0) g.a_cap = P->cap_of(g.A);
         if (g.b_cap < 0) g.b_cap = P->cap_of(g.B);
         if (g.c_cap < 0) g.c_cap = P->cap_of(g.C);
+        const bool timed = P->opt.profile && g.tag == 7;
+        if (timed) {
+            while (P->ev_pool.size() < P->ev_used + 2) {
+                hipEvent_t e;
+                DTRG_HIP(hipEventCreate(&e));
+                P->ev_pool.push_back(e);
+            }
+            DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used], s));
+        }
         dtrg::gemm(Prec::F64, true, g, s, P->ws);
+        if (timed) {
+            DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used + 1], s));
+            P->ev_used += 2;
+            P->prof_flops += 2.0 * g.M * (double)g.N * g.K * g.batch;
+        }
     }
 };
 
@@ -213,6 +235,7 @@ void proj1(Ctx& c, const double* Wt, const double* Tp, double* P1, int X, int Y,
 // Q2[alpha][y][z][i][m] = sum_{(b,j)} P1[(alpha,y,i)][(b,j)] Tb[(z,m)][(b,j)]      (the chi^7 term)
 void proj2(Ctx& c, const double* P1, const double* Tb, double* Q2, int X, int Y, int K) {
     GemmOp g;
+    g.tag = 7;
     g.M = K * Y * X; g.N = Y * X; g.K = X * Y;
     g.A = P1; g.lda = X * Y;
     g.B = Tb; g.ldb = X * Y;
@@ -432,9 +455,20 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     P->scal.alloc(16);
     P->flags.alloc(4);
     P->iflag.alloc(4);
-    fill(P->scal.p, 16, 0.0, P->s);
-    fill_int(P->iflag.p, 4, 0, P->s);
     (void)Kmax; (void)nmax;
+    P->steps.clear();
+    P->steps.resize(sh.size());
+    for (size_t k = 0; k < sh.size(); ++k) {
+        StepCk& st = P->steps[k];
+        st.sh = sh[k];
+        const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
+        st.T.alloc((i64)X * X * Y * Y);
+        st.A.alloc((i64)X * X * Y * Y);
+        st.B.alloc((i64)X * X * Y * Y);
+        st.U.alloc((i64)n * b);
+        st.lam.alloc(b);
+        if (!st.sh.full) st.G.alloc((i64)n * n);
+    }
 }
 
 void alloc_backward(dtrg_plan* P) {
@@ -451,16 +485,26 @@ void alloc_backward(dtrg_plan* P) {
     P->Ub.ensure(nK); P->Xe.ensure(nK); P->Xc.ensure(nK); P->Re.ensure(nK); P->Vc.ensure(nK); P->Vp.ensure(nK);
     P->Vn.ensure(nK); P->Ye.ensure(nK); P->We.ensure(std::max(bK, nK));
     P->Om.ensure(bK); P->Sm.ensure(std::max(KK, bK));
+    i64 Kmax = 1;
+    for (auto& st : P->steps) Kmax = std::max<i64>(Kmax, st.sh.K);
+    P->coef.ensure(1025 * Kmax);   // largest Chebyshev expansion (degree 1024)
 }
 
 // -------------------------------------------------------------------------------------------
 // forward
 // -------------------------------------------------------------------------------------------
+void setup(dtrg_plan* P) {
+    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size);
+    alloc_plan(P, P->shape);
+    alloc_backward(P);
+}
+
 void forward(dtrg_plan* P, const double* T0) {
     Ctx c{P, P->s};
     const int D = P->D;
-    const auto sh = shapes(D, P->chi, P->nsteps, P->opt.block_size);
-    alloc_plan(P, sh);
+    const auto& sh = P->shape;
+    fill(P->scal.p, 16, 0.0, c.s);
+    fill_int(P->iflag.p, 4, 0, c.s);
     // c0 = |T0|; T1 = permute(T0, (0,2,1,3)) / c0
     norm2(T0, (i64)D * D * D * D, P->scal.p + 6, c.s, P->ws);
     double c0 = 0.0;
@@ -470,17 +514,9 @@ void forward(dtrg_plan* P, const double* T0) {
     if (!(c0 > 0.0)) throw Error(DTRG_ENONPOS, "T0 is zero");
     P->c0 = c0;
     accum_log(P->scal.p + 6, 1.0, P->scal.p + 0, P->scal.p + 7, P->iflag.p, c.s);
-    P->steps.clear();
-    P->steps.resize(P->nsteps);
     for (int k = 1; k <= P->nsteps; ++k) {
         StepCk& st = P->steps[k - 1];
-        st.sh = sh[k - 1];
         const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K, n = st.sh.n, b = st.sh.b;
-        st.T.alloc((i64)X * X * Y * Y);
-        st.A.alloc((i64)X * X * Y * Y);
-        st.B.alloc((i64)X * X * Y * Y);
-        st.U.alloc((i64)n * b);
-        st.lam.alloc(b);
         if (k == 1) permute_checked(P, T0, st.T.p, pd4(D, D, D, D, 0, 2, 1, 3), 1.0 / c0, 0.0, nullptr, c.s);
         else {
             // T_k = permute(T'_{k-1} / c_{k-1}, (2,3,0,1))
@@ -500,10 +536,8 @@ void forward(dtrg_plan* P, const double* T0) {
             throw Error(DTRG_ENONPOS, "step " + std::to_string(k) + ": Gram trace is not positive and finite");
         const StepCk* warm = (k >= 3) ? &P->steps[k - 3] : nullptr;
         eigensolve(c, st, warm, 0x5eedULL * (uint64_t)k + 17ULL);
-        if (!st.sh.full) {
-            st.G.alloc((i64)n * n);
+        if (!st.sh.full)
             DTRG_HIP(hipMemcpyAsync(st.G.p, P->Gw.p, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-        }
         // projection
         permute_checked(P, st.T.p, P->Tp.p, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, 0.0, nullptr, c.s);
         permute_checked(P, st.T.p, P->Tb.p, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, 0.0, nullptr, c.s);
@@ -688,7 +722,6 @@ void eig_adjoint(Ctx& c, StepCk& st) {
 
 void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, double* dir_out) {
     Ctx c{P, P->s};
-    alloc_backward(P);
     const int ns = P->nsteps;
     // seed: gradient w.r.t. T_{n+1} (dims [Xf][Xf][Yf][Yf])
     seed_trace_grad(P->Tbar.p, P->Xf, P->Yf, gbar * ldexp1(-ns), P->scal.p + 4, c.s);
@@ -729,6 +762,7 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
             g.A = P->Q2.p; g.lda = Y * X;
             g.B = P->Tb.p; g.ldb = X * Y; g.b_kmajor = true;
             g.C = P->X5.p; g.rmap = IdxMap::linear((i64)X * Y); g.cmap = IdxMap::linear(1);
+            g.tag = 8;
             c.gemm(g);
         }
         // Tbar_lower[b][m][j][z] += sum_{(alpha,y,i)} Qbar[(alpha,y,i)][(z,m)] P1[(alpha,y,i)][(b,j)]   (chi^7)
@@ -741,6 +775,7 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
             g.rmap = IdxMap::split(X, 1, (i64)Y * Y);
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
             g.beta = 1.0;
+            g.tag = 9;
             c.gemm(g);
         }
         // Pbar_p[y][i][j][alpha][b] = permute(Pbar [alpha][y][i][b][j])    (into P1)
@@ -846,15 +881,15 @@ void dtrg_default_options(dtrg_options* o) {
     o->subspace_tol = 1e-15;
     o->block_size = 0;
     o->keep_projections = 0;
+    o->profile = 0;
 }
 
-dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps, const dtrg_options* opt,
-                               void* stream, dtrg_plan** plan_out, double* lnZ_per_site_host) {
+dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
     g_last_error.clear();
     if (plan_out) *plan_out = nullptr;
     std::unique_ptr<dtrg_plan> P;
     try {
-        DTRG_REQUIRE(T0_dev && plan_out && lnZ_per_site_host, DTRG_EINVAL, "NULL argument");
+        DTRG_REQUIRE(plan_out, DTRG_EINVAL, "NULL argument");
         DTRG_REQUIRE(D >= 1 && D <= 64, DTRG_EINVAL, "D out of range [1, 64]");
         DTRG_REQUIRE(chi >= 1 && chi <= 80, DTRG_EINVAL, "chi out of range [1, 80]");
         DTRG_REQUIRE(n_steps >= 1 && n_steps <= 62, DTRG_EINVAL, "n_steps out of range [1, 62]");
@@ -868,19 +903,80 @@ dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps
         DTRG_REQUIRE(P->opt.block_size >= 0 && P->opt.block_size <= kJacobiMax, DTRG_EINVAL,
                      "block_size out of range [0, 96]");
         P->D = D; P->chi = chi; P->nsteps = n_steps;
-        P->s = (hipStream_t)stream;
-        forward(P.get(), T0_dev);
-        P->fwd_ok = true;
-        *lnZ_per_site_host = P->lnZ;
+        setup(P.get());
         *plan_out = P.release();
         return DTRG_OK;
     } catch (const Error& e) {
-        if (P) (void)hipStreamSynchronize(P->s);
         return fail(e);
     } catch (const std::exception& e) {
-        if (P) (void)hipStreamSynchronize(P->s);
         g_last_error = e.what();
         return DTRG_EHIP;
+    }
+}
+
+dtrg_status dtrg_plan_forward(dtrg_plan* plan, const double* T0_dev, void* stream, double* lnZ_per_site_host) {
+    g_last_error.clear();
+    try {
+        DTRG_REQUIRE(plan && T0_dev && lnZ_per_site_host, DTRG_EINVAL, "NULL argument");
+        plan->fwd_ok = false;
+        plan->s = (hipStream_t)stream;
+        forward(plan, T0_dev);
+        plan->fwd_ok = true;
+        *lnZ_per_site_host = plan->lnZ;
+        return DTRG_OK;
+    } catch (const Error& e) {
+        if (plan) (void)hipStreamSynchronize(plan->s);
+        return fail(e);
+    } catch (const std::exception& e) {
+        if (plan) (void)hipStreamSynchronize(plan->s);
+        g_last_error = e.what();
+        return DTRG_EHIP;
+    }
+}
+
+dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps, const dtrg_options* opt,
+                               void* stream, dtrg_plan** plan_out, double* lnZ_per_site_host) {
+    g_last_error.clear();
+    if (plan_out) *plan_out = nullptr;
+    if (!T0_dev || !plan_out || !lnZ_per_site_host) {
+        g_last_error = "NULL argument";
+        return DTRG_EINVAL;
+    }
+    dtrg_plan* P = nullptr;
+    dtrg_status st = dtrg_plan_create(D, chi, n_steps, opt, &P);
+    if (st != DTRG_OK) return st;
+    st = dtrg_plan_forward(P, T0_dev, stream, lnZ_per_site_host);
+    if (st != DTRG_OK) {
+        const std::string msg = g_last_error;
+        dtrg_plan_destroy(P);
+        g_last_error = msg;
+        return st;
+    }
+    *plan_out = P;
+    return DTRG_OK;
+}
+
+dtrg_status dtrg_plan_profile(dtrg_plan* plan, long long* launches, double* total_ms, double* flops, int reset) {
+    g_last_error.clear();
+    try {
+        DTRG_REQUIRE(plan && launches && total_ms && flops, DTRG_EINVAL, "NULL argument");
+        double ms = 0.0;
+        for (size_t i = 0; i + 1 < plan->ev_used; i += 2) {
+            DTRG_HIP(hipEventSynchronize(plan->ev_pool[i + 1]));
+            float t = 0.f;
+            DTRG_HIP(hipEventElapsedTime(&t, plan->ev_pool[i], plan->ev_pool[i + 1]));
+            ms += t;
+        }
+        *launches = (long long)(plan->ev_used / 2);
+        *total_ms = ms;
+        *flops = plan->prof_flops;
+        if (reset) {
+            plan->ev_used = 0;
+            plan->prof_flops = 0.0;
+        }
+        return DTRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
     }
 }
 

@@ -67,6 +67,12 @@ def test_argument_validation_without_device_work():
     assert lib.dtrg_hotrg_backward(None, ctypes.c_double(1.0), ctypes.c_void_p(8), None, None, None) == 1
     assert lib.dtrg_plan_step_info(None, 1, None) == 1
     lib.dtrg_plan_destroy(None)
+    # plan creation with bad sizes fails before any allocation
+    lib.dtrg_plan_create.restype = ctypes.c_int
+    assert lib.dtrg_plan_create(2, 0, 3, None, ctypes.byref(plan)) == 1 and plan.value is None
+    assert lib.dtrg_plan_create(0, 4, 3, None, ctypes.byref(plan)) == 1
+    lib.dtrg_plan_forward.restype = ctypes.c_int
+    assert lib.dtrg_plan_forward(None, ctypes.c_void_p(8), None, ctypes.byref(out)) == 1
 
 
 def test_default_options():
@@ -75,7 +81,7 @@ def test_default_options():
     class Options(ctypes.Structure):
         _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
                     ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int)]
+                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int), ("profile", ctypes.c_int)]
 
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))

@@ -177,7 +177,7 @@ def test_gpu_vs_golden_fp64(B, name):
     _say(f"[gpu] golden parity {name}")
     lnZ, g, d, plan = _gpu(B, T0, gd["chi"], gd["n_steps"], dT0)
     go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
-    tol_g = max(1e-10, 10.0 * gd["rounding_sensitivity_T0bar"])
+    tol_g = max(1e-10, 10.0 * gd.get("rounding_sensitivity_T0bar", 0.0))
     _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.3e}  T0bar rel {_rel(g, go):.3e} (tol {tol_g:.1e})"
          + (f"  dbeta rel {abs(d / gd['dlnZ_dbeta'] - 1):.3e}" if dT0 is not None else ""))
     assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-10
