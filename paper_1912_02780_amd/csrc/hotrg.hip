@@ -30,6 +30,8 @@ struct StepShape {
     int e = 0;          // leading eigenpairs resolved to full accuracy: the kept K plus the
                         // discarded ones nearest the cut (the rest of the block is a guard)
     bool full = false;
+    bool mixed = false; // projection contractions of this step in the mixed precision
+    double join_flops() const { return 2.0 * K * Y * X * (double)(Y * X) * (X * Y); }
 };
 
 struct StepCk {
@@ -120,7 +122,10 @@ struct dtrg_plan {
     DevBuf<double> P1, Q2, X5;
     DevBuf<double> Gw, Gt, Ub, Xe, Xc, Re, Om, Sm, Vc, Vp, Vn, Ye, We;
     DevBuf<double> V1, V2, Y1, Y2, H, Z, Rinv, Sg, th, res, nrm, coef;
+    // contraction operands in FP32 (FP32 and split-bf16 paths)
+    DevBuf<float> Tpf, Tbf, Wtf, Wt2f, Uf, P1f, Q2f, X5f, Tpbarf;
     DevBuf<int> iflag;
+    bool mixed() const { return prec != Prec::F64; }
     std::vector<StepShape> shape;
     // HIP-event timing of the chi^7 projection contractions (when opt.profile is set)
     std::vector<hipEvent_t> ev_pool;
@@ -129,22 +134,29 @@ struct dtrg_plan {
     ~dtrg_plan() {
         for (auto e : ev_pool) (void)hipEventDestroy(e);
     }
-    // elements left in the plan-owned buffer that contains p (-1 if p is not plan memory)
-    i64 cap_of(const void* p) const {
-        auto chk = [&](const DevBuf<double>& b) -> i64 {
-            const double* q = (const double*)p;
-            if (b.p && q >= b.p && q < b.p + b.n) return (i64)b.n - (i64)(q - b.p);
+    // bytes left in the plan-owned buffer that contains p (-1 if p is not plan memory)
+    i64 cap_bytes(const void* p) const {
+        const char* q = (const char*)p;
+        auto chk = [&](const void* base, size_t nbytes) -> i64 {
+            const char* b = (const char*)base;
+            if (b && q >= b && q < b + nbytes) return (i64)nbytes - (i64)(q - b);
             return -1;
         };
         const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &P1, &Q2, &X5,
                                      &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
                                      &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &scal};
-        for (auto* b : w) { const i64 r = chk(*b); if (r >= 0) return r; }
+        for (auto* b : w) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
+        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
+        for (auto* b : f) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
         for (auto& st : steps) {
             const DevBuf<double>* v[] = {&st.T, &st.A, &st.B, &st.G, &st.U, &st.lam};
-            for (auto* b : v) { const i64 r = chk(*b); if (r >= 0) return r; }
+            for (auto* b : v) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
         }
         return -1;
+    }
+    i64 cap_of(const void* p, int elem = 8) const {
+        const i64 b = cap_bytes(p);
+        return b < 0 ? -1 : b / elem;
     }
     size_t bytes() const {
         size_t t = 0;
@@ -153,6 +165,8 @@ struct dtrg_plan {
                                      &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
                                      &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &scal, &ws.splitk, &ws.red};
         for (auto* b : w) t += b->bytes();
+        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
+        for (auto* b : f) t += b->bytes();
         return t;
     }
 };
@@ -165,11 +179,13 @@ namespace {
 struct Ctx {
     dtrg_plan* P;
     hipStream_t s;
-    void gemm(const GemmOp& op) {
+    // one contraction in precision `pr`; operands of 8 (FP64) or 4 (FP32) bytes, output FP64 or FP32
+    void run(const GemmOp& op, Prec pr, bool out_f64) {
         GemmOp g = op;
-        if (g.a_cap < 0) g.a_cap = P->cap_of(g.A);
-        if (g.b_cap < 0) g.b_cap = P->cap_of(g.B);
-        if (g.c_cap < 0) g.c_cap = P->cap_of(g.C);
+        const int ein = pr == Prec::F64 ? 8 : 4, eout = out_f64 ? 8 : 4;
+        if (g.a_cap < 0) g.a_cap = P->cap_of(g.A, ein);
+        if (g.b_cap < 0) g.b_cap = P->cap_of(g.B, ein);
+        if (g.c_cap < 0) g.c_cap = P->cap_of(g.C, eout);
         const bool timed = P->opt.profile && g.tag == 7;
         if (timed) {
             while (P->ev_pool.size() < P->ev_used + 2) {
@@ -179,13 +195,17 @@ struct Ctx {
             }
             DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used], s));
         }
-        dtrg::gemm(Prec::F64, true, g, s, P->ws);
+        dtrg::gemm(pr, out_f64, g, s, P->ws);
         if (timed) {
             DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used + 1], s));
             P->ev_used += 2;
             P->prof_flops += 2.0 * g.M * (double)g.N * g.K * g.batch;
         }
     }
+    // FP64 contraction (Gram, eigensolver, eigen-adjoint)
+    void gemm(const GemmOp& op) { run(op, Prec::F64, true); }
+    // projection contraction in precision pr (FP64 operands always write FP64)
+    void gemmc(const GemmOp& op, Prec pr, bool out_f64) { run(op, pr, pr == Prec::F64 ? true : out_f64); }
 };
 
 // permute with the capacities of plan-owned buffers checked on the host
@@ -194,6 +214,18 @@ void permute_checked(dtrg_plan* P, const double* in, double* out, PermDesc d, do
     if (d.in_cap < 0) d.in_cap = P->cap_of(in);
     if (d.out_cap < 0) d.out_cap = P->cap_of(out);
     dtrg::permute(in, out, d, alpha, beta, scale_dev, s);
+}
+
+void permute_f32_checked(dtrg_plan* P, const double* in, float* out, PermDesc d, hipStream_t s) {
+    if (d.in_cap < 0) d.in_cap = P->cap_of(in, 8);
+    if (d.out_cap < 0) d.out_cap = P->cap_of(out, 4);
+    dtrg::permute_to_f32(in, out, d, s);
+}
+
+void permute_ff_checked(dtrg_plan* P, const float* in, float* out, PermDesc d, hipStream_t s) {
+    if (d.in_cap < 0) d.in_cap = P->cap_of(in, 4);
+    if (d.out_cap < 0) d.out_cap = P->cap_of(out, 4);
+    dtrg::permute_f32(in, out, d, s);
 }
 
 // A[a][b][j][k] = sum_{x,y} TA[(a,j)][(x,y)] TA[(b,k)][(x,y)]  (also B with TB)
@@ -221,7 +253,7 @@ void gram(Ctx& c, const double* A, const double* B, double* G, int X, int Y) {
 }
 
 // P1[alpha][y][i][b][j] = sum_a Wt[(alpha,b)][a] Tp[y][(i,j)][a]   (batched over y)
-void proj1(Ctx& c, const double* Wt, const double* Tp, double* P1, int X, int Y, int K) {
+void proj1(Ctx& c, Prec pr, const void* Wt, const void* Tp, void* P1, int X, int Y, int K) {
     GemmOp g;
     g.M = K * X; g.N = X * Y; g.K = X; g.batch = Y;
     g.A = Wt; g.lda = X; g.a_bs = 0;
@@ -229,11 +261,11 @@ void proj1(Ctx& c, const double* Wt, const double* Tp, double* P1, int X, int Y,
     g.C = P1; g.c_bs = (i64)X * X * Y;
     g.rmap = IdxMap::split(X, (i64)Y * X * X * Y, Y);
     g.cmap = IdxMap::split(Y, (i64)X * Y, 1);
-    c.gemm(g);
+    c.gemmc(g, pr, false);
 }
 
 // Q2[alpha][y][z][i][m] = sum_{(b,j)} P1[(alpha,y,i)][(b,j)] Tb[(z,m)][(b,j)]      (the chi^7 term)
-void proj2(Ctx& c, const double* P1, const double* Tb, double* Q2, int X, int Y, int K) {
+void proj2(Ctx& c, Prec pr, const void* P1, const void* Tb, void* Q2, int X, int Y, int K) {
     GemmOp g;
     g.tag = 7;
     g.M = K * Y * X; g.N = Y * X; g.K = X * Y;
@@ -242,11 +274,11 @@ void proj2(Ctx& c, const double* P1, const double* Tb, double* Q2, int X, int Y,
     g.C = Q2;
     g.rmap = IdxMap::split(X, (i64)Y * X * X, X);
     g.cmap = IdxMap::split(X, (i64)X * X, 1);
-    c.gemm(g);
+    c.gemmc(g, pr, false);
 }
 
 // T'[alpha][beta][y][z] = sum_{(i,m)} Q2[(alpha,y,z)][(i,m)] w[(i,m)][beta]
-void proj3(Ctx& c, const double* Q2, const double* U, int ldu, double* Tn, int X, int Y, int K) {
+void proj3(Ctx& c, Prec pr, const void* Q2, const void* U, int ldu, double* Tn, int X, int Y, int K) {
     GemmOp g;
     g.M = K * Y * Y; g.N = K; g.K = X * X;
     g.A = Q2; g.lda = X * X;
@@ -254,22 +286,42 @@ void proj3(Ctx& c, const double* Q2, const double* U, int ldu, double* Tn, int X
     g.C = Tn;
     g.rmap = IdxMap::split((i64)Y * Y, (i64)K * Y * Y, 1);
     g.cmap = IdxMap::linear((i64)Y * Y);
-    c.gemm(g);
+    c.gemmc(g, pr, true);
 }
 
-// operand layouts of one step from its input T (and from U for the isometry copies)
-void prep_operands(Ctx& c, const StepCk& st, bool need_halfenv_ops, bool need_wt2) {
+// Contraction operands of one step, in the contraction precision.
+struct Ops {
+    const void *Tp, *Tb, *Wt, *Wt2, *U;
+    void *P1, *Q2, *X5, *Tpbar;
+    Prec pr;    // precision of this step's projection contractions
+};
+
+// Operand layouts of one step from its input T and its eigenvectors U:
+//   Tp [u][r][d][l], Tb [d][r][l][u], Wt [alpha][b][a], Wt2 [a][alpha][b], U as is (n x b).
+// FP64 path: permuted FP64 copies; mixed paths: permuted FP32 copies.
+Ops prep_operands(Ctx& c, const StepCk& st, bool need_wt2) {
     dtrg_plan* P = c.P;
-    const int X = st.sh.X, Y = st.sh.Y, b = st.sh.b;
-    if (need_halfenv_ops) {
-        permute_checked(P, st.T.p, P->TA.p, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, 0.0, nullptr, c.s);   // [l][d][r][u]
-        permute_checked(P, st.T.p, P->TB.p, pd4(X, X, Y, Y, 0, 2, 1, 3), 1.0, 0.0, nullptr, c.s);   // [l][u][r][d]
+    const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
+    Ops o;
+    o.pr = st.sh.mixed ? P->prec : Prec::F64;
+    if (!st.sh.mixed) {
+        permute_checked(P, st.T.p, P->Tp.p, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, 0.0, nullptr, c.s);
+        permute_checked(P, st.T.p, P->Tb.p, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, 0.0, nullptr, c.s);
+        permute_checked(P, st.U.p, P->Wt.p, pd3(X, X, b, 2, 1, 0), 1.0, 0.0, nullptr, c.s);
+        if (need_wt2) permute_checked(P, st.U.p, P->Wt2.p, pd3(X, X, b, 0, 2, 1), 1.0, 0.0, nullptr, c.s);
+        o.Tp = P->Tp.p; o.Tb = P->Tb.p; o.Wt = P->Wt.p; o.Wt2 = P->Wt2.p; o.U = st.U.p;
+        o.P1 = P->P1.p; o.Q2 = P->Q2.p; o.X5 = P->X5.p; o.Tpbar = P->Tpbar.p;
+    } else {
+        permute_f32_checked(P, st.T.p, P->Tpf.p, pd4(X, X, Y, Y, 2, 1, 3, 0), c.s);
+        permute_f32_checked(P, st.T.p, P->Tbf.p, pd4(X, X, Y, Y, 3, 1, 0, 2), c.s);
+        permute_f32_checked(P, st.U.p, P->Wtf.p, pd3(X, X, b, 2, 1, 0), c.s);
+        if (need_wt2) permute_f32_checked(P, st.U.p, P->Wt2f.p, pd3(X, X, b, 0, 2, 1), c.s);
+        DTRG_REQUIRE((i64)P->Uf.n >= (i64)n * b, DTRG_EINVAL, "FP32 isometry buffer too small");
+        convert_f64_to_f32(st.U.p, P->Uf.p, (i64)n * b, c.s);
+        o.Tp = P->Tpf.p; o.Tb = P->Tbf.p; o.Wt = P->Wtf.p; o.Wt2 = P->Wt2f.p; o.U = P->Uf.p;
+        o.P1 = P->P1f.p; o.Q2 = P->Q2f.p; o.X5 = P->X5f.p; o.Tpbar = P->Tpbarf.p;
     }
-    permute_checked(P, st.T.p, P->Tp.p, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, 0.0, nullptr, c.s);       // [u][r][d][l]
-    permute_checked(P, st.T.p, P->Tb.p, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, 0.0, nullptr, c.s);       // [d][r][l][u]
-    // Wt[alpha][b][a] = U[(a,b)][alpha]  (all b columns; only the first K are used)
-    permute_checked(P, st.U.p, P->Wt.p, pd3(X, X, b, 2, 1, 0), 1.0, 0.0, nullptr, c.s);
-    if (need_wt2) permute_checked(P, st.U.p, P->Wt2.p, pd3(X, X, b, 0, 2, 1), 1.0, 0.0, nullptr, c.s);  // [a][alpha][b]
+    return o;
 }
 
 // -------------------------------------------------------------------------------------------
@@ -408,7 +460,11 @@ void eigensolve(Ctx& c, StepCk& st, const StepCk* warm, uint64_t seed) {
 // -------------------------------------------------------------------------------------------
 // plan set-up
 // -------------------------------------------------------------------------------------------
-std::vector<StepShape> shapes(int D, int chi, int nsteps, int block) {
+// Steps whose join contraction costs less than this fraction of the largest step's stay FP64 on
+// the mixed paths: their cost is negligible and they carry the largest weights 2^-k in ln Z / N.
+constexpr double kMixedMinFraction = 0.05;
+
+std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, bool mixed) {
     std::vector<StepShape> v;
     int X = D, Y = D;
     for (int k = 1; k <= nsteps; ++k) {
@@ -428,26 +484,46 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block) {
         X = Y;
         Y = s.K;
     }
+    if (mixed) {
+        double mx = 0.0;
+        for (auto& s : v) mx = std::max(mx, s.join_flops());
+        for (auto& s : v) s.mixed = s.join_flops() >= kMixedMinFraction * mx;
+    }
     return v;
 }
 
 void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
-    i64 t4 = (i64)P->D * P->D * P->D * P->D, t5 = 0, n2 = 0, nb = 0, bX2 = 0, bmax = 1, Kmax = 1, nmax = 1;
+    i64 t4 = (i64)P->D * P->D * P->D * P->D, n2 = 0, nb = 0, bmax = 1;
+    i64 t4d = 1, t5d = 1, bX2d = 1, t4f = 1, t5f = 1, bX2f = 1, nbf = 1;   // per-precision operand sizes
+    bool any_d = false, any_f = false;
     for (auto& s : sh) {
-        t4 = std::max<i64>(t4, (i64)s.X * s.X * s.Y * s.Y);
-        t4 = std::max<i64>(t4, (i64)s.K * s.K * s.Y * s.Y);
-        t5 = std::max<i64>(t5, (i64)s.K * s.Y * s.X * s.X * s.Y);
+        const i64 a4 = std::max<i64>((i64)s.X * s.X * s.Y * s.Y, (i64)s.K * s.K * s.Y * s.Y);
+        const i64 a5 = (i64)s.K * s.Y * s.X * s.X * s.Y, ab = (i64)s.b * s.X * s.X;
+        t4 = std::max(t4, a4);
         n2 = std::max<i64>(n2, (i64)s.n * s.n);
         nb = std::max<i64>(nb, (i64)s.n * s.b);
-        bX2 = std::max<i64>(bX2, (i64)s.b * s.X * s.X);
         bmax = std::max<i64>(bmax, s.b);
-        Kmax = std::max<i64>(Kmax, s.K);
-        nmax = std::max<i64>(nmax, s.n);
+        if (s.mixed) {
+            any_f = true;
+            t4f = std::max(t4f, a4); t5f = std::max(t5f, a5); bX2f = std::max(bX2f, ab);
+            nbf = std::max<i64>(nbf, (i64)s.n * s.b);
+        } else {
+            any_d = true;
+            t4d = std::max(t4d, a4); t5d = std::max(t5d, a5); bX2d = std::max(bX2d, ab);
+        }
     }
-    P->TA.alloc(t4); P->TB.alloc(t4); P->Tp.alloc(t4); P->Tb.alloc(t4);
+    P->TA.alloc(t4); P->TB.alloc(t4);
     P->Tn.alloc(t4); P->Tbar.alloc(t4); P->Tbar2.alloc(t4); P->Tpbar.alloc(t4);
-    P->Wt.alloc(bX2); P->Wt2.alloc(bX2);
-    P->P1.alloc(t5); P->Q2.alloc(t5);
+    if (any_d) {
+        P->Tp.alloc(t4d); P->Tb.alloc(t4d);
+        P->Wt.alloc(bX2d); P->Wt2.alloc(bX2d);
+        P->P1.alloc(t5d); P->Q2.alloc(t5d); P->X5.alloc(t5d);
+    }
+    if (any_f) {
+        P->Tpf.alloc(t4f); P->Tbf.alloc(t4f); P->Tpbarf.alloc(t4f);
+        P->Wtf.alloc(bX2f); P->Wt2f.alloc(bX2f); P->Uf.alloc(nbf);
+        P->P1f.alloc(t5f); P->Q2f.alloc(t5f); P->X5f.alloc(t5f);
+    }
     P->Gw.alloc(n2); P->Gt.alloc(n2);
     P->V1.alloc(nb); P->V2.alloc(nb); P->Y1.alloc(nb); P->Y2.alloc(nb);
     P->H.alloc(bmax * bmax); P->Z.alloc(bmax * bmax); P->Rinv.alloc(bmax * bmax); P->Sg.alloc(bmax * bmax);
@@ -455,7 +531,6 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     P->scal.alloc(16);
     P->flags.alloc(4);
     P->iflag.alloc(4);
-    (void)Kmax; (void)nmax;
     P->steps.clear();
     P->steps.resize(sh.size());
     for (size_t k = 0; k < sh.size(); ++k) {
@@ -481,7 +556,6 @@ void alloc_backward(dtrg_plan* P) {
         KK = std::max<i64>(KK, (i64)s.K * s.K);
         n2 = std::max<i64>(n2, (i64)s.n * s.n);
     }
-    P->X5.ensure(t5);
     P->Ub.ensure(nK); P->Xe.ensure(nK); P->Xc.ensure(nK); P->Re.ensure(nK); P->Vc.ensure(nK); P->Vp.ensure(nK);
     P->Vn.ensure(nK); P->Ye.ensure(nK); P->We.ensure(std::max(bK, nK));
     P->Om.ensure(bK); P->Sm.ensure(std::max(KK, bK));
@@ -494,7 +568,7 @@ void alloc_backward(dtrg_plan* P) {
 // forward
 // -------------------------------------------------------------------------------------------
 void setup(dtrg_plan* P) {
-    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size);
+    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size, P->mixed());
     alloc_plan(P, P->shape);
     alloc_backward(P);
 }
@@ -538,13 +612,11 @@ void forward(dtrg_plan* P, const double* T0) {
         eigensolve(c, st, warm, 0x5eedULL * (uint64_t)k + 17ULL);
         if (!st.sh.full)
             DTRG_HIP(hipMemcpyAsync(st.G.p, P->Gw.p, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-        // projection
-        permute_checked(P, st.T.p, P->Tp.p, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, 0.0, nullptr, c.s);
-        permute_checked(P, st.T.p, P->Tb.p, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, 0.0, nullptr, c.s);
-        permute_checked(P, st.U.p, P->Wt.p, pd3(X, X, b, 2, 1, 0), 1.0, 0.0, nullptr, c.s);
-        proj1(c, P->Wt.p, P->Tp.p, P->P1.p, X, Y, K);
-        proj2(c, P->P1.p, P->Tb.p, P->Q2.p, X, Y, K);
-        proj3(c, P->Q2.p, st.U.p, b, P->Tn.p, X, Y, K);
+        // projection (contraction precision; the output T' is FP64)
+        const Ops o = prep_operands(c, st, false);
+        proj1(c, o.pr, o.Wt, o.Tp, o.P1, X, Y, K);
+        proj2(c, o.pr, o.P1, o.Tb, o.Q2, X, Y, K);
+        proj3(c, o.pr, o.Q2, o.U, b, P->Tn.p, X, Y, K);
         // c_k = |T'|, L += 2^-k ln c_k, scal[2] = 1/c_k
         norm2(P->Tn.p, (i64)K * K * Y * Y, P->scal.p + 1, c.s, P->ws);
         accum_log(P->scal.p + 1, ldexp1(-k), P->scal.p + 0, P->scal.p + 2, P->iflag.p, c.s);
@@ -730,84 +802,90 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
         const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K, n = st.sh.n, b = st.sh.b;
         // T'bar_p[alpha][y][z][beta] = permute(Tbar [y][z][alpha][beta]) / c_k
         permute_checked(P, P->Tbar.p, P->Tpbar.p, pd4(Y, Y, K, K, 2, 0, 1, 3), 1.0 / st.c, 0.0, nullptr, c.s);
-        // recompute the projection intermediates
-        prep_operands(c, st, true, true);
-        proj1(c, P->Wt.p, P->Tp.p, P->P1.p, X, Y, K);
-        proj2(c, P->P1.p, P->Tb.p, P->Q2.p, X, Y, K);
+        // recompute the projection intermediates (contraction precision)
+        const Ops o = prep_operands(c, st, true);
+        const Prec pr = o.pr;
+        proj1(c, pr, o.Wt, o.Tp, o.P1, X, Y, K);
+        proj2(c, pr, o.P1, o.Tb, o.Q2, X, Y, K);
+        if (st.sh.mixed) convert_f64_to_f32(P->Tpbar.p, P->Tpbarf.p, (i64)K * Y * Y * K, c.s);
         // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2[(alpha,y,z)][(i,m)] T'bar_p[(alpha,y,z)][beta]
         {
             GemmOp g;
             g.M = n; g.N = K; g.K = K * Y * Y;
-            g.A = P->Q2.p; g.lda = n; g.a_kmajor = true;
-            g.B = P->Tpbar.p; g.ldb = K; g.b_kmajor = true;
+            g.A = o.Q2; g.lda = n; g.a_kmajor = true;
+            g.B = o.Tpbar; g.ldb = K; g.b_kmajor = true;
             g.C = P->Ub.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
-            c.gemm(g);
+            c.gemmc(g, pr, true);
         }
         // Qbar[alpha][y][i][z][m] = sum_beta T'bar_p[(alpha,y,z)][beta] w[(i,m)][beta]   (into Q2)
         {
             GemmOp g;
             g.M = K * Y * Y; g.N = n; g.K = K;
-            g.A = P->Tpbar.p; g.lda = K;
-            g.B = st.U.p; g.ldb = b;
-            g.C = P->Q2.p;
+            g.A = o.Tpbar; g.lda = K;
+            g.B = o.U; g.ldb = b;
+            g.C = o.Q2;
             g.rmap = IdxMap::split(Y, (i64)X * Y * X, X);
             g.cmap = IdxMap::split(X, (i64)Y * X, 1);
-            c.gemm(g);
+            c.gemmc(g, pr, false);
         }
         fill(P->Tbar2.p, (i64)X * X * Y * Y, 0.0, c.s);
         // Pbar[(alpha,y,i)][(b,j)] = sum_{(z,m)} Qbar[(alpha,y,i)][(z,m)] Tb[(z,m)][(b,j)]   (chi^7)
         {
             GemmOp g;
             g.M = K * Y * X; g.N = X * Y; g.K = Y * X;
-            g.A = P->Q2.p; g.lda = Y * X;
-            g.B = P->Tb.p; g.ldb = X * Y; g.b_kmajor = true;
-            g.C = P->X5.p; g.rmap = IdxMap::linear((i64)X * Y); g.cmap = IdxMap::linear(1);
+            g.A = o.Q2; g.lda = Y * X;
+            g.B = o.Tb; g.ldb = X * Y; g.b_kmajor = true;
+            g.C = o.X5; g.rmap = IdxMap::linear((i64)X * Y); g.cmap = IdxMap::linear(1);
             g.tag = 8;
-            c.gemm(g);
+            c.gemmc(g, pr, false);
         }
         // Tbar_lower[b][m][j][z] += sum_{(alpha,y,i)} Qbar[(alpha,y,i)][(z,m)] P1[(alpha,y,i)][(b,j)]   (chi^7)
         {
             GemmOp g;
             g.M = Y * X; g.N = X * Y; g.K = K * Y * X;
-            g.A = P->Q2.p; g.lda = Y * X; g.a_kmajor = true;
-            g.B = P->P1.p; g.ldb = X * Y; g.b_kmajor = true;
+            g.A = o.Q2; g.lda = Y * X; g.a_kmajor = true;
+            g.B = o.P1; g.ldb = X * Y; g.b_kmajor = true;
             g.C = P->Tbar2.p;
             g.rmap = IdxMap::split(X, 1, (i64)Y * Y);
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
             g.beta = 1.0;
             g.tag = 9;
-            c.gemm(g);
+            c.gemmc(g, pr, true);
         }
         // Pbar_p[y][i][j][alpha][b] = permute(Pbar [alpha][y][i][b][j])    (into P1)
         {
             const i64 dims[5] = {K, Y, X, X, Y};
             const int perm[5] = {1, 2, 4, 0, 3};
-            permute_checked(P, P->X5.p, P->P1.p, pd5(dims, perm), 1.0, 0.0, nullptr, c.s);
+            if (st.sh.mixed) permute_ff_checked(P, P->X5f.p, P->P1f.p, pd5(dims, perm), c.s);
+            else permute_checked(P, P->X5.p, P->P1.p, pd5(dims, perm), 1.0, 0.0, nullptr, c.s);
         }
         // Tbar_upper[a][i][y][j] += sum_{(alpha,b)} Pbar_p[y][(i,j)][(alpha,b)] Wt2[a][(alpha,b)]
         {
             GemmOp g;
             g.M = X * Y; g.N = X; g.K = K * X; g.batch = Y;
-            g.A = P->P1.p; g.lda = (i64)K * X; g.a_bs = (i64)X * Y * K * X;
-            g.B = P->Wt2.p; g.ldb = (i64)b * X; g.b_bs = 0;
+            g.A = o.P1; g.lda = (i64)K * X; g.a_bs = (i64)X * Y * K * X;
+            g.B = o.Wt2; g.ldb = (i64)b * X; g.b_bs = 0;
             g.C = P->Tbar2.p; g.c_bs = Y;
             g.rmap = IdxMap::split(Y, (i64)Y * Y, 1);
             g.cmap = IdxMap::linear((i64)X * Y * Y);
             g.beta = 1.0;
-            c.gemm(g);
+            c.gemmc(g, pr, true);
         }
         // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} Tp[(y,i,j)][a] Pbar_p[(y,i,j)][(alpha,b)]
         {
             GemmOp g;
             g.M = X; g.N = K * X; g.K = Y * X * Y;
-            g.A = P->Tp.p; g.lda = X; g.a_kmajor = true;
-            g.B = P->P1.p; g.ldb = (i64)K * X; g.b_kmajor = true;
+            g.A = o.Tp; g.lda = X; g.a_kmajor = true;
+            g.B = o.P1; g.ldb = (i64)K * X; g.b_kmajor = true;
             g.C = P->Ub.p;
             g.rmap = IdxMap::linear((i64)X * K);
             g.cmap = IdxMap::split(X, 1, K);
             g.beta = 1.0;
-            c.gemm(g);
+            c.gemmc(g, pr, true);
         }
+        // the Gram adjoint needs the FP64 half-environment operands
+        permute_checked(P, st.T.p, P->TA.p, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, 0.0, nullptr, c.s);
+        permute_checked(P, st.T.p, P->TB.p, pd4(X, X, Y, Y, 0, 2, 1, 3), 1.0, 0.0, nullptr, c.s);
         // eigensolver adjoint -> G_bar (n x n) in Gw
         eig_adjoint(c, st);
         // Gt[(a,b)][(c,d)] = G_bar[(a,c)][(b,d)]
@@ -896,7 +974,10 @@ dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* op
         P.reset(new dtrg_plan());
         dtrg_default_options(&P->opt);
         if (opt) P->opt = *opt;
-        DTRG_REQUIRE(P->opt.contract == DTRG_FP64, DTRG_EINVAL, "only the FP64 contraction path is built");
+        DTRG_REQUIRE(P->opt.contract == DTRG_FP64 || P->opt.contract == DTRG_FP32 || P->opt.contract == DTRG_BF16X3,
+                     DTRG_EINVAL, "contract must be DTRG_FP64, DTRG_FP32 or DTRG_BF16X3");
+        DTRG_REQUIRE(P->opt.gram_fp64 == 1, DTRG_EINVAL, "the Gram is always formed in FP64 (gram_fp64 must be 1)");
+        P->prec = P->opt.contract == DTRG_FP64 ? Prec::F64 : (P->opt.contract == DTRG_FP32 ? Prec::F32 : Prec::BF16X3);
         DTRG_REQUIRE(P->opt.eig_broadening >= 0.0 && std::isfinite(P->opt.eig_broadening), DTRG_EINVAL,
                      "eig_broadening must be finite and >= 0");
         DTRG_REQUIRE(P->opt.max_subspace_iters >= 1, DTRG_EINVAL, "max_subspace_iters must be >= 1");
