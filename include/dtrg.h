@@ -77,6 +77,13 @@ typedef struct {
                                  of recomputing them (more memory, fewer flops); default 0 */
     int profile;              /* 1: time every chi^7 join contraction with HIP events on the plan's
                                  stream (read with dtrg_plan_profile); default 0 */
+    int bf16x3_mask;          /* with contract = DTRG_BF16X3: which contractions use split-bf16
+                                 (the others use FP32).  Bit 0: the chi^7 join (forward and its
+                                 recompute); bit 1: its adjoint w.r.t. the upper product; bit 2: its
+                                 adjoint w.r.t. the lower copy; bit 3: the six chi^6 projection
+                                 contractions.  Default 15 (all): the gradient is most accurate
+                                 when forward and adjoint contractions round alike, since the
+                                 broadened inverse gaps amplify any mismatch between them. */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */

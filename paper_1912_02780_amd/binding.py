@@ -30,7 +30,7 @@ EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "d
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("keep_projections", c_int), ("profile", c_int)]
+                ("keep_projections", c_int), ("profile", c_int), ("bf16x3_mask", c_int)]
 
 
 class StepInfo(ctypes.Structure):

@@ -92,8 +92,12 @@ void gemm(Prec prec, bool out_f64, const GemmOp& op, hipStream_t s, Scratch& ws)
         ws.splitk.ensure((size_t)need_d);
         a.W = ws.splitk.p;
     }
-    dim3 grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, op.batch * splits);
-    DTRG_REQUIRE(grid.y < 65536 && grid.x < (1u << 31), DTRG_EINVAL, "gemm: grid too large");
+    a.tiles_m = (op.M + BM - 1) / BM;
+    a.tiles_n = (op.N + BN - 1) / BN;
+    const i64 total = (i64)a.tiles_m * a.tiles_n;
+    const i64 chunk = (total + kXcds - 1) / kXcds;
+    DTRG_REQUIRE(total < (1LL << 30), DTRG_EINVAL, "gemm: grid too large");
+    dim3 grid((unsigned)(chunk * kXcds), 1, op.batch * splits);
 
     switch (prec) {
         case Prec::F64:

@@ -21,6 +21,27 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// Tile of a block.  The grid is one-dimensional in x (z = batch x split-K).  Blocks are handed
+// to the 8 XCDs round-robin (block b runs on XCD b % 8), so block b = 8 q + x is given the q-th
+// tile of XCD x's contiguous share of the tile sequence; the sequence walks bands of kGroupM
+// row tiles across all column tiles, so the blocks of one XCD reuse the same A and B tiles from
+// that XCD's L2.
+constexpr int kXcds = 8;
+constexpr int kGroupM = 4;
+
+__device__ inline bool tile_of(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int total = tiles_m * tiles_n;
+    const int chunk = (total + kXcds - 1) / kXcds;
+    const int t = (pid % kXcds) * chunk + pid / kXcds;
+    if (t >= total) return false;
+    const int band = t / (kGroupM * tiles_n);
+    const int rows = min(kGroupM, tiles_m - band * kGroupM);
+    const int r = t - band * kGroupM * tiles_n;
+    tm = band * kGroupM + r % rows;
+    tn = r / rows;
+    return true;
+}
+
 struct KArgs {
     int M, N, K;
     const void* A; i64 lda, a_bs;
@@ -29,6 +50,7 @@ struct KArgs {
     IdxMap rmap, cmap;
     double alpha, beta;
     int splits, k_chunk, batch;
+    int tiles_m, tiles_n;
     void* W;  // split-K partials [batch * splits][M][N], accumulator type
 };
 
@@ -63,7 +85,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
-    constexpr int PAD = 0;
+    constexpr int PAD = 1;   // odd row stride: the transposing LDS stores of K-contiguous tiles spread over banks
     static_assert(AE >= 1 && BE >= 1, "tile too small");
     __shared__ T As[2][BK][BM + PAD];
     __shared__ T Bs[2][BK][BN + PAD];
@@ -71,7 +93,9 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    int tmi, tni;
+    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
+    const int m0 = tmi * BM, n0 = tni * BN;
     const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
     const int kbeg = zs * p.k_chunk;
     const int kend = min(p.K, kbeg + p.k_chunk);
@@ -90,7 +114,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
         for (int e = 0; e < AE; ++e) {
             int m, k;
             if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
             int gm = m0 + m, gk = k0 + k;
             ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : T(0);
         }
@@ -98,7 +122,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
         for (int e = 0; e < BE; ++e) {
             int n, k;
             if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
             int gn = n0 + n, gk = k0 + k;
             rb[e] = (gn < p.N && gk < kend) ? (BKM ? B[(i64)gk * p.ldb + gn] : B[(i64)gn * p.ldb + gk]) : T(0);
         }
@@ -108,14 +132,14 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
         for (int e = 0; e < AE; ++e) {
             int m, k;
             if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
             As[buf][k][m] = ra[e];
         }
 #pragma unroll
         for (int e = 0; e < BE; ++e) {
             int n, k;
             if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
             Bs[buf][k][n] = rb[e];
         }
     };
@@ -200,7 +224,9 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    int tmi, tni;
+    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
+    const int m0 = tmi * BM, n0 = tni * BN;
     const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
     const int kbeg = zs * p.k_chunk;
     const int kend = min(p.K, kbeg + p.k_chunk);
@@ -219,7 +245,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
         for (int e = 0; e < AE; ++e) {
             int m, k;
             if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
             int gm = m0 + m, gk = k0 + k;
             ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : 0.f;
         }
@@ -227,7 +253,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
         for (int e = 0; e < BE; ++e) {
             int n, k;
             if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
             int gn = n0 + n, gk = k0 + k;
             rb[e] = (gn < p.N && gk < kend) ? (BKM ? B[(i64)gk * p.ldb + gn] : B[(i64)gn * p.ldb + gk]) : 0.f;
         }
@@ -237,7 +263,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
         for (int e = 0; e < AE; ++e) {
             int m, k;
             if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid * AE + e; m = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
             __bf16 h = f2bf(ra[e]);
             Ah[buf][m][k] = h;
             Al[buf][m][k] = f2bf(ra[e] - (float)h);
@@ -246,7 +272,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
         for (int e = 0; e < BE; ++e) {
             int n, k;
             if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid * BE + e; n = idx / BK; k = idx % BK; }
+            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
             __bf16 h = f2bf(rb[e]);
             Bh[buf][n][k] = h;
             Bl[buf][n][k] = f2bf(rb[e] - (float)h);

@@ -118,12 +118,12 @@ struct dtrg_plan {
     DevBuf<int> flags;
     Scratch ws;
     // workspaces
-    DevBuf<double> TA, TB, Tp, Tb, Wt, Wt2, Tn, Tbar, Tbar2, Tpbar;
+    DevBuf<double> TA, TB, Tp, Tb, Tb2, Wt, Wt2, Tn, Tbar, Tbar2, Tpbar;
     DevBuf<double> P1, Q2, X5;
     DevBuf<double> Gw, Gt, Ub, Xe, Xc, Re, Om, Sm, Vc, Vp, Vn, Ye, We;
     DevBuf<double> V1, V2, Y1, Y2, H, Z, Rinv, Sg, th, res, nrm, coef;
     // contraction operands in FP32 (FP32 and split-bf16 paths)
-    DevBuf<float> Tpf, Tbf, Wtf, Wt2f, Uf, P1f, Q2f, X5f, Tpbarf;
+    DevBuf<float> Tpf, Tbf, Tb2f, Wtf, Wt2f, Uf, P1f, Q2f, X5f, Tpbarf;
     DevBuf<int> iflag;
     bool mixed() const { return prec != Prec::F64; }
     std::vector<StepShape> shape;
@@ -142,11 +142,11 @@ struct dtrg_plan {
             if (b && q >= b && q < b + nbytes) return (i64)nbytes - (i64)(q - b);
             return -1;
         };
-        const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &P1, &Q2, &X5,
+        const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Tb2, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &P1, &Q2, &X5,
                                      &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
                                      &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &scal};
         for (auto* b : w) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
-        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
+        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Tb2f, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
         for (auto* b : f) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
         for (auto& st : steps) {
             const DevBuf<double>* v[] = {&st.T, &st.A, &st.B, &st.G, &st.U, &st.lam};
@@ -161,11 +161,11 @@ struct dtrg_plan {
     size_t bytes() const {
         size_t t = 0;
         for (auto& st : steps) t += st.T.bytes() + st.A.bytes() + st.B.bytes() + st.G.bytes() + st.U.bytes() + st.lam.bytes();
-        const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &P1, &Q2, &X5,
+        const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Tb2, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &P1, &Q2, &X5,
                                      &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
                                      &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &scal, &ws.splitk, &ws.red};
         for (auto* b : w) t += b->bytes();
-        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
+        const DevBuf<float>* f[] = {&Tpf, &Tbf, &Tb2f, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
         for (auto* b : f) t += b->bytes();
         return t;
     }
@@ -291,34 +291,45 @@ void proj3(Ctx& c, Prec pr, const void* Q2, const void* U, int ldu, double* Tn, 
 
 // Contraction operands of one step, in the contraction precision.
 struct Ops {
-    const void *Tp, *Tb, *Wt, *Wt2, *U;
+    const void *Tp, *Tb, *Tb2, *Wt, *Wt2, *U;
     void *P1, *Q2, *X5, *Tpbar;
-    Prec pr;    // precision of this step's projection contractions
+    Prec pr;    // precision of this step's contractions (FP64, FP32 or split-bf16)
+    int mask;   // with split-bf16: bit 0 join, 1 adjoint w.r.t. P, 2 w.r.t. the lower copy, 3 chi^6
+    // precision of contraction `bit`: split-bf16 only where the mask selects it, FP32 otherwise
+    Prec at(int bit) const { return (pr == Prec::BF16X3 && !(mask & (1 << bit))) ? Prec::F32 : pr; }
 };
 
 // Operand layouts of one step from its input T and its eigenvectors U:
-//   Tp [u][r][d][l], Tb [d][r][l][u], Wt [alpha][b][a], Wt2 [a][alpha][b], U as is (n x b).
+//   Tp [u][r][d][l], Tb [d][r][l][u], Wt [alpha][b][a], U as is (n x b); for the backward also
+//   Wt2 [a][alpha][b] and Tb2 [d][r][u][l].
 // FP64 path: permuted FP64 copies; mixed paths: permuted FP32 copies.
 Ops prep_operands(Ctx& c, const StepCk& st, bool need_wt2) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
     Ops o;
     o.pr = st.sh.mixed ? P->prec : Prec::F64;
+    o.mask = P->opt.bf16x3_mask;
     if (!st.sh.mixed) {
         permute_checked(P, st.T.p, P->Tp.p, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, 0.0, nullptr, c.s);
         permute_checked(P, st.T.p, P->Tb.p, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, 0.0, nullptr, c.s);
         permute_checked(P, st.U.p, P->Wt.p, pd3(X, X, b, 2, 1, 0), 1.0, 0.0, nullptr, c.s);
-        if (need_wt2) permute_checked(P, st.U.p, P->Wt2.p, pd3(X, X, b, 0, 2, 1), 1.0, 0.0, nullptr, c.s);
-        o.Tp = P->Tp.p; o.Tb = P->Tb.p; o.Wt = P->Wt.p; o.Wt2 = P->Wt2.p; o.U = st.U.p;
+        if (need_wt2) {
+            permute_checked(P, st.U.p, P->Wt2.p, pd3(X, X, b, 0, 2, 1), 1.0, 0.0, nullptr, c.s);
+            permute_checked(P, st.T.p, P->Tb2.p, pd4(X, X, Y, Y, 3, 1, 2, 0), 1.0, 0.0, nullptr, c.s);
+        }
+        o.Tp = P->Tp.p; o.Tb = P->Tb.p; o.Tb2 = P->Tb2.p; o.Wt = P->Wt.p; o.Wt2 = P->Wt2.p; o.U = st.U.p;
         o.P1 = P->P1.p; o.Q2 = P->Q2.p; o.X5 = P->X5.p; o.Tpbar = P->Tpbar.p;
     } else {
         permute_f32_checked(P, st.T.p, P->Tpf.p, pd4(X, X, Y, Y, 2, 1, 3, 0), c.s);
         permute_f32_checked(P, st.T.p, P->Tbf.p, pd4(X, X, Y, Y, 3, 1, 0, 2), c.s);
         permute_f32_checked(P, st.U.p, P->Wtf.p, pd3(X, X, b, 2, 1, 0), c.s);
-        if (need_wt2) permute_f32_checked(P, st.U.p, P->Wt2f.p, pd3(X, X, b, 0, 2, 1), c.s);
+        if (need_wt2) {
+            permute_f32_checked(P, st.U.p, P->Wt2f.p, pd3(X, X, b, 0, 2, 1), c.s);
+            permute_f32_checked(P, st.T.p, P->Tb2f.p, pd4(X, X, Y, Y, 3, 1, 2, 0), c.s);
+        }
         DTRG_REQUIRE((i64)P->Uf.n >= (i64)n * b, DTRG_EINVAL, "FP32 isometry buffer too small");
         convert_f64_to_f32(st.U.p, P->Uf.p, (i64)n * b, c.s);
-        o.Tp = P->Tpf.p; o.Tb = P->Tbf.p; o.Wt = P->Wtf.p; o.Wt2 = P->Wt2f.p; o.U = P->Uf.p;
+        o.Tp = P->Tpf.p; o.Tb = P->Tbf.p; o.Tb2 = P->Tb2f.p; o.Wt = P->Wtf.p; o.Wt2 = P->Wt2f.p; o.U = P->Uf.p;
         o.P1 = P->P1f.p; o.Q2 = P->Q2f.p; o.X5 = P->X5f.p; o.Tpbar = P->Tpbarf.p;
     }
     return o;
@@ -515,12 +526,12 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     P->TA.alloc(t4); P->TB.alloc(t4);
     P->Tn.alloc(t4); P->Tbar.alloc(t4); P->Tbar2.alloc(t4); P->Tpbar.alloc(t4);
     if (any_d) {
-        P->Tp.alloc(t4d); P->Tb.alloc(t4d);
+        P->Tp.alloc(t4d); P->Tb.alloc(t4d); P->Tb2.alloc(t4d);
         P->Wt.alloc(bX2d); P->Wt2.alloc(bX2d);
         P->P1.alloc(t5d); P->Q2.alloc(t5d); P->X5.alloc(t5d);
     }
     if (any_f) {
-        P->Tpf.alloc(t4f); P->Tbf.alloc(t4f); P->Tpbarf.alloc(t4f);
+        P->Tpf.alloc(t4f); P->Tbf.alloc(t4f); P->Tb2f.alloc(t4f); P->Tpbarf.alloc(t4f);
         P->Wtf.alloc(bX2f); P->Wt2f.alloc(bX2f); P->Uf.alloc(nbf);
         P->P1f.alloc(t5f); P->Q2f.alloc(t5f); P->X5f.alloc(t5f);
     }
@@ -614,9 +625,9 @@ void forward(dtrg_plan* P, const double* T0) {
             DTRG_HIP(hipMemcpyAsync(st.G.p, P->Gw.p, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, c.s));
         // projection (contraction precision; the output T' is FP64)
         const Ops o = prep_operands(c, st, false);
-        proj1(c, o.pr, o.Wt, o.Tp, o.P1, X, Y, K);
-        proj2(c, o.pr, o.P1, o.Tb, o.Q2, X, Y, K);
-        proj3(c, o.pr, o.Q2, o.U, b, P->Tn.p, X, Y, K);
+        proj1(c, o.at(3), o.Wt, o.Tp, o.P1, X, Y, K);
+        proj2(c, o.at(0), o.P1, o.Tb, o.Q2, X, Y, K);
+        proj3(c, o.at(3), o.Q2, o.U, b, P->Tn.p, X, Y, K);
         // c_k = |T'|, L += 2^-k ln c_k, scal[2] = 1/c_k
         norm2(P->Tn.p, (i64)K * K * Y * Y, P->scal.p + 1, c.s, P->ws);
         accum_log(P->scal.p + 1, ldexp1(-k), P->scal.p + 0, P->scal.p + 2, P->iflag.p, c.s);
@@ -804,9 +815,9 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
         permute_checked(P, P->Tbar.p, P->Tpbar.p, pd4(Y, Y, K, K, 2, 0, 1, 3), 1.0 / st.c, 0.0, nullptr, c.s);
         // recompute the projection intermediates (contraction precision)
         const Ops o = prep_operands(c, st, true);
-        const Prec pr = o.pr;
-        proj1(c, pr, o.Wt, o.Tp, o.P1, X, Y, K);
-        proj2(c, pr, o.P1, o.Tb, o.Q2, X, Y, K);
+        const Prec pr6 = o.at(3);
+        proj1(c, pr6, o.Wt, o.Tp, o.P1, X, Y, K);
+        proj2(c, o.at(0), o.P1, o.Tb, o.Q2, X, Y, K);
         if (st.sh.mixed) convert_f64_to_f32(P->Tpbar.p, P->Tpbarf.p, (i64)K * Y * Y * K, c.s);
         // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2[(alpha,y,z)][(i,m)] T'bar_p[(alpha,y,z)][beta]
         {
@@ -815,7 +826,7 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
             g.A = o.Q2; g.lda = n; g.a_kmajor = true;
             g.B = o.Tpbar; g.ldb = K; g.b_kmajor = true;
             g.C = P->Ub.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
-            c.gemmc(g, pr, true);
+            c.gemmc(g, pr6, true);
         }
         // Qbar[alpha][y][i][z][m] = sum_beta T'bar_p[(alpha,y,z)][beta] w[(i,m)][beta]   (into Q2)
         {
@@ -826,18 +837,22 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
             g.C = o.Q2;
             g.rmap = IdxMap::split(Y, (i64)X * Y * X, X);
             g.cmap = IdxMap::split(X, (i64)Y * X, 1);
-            c.gemmc(g, pr, false);
+            c.gemmc(g, pr6, false);
         }
         fill(P->Tbar2.p, (i64)X * X * Y * Y, 0.0, c.s);
-        // Pbar[(alpha,y,i)][(b,j)] = sum_{(z,m)} Qbar[(alpha,y,i)][(z,m)] Tb[(z,m)][(b,j)]   (chi^7)
+        // Pbar_p[y][i][j][alpha][b] = sum_{(z,m)} Qbar[(alpha,y,i)][(z,m)] Tb2[(z,m)][(j,b)]   (chi^7)
+        // (the adjoint of the join with respect to P, written straight in the layout of its two
+        // consumers below: rows (alpha,(y,i)), columns (j,b))
         {
             GemmOp g;
-            g.M = K * Y * X; g.N = X * Y; g.K = Y * X;
+            g.M = K * Y * X; g.N = Y * X; g.K = Y * X;
             g.A = o.Q2; g.lda = Y * X;
-            g.B = o.Tb; g.ldb = X * Y; g.b_kmajor = true;
-            g.C = o.X5; g.rmap = IdxMap::linear((i64)X * Y); g.cmap = IdxMap::linear(1);
+            g.B = o.Tb2; g.ldb = Y * X; g.b_kmajor = true;
+            g.C = o.X5;
+            g.rmap = IdxMap::split((i64)Y * X, X, (i64)Y * K * X);
+            g.cmap = IdxMap::split(X, (i64)K * X, 1);
             g.tag = 8;
-            c.gemmc(g, pr, false);
+            c.gemmc(g, o.at(1), false);
         }
         // Tbar_lower[b][m][j][z] += sum_{(alpha,y,i)} Qbar[(alpha,y,i)][(z,m)] P1[(alpha,y,i)][(b,j)]   (chi^7)
         {
@@ -850,38 +865,31 @@ void backward(dtrg_plan* P, double gbar, double* T0bar, const double* dT0, doubl
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
             g.beta = 1.0;
             g.tag = 9;
-            c.gemmc(g, pr, true);
-        }
-        // Pbar_p[y][i][j][alpha][b] = permute(Pbar [alpha][y][i][b][j])    (into P1)
-        {
-            const i64 dims[5] = {K, Y, X, X, Y};
-            const int perm[5] = {1, 2, 4, 0, 3};
-            if (st.sh.mixed) permute_ff_checked(P, P->X5f.p, P->P1f.p, pd5(dims, perm), c.s);
-            else permute_checked(P, P->X5.p, P->P1.p, pd5(dims, perm), 1.0, 0.0, nullptr, c.s);
+            c.gemmc(g, o.at(2), true);
         }
         // Tbar_upper[a][i][y][j] += sum_{(alpha,b)} Pbar_p[y][(i,j)][(alpha,b)] Wt2[a][(alpha,b)]
         {
             GemmOp g;
             g.M = X * Y; g.N = X; g.K = K * X; g.batch = Y;
-            g.A = o.P1; g.lda = (i64)K * X; g.a_bs = (i64)X * Y * K * X;
+            g.A = o.X5; g.lda = (i64)K * X; g.a_bs = (i64)X * Y * K * X;
             g.B = o.Wt2; g.ldb = (i64)b * X; g.b_bs = 0;
             g.C = P->Tbar2.p; g.c_bs = Y;
             g.rmap = IdxMap::split(Y, (i64)Y * Y, 1);
             g.cmap = IdxMap::linear((i64)X * Y * Y);
             g.beta = 1.0;
-            c.gemmc(g, pr, true);
+            c.gemmc(g, pr6, true);
         }
         // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} Tp[(y,i,j)][a] Pbar_p[(y,i,j)][(alpha,b)]
         {
             GemmOp g;
             g.M = X; g.N = K * X; g.K = Y * X * Y;
             g.A = o.Tp; g.lda = X; g.a_kmajor = true;
-            g.B = o.P1; g.ldb = (i64)K * X; g.b_kmajor = true;
+            g.B = o.X5; g.ldb = (i64)K * X; g.b_kmajor = true;
             g.C = P->Ub.p;
             g.rmap = IdxMap::linear((i64)X * K);
             g.cmap = IdxMap::split(X, 1, K);
             g.beta = 1.0;
-            c.gemmc(g, pr, true);
+            c.gemmc(g, pr6, true);
         }
         // the Gram adjoint needs the FP64 half-environment operands
         permute_checked(P, st.T.p, P->TA.p, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, 0.0, nullptr, c.s);
@@ -960,6 +968,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->block_size = 0;
     o->keep_projections = 0;
     o->profile = 0;
+    o->bf16x3_mask = 15;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -976,6 +985,7 @@ dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* op
         if (opt) P->opt = *opt;
         DTRG_REQUIRE(P->opt.contract == DTRG_FP64 || P->opt.contract == DTRG_FP32 || P->opt.contract == DTRG_BF16X3,
                      DTRG_EINVAL, "contract must be DTRG_FP64, DTRG_FP32 or DTRG_BF16X3");
+        DTRG_REQUIRE(P->opt.bf16x3_mask >= 0 && P->opt.bf16x3_mask <= 15, DTRG_EINVAL, "bf16x3_mask out of range [0, 15]");
         DTRG_REQUIRE(P->opt.gram_fp64 == 1, DTRG_EINVAL, "the Gram is always formed in FP64 (gram_fp64 must be 1)");
         P->prec = P->opt.contract == DTRG_FP64 ? Prec::F64 : (P->opt.contract == DTRG_FP32 ? Prec::F32 : Prec::BF16X3);
         DTRG_REQUIRE(P->opt.eig_broadening >= 0.0 && std::isfinite(P->opt.eig_broadening), DTRG_EINVAL,

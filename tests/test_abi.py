@@ -81,7 +81,8 @@ def test_default_options():
     class Options(ctypes.Structure):
         _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
                     ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int), ("profile", ctypes.c_int)]
+                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int), ("profile", ctypes.c_int),
+                    ("bf16x3_mask", ctypes.c_int)]
 
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))
