@@ -19,7 +19,8 @@ namespace {
 
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
-constexpr int JT = 1024;
+constexpr int JT = 512;    // Jacobi: 8 waves
+constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda,
                                                      double* __restrict__ lam, double* __restrict__ Vout,
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     __shared__ double V[JM * JLD];
     __shared__ int rp[JM / 2], rq[JM / 2];
     __shared__ double rc[JM / 2], rs[JM / 2];
-    __shared__ int nrot;
+    __shared__ int nrot, nact;
     __shared__ double fro;
     const int tid = threadIdx.x;
     const int m = n + (n & 1);  // players, padded to even with a dummy index n
@@ -46,65 +47,67 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
         if (tid == 0) fro = sqrt(s);
     }
     __syncthreads();
-    const double abs_floor = 1e-32 * fro + 1e-300;
+    // entries below the rounding level of the matrix are not rotated away (they are noise; rotating
+    // them only costs sweeps on spectra that reach the FP64 floor)
+    const double abs_floor = 0x1p-60 * fro + 1e-300;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (tid == 0) nrot = 0;
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {
-            if (tid < m / 2) {
-                int p, q;
-                if (tid == 0) { p = m - 1; q = round; }
-                else { p = (round + tid) % (m - 1); q = (round - tid + (m - 1)) % (m - 1); }
-                if (p > q) { const int t = p; p = q; q = t; }
+            // the n/2 pairs of this round are handled by wave 0 (m/2 <= 48 lanes); the pairs that
+            // need a rotation are compacted into slots 0..nact-1
+            if (tid < 64) {
+                int p = 0, q = 0, active = 0;
                 double c = 1.0, s = 0.0;
-                int active = 0;
-                if (q < n) {
-                    const double apq = A[p * JLD + q];
-                    const double app = A[p * JLD + p], aqq = A[q * JLD + q];
-                    if (fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), abs_floor)) {
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        double t;
-                        if (fabs(theta) > 1e150) t = 0.5 / theta;
-                        else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                        active = 1;
+                if (tid < m / 2) {
+                    if (tid == 0) { p = m - 1; q = round; }
+                    else { p = (round + tid) % (m - 1); q = (round - tid + (m - 1)) % (m - 1); }
+                    if (p > q) { const int t = p; p = q; q = t; }
+                    if (q < n) {
+                        const double apq = A[p * JLD + q];
+                        const double app = A[p * JLD + p], aqq = A[q * JLD + q];
+                        if (fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), abs_floor)) {
+                            const double theta = (aqq - app) / (2.0 * apq);
+                            double t;
+                            if (fabs(theta) > 1e150) t = 0.5 / theta;
+                            else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                            c = 1.0 / sqrt(1.0 + t * t);
+                            s = t * c;
+                            active = 1;
+                        }
                     }
                 }
-                rp[tid] = active ? p : -1;
-                rq[tid] = q;
-                rc[tid] = c;
-                rs[tid] = s;
-                if (active) atomicAdd(&nrot, 1);
+                const unsigned long long mask = __ballot(active);
+                const int slot = __popcll(mask & ((1ull << tid) - 1ull));
+                if (active) { rp[slot] = p; rq[slot] = q; rc[slot] = c; rs[slot] = s; }
+                if (tid == 0) { nact = __popcll(mask); nrot += nact; }
             }
             __syncthreads();
-            const int half = m / 2;
-            // rows:  row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q
-            for (int idx = tid; idx < half * n; idx += JT) {
-                const int i = idx / n, j = idx % n;
-                const int p = rp[i];
-                if (p < 0) continue;
-                const int q = rq[i];
-                const double c = rc[i], s = rs[i];
-                const double ap = A[p * JLD + j], aq = A[q * JLD + j];
-                A[p * JLD + j] = c * ap - s * aq;
-                A[q * JLD + j] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns of A and of V
-            for (int idx = tid; idx < half * n; idx += JT) {
-                const int i = idx / n, r = idx % n;
-                const int p = rp[i];
-                if (p < 0) continue;
-                const int q = rq[i];
-                const double c = rc[i], s = rs[i];
-                const double ap = A[r * JLD + p], aq = A[r * JLD + q];
-                A[r * JLD + p] = c * ap - s * aq;
-                A[r * JLD + q] = s * ap + c * aq;
-                const double vp = V[r * JLD + p], vq = V[r * JLD + q];
-                V[r * JLD + p] = c * vp - s * vq;
-                V[r * JLD + q] = s * vp + c * vq;
+            const int na = nact;
+            if (na > 0) {
+                // rows:  row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q
+                for (int idx = tid; idx < na * n; idx += JT) {
+                    const int i = idx / n, j = idx % n;
+                    const int p = rp[i], q = rq[i];
+                    const double c = rc[i], s = rs[i];
+                    const double ap = A[p * JLD + j], aq = A[q * JLD + j];
+                    A[p * JLD + j] = c * ap - s * aq;
+                    A[q * JLD + j] = s * ap + c * aq;
+                }
+                __syncthreads();
+                // columns of A and of V
+                for (int idx = tid; idx < na * n; idx += JT) {
+                    const int i = idx / n, r = idx % n;
+                    const int p = rp[i], q = rq[i];
+                    const double c = rc[i], s = rs[i];
+                    const double ap = A[r * JLD + p], aq = A[r * JLD + q];
+                    A[r * JLD + p] = c * ap - s * aq;
+                    A[r * JLD + q] = s * ap + c * aq;
+                    const double vp = V[r * JLD + p], vq = V[r * JLD + q];
+                    V[r * JLD + p] = c * vp - s * vq;
+                    V[r * JLD + q] = s * vp + c * vq;
+                }
             }
             __syncthreads();
         }
@@ -127,15 +130,19 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
 }
 
 // Lower Cholesky factor L of S + shift I in LDS, then Rinv = (L^T)^{-1} (upper) to global.
-__global__ __launch_bounds__(JT) void chol_inv_kernel(const double* __restrict__ S, int b, double shift_rel,
+// Lower Cholesky factor L of (S + shift I) in LDS (right-looking, rank-1 trailing updates in
+// parallel), then X = L^{-1} by the same elimination applied to the identity (row k of X is
+// final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.
+__global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, int b, double shift_rel,
                                                        double* __restrict__ Rinv, int* flag) {
     __shared__ double L[JM * JLD];
     __shared__ double Xs[JM * JLD];
     __shared__ double tr;
     const int tid = threadIdx.x;
-    for (int i = tid; i < b * b; i += JT) {
+    for (int i = tid; i < b * b; i += CT) {
         const int r = i / b, c = i % b;
         L[r * JLD + c] = 0.5 * (S[(i64)r * b + c] + S[(i64)c * b + r]);
+        Xs[r * JLD + c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -145,40 +152,40 @@ __global__ __launch_bounds__(JT) void chol_inv_kernel(const double* __restrict__
     }
     __syncthreads();
     const double shift = shift_rel * tr;
-    for (int i = tid; i < b; i += JT) L[i * JLD + i] += shift;
+    for (int i = tid; i < b; i += CT) L[i * JLD + i] += shift;
     __syncthreads();
     for (int k = 0; k < b; ++k) {
-        if (tid == 0) {
-            double d = L[k * JLD + k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                if (flag) atomicOr(flag, 2);
-                d = 1e-300;
-            }
-            L[k * JLD + k] = sqrt(d);
+        double d = L[k * JLD + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (tid == 0 && flag) atomicOr(flag, 2);
+            d = 1e-300;
         }
+        const double dk = sqrt(d);
+        // column k of L below the diagonal; lanes read L[k][k] before it is overwritten
+        for (int i = k + 1 + tid; i < b; i += CT) L[i * JLD + k] /= dk;
         __syncthreads();
-        const double dk = L[k * JLD + k];
-        for (int i = k + 1 + tid; i < b; i += JT) L[i * JLD + k] /= dk;
-        __syncthreads();
+        if (tid == 0) L[k * JLD + k] = dk;
         const int rem = b - k - 1;
-        for (int idx = tid; idx < rem * rem; idx += JT) {
+        for (int idx = tid; idx < rem * rem; idx += CT) {
             const int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
             if (j <= i) L[i * JLD + j] -= L[i * JLD + k] * L[j * JLD + k];
         }
         __syncthreads();
     }
-    // column j of L^{-1} by forward substitution, one thread per column
-    for (int j = tid; j < b; j += JT) {
-        for (int i = 0; i < j; ++i) Xs[i * JLD + j] = 0.0;
-        for (int i = j; i < b; ++i) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int k = j; k < i; ++k) s -= L[i * JLD + k] * Xs[k * JLD + j];
-            Xs[i * JLD + j] = s / L[i * JLD + i];
+    // X = L^{-1}: for k = 0..b-1, scale row k by 1/L[k][k], then remove it from the rows below
+    for (int k = 0; k < b; ++k) {
+        const double inv = 1.0 / L[k * JLD + k];
+        for (int j = tid; j <= k; j += CT) Xs[k * JLD + j] *= inv;
+        __syncthreads();
+        const int rem = b - k - 1;
+        for (int idx = tid; idx < rem * (k + 1); idx += CT) {
+            const int i = k + 1 + idx / (k + 1), j = idx % (k + 1);
+            Xs[i * JLD + j] -= L[i * JLD + k] * Xs[k * JLD + j];
         }
+        __syncthreads();
     }
-    __syncthreads();
     // Rinv = (L^{-1})^T
-    for (int idx = tid; idx < b * b; idx += JT) {
+    for (int idx = tid; idx < b * b; idx += CT) {
         const int i = idx / b, j = idx % b;
         Rinv[(i64)i * b + j] = (i <= j) ? Xs[j * JLD + i] : 0.0;
     }
@@ -288,7 +295,7 @@ void jacobi_eig(const double* A, int n, int lda, double* lam_dev, double* V, int
 
 void chol_inverse(const double* S, int b, double shift_rel, double* Rinv, int* flag_dev, hipStream_t s) {
     DTRG_REQUIRE(b >= 1 && b <= kJacobiMax, DTRG_EINVAL, "chol_inverse: b out of range");
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(JT), 0, s, S, b, shift_rel, Rinv, flag_dev);
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CT), 0, s, S, b, shift_rel, Rinv, flag_dev);
     DTRG_HIP(hipGetLastError());
 }
 

@@ -339,12 +339,15 @@ Ops prep_operands(Ctx& c, const StepCk& st, bool need_wt2) {
 // truncated eigensolve
 // -------------------------------------------------------------------------------------------
 
-// Orthonormalise the n x b block V in place (shifted CholeskyQR followed by two plain passes).
-void orthonormalise(Ctx& c, double* V, double* Vtmp, int n, int b) {
+// Orthonormalise the n x b block V in place: a shifted CholeskyQR pass (stable for any condition
+// number up to 1/u, which the normalised iterate can reach when the Gram has a cluster of noise-level
+// eigenvalues) followed by two plain passes.
+void orthonormalise(Ctx& c, double* V, double* Vtmp, int n, int b, bool shifted = true) {
     dtrg_plan* P = c.P;
     double* cur = V;
     double* oth = Vtmp;
-    for (int pass = 0; pass < 3; ++pass) {
+    const int first = shifted ? 0 : 1;
+    for (int pass = first; pass < 3; ++pass) {
         GemmOp g;
         g.M = g.N = b; g.K = n;
         g.A = cur; g.lda = b; g.a_kmajor = true;
@@ -363,7 +366,6 @@ void orthonormalise(Ctx& c, double* V, double* Vtmp, int n, int b) {
         c.gemm(h);
         std::swap(cur, oth);
     }
-    // three passes: the result is in the buffer V was not (odd count) -> copy back
     if (cur != V) copy2d(cur, b, V, b, n, b, c.s);
 }
 
@@ -402,9 +404,14 @@ void eigensolve(Ctx& c, StepCk& st, const StepCk* warm, uint64_t seed) {
     // block subspace iteration with Rayleigh-Ritz on the (kept) normalised Gram
     double* V = P->V1.p;
     double* Y = P->Y1.p;
-    if (warm && warm->sh.n == n && warm->sh.b == b) copy2d(warm->U.p, b, V, b, n, b, c.s);
-    else hash_fill(V, (i64)n * b, seed, c.s);
-    orthonormalise(c, V, P->V2.p, n, b);
+    // warm start: the Ritz vectors of the previous step in the same direction (orthonormal already)
+    const bool warm_used = warm && warm->sh.n == n && warm->sh.b == b;
+    if (warm_used) {
+        copy2d(warm->U.p, b, V, b, n, b, c.s);
+    } else {
+        hash_fill(V, (i64)n * b, seed, c.s);
+        orthonormalise(c, V, P->V2.p, n, b, true);
+    }
     const double tol = P->opt.subspace_tol;
     double prev = INFINITY;
     int stall = 0;
@@ -450,7 +457,7 @@ void eigensolve(Ctx& c, StepCk& st, const StepCk* warm, uint64_t seed) {
         std::swap(P->V1, P->Y1);
         V = P->V1.p;
         Y = P->Y1.p;
-        orthonormalise(c, V, P->V2.p, n, b);
+        orthonormalise(c, V, P->V2.p, n, b, true);
     }
     if (!(best <= 1e-12))
         throw Error(DTRG_ENOCONV, "truncated eigensolve: residual " + std::to_string(best) + " after " +
@@ -709,8 +716,11 @@ void eig_adjoint(Ctx& c, StepCk& st) {
     }
     if (!st.sh.full) {
         // spectrum of G_r: below the first unresolved eigenvalue, bounded by that Ritz value plus
-        // its residual (with a margin); PSD up to rounding
-        double hi = 1.1 * (std::max(st.lam_h[E], 0.0) + st.res_next) + 1e-300;
+        // its residual (with a margin), and never narrower than the rounding noise of the Gram,
+        // +-nu with nu = 64 n u lam_1 (an unconverged Ritz value of a noise cluster can sit far
+        // below the noise it came from)
+        const double nu = 64.0 * n * 0x1p-53 * std::max(st.lam_h[0], 0.0);
+        double hi = std::max(1.1 * (std::max(st.lam_h[E], 0.0) + st.res_next), nu) + 1e-300;
         std::vector<double> lamK(st.lam_h.begin(), st.lam_h.begin() + K);
         std::vector<double> cf;
         auto apply_Gr = [&](const double* v) {
@@ -740,9 +750,10 @@ void eig_adjoint(Ctx& c, StepCk& st) {
         DTRG_HIP(hipMemcpyAsync(&v0n, P->scal.p + 8, sizeof(double), hipMemcpyDeviceToHost, c.s));
         DTRG_HIP(hipStreamSynchronize(c.s));
         bool ok = (v0n == 0.0);
+        std::string trail;
         // the explicit part stays in Xe; the expansion accumulates into Xc
         for (int attempt = 0; attempt < 4 && !ok; ++attempt, hi *= 4.0) {
-            const double lo = -std::max(1e-14, 0.05 * hi);
+            const double lo = -std::max(nu, 0.05 * hi);
             int m = 8;
             for (;; m *= 2) {
                 cheb_coeffs(lamK, eps, lo, hi, m, cf);
@@ -780,8 +791,13 @@ void eig_adjoint(Ctx& c, StepCk& st) {
             DTRG_HIP(hipMemcpyAsync(&vmn, P->scal.p + 8, sizeof(double), hipMemcpyDeviceToHost, c.s));
             DTRG_HIP(hipStreamSynchronize(c.s));
             ok = std::isfinite(vmn) && vmn <= 1.5 * v0n;
+            trail += " [hi " + std::to_string(hi) + " m " + std::to_string(m) + " |v_m|/|v_0| " +
+                     std::to_string(vmn / v0n) + "]";
         }
-        if (!ok) throw Error(DTRG_ENOCONV, "eigen-adjoint: complement expansion diverged");
+        if (!ok)
+            throw Error(DTRG_ENOCONV, "eigen-adjoint: complement expansion diverged (theta_e " +
+                                          std::to_string(st.lam_h[E]) + ", residual " + std::to_string(st.res_next) +
+                                          ")" + trail);
         if (v0n != 0.0) axpy(P->Xc.p, P->Xe.p, (i64)n * K, 1.0, c.s);   // Xe += Xc
     }
     // W = X + U_K S / 2;  G_bar = (W U_K^T + U_K W^T) / t
