@@ -15,7 +15,7 @@ Also reported (one JSON line on stdout):
     workload (the 4 small steps plus one full-size step, forward and backward), extrapolated to
     the 24-step run.
 
-    python bench.py [--steps K] [--warmup W] [--contract fp64] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--contract fp32|fp64|bf16x3] [--no-cpu-baseline]
 """
 
 from __future__ import annotations
@@ -78,7 +78,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--contract", default="fp64", choices=sorted(PEAK_TFLOPS))
+    # default: the fastest path that meets both accuracy targets (lnZ/N <= 1e-6, gradient <= 1e-5)
+    ap.add_argument("--contract", default="fp32", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--chi", type=int, default=48)
     ap.add_argument("--n-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
