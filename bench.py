@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--chi", type=int, default=48)
     ap.add_argument("--n-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the path is not sharded across GPUs); "
@@ -95,6 +97,14 @@ def main():
     from paper_1912_02780_amd import inputs as I
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        # a plain copy of known size (reads and writes exactly this many bytes) for counter scaling
+        src = torch.ones(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     D, chi, n = 4, args.chi, args.n_steps
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
     opts = B.default_options(contract=args.contract, profile=1)
