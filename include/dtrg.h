@@ -21,8 +21,10 @@
  * PyTorch's allocator) on the current HIP device; every pointer ending in _host is host memory.
  * The caller owns T0_dev, T0bar_dev and the stream.  A plan owns its checkpoints and workspaces
  * (device memory allocated with hipMalloc when the plan is created, released by
- * dtrg_plan_destroy).  The contraction kernel's split-K scratch grows on the first forward and
- * backward of a plan; later calls on the plan allocate no device memory.
+ * dtrg_plan_destroy).  A step's checkpoint is its normalised input tensor, its isometry and its
+ * spectrum; the backward recomputes the rest of the step from it.  The contraction kernel's
+ * split-K scratch (and the autotuner's trial output) grows on the first forward and backward of a
+ * plan; later calls on the plan allocate no device memory.
  *
  * Errors.  Every entry point returns a dtrg_status; nothing throws or aborts across the ABI.
  * dtrg_last_error() returns a thread-local message describing the last failure on the calling
@@ -72,9 +74,13 @@ typedef struct {
                                  the kept Ritz vectors count as converged; default 1e-15.  If the
                                  residual stops decreasing above it, the step is accepted when the
                                  residual is below 1e-12 and fails with DTRG_ENOCONV otherwise. */
-    int block_size;           /* subspace block b (>= chi'); 0 = automatic (min(96, 2 chi')) */
-    int keep_projections;     /* 1: keep every step's chi^5 intermediates for the backward instead
-                                 of recomputing them (more memory, fewer flops); default 0 */
+    int block_size;           /* subspace block b (> chi', <= 96); 0 = automatic (min(96, max(chi' + 16,
+                                 2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates */
+    int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
+                                 (64 x 64, 128 x 128) and split-K factor (1..32) of the MFMA kernel
+                                 on a scratch output and keep the fastest for that shape (a table
+                                 shared by all plans of the process); 0: fixed heuristic.
+                                 Default 0 */
     int profile;              /* 1: time every chi^7 join contraction with HIP events on the plan's
                                  stream (read with dtrg_plan_profile); default 0 */
     int bf16x3_mask;          /* with contract = DTRG_BF16X3: which contractions use split-bf16
@@ -157,6 +163,57 @@ dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* in
  * flops (2 M N K per launch).  Synchronises on the recorded events; reset != 0 clears the record.
  */
 dtrg_status dtrg_plan_profile(dtrg_plan* plan, long long* launches, double* total_ms, double* flops, int reset);
+
+/*
+ * Batches.  n_inst independent problems with the same D and n_steps and their own chi (e.g. an
+ * Ising model at many temperatures and mixed bond dimensions) in one call.  Instances of equal chi
+ * share every shape and run as one batched problem (each contraction, eigensolve and reduction is
+ * one launch over all of them); the groups of different chi are independent branches.
+ *
+ * dtrg_batch_create: chi_host[n_inst] (host) holds each instance's chi; D, n_steps and each chi in
+ * the ranges of dtrg_hotrg_forward, 1 <= n_inst <= 65535; opt as for plans (shared by all).
+ * Allocates every group's checkpoints and workspaces.
+ */
+typedef struct dtrg_batch dtrg_batch;
+dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_steps, const dtrg_options* opt,
+                              dtrg_batch** batch_out);
+
+/*
+ * Forward (and backward, when T0bar_dev is not NULL) of all instances.
+ *   T0s_dev       device, n_inst x D^4 doubles, instance i at T0s_dev + i D^4, [l][u][r][d].
+ *   dT0s_dev      device, same shape, or NULL: directions for <T0bar_i, dT0_i>.
+ *   gbar          seed of the backward (the same for all instances).
+ *   lnZ_host      host, n_inst: ln Z / N of each instance.
+ *   T0bar_dev     device, n_inst x D^4 or NULL (forward only): gbar * d(lnZ/N)/dT0 per instance.
+ *   dlnZ_dir_host host, n_inst or NULL: <T0bar_i, dT0_i> (needs dT0s_dev and T0bar_dev).
+ *   replay = 0    adaptive run: iterates every eigensolve to convergence and sizes every complement
+ *                 expansion from the data (reading small results back to the host), and records
+ *                 these decisions as the batch's schedule.  Groups run one after the other on
+ *                 `stream`.
+ *   replay = 1    replays the recorded schedule from one HIP graph (captured on first use, and again
+ *                 whenever the pointer arguments or gbar differ from the captured ones) in which the
+ *                 groups are parallel branches; nothing is read back while it runs.  Every acceptance
+ *                 test of the adaptive run (eigensolver residuals, expansion decay and boundedness,
+ *                 positivity of norms and traces) is evaluated on the device and checked afterwards:
+ *                 inputs the schedule does not fit give DTRG_ENOCONV (or DTRG_ENONPOS) naming the
+ *                 instance, and a new adaptive run is needed.  DTRG_ESTATE without a prior adaptive
+ *                 run that covered the backward when T0bar_dev is given.
+ * Synchronises `stream`.  Errors otherwise as dtrg_hotrg_forward / dtrg_hotrg_backward.
+ */
+dtrg_status dtrg_batch_run(dtrg_batch* batch, const double* T0s_dev, const double* dT0s_dev, double gbar,
+                           double* lnZ_host, double* T0bar_dev, double* dlnZ_dir_host, int replay, void* stream);
+
+/* Diagnostics of step k of instance inst (0-based) after a successful run. */
+dtrg_status dtrg_batch_step_info(const dtrg_batch* batch, int inst, int k, dtrg_step_info* info);
+
+/* Device bytes held by the batch. */
+size_t dtrg_batch_device_bytes(const dtrg_batch* batch);
+
+/* Release a batch (NULL is allowed). */
+void dtrg_batch_destroy(dtrg_batch* batch);
+
+/* Number of contraction shapes in the process's autotuning table. */
+int dtrg_tuned_shapes(void);
 
 /* Device bytes held by the plan (checkpoints + workspaces). */
 size_t dtrg_plan_device_bytes(const dtrg_plan* plan);

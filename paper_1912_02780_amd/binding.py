@@ -23,14 +23,15 @@ DTRG_FP64, DTRG_FP32, DTRG_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3}
 
 EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "dtrg_plan_forward",
-            "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_plan_device_bytes",
-            "dtrg_plan_destroy", "dtrg_last_error", "dtrg_version", "dtrg_contract"]
+            "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_batch_create", "dtrg_batch_run",
+            "dtrg_batch_step_info", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
+            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_version"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("keep_projections", c_int), ("profile", c_int), ("bf16x3_mask", c_int)]
+                ("autotune", c_int), ("profile", c_int), ("bf16x3_mask", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -67,6 +68,19 @@ def _load():
     lib.dtrg_hotrg_backward.restype = c_int
     lib.dtrg_plan_step_info.argtypes = [c_void_p, c_int, POINTER(StepInfo)]
     lib.dtrg_plan_step_info.restype = c_int
+    lib.dtrg_batch_create.argtypes = [c_int, c_int, POINTER(c_int), c_int, POINTER(Options), POINTER(c_void_p)]
+    lib.dtrg_batch_create.restype = c_int
+    lib.dtrg_batch_run.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(c_double), c_void_p,
+                                   POINTER(c_double), c_int, c_void_p]
+    lib.dtrg_batch_run.restype = c_int
+    lib.dtrg_batch_step_info.argtypes = [c_void_p, c_int, c_int, POINTER(StepInfo)]
+    lib.dtrg_batch_step_info.restype = c_int
+    lib.dtrg_batch_device_bytes.argtypes = [c_void_p]
+    lib.dtrg_batch_device_bytes.restype = c_size_t
+    lib.dtrg_batch_destroy.argtypes = [c_void_p]
+    lib.dtrg_batch_destroy.restype = None
+    lib.dtrg_tuned_shapes.argtypes = []
+    lib.dtrg_tuned_shapes.restype = c_int
     lib.dtrg_plan_device_bytes.argtypes = [c_void_p]
     lib.dtrg_plan_device_bytes.restype = c_size_t
     lib.dtrg_plan_destroy.argtypes = [c_void_p]
@@ -198,6 +212,81 @@ def dtrg_hotrg_backward(plan: Plan, gbar: float = 1.0, dT0: torch.Tensor | None 
         _check(lib.dtrg_hotrg_backward(plan._h, float(gbar), c_void_p(T0bar.data_ptr()), dptr,
                                        byref(val) if dT0 is not None else None, _stream(stream)))
     return T0bar, (val.value if dT0 is not None else None)
+
+
+class Batch:
+    """Owns a dtrg_batch: n_inst instances of D^4 inputs with per-instance chi; released with the object."""
+
+    def __init__(self, handle: int, n_inst: int, D: int, n_steps: int, device):
+        self._h = c_void_p(handle)
+        self.n_inst = n_inst
+        self.D = D
+        self.n_steps = n_steps
+        self.device = device
+
+    def step_info(self, inst: int, k: int) -> dict:
+        info = StepInfo()
+        _check(lib.dtrg_batch_step_info(self._h, int(inst), int(k), byref(info)))
+        return info.as_dict()
+
+    def device_bytes(self) -> int:
+        return int(lib.dtrg_batch_device_bytes(self._h))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib.dtrg_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dtrg_batch_create(D: int, chis, n_steps: int, options: Options | None = None, device=None) -> Batch:
+    """Allocate a batch of len(chis) instances (instance i with bond dimension chis[i])."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    n = len(chis)
+    arr = (c_int * n)(*[int(c) for c in chis])
+    h = c_void_p()
+    with torch.cuda.device(device):
+        _check(lib.dtrg_batch_create(n, int(D), arr, int(n_steps), byref(options) if options is not None else None,
+                                     byref(h)))
+    return Batch(h.value, n, D, n_steps, device)
+
+
+def dtrg_batch_run(batch: Batch, T0s: torch.Tensor, dT0s: torch.Tensor | None = None, gbar: float = 1.0,
+                   backward: bool = True, replay: bool = False, T0bar: torch.Tensor | None = None, stream=None):
+    """Forward (+ backward) of every instance.  T0s: [n_inst][D][D][D][D] float64 CUDA tensor.
+    Returns (lnZ per instance (list), T0bar tensor or None, <T0bar_i, dT0_i> list or None)."""
+    n, D = batch.n_inst, batch.D
+    T0s = _dev_f64(T0s, "T0s")
+    if tuple(T0s.shape) != (n, D, D, D, D):
+        raise ValueError("T0s must be n_inst x D x D x D x D")
+    dptr = None
+    if dT0s is not None:
+        dT0s = _dev_f64(dT0s, "dT0s")
+        if tuple(dT0s.shape) != tuple(T0s.shape):
+            raise ValueError("dT0s must have the shape of T0s")
+        dptr = c_void_p(dT0s.data_ptr())
+    bptr = None
+    if backward:
+        if T0bar is None:
+            T0bar = torch.empty_like(T0s)
+        T0bar = _dev_f64(T0bar, "T0bar")
+        bptr = c_void_p(T0bar.data_ptr())
+    lnZ = (c_double * n)()
+    dirs = (c_double * n)()
+    want_dir = backward and dT0s is not None
+    with torch.cuda.device(batch.device):
+        _check(lib.dtrg_batch_run(batch._h, c_void_p(T0s.data_ptr()), dptr, float(gbar), lnZ, bptr,
+                                  dirs if want_dir else None, int(bool(replay)), _stream(stream)))
+    return list(lnZ), (T0bar if backward else None), (list(dirs) if want_dir else None)
+
+
+def tuned_shapes() -> int:
+    return int(lib.dtrg_tuned_shapes())
 
 
 def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, a_kmajor=False, b_kmajor=False,

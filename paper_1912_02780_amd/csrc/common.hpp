@@ -31,18 +31,20 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::dtrg::Error(code, msg);                                      \
     } while (0)
 
-// Owning device buffer (hipMalloc / hipFree).
+// Owning device buffer (hipMalloc / hipFree).  A buffer holding nb instances of a tensor keeps
+// the instance stride bs (elements): instance i starts at p + i * bs.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    i64 bs = 0;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), bs(o.bs) { o.p = nullptr; o.n = 0; o.bs = 0; }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; bs = o.bs; o.p = nullptr; o.n = 0; o.bs = 0; }
         return *this;
     }
     ~DevBuf() { release(); }
@@ -58,11 +60,17 @@ struct DevBuf {
         }
         n = count;
     }
+    // nb instances of `per` elements each
+    void alloc_inst(int nb, i64 per) {
+        alloc((size_t)nb * (size_t)per);
+        bs = per;
+    }
     void ensure(size_t count) { if (count > n) alloc(count); }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        bs = 0;
     }
     size_t bytes() const { return n * sizeof(T); }
 };
@@ -81,18 +89,27 @@ __host__ __device__ inline i64 idx_off(const IdxMap& m, i64 i) { return (i / m.d
 // Element types of a contraction.
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
-// One (batched) contraction C[b](r, c) = alpha * sum_k A[b](r, k) B[b](c, k) + beta * C[b](r, c).
+// Tile configuration of one contraction: tile 0 = automatic, 1 = 64 x 64, 2 = 128 x 128;
+// splits 0 = automatic split-K.
+struct GemmCfg {
+    int tile = 0;
+    int splits = 0;
+};
+
+// One (batched) contraction C[z](r, c) = alpha * sum_k A[z](r, k) B[z](c, k) + beta * C[z](r, c).
 //   A stored as [M][K] (a_kmajor = false: A[m * lda + k]) or [K][M] (a_kmajor = true: A[k * lda + m]).
 //   B stored as [N][K] (b_kmajor = false: B[n * ldb + k]) or [K][N] (b_kmajor = true: B[k * ldb + n]).
-//   C element (b, r, c) lives at C + b * c_bs + idx_off(rmap, r) + idx_off(cmap, c).
+//   Two batch levels: z = (z2, z1), z1 < batch, z2 < batch2 (the problem instance); operand X of
+//   batch element z starts at X + z1 * x_bs + z2 * x_bs2.
+//   C element (z, r, c) lives at C + z1 * c_bs + z2 * c_bs2 + idx_off(rmap, r) + idx_off(cmap, c).
 struct GemmOp {
-    int M = 0, N = 0, K = 0, batch = 1;
-    const void* A = nullptr; i64 lda = 0, a_bs = 0; bool a_kmajor = false;
-    const void* B = nullptr; i64 ldb = 0, b_bs = 0; bool b_kmajor = false;
-    void* C = nullptr; i64 c_bs = 0;
+    int M = 0, N = 0, K = 0, batch = 1, batch2 = 1;
+    const void* A = nullptr; i64 lda = 0, a_bs = 0, a_bs2 = 0; bool a_kmajor = false;
+    const void* B = nullptr; i64 ldb = 0, b_bs = 0, b_bs2 = 0; bool b_kmajor = false;
+    void* C = nullptr; i64 c_bs = 0, c_bs2 = 0;
     IdxMap rmap, cmap;
     double alpha = 1.0, beta = 0.0;
-    int splits = 0;  // 0 = automatic
+    GemmCfg cfg;
     // element capacities of the buffers behind A, B, C (-1: unchecked); checked on the host
     // against the largest offset the kernel can touch before anything is launched
     i64 a_cap = -1, b_cap = -1, c_cap = -1;
@@ -108,70 +125,114 @@ struct Scratch {
 };
 
 // gemm.hip
+// Tile configuration gemm() would pick for op (after the automatic choices are resolved).
+GemmCfg gemm_resolve(Prec in_prec, const GemmOp& op);
+// Largest element offset (plus one) the epilogue of op can write, over all batch elements.
+i64 gemm_c_extent(const GemmOp& op);
 void gemm(Prec in_prec, bool out_f64, const GemmOp& op, hipStream_t s, Scratch& ws);
 
 // tensor_ops.hip
+// Batched helpers: instance i < nb of a buffer p with instance stride bs starts at p + i * bs;
+// per-instance device scalars x_dev with stride x_bs are read at x_dev + i * x_bs.
 struct PermDesc {
     int rank = 0;
     i64 in_dims[6];
     int perm[6];
+    int nb = 1;                      // instances
+    i64 in_bs = 0, out_bs = 0;       // instance strides (elements)
     i64 in_cap = -1, out_cap = -1;   // element capacities (-1: unchecked)
 };
-// out = alpha * (*scale_dev if non-null) * transpose(in, perm) + beta * out   (numpy transpose semantics)
+// out = alpha * (scale_dev[i * scale_bs] if scale_dev) * transpose(in, perm) + beta * out
+// (numpy transpose semantics, per instance)
 void permute(const double* in, double* out, const PermDesc& d, double alpha, double beta,
-             const double* scale_dev, hipStream_t s);
+             const double* scale_dev, i64 scale_bs, hipStream_t s);
 void permute_to_f32(const double* in, float* out, const PermDesc& d, hipStream_t s);
 void permute_f32(const float* in, float* out, const PermDesc& d, hipStream_t s);
-void convert_f64_to_f32(const double* in, float* out, i64 n, hipStream_t s);
-void fill(double* p, i64 n, double v, hipStream_t s);
+void convert_f64_to_f32(const double* in, i64 in_bs, float* out, i64 out_bs, i64 n, int nb, hipStream_t s);
+void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s);
 // y += a * x
-void axpy(const double* x, double* y, i64 n, double a, hipStream_t s);
-void scale_inplace(double* p, i64 n, double alpha, const double* scale_dev, bool reciprocal, hipStream_t s);
-// out[0] = sqrt(sum x^2) (deterministic two-pass reduction)
-void norm2(const double* x, i64 n, double* out_dev, hipStream_t s, Scratch& ws);
-void dot(const double* x, const double* y, i64 n, double* out_dev, hipStream_t s, Scratch& ws);
-// out[0] = sum_{x,y} T[x][x][y][y]  for T of shape [X][X][Y][Y]
-void trace_xxyy(const double* T, int X, int Y, double* out_dev, hipStream_t s);
-// G (n x n, ld n) <- (G + G^T) / (2 * t_dev[0]), with t_dev[0] = trace(G) computed first
-void sym_normalise(double* G, int n, double* t_dev, hipStream_t s);
-// L_dev[0] += weight * log(x_dev[0]); inv_dev[0] = 1 / x_dev[0] (if inv_dev); flag bit 0 if x is
-// not positive and finite
-void accum_log(const double* x_dev, double weight, double* L_dev, double* inv_dev, int* flag_dev, hipStream_t s);
+void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s);
+// p *= alpha * (scale_dev[i * scale_bs], or its reciprocal)
+void scale_inplace(double* p, i64 bs, i64 n, int nb, double alpha, const double* scale_dev, i64 scale_bs,
+                   bool reciprocal, hipStream_t s);
+// out_dev[i * out_bs] = sqrt(sum x_i^2) (deterministic two-pass reduction)
+void norm2(const double* x, i64 bs, i64 n, int nb, double* out_dev, i64 out_bs, hipStream_t s, Scratch& ws);
+void dot(const double* x, const double* y, i64 bs, i64 n, int nb, double* out_dev, i64 out_bs, hipStream_t s,
+         Scratch& ws);
+// out = sum_{x,y} T[x][x][y][y]  for T of shape [X][X][Y][Y]
+void trace_xxyy(const double* T, i64 bs, int X, int Y, int nb, double* out_dev, i64 out_bs, hipStream_t s);
+// G (n x n, ld n) <- (G + G^T) / (2 t), with t = trace(G) written to t_dev first; flag_dev[i] bit 0
+// if t is not positive and finite
+void sym_normalise(double* G, i64 bs, int n, int nb, double* t_dev, i64 t_bs, int* flag_dev, hipStream_t s);
+// L += weight * log(x); inv = 1 / x (if inv_dev); flag_dev[i] bit 0 if x is not positive, bit 2
+// if it is not finite (per instance, scalars at stride sc_bs)
+void accum_log(const double* x_dev, double weight, double* L_dev, double* inv_dev, i64 sc_bs, int nb, int* flag_dev,
+               hipStream_t s);
 void fill_int(int* p, i64 n, int v, hipStream_t s);
-// seed of the backward: T[x][x][y][y] = gbar * weight / tr_dev[0], zero elsewhere
-void seed_trace_grad(double* T, int X, int Y, double gbar_weight, const double* tr_dev, hipStream_t s);
-// pseudo-random fill in [-1, 1) from a counter-based hash
-void hash_fill(double* p, i64 n, uint64_t seed, hipStream_t s);
+// seed of the backward: T[x][x][y][y] = gbar * weight / tr, zero elsewhere
+void seed_trace_grad(double* T, i64 bs, int X, int Y, int nb, double gbar_weight, const double* tr_dev, i64 tr_bs,
+                     hipStream_t s);
+// pseudo-random fill in [-1, 1) from a counter-based hash (stream seed ^ instance)
+void hash_fill(double* p, i64 bs, i64 n, int nb, uint64_t seed, hipStream_t s);
 // copy a rows x cols block between row-major matrices with leading dimensions
-void copy2d(const double* src, i64 lds, double* dst, i64 ldd, int rows, int cols, hipStream_t s);
+void copy2d(const double* src, i64 lds, i64 src_bs, double* dst, i64 ldd, i64 dst_bs, int rows, int cols, int nb,
+            hipStream_t s);
+// dst + i * dst_bs <- src + idx[i] * src_bs (len elements; gather) or the reverse (scatter)
+void gather_rows(const double* src, i64 src_bs, const int* idx_dev, double* dst, i64 dst_bs, i64 len, int nb,
+                 bool scatter, hipStream_t s);
+// flag_dev[i] |= bit where max_{j < k} v[i * v_bs + j] > thr (or is not finite); mx_dev[i * mx_bs] = that max
+void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_dev, i64 mx_bs, int* flag_dev,
+               int bit, hipStream_t s);
 
 // eig.hip
 // Full symmetric eigendecomposition of an n x n matrix (n <= kJacobiMax) by parallel cyclic
-// Jacobi in one workgroup: eigenvalues descending into lam_dev[0..n), eigenvectors as the
-// columns of V (row-major, leading dimension ldv).
+// Jacobi, one workgroup per instance: eigenvalues descending into lam_dev[0..n), eigenvectors as
+// the columns of V (row-major, leading dimension ldv).
 constexpr int kJacobiMax = 96;
-void jacobi_eig(const double* A, int n, int lda, double* lam_dev, double* V, int ldv, int max_sweeps,
-                int* sweeps_dev, hipStream_t s);
+void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s);
 // Upper-triangular R^{-1} of the Cholesky factor of (S + shift * I), S b x b (ld b); the
-// shift is shift_rel * trace(S).  flag_dev[0] |= 2 on a non-positive pivot.
-void chol_inverse(const double* S, int b, double shift_rel, double* Rinv, int* flag_dev, hipStream_t s);
+// shift is shift_rel * trace(S).  flag_dev[i] |= 2 on a non-positive pivot.
+void chol_inverse(const double* S, i64 s_bs, int b, double shift_rel, double* Rinv, i64 r_bs, int nb, int* flag_dev,
+                  hipStream_t s);
 // norms of the b columns of V (n x b, ld ldv) -> out[0..b)
-void col_norms(const double* V, int n, int b, int ldv, double* out_dev, hipStream_t s);
+void col_norms(const double* V, int n, int b, int ldv, i64 v_bs, double* out_dev, i64 out_bs, int nb, hipStream_t s);
 // V[:, j] /= nrm[j] where nrm[j] > tiny * max(nrm); other columns replaced by hash noise
-void col_normalise(double* V, int n, int b, int ldv, const double* nrm_dev, uint64_t seed, hipStream_t s);
+void col_normalise(double* V, int n, int b, int ldv, i64 v_bs, const double* nrm_dev, i64 nrm_bs, int nb,
+                   uint64_t seed, hipStream_t s);
 // res[j] = |Y[:, j] - theta[j] V[:, j]| for j < k
-void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, const double* theta_dev,
-                    double* res_dev, hipStream_t s);
+void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, i64 v_bs, const double* theta_dev,
+                    i64 th_bs, double* res_dev, i64 res_bs, int nb, hipStream_t s);
 // S[i][j] = F(lam_j - lam_i) * (Om[i][j] - Om[j][i]) / 2 on the k x k kept block (F_ii = 0),
 // F(d) = d / (d^2 + eps)
-void kept_block_adjoint(const double* Om, const double* lam_dev, int k, double eps, double* S, hipStream_t s);
-// M[i][j] = F(lam_j - theta_i) * Om[i][j] / 2 for i < p (oversampled), j < k
-void over_block_adjoint(const double* Om, const double* theta_dev, const double* lam_dev, int p, int k,
-                        double eps, double* M, hipStream_t s);
-// Chebyshev three-term step on n x k blocks:
+void kept_block_adjoint(const double* Om, i64 om_bs, const double* lam_dev, i64 lam_bs, int k, double eps, double* S,
+                        i64 s_bs, int nb, hipStream_t s);
+// M[i][j] = F(lam_j - theta_i) * Om[i][j] / 2 for i < p, j < k, theta = lam + k
+void over_block_adjoint(const double* Om, i64 om_bs, const double* lam_dev, i64 lam_bs, int p, int k, double eps,
+                        double* M, i64 m_bs, int nb, hipStream_t s);
+// Chebyshev three-term step on n x k blocks (all with instance stride bs), interval [lo, hi] of
+// instance i at lohi_dev[i * lohi_bs + {0, 1}]:
 //   Vn = a * (2 * Y - (hi + lo) * Vc) - Vp (a = 2 / (hi - lo), or half that for the first step with Vp = 0)
 //   X += coef[j] * Vn[:, j]   (first step: X += coef[j] * Vc[:, j] + coef[K + j] * Vn[:, j])
-void cheb_step(const double* Y, const double* Vc, const double* Vp, double* Vn, double* X, int n, int k,
-               double lo, double hi, bool first, const double* coef_dev, hipStream_t s);
+void cheb_step(const double* Y, const double* Vc, const double* Vp, double* Vn, double* X, i64 bs, int n, int k,
+               const double* lohi_dev, i64 lohi_bs, bool first, const double* coef_dev, i64 coef_bs, int nb,
+               hipStream_t s);
+// Interval of the complement expansion of instance i from its Ritz values th (th[0] the largest,
+// th[e] the first unresolved one) and res_next (the residual of th[e]), n the matrix order:
+//   nu = 64 n 2^-53 max(th[0], 0);  hi = mult * (max(1.1 (max(th[e], 0) + res_next), nu) + 1e-300);
+//   lo = -max(nu, 0.05 hi).
+void cheb_interval(const double* th, i64 th_bs, int e, const double* res_next, i64 rn_bs, int n, double mult,
+                   double* lohi_dev, i64 lohi_bs, int nb, hipStream_t s);
+// DCT table of degree m at the N = m + 1 first-kind Chebyshev nodes: ct[q][k] = w_q cos(pi q (k + 1/2) / N),
+// w_0 = 1 / N, w_q = 2 / N.
+void cheb_table(double* ct, int m, hipStream_t s);
+// fv[k][j] = (1/2) d / (d^2 + eps), d = lam[j] - t_k, t_k the k-th node on [lo, hi], k <= m, j < K
+void cheb_fvals(const double* lam, i64 lam_bs, int K, double eps, const double* lohi_dev, i64 lohi_bs, int m,
+                double* fv, i64 fv_bs, int nb, hipStream_t s);
+// ratio[i] = max_{q >= m - 1, j} |c[q][j]| / max_{q, j} |c[q][j]| of instance i's (m + 1) x K coefficients
+void cheb_tail(const double* coef, i64 coef_bs, int m, int K, double* ratio_dev, i64 ratio_bs, int nb, hipStream_t s);
+// flag_dev[i] |= bit unless |v_m| <= 1.5 |v_0| (both finite): the expansion stayed bounded
+void cheb_bound_check(const double* vm_dev, const double* v0_dev, i64 bs, int nb, int* flag_dev, int bit,
+                      hipStream_t s);
 
 }  // namespace dtrg

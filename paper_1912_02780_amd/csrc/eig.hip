@@ -8,7 +8,9 @@
 // * chol_inverse: Cholesky of a (shifted) b x b Gram in LDS and the inverse of its triangular
 //   factor, for CholeskyQR of the subspace block.
 // * element-wise helpers for Ritz residuals, column normalisation, the broadened inverse gaps of
-//   the eigenvector adjoint and the Chebyshev three-term recurrence.
+//   the eigenvector adjoint and the Chebyshev expansion of the complement (interval, node values,
+//   three-term recurrence, coefficient tail and boundedness checks).
+// Every kernel serves nb independent instances (one workgroup or one y-slice of the grid each).
 #include "common.hpp"
 
 #include <algorithm>
@@ -22,9 +24,9 @@ constexpr int JLD = JM + 1;
 constexpr int JT = 512;    // Jacobi: 8 waves
 constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
-__global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda,
-                                                     double* __restrict__ lam, double* __restrict__ Vout,
-                                                     int ldv, int max_sweeps, int* sweeps_out) {
+__global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
+                                                     double* __restrict__ lam, i64 lam_bs, double* __restrict__ Vout,
+                                                     int ldv, i64 v_bs, int max_sweeps, int* sweeps_out) {
     __shared__ double A[JM * JLD];
     __shared__ double V[JM * JLD];
     __shared__ int rp[JM / 2], rq[JM / 2];
@@ -32,6 +34,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     __shared__ int nrot, nact;
     __shared__ double fro;
     const int tid = threadIdx.x;
+    Ain += blockIdx.x * a_bs;
+    lam += blockIdx.x * lam_bs;
+    Vout += blockIdx.x * v_bs;
     const int m = n + (n & 1);  // players, padded to even with a dummy index n
     for (int i = tid; i < n * n; i += JT) {
         const int r = i / n, c = i % n;
@@ -126,19 +131,23 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
         lam[rank] = li;
         for (int r = 0; r < n; ++r) Vout[(i64)r * ldv + rank] = V[r * JLD + i];
     }
-    if (tid == 0 && sweeps_out) sweeps_out[0] = sweep;
+    if (tid == 0 && sweeps_out) atomicMax(sweeps_out, sweep);
 }
 
 // Lower Cholesky factor L of S + shift I in LDS, then Rinv = (L^T)^{-1} (upper) to global.
 // Lower Cholesky factor L of (S + shift I) in LDS (right-looking, rank-1 trailing updates in
 // parallel), then X = L^{-1} by the same elimination applied to the identity (row k of X is
 // final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.
-__global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, int b, double shift_rel,
-                                                       double* __restrict__ Rinv, int* flag) {
+__global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, i64 s_bs, int b,
+                                                       double shift_rel, double* __restrict__ Rinv, i64 r_bs,
+                                                       int* flag) {
     __shared__ double L[JM * JLD];
     __shared__ double Xs[JM * JLD];
     __shared__ double tr;
     const int tid = threadIdx.x;
+    S += blockIdx.x * s_bs;
+    Rinv += blockIdx.x * r_bs;
+    flag += blockIdx.x;
     for (int i = tid; i < b * b; i += CT) {
         const int r = i / b, c = i % b;
         L[r * JLD + c] = 0.5 * (S[(i64)r * b + c] + S[(i64)c * b + r]);
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
     for (int k = 0; k < b; ++k) {
         double d = L[k * JLD + k];
         if (!(d > 0.0) || !isfinite(d)) {
-            if (tid == 0 && flag) atomicOr(flag, 2);
+            if (tid == 0) flag[0] |= 2;
             d = 1e-300;
         }
         const double dk = sqrt(d);
@@ -204,8 +213,11 @@ __device__ inline double block_sum256(double v) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void col_norms_kernel(const double* V, int n, int ldv, double* out) {
+__global__ __launch_bounds__(256) void col_norms_kernel(const double* V, int n, int ldv, i64 v_bs, double* out,
+                                                         i64 out_bs) {
     const int j = blockIdx.x;
+    V += blockIdx.y * v_bs;
+    out += blockIdx.y * out_bs;
     double s = 0.0;
     for (int r = threadIdx.x; r < n; r += 256) { const double v = V[(i64)r * ldv + j]; s += v * v; }
     s = block_sum256(s);
@@ -219,8 +231,11 @@ __device__ inline uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(256) void col_normalise_kernel(double* V, int n, int b, int ldv, const double* nrm,
-                                                             uint64_t seed) {
+__global__ __launch_bounds__(256) void col_normalise_kernel(double* V, int n, int b, int ldv, i64 v_bs,
+                                                             const double* nrm, i64 nrm_bs, uint64_t seed) {
+    V += blockIdx.y * v_bs;
+    nrm += blockIdx.y * nrm_bs;
+    if (blockIdx.y) seed = mix64(seed ^ (0x5bd1e995ULL + blockIdx.y));
     double mx = 0.0;
     for (int j = 0; j < b; ++j) mx = fmax(mx, nrm[j]);
     const double tiny = 1e-200 + 1e-30 * mx;
@@ -236,9 +251,13 @@ __global__ __launch_bounds__(256) void col_normalise_kernel(double* V, int n, in
     }
 }
 
-__global__ __launch_bounds__(256) void ritz_res_kernel(const double* V, const double* Y, int n, int ld,
-                                                        const double* theta, double* res) {
+__global__ __launch_bounds__(256) void ritz_res_kernel(const double* V, const double* Y, int n, int ld, i64 v_bs,
+                                                        const double* theta, i64 th_bs, double* res, i64 res_bs) {
     const int j = blockIdx.x;
+    V += blockIdx.y * v_bs;
+    Y += blockIdx.y * v_bs;
+    theta += blockIdx.y * th_bs;
+    res += blockIdx.y * res_bs;
     const double th = theta[j];
     double s = 0.0;
     for (int r = threadIdx.x; r < n; r += 256) {
@@ -251,16 +270,23 @@ __global__ __launch_bounds__(256) void ritz_res_kernel(const double* V, const do
 
 __device__ inline double bgap(double d, double eps) { return d / (d * d + eps); }
 
-__global__ __launch_bounds__(256) void kept_block_kernel(const double* Om, const double* lam, int k, double eps,
-                                                          double* S) {
+__global__ __launch_bounds__(256) void kept_block_kernel(const double* Om, i64 om_bs, const double* lam,
+                                                          i64 lam_bs, int k, double eps, double* S, i64 s_bs) {
+    Om += blockIdx.y * om_bs;
+    lam += blockIdx.y * lam_bs;
+    S += blockIdx.y * s_bs;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < k * k; idx += gridDim.x * blockDim.x) {
         const int i = idx / k, j = idx % k;
         S[idx] = (i == j) ? 0.0 : bgap(lam[j] - lam[i], eps) * 0.5 * (Om[i * k + j] - Om[j * k + i]);
     }
 }
 
-__global__ __launch_bounds__(256) void over_block_kernel(const double* Om, const double* theta, const double* lam,
-                                                          int p, int k, double eps, double* M) {
+__global__ __launch_bounds__(256) void over_block_kernel(const double* Om, i64 om_bs, const double* lam,
+                                                          i64 lam_bs, int p, int k, double eps, double* M, i64 m_bs) {
+    Om += blockIdx.y * om_bs;
+    lam += blockIdx.y * lam_bs;
+    M += blockIdx.y * m_bs;
+    const double* theta = lam + k;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * k; idx += gridDim.x * blockDim.x) {
         const int i = idx / k, j = idx % k;
         M[idx] = bgap(lam[j] - theta[i], eps) * 0.5 * Om[idx];
@@ -268,70 +294,190 @@ __global__ __launch_bounds__(256) void over_block_kernel(const double* Om, const
 }
 
 __global__ __launch_bounds__(256) void cheb_step_kernel(const double* Y, const double* Vc, const double* Vp,
-                                                         double* Vn, double* X, int n, int k, double a, double sum,
-                                                         int first, const double* coef) {
+                                                         double* Vn, double* X, i64 bs, int n, int k,
+                                                         const double* lohi, i64 lohi_bs, int first,
+                                                         const double* coef, i64 coef_bs) {
+    const int z = blockIdx.y;
+    const i64 o = z * bs;
+    const double lo = lohi[z * lohi_bs], hi = lohi[z * lohi_bs + 1];
+    const double a = (first ? 1.0 : 2.0) / (hi - lo), sum = hi + lo;
+    coef += z * coef_bs;
     const i64 total = (i64)n * k;
     for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
         const int j = (int)(idx % k);
-        const double vc = Vc[idx];
-        double v = a * (2.0 * Y[idx] - sum * vc);
-        if (!first) v -= Vp[idx];
-        Vn[idx] = v;
-        if (first) X[idx] += coef[j] * vc + coef[k + j] * v;
-        else X[idx] += coef[j] * v;
+        const double vc = Vc[o + idx];
+        double v = a * (2.0 * Y[o + idx] - sum * vc);
+        if (!first) v -= Vp[o + idx];
+        Vn[o + idx] = v;
+        if (first) X[o + idx] += coef[j] * vc + coef[k + j] * v;
+        else X[o + idx] += coef[j] * v;
     }
 }
 
-int grid_for(i64 n) { return (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 8192)); }
+__global__ void cheb_interval_kernel(const double* th, i64 th_bs, int e, const double* rn, i64 rn_bs, int n,
+                                     double mult, double* lohi, i64 lohi_bs, int nb) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nb) return;
+    const double* t = th + z * th_bs;
+    const double nu = 64.0 * n * 0x1p-53 * fmax(t[0], 0.0);
+    const double hi = mult * (fmax(1.1 * (fmax(t[e], 0.0) + rn[z * rn_bs]), nu) + 1e-300);
+    lohi[z * lohi_bs] = -fmax(nu, 0.05 * hi);
+    lohi[z * lohi_bs + 1] = hi;
+}
+
+__global__ __launch_bounds__(256) void cheb_table_kernel(double* ct, int m) {
+    const int N = m + 1;
+    const i64 total = (i64)N * N;
+    for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
+        const int q = (int)(idx / N), k = (int)(idx % N);
+        // q (k + 1/2) / N reduced modulo 2 keeps the argument of cospi small and exact
+        const i64 num = (i64)q * (2 * k + 1) % (4 * (i64)N);
+        ct[idx] = (q == 0 ? 1.0 : 2.0) / N * cospi((double)num / (2.0 * N));
+    }
+}
+
+__global__ __launch_bounds__(256) void cheb_fvals_kernel(const double* lam, i64 lam_bs, int K, double eps,
+                                                          const double* lohi, i64 lohi_bs, int m, double* fv,
+                                                          i64 fv_bs) {
+    const int z = blockIdx.y;
+    lam += z * lam_bs;
+    fv += z * fv_bs;
+    const double lo = lohi[z * lohi_bs], hi = lohi[z * lohi_bs + 1];
+    const int N = m + 1;
+    const i64 total = (i64)N * K;
+    for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
+        const int k = (int)(idx / K), j = (int)(idx % K);
+        const double x = cospi((2.0 * k + 1.0) / (2.0 * N));
+        const double t = 0.5 * (hi - lo) * x + 0.5 * (hi + lo);
+        const double d = lam[j] - t;
+        fv[idx] = 0.5 * d / (d * d + eps);
+    }
+}
+
+__global__ __launch_bounds__(256) void cheb_tail_kernel(const double* coef, i64 coef_bs, int m, int K, double* ratio,
+                                                         i64 ratio_bs) {
+    const int z = blockIdx.x;
+    coef += z * coef_bs;
+    double mx = 0.0, tail = 0.0;
+    const i64 total = (i64)(m + 1) * K;
+    for (i64 idx = threadIdx.x; idx < total; idx += 256) {
+        const double a = fabs(coef[idx]);
+        const double a2 = isfinite(a) ? a : INFINITY;
+        mx = fmax(mx, a2);
+        if (idx / K >= m - 1) tail = fmax(tail, a2);
+    }
+    __shared__ double s1[256], s2[256];
+    s1[threadIdx.x] = mx;
+    s2[threadIdx.x] = tail;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + st]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ratio[z * ratio_bs] = s1[0] > 0.0 ? s2[0] / s1[0] : 0.0;
+}
+
+__global__ void cheb_bound_kernel(const double* vm, const double* v0, i64 bs, int nb, int* flag, int bit) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nb) return;
+    const double a = vm[z * bs], b = v0[z * bs];
+    if (!(isfinite(a) && isfinite(b) && a <= 1.5 * b)) flag[z] |= bit;
+}
+
+dim3 grid2(i64 n, int nb) {
+    const i64 per = std::max<i64>(1, std::min<i64>((n + 255) / 256, std::max<i64>(1, 8192 / nb)));
+    return dim3((unsigned)per, (unsigned)nb);
+}
 
 }  // namespace
 
-void jacobi_eig(const double* A, int n, int lda, double* lam_dev, double* V, int ldv, int max_sweeps,
-                int* sweeps_dev, hipStream_t s) {
+void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s) {
     DTRG_REQUIRE(n >= 1 && n <= kJacobiMax, DTRG_EINVAL, "jacobi_eig: n out of range");
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JT), 0, s, A, n, lda, lam_dev, V, ldv, max_sweeps, sweeps_dev);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv, v_bs,
+                       max_sweeps, sweeps_dev);
     DTRG_HIP(hipGetLastError());
 }
 
-void chol_inverse(const double* S, int b, double shift_rel, double* Rinv, int* flag_dev, hipStream_t s) {
+void chol_inverse(const double* S, i64 s_bs, int b, double shift_rel, double* Rinv, i64 r_bs, int nb, int* flag_dev,
+                  hipStream_t s) {
     DTRG_REQUIRE(b >= 1 && b <= kJacobiMax, DTRG_EINVAL, "chol_inverse: b out of range");
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CT), 0, s, S, b, shift_rel, Rinv, flag_dev);
+    DTRG_REQUIRE(flag_dev, DTRG_EINVAL, "chol_inverse: flag array required");
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(nb), dim3(CT), 0, s, S, s_bs, b, shift_rel, Rinv, r_bs, flag_dev);
     DTRG_HIP(hipGetLastError());
 }
 
-void col_norms(const double* V, int n, int b, int ldv, double* out_dev, hipStream_t s) {
-    hipLaunchKernelGGL(col_norms_kernel, dim3(b), dim3(256), 0, s, V, n, ldv, out_dev);
+void col_norms(const double* V, int n, int b, int ldv, i64 v_bs, double* out_dev, i64 out_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(col_norms_kernel, dim3(b, nb), dim3(256), 0, s, V, n, ldv, v_bs, out_dev, out_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void col_normalise(double* V, int n, int b, int ldv, const double* nrm_dev, uint64_t seed, hipStream_t s) {
-    hipLaunchKernelGGL(col_normalise_kernel, dim3(grid_for((i64)n * b)), dim3(256), 0, s, V, n, b, ldv, nrm_dev, seed);
+void col_normalise(double* V, int n, int b, int ldv, i64 v_bs, const double* nrm_dev, i64 nrm_bs, int nb,
+                   uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(col_normalise_kernel, grid2((i64)n * b, nb), dim3(256), 0, s, V, n, b, ldv, v_bs, nrm_dev,
+                       nrm_bs, seed);
     DTRG_HIP(hipGetLastError());
 }
 
-void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, const double* theta_dev,
-                    double* res_dev, hipStream_t s) {
-    hipLaunchKernelGGL(ritz_res_kernel, dim3(k), dim3(256), 0, s, V, Y, n, ld, theta_dev, res_dev);
+void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, i64 v_bs, const double* theta_dev,
+                    i64 th_bs, double* res_dev, i64 res_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(ritz_res_kernel, dim3(k, nb), dim3(256), 0, s, V, Y, n, ld, v_bs, theta_dev, th_bs, res_dev,
+                       res_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void kept_block_adjoint(const double* Om, const double* lam_dev, int k, double eps, double* S, hipStream_t s) {
-    hipLaunchKernelGGL(kept_block_kernel, dim3(grid_for((i64)k * k)), dim3(256), 0, s, Om, lam_dev, k, eps, S);
+void kept_block_adjoint(const double* Om, i64 om_bs, const double* lam_dev, i64 lam_bs, int k, double eps, double* S,
+                        i64 s_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(kept_block_kernel, grid2((i64)k * k, nb), dim3(256), 0, s, Om, om_bs, lam_dev, lam_bs, k, eps,
+                       S, s_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void over_block_adjoint(const double* Om, const double* theta_dev, const double* lam_dev, int p, int k, double eps,
-                        double* M, hipStream_t s) {
-    hipLaunchKernelGGL(over_block_kernel, dim3(grid_for((i64)p * k)), dim3(256), 0, s, Om, theta_dev, lam_dev, p, k,
-                       eps, M);
+void over_block_adjoint(const double* Om, i64 om_bs, const double* lam_dev, i64 lam_bs, int p, int k, double eps,
+                        double* M, i64 m_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(over_block_kernel, grid2((i64)p * k, nb), dim3(256), 0, s, Om, om_bs, lam_dev, lam_bs, p, k,
+                       eps, M, m_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void cheb_step(const double* Y, const double* Vc, const double* Vp, double* Vn, double* X, int n, int k, double lo,
-               double hi, bool first, const double* coef_dev, hipStream_t s) {
-    const double a = (first ? 1.0 : 2.0) / (hi - lo);
-    hipLaunchKernelGGL(cheb_step_kernel, dim3(grid_for((i64)n * k)), dim3(256), 0, s, Y, Vc, Vp, Vn, X, n, k, a,
-                       hi + lo, first ? 1 : 0, coef_dev);
+void cheb_step(const double* Y, const double* Vc, const double* Vp, double* Vn, double* X, i64 bs, int n, int k,
+               const double* lohi_dev, i64 lohi_bs, bool first, const double* coef_dev, i64 coef_bs, int nb,
+               hipStream_t s) {
+    hipLaunchKernelGGL(cheb_step_kernel, grid2((i64)n * k, nb), dim3(256), 0, s, Y, Vc, Vp, Vn, X, bs, n, k, lohi_dev,
+                       lohi_bs, first ? 1 : 0, coef_dev, coef_bs);
+    DTRG_HIP(hipGetLastError());
+}
+
+void cheb_interval(const double* th, i64 th_bs, int e, const double* res_next, i64 rn_bs, int n, double mult,
+                   double* lohi_dev, i64 lohi_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(cheb_interval_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, th, th_bs, e, res_next, rn_bs, n,
+                       mult, lohi_dev, lohi_bs, nb);
+    DTRG_HIP(hipGetLastError());
+}
+
+void cheb_table(double* ct, int m, hipStream_t s) {
+    hipLaunchKernelGGL(cheb_table_kernel, grid2((i64)(m + 1) * (m + 1), 1), dim3(256), 0, s, ct, m);
+    DTRG_HIP(hipGetLastError());
+}
+
+void cheb_fvals(const double* lam, i64 lam_bs, int K, double eps, const double* lohi_dev, i64 lohi_bs, int m,
+                double* fv, i64 fv_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(cheb_fvals_kernel, grid2((i64)(m + 1) * K, nb), dim3(256), 0, s, lam, lam_bs, K, eps, lohi_dev,
+                       lohi_bs, m, fv, fv_bs);
+    DTRG_HIP(hipGetLastError());
+}
+
+void cheb_tail(const double* coef, i64 coef_bs, int m, int K, double* ratio_dev, i64 ratio_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(cheb_tail_kernel, dim3(nb), dim3(256), 0, s, coef, coef_bs, m, K, ratio_dev, ratio_bs);
+    DTRG_HIP(hipGetLastError());
+}
+
+void cheb_bound_check(const double* vm_dev, const double* v0_dev, i64 bs, int nb, int* flag_dev, int bit,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(cheb_bound_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, vm_dev, v0_dev, bs, nb, flag_dev, bit);
     DTRG_HIP(hipGetLastError());
 }
 

@@ -44,15 +44,20 @@ __device__ inline bool tile_of(int pid, int tiles_m, int tiles_n, int& tm, int& 
 
 struct KArgs {
     int M, N, K;
-    const void* A; i64 lda, a_bs;
-    const void* B; i64 ldb, b_bs;
-    void* C; i64 c_bs;
+    const void* A; i64 lda, a_bs, a_bs2;
+    const void* B; i64 ldb, b_bs, b_bs2;
+    void* C; i64 c_bs, c_bs2;
     IdxMap rmap, cmap;
     double alpha, beta;
-    int splits, k_chunk, batch;
+    int splits, k_chunk, batch, batch2;
     int tiles_m, tiles_n;
-    void* W;  // split-K partials [batch * splits][M][N], accumulator type
+    void* W;  // split-K partials [batch2 * batch * splits][M][N], accumulator type
 };
+
+// offset of batch element zb = z2 * batch + z1 in an operand with strides (bs, bs2)
+__host__ __device__ inline i64 batch_off(const KArgs& p, int zb, i64 bs, i64 bs2) {
+    return (i64)(zb % p.batch) * bs + (i64)(zb / p.batch) * bs2;
+}
 
 // ------------------------------------------------------------------------------------------
 // FP64 / FP32: 16x16x4 MFMA.  Fragment layout (A 16x4, B 4x16, D 16x16) for lane l:
@@ -99,8 +104,8 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
     const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
     const int kbeg = zs * p.k_chunk;
     const int kend = min(p.K, kbeg + p.k_chunk);
-    const T* A = (const T*)p.A + (i64)zb * p.a_bs;
-    const T* B = (const T*)p.B + (i64)zb * p.b_bs;
+    const T* A = (const T*)p.A + batch_off(p, zb, p.a_bs, p.a_bs2);
+    const T* B = (const T*)p.B + batch_off(p, zb, p.b_bs, p.b_bs2);
 
     acc_t acc[TM][TN];
 #pragma unroll
@@ -184,7 +189,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
                 }
         return;
     }
-    TO* C = (TO*)p.C + (i64)zb * p.c_bs;
+    TO* C = (TO*)p.C + batch_off(p, zb, p.c_bs, p.c_bs2);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -230,8 +235,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
     const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
     const int kbeg = zs * p.k_chunk;
     const int kend = min(p.K, kbeg + p.k_chunk);
-    const float* A = (const float*)p.A + (i64)zb * p.a_bs;
-    const float* B = (const float*)p.B + (i64)zb * p.b_bs;
+    const float* A = (const float*)p.A + batch_off(p, zb, p.a_bs, p.a_bs2);
+    const float* B = (const float*)p.B + batch_off(p, zb, p.b_bs, p.b_bs2);
 
     v4f acc[TM][TN];
 #pragma unroll
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
                 }
         return;
     }
-    TO* C = (TO*)p.C + (i64)zb * p.c_bs;
+    TO* C = (TO*)p.C + batch_off(p, zb, p.c_bs, p.c_bs2);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll

@@ -1,0 +1,128 @@
+// The HOTRG plan: checkpoints, workspaces and the per-step schedule of nb independent problem
+// instances that share (D, chi, n_steps), and the engine that runs their forward and backward
+// passes.
+//
+// Two modes.  An adaptive pass reads small results back to the host to take its data-dependent
+// decisions (subspace iterations to convergence, the degree and interval of the complement
+// expansion, the tile autotuner) and records them in the schedule.  A fixed pass replays the
+// recorded schedule without any host read-back or allocation, so it can be captured into a HIP
+// graph; its acceptance tests run on the device and leave per-instance flags that the caller
+// reads afterwards.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace dtrg {
+
+enum class Mode { Adaptive, Fixed };
+
+// Per-instance error flags (device int per instance).
+enum : int {
+    kFlagNonPos = 1,      // a norm or trace is not positive
+    kFlagChol = 2,        // non-positive pivot in CholeskyQR (diagnostic only)
+    kFlagNonFinite = 4,   // a norm or trace is not finite
+    kFlagSubspace = 8,    // subspace iteration residual above the acceptance bound
+    kFlagChebTail = 16,   // complement expansion coefficients not decayed at the recorded degree
+    kFlagChebBound = 32,  // complement expansion not bounded (spectrum outside its interval)
+};
+
+// Per-instance FP64 scalars: one row of kScPlan + kScStep * n_steps doubles per instance.
+constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace, 5 <T0bar, dT0>, 6 c0, 7 1/c0
+constexpr int kScStep = 12;   // per step: 0 c_k, 1 1/c_k, 2 trace of the Gram, 3 residual of the first
+                              // unresolved Ritz pair, 4 lo, 5 hi (complement interval), 6 |v_0|,
+                              // 7 |v_m|, 8 largest resolved residual, 9 coefficient tail ratio
+
+struct StepShape {
+    int X = 0, Y = 0, K = 0, n = 0, b = 0;
+    int e = 0;          // leading eigenpairs resolved to full accuracy: the kept K plus the
+                        // discarded ones nearest the cut (the rest of the block is a guard)
+    bool full = false;
+    bool mixed = false; // projection contractions of this step in the mixed precision
+    double join_flops() const { return 2.0 * K * Y * X * (double)(Y * X) * (X * Y); }
+};
+
+struct StepCk {
+    StepShape sh;
+    DevBuf<double> T;      // normalised input [X][X][Y][Y] (checkpoint)
+    DevBuf<double> U;      // [n][b] eigenvectors / Ritz vectors (first K columns: w)
+    DevBuf<double> lam;    // b eigenvalues / Ritz values, descending
+    // schedule (written by adaptive passes, replayed by fixed passes)
+    int iters = 0;         // subspace iterations
+    int cheb = 0;          // degree of the complement expansion (0: none)
+    double hi_mult = 1.0;  // widening factor of the complement interval
+};
+
+}  // namespace dtrg
+
+struct dtrg_plan {
+    int D = 0, chi = 0, nsteps = 0, nb = 1;
+    dtrg_options opt{};
+    dtrg::Prec prec = dtrg::Prec::F64;
+    hipStream_t s = nullptr;
+    std::vector<dtrg::StepCk> steps;
+    std::vector<dtrg::StepShape> shape;
+    bool fwd_ok = false;        // a forward pass succeeded (checkpoints valid)
+    bool sched_fwd = false;     // the schedule of the forward pass is recorded
+    bool sched_bwd = false;     // the schedule of the backward pass is recorded
+    int Xf = 0, Yf = 0;
+    dtrg::i64 S = 0;            // scalar row length per instance (kScPlan + kScStep * nsteps)
+    dtrg::DevBuf<double> scal;  // nb x S
+    dtrg::DevBuf<int> flags;    // nb error flags
+    dtrg::DevBuf<int> misc;     // 4 ints: Jacobi sweep counter
+    std::vector<double> scal_h; // host copy of scal after a pass (adaptive passes, or on demand)
+    std::vector<int> flags_h;
+    dtrg::Scratch ws;
+    // inputs and outputs of the nb instances ([nb][D^4])
+    dtrg::DevBuf<double> T0buf, T0barbuf, dT0buf;
+    // workspaces (instance stride bs)
+    dtrg::DevBuf<double> TA, TB, Tp, Tb, Tb2, Wt, Wt2, Tn, Tbar, Tbar2, Tpbar;
+    dtrg::DevBuf<double> A, B, P1, Q2, X5;
+    dtrg::DevBuf<double> Gw, Gt, Ub, Xe, Xc, Re, Om, Sm, Vc, Vp, Vn, Ye, We;
+    dtrg::DevBuf<double> V1, V2, Y1, Y2, H, Z, Rinv, Sg, th, res, nrm, coef, fv;
+    dtrg::DevBuf<double> ctab;  // Chebyshev DCT tables of degree 8, 16, ..., 1024
+    bool ctab_ready = false;
+    dtrg::DevBuf<double> tune_c;  // autotuner output scratch
+    // contraction operands in FP32 (FP32 and split-bf16 paths)
+    dtrg::DevBuf<float> Tpf, Tbf, Tb2f, Wtf, Wt2f, Uf, P1f, Q2f, X5f, Tpbarf;
+    bool mixed() const { return prec != dtrg::Prec::F64; }
+    // HIP-event timing of the chi^7 join contractions (adaptive passes with opt.profile)
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_flops = 0.0;
+    ~dtrg_plan();
+    double* sc(int k, int slot) { return scal.p + dtrg::kScPlan + (dtrg::i64)dtrg::kScStep * (k - 1) + slot; }
+    double* sp(int slot) { return scal.p + slot; }
+    dtrg::i64 cap_bytes(const void* p) const;
+    dtrg::i64 cap_of(const void* p, int elem = 8) const {
+        const dtrg::i64 b = cap_bytes(p);
+        return b < 0 ? -1 : b / elem;
+    }
+    size_t bytes() const;
+};
+
+namespace dtrg {
+
+// Allocate the plan of nb instances of (D, chi, nsteps) with options opt (validated by the caller).
+void plan_setup(dtrg_plan* P);
+// Forward pass of the nb instances in P->T0buf (adaptive or fixed); in adaptive mode throws on
+// the first failed instance and leaves ln Z / N in P->scal_h.
+void plan_forward(dtrg_plan* P, Mode mode);
+// Backward pass into P->T0barbuf (and <T0bar, dT0> with dT0 from P->dT0buf if with_dir).
+void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode);
+// Read scalars and flags back (synchronises the plan's stream); throw the error of the first
+// flagged instance (bits in mask).
+void plan_read_back(dtrg_plan* P);
+void plan_throw_flags(const dtrg_plan* P, int mask, const std::string& where);
+
+// tune.hip: the tile configuration for op, measured once per shape when tuning is allowed
+// (adaptive passes with the autotuner on) and reused afterwards; `scratch` receives the trial
+// outputs.
+GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
+                  DevBuf<double>& scratch);
+// Number of shapes in the tuning table (for tests and diagnostics).
+int tuned_count();
+
+}  // namespace dtrg

@@ -1,5 +1,8 @@
 // Memory-bound helpers of the HOTRG path: permutations, conversions, deterministic reductions,
 // traces, log-scale accumulation, the backward's seed and pseudo-random fills.
+//
+// Every helper works on nb independent instances at once: blockIdx.y is the instance, the x
+// blocks of an instance stride over its elements, so one launch serves a whole batch.
 #include "common.hpp"
 
 #include <algorithm>
@@ -8,17 +11,18 @@ namespace dtrg {
 
 namespace {
 
-constexpr int kRedBlocks = 1024;   // fixed number of partials: reductions are bit-reproducible
+constexpr int kRedBlocks = 1024;   // partials of a single-instance reduction
 
 struct PermK {
     int rank;
     i64 odims[6];     // output dims
     i64 istr[6];      // input stride of each output axis
-    i64 total;
+    i64 total;        // elements per instance
 };
 
 PermK make_perm(const PermDesc& d) {
     DTRG_REQUIRE(d.rank >= 1 && d.rank <= 6, DTRG_EINVAL, "permute: rank out of range");
+    DTRG_REQUIRE(d.nb >= 1 && d.nb < 65536, DTRG_EINVAL, "permute: instance count out of range");
     PermK k;
     k.rank = d.rank;
     i64 in_str[6];
@@ -35,8 +39,11 @@ PermK make_perm(const PermDesc& d) {
         k.total *= k.odims[i];
     }
     for (int i = d.rank; i < 6; ++i) { k.odims[i] = 1; k.istr[i] = 0; }
-    DTRG_REQUIRE(d.in_cap < 0 || k.total <= d.in_cap, DTRG_EINVAL, "permute: input out of bounds");
-    DTRG_REQUIRE(d.out_cap < 0 || k.total <= d.out_cap, DTRG_EINVAL, "permute: output out of bounds");
+    const i64 in_ext = (i64)(d.nb - 1) * d.in_bs + k.total, out_ext = (i64)(d.nb - 1) * d.out_bs + k.total;
+    DTRG_REQUIRE(d.in_cap < 0 || in_ext <= d.in_cap, DTRG_EINVAL, "permute: input out of bounds");
+    DTRG_REQUIRE(d.out_cap < 0 || out_ext <= d.out_cap, DTRG_EINVAL, "permute: output out of bounds");
+    DTRG_REQUIRE(d.nb == 1 || (d.in_bs >= k.total && d.out_bs >= k.total), DTRG_EINVAL,
+                 "permute: instance stride smaller than an instance");
     return k;
 }
 
@@ -50,18 +57,26 @@ __device__ inline i64 perm_src(const PermK& p, i64 idx) {
     return off;
 }
 
+// x blocks per instance for n elements, keeping the whole grid near 8192 blocks
+dim3 grid2(i64 n, int nb) {
+    const i64 per = std::max<i64>(1, std::min<i64>((n + 255) / 256, std::max<i64>(1, 8192 / nb)));
+    return dim3((unsigned)per, (unsigned)nb);
+}
+
 template <class TI, class TO>
 __global__ __launch_bounds__(256) void permute_kernel(const TI* __restrict__ in, TO* __restrict__ out, PermK p,
-                                                      double alpha, double beta, const double* scale) {
-    const double a = scale ? alpha * scale[0] : alpha;
+                                                      i64 in_bs, i64 out_bs, double alpha, double beta,
+                                                      const double* scale, i64 scale_bs) {
+    const int z = blockIdx.y;
+    in += z * in_bs;
+    out += z * out_bs;
+    const double a = scale ? alpha * scale[z * scale_bs] : alpha;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < p.total; i += (i64)gridDim.x * blockDim.x) {
         double v = a * (double)in[perm_src(p, i)];
         if (beta != 0.0) v += beta * (double)out[i];
         out[i] = (TO)v;
     }
 }
-
-int grid_for(i64 n) { return (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 8192)); }
 
 __device__ inline double block_sum(double v) {
     __shared__ double sh[256];
@@ -76,60 +91,86 @@ __device__ inline double block_sum(double v) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void sumsq_partial_kernel(const double* x, const double* y, i64 n, double* part) {
+// partial sums of x*y (x*x when y is null): part[z * gridDim.x + blockIdx.x]
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(const double* x, const double* y, i64 bs, i64 n,
+                                                            double* part) {
+    const int z = blockIdx.y;
+    x += z * bs;
+    if (y) y += z * bs;
     double s = 0.0;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
         s += x[i] * (y ? y[i] : x[i]);
     s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[(i64)z * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void finish_sum_kernel(const double* part, int np, double* out, int take_sqrt) {
+__global__ __launch_bounds__(256) void finish_sum_kernel(const double* part, int np, double* out, i64 out_bs,
+                                                         int take_sqrt) {
+    const int z = blockIdx.x;
     double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[(i64)z * np + i];
     s = block_sum(s);
-    if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(s) : s;
+    if (threadIdx.x == 0) out[z * out_bs] = take_sqrt ? sqrt(s) : s;
 }
 
-__global__ __launch_bounds__(256) void fill_kernel(double* p, i64 n, double v) {
+__global__ __launch_bounds__(256) void fill_kernel(double* p, i64 bs, i64 n, double v) {
+    p += blockIdx.y * bs;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void axpy_kernel(const double* x, double* y, i64 n, double a) {
+__global__ __launch_bounds__(256) void axpy_kernel(const double* x, double* y, i64 bs, i64 n, double a) {
+    x += blockIdx.y * bs;
+    y += blockIdx.y * bs;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) y[i] += a * x[i];
 }
 
-__global__ __launch_bounds__(256) void scale_kernel(double* p, i64 n, double alpha, const double* sc, int recip) {
+__global__ __launch_bounds__(256) void scale_kernel(double* p, i64 bs, i64 n, double alpha, const double* sc,
+                                                    i64 sc_bs, int recip) {
+    const int z = blockIdx.y;
+    p += z * bs;
     double a = alpha;
-    if (sc) a *= recip ? 1.0 / sc[0] : sc[0];
+    if (sc) a *= recip ? 1.0 / sc[z * sc_bs] : sc[z * sc_bs];
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] *= a;
 }
 
-__global__ __launch_bounds__(256) void convert_kernel(const double* in, float* out, i64 n) {
+__global__ __launch_bounds__(256) void convert_kernel(const double* in, i64 in_bs, float* out, i64 out_bs, i64 n) {
+    in += blockIdx.y * in_bs;
+    out += blockIdx.y * out_bs;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
         out[i] = (float)in[i];
 }
 
-__global__ __launch_bounds__(256) void trace_xxyy_kernel(const double* T, int X, int Y, double* out) {
+__global__ __launch_bounds__(256) void trace_xxyy_kernel(const double* T, i64 bs, int X, int Y, double* out,
+                                                         i64 out_bs) {
+    const int z = blockIdx.x;
+    T += z * bs;
     double s = 0.0;
     for (int i = threadIdx.x; i < X * Y; i += blockDim.x) {
         const int x = i / Y, y = i % Y;
         s += T[(((i64)x * X + x) * Y + y) * Y + y];
     }
     s = block_sum(s);
-    if (threadIdx.x == 0) out[0] = s;
+    if (threadIdx.x == 0) out[z * out_bs] = s;
 }
 
-__global__ __launch_bounds__(256) void diag_sum_kernel(const double* G, int n, double* out) {
+__global__ __launch_bounds__(256) void diag_sum_kernel(const double* G, i64 bs, int n, double* out, i64 out_bs,
+                                                       int* flag) {
+    const int z = blockIdx.x;
+    G += z * bs;
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += G[(i64)i * n + i];
     s = block_sum(s);
-    if (threadIdx.x == 0) out[0] = s;
+    if (threadIdx.x == 0) {
+        out[z * out_bs] = s;
+        if (!(s > 0.0) || !isfinite(s)) flag[z] |= 1;
+    }
 }
 
 // G <- (G + G^T) / (2 t), one thread per (i <= j) pair
-__global__ __launch_bounds__(256) void sym_norm_kernel(double* G, int n, const double* t) {
-    const double inv = 0.5 / t[0];
+__global__ __launch_bounds__(256) void sym_norm_kernel(double* G, i64 bs, int n, const double* t, i64 t_bs) {
+    const int z = blockIdx.y;
+    G += z * bs;
+    const double inv = 0.5 / t[z * t_bs];
     const i64 total = (i64)n * n;
     for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
         const int i = (int)(idx / n), j = (int)(idx % n);
@@ -140,20 +181,26 @@ __global__ __launch_bounds__(256) void sym_norm_kernel(double* G, int n, const d
     }
 }
 
-__global__ void accum_log_kernel(const double* x, double w, double* L, double* inv, int* flag) {
-    const double v = x[0];
-    if (!(v > 0.0) || !isfinite(v)) { if (flag) flag[0] |= 1; return; }
-    L[0] += w * log(v);
-    if (inv) inv[0] = 1.0 / v;
+__global__ void accum_log_kernel(const double* x, double w, double* L, double* inv, i64 sc_bs, int nb, int* flag) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nb) return;
+    const double v = x[z * sc_bs];
+    if (!isfinite(v)) { flag[z] |= 4; return; }
+    if (!(v > 0.0)) { flag[z] |= 1; return; }
+    L[z * sc_bs] += w * log(v);
+    if (inv) inv[z * sc_bs] = 1.0 / v;
 }
 
 __global__ __launch_bounds__(256) void fill_int_kernel(int* p, i64 n, int v) {
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void seed_kernel(double* T, int X, int Y, double gw, const double* tr) {
+__global__ __launch_bounds__(256) void seed_kernel(double* T, i64 bs, int X, int Y, double gw, const double* tr,
+                                                   i64 tr_bs) {
+    const int z = blockIdx.y;
+    T += z * bs;
     const i64 total = (i64)X * X * Y * Y;
-    const double v = gw / tr[0];
+    const double v = gw / tr[z * tr_bs];
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < total; i += (i64)gridDim.x * blockDim.x) {
         i64 r = i;
         const int d = (int)(r % Y); r /= Y;
@@ -171,14 +218,20 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(256) void hash_fill_kernel(double* p, i64 n, uint64_t seed) {
+__global__ __launch_bounds__(256) void hash_fill_kernel(double* p, i64 bs, i64 n, uint64_t seed) {
+    const int z = blockIdx.y;
+    p += z * bs;
+    const uint64_t sz = z == 0 ? seed : splitmix64(seed ^ (0xa5a5a5a5ULL + (uint64_t)z));
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        const uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)i));
+        const uint64_t h = splitmix64(sz ^ splitmix64((uint64_t)i));
         p[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     }
 }
 
-__global__ __launch_bounds__(256) void copy2d_kernel(const double* src, i64 lds, double* dst, i64 ldd, int rows, int cols) {
+__global__ __launch_bounds__(256) void copy2d_kernel(const double* src, i64 lds, i64 src_bs, double* dst, i64 ldd,
+                                                     i64 dst_bs, int rows, int cols) {
+    src += blockIdx.y * src_bs;
+    dst += blockIdx.y * dst_bs;
     const i64 total = (i64)rows * cols;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < total; i += (i64)gridDim.x * blockDim.x) {
         const i64 r = i / cols, c = i % cols;
@@ -186,100 +239,155 @@ __global__ __launch_bounds__(256) void copy2d_kernel(const double* src, i64 lds,
     }
 }
 
+__global__ __launch_bounds__(256) void gather_kernel(const double* src, i64 src_bs, const int* idx, double* dst,
+                                                     i64 dst_bs, i64 len, int scatter) {
+    const int z = blockIdx.y;
+    const i64 so = scatter ? (i64)z * src_bs : (i64)idx[z] * src_bs;
+    const i64 dof = scatter ? (i64)idx[z] * dst_bs : (i64)z * dst_bs;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < len; i += (i64)gridDim.x * blockDim.x)
+        dst[dof + i] = src[so + i];
+}
+
+__global__ __launch_bounds__(64) void max_check_kernel(const double* v, i64 v_bs, int k, double thr, double* mx,
+                                                       i64 mx_bs, int* flag, int bit) {
+    const int z = blockIdx.x;
+    v += z * v_bs;
+    double m = 0.0;
+    for (int j = threadIdx.x; j < k; j += 64) m = fmax(m, isfinite(v[j]) ? v[j] : INFINITY);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
+    if (threadIdx.x == 0) {
+        if (mx) mx[z * mx_bs] = m;
+        if (!(m <= thr)) flag[z] |= bit;
+    }
+}
+
+int np_of(int nb) {
+    // fixed partial count for a given batch size: reductions are bit-reproducible
+    return nb == 1 ? kRedBlocks : std::max(16, std::min(kRedBlocks, 4096 / nb));
+}
+
 }  // namespace
 
 void permute(const double* in, double* out, const PermDesc& d, double alpha, double beta,
-             const double* scale_dev, hipStream_t s) {
+             const double* scale_dev, i64 scale_bs, hipStream_t s) {
     PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<double, double>), dim3(grid_for(k.total)), dim3(256), 0, s, in, out, k, alpha,
-                       beta, scale_dev);
+    hipLaunchKernelGGL((permute_kernel<double, double>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
+                       d.out_bs, alpha, beta, scale_dev, scale_bs);
     DTRG_HIP(hipGetLastError());
 }
 
 void permute_to_f32(const double* in, float* out, const PermDesc& d, hipStream_t s) {
     PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<double, float>), dim3(grid_for(k.total)), dim3(256), 0, s, in, out, k, 1.0,
-                       0.0, (const double*)nullptr);
+    hipLaunchKernelGGL((permute_kernel<double, float>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
+                       d.out_bs, 1.0, 0.0, (const double*)nullptr, (i64)0);
     DTRG_HIP(hipGetLastError());
 }
 
 void permute_f32(const float* in, float* out, const PermDesc& d, hipStream_t s) {
     PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<float, float>), dim3(grid_for(k.total)), dim3(256), 0, s, in, out, k, 1.0,
-                       0.0, (const double*)nullptr);
+    hipLaunchKernelGGL((permute_kernel<float, float>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
+                       d.out_bs, 1.0, 0.0, (const double*)nullptr, (i64)0);
     DTRG_HIP(hipGetLastError());
 }
 
-void convert_f64_to_f32(const double* in, float* out, i64 n, hipStream_t s) {
-    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
-    DTRG_HIP(hipGetLastError());
-}
-
-void fill(double* p, i64 n, double v, hipStream_t s) {
+void convert_f64_to_f32(const double* in, i64 in_bs, float* out, i64 out_bs, i64 n, int nb, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(convert_kernel, grid2(n, nb), dim3(256), 0, s, in, in_bs, out, out_bs, n);
     DTRG_HIP(hipGetLastError());
 }
 
-void axpy(const double* x, double* y, i64 n, double a, hipStream_t s) {
+void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n, a);
+    hipLaunchKernelGGL(fill_kernel, grid2(n, nb), dim3(256), 0, s, p, bs, n, v);
     DTRG_HIP(hipGetLastError());
 }
 
-void scale_inplace(double* p, i64 n, double alpha, const double* scale_dev, bool reciprocal, hipStream_t s) {
-    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, alpha, scale_dev, reciprocal ? 1 : 0);
+void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpy_kernel, grid2(n, nb), dim3(256), 0, s, x, y, bs, n, a);
     DTRG_HIP(hipGetLastError());
 }
 
-void norm2(const double* x, i64 n, double* out_dev, hipStream_t s, Scratch& ws) {
-    ws.red.ensure(kRedBlocks);
-    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kRedBlocks), dim3(256), 0, s, x, (const double*)nullptr, n, ws.red.p);
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(256), 0, s, (const double*)ws.red.p, kRedBlocks, out_dev, 1);
+void scale_inplace(double* p, i64 bs, i64 n, int nb, double alpha, const double* scale_dev, i64 scale_bs,
+                   bool reciprocal, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(scale_kernel, grid2(n, nb), dim3(256), 0, s, p, bs, n, alpha, scale_dev, scale_bs,
+                       reciprocal ? 1 : 0);
     DTRG_HIP(hipGetLastError());
 }
 
-void dot(const double* x, const double* y, i64 n, double* out_dev, hipStream_t s, Scratch& ws) {
-    ws.red.ensure(kRedBlocks);
-    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kRedBlocks), dim3(256), 0, s, x, y, n, ws.red.p);
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(256), 0, s, (const double*)ws.red.p, kRedBlocks, out_dev, 0);
+void norm2(const double* x, i64 bs, i64 n, int nb, double* out_dev, i64 out_bs, hipStream_t s, Scratch& ws) {
+    const int np = np_of(nb);
+    ws.red.ensure((size_t)np * nb);
+    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(np, nb), dim3(256), 0, s, x, (const double*)nullptr, bs, n, ws.red.p);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(nb), dim3(256), 0, s, (const double*)ws.red.p, np, out_dev, out_bs, 1);
     DTRG_HIP(hipGetLastError());
 }
 
-void trace_xxyy(const double* T, int X, int Y, double* out_dev, hipStream_t s) {
-    hipLaunchKernelGGL(trace_xxyy_kernel, dim3(1), dim3(256), 0, s, T, X, Y, out_dev);
+void dot(const double* x, const double* y, i64 bs, i64 n, int nb, double* out_dev, i64 out_bs, hipStream_t s,
+         Scratch& ws) {
+    const int np = np_of(nb);
+    ws.red.ensure((size_t)np * nb);
+    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(np, nb), dim3(256), 0, s, x, y, bs, n, ws.red.p);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(nb), dim3(256), 0, s, (const double*)ws.red.p, np, out_dev, out_bs, 0);
     DTRG_HIP(hipGetLastError());
 }
 
-void sym_normalise(double* G, int n, double* t_dev, hipStream_t s) {
-    hipLaunchKernelGGL(diag_sum_kernel, dim3(1), dim3(256), 0, s, (const double*)G, n, t_dev);
-    hipLaunchKernelGGL(sym_norm_kernel, dim3(grid_for((i64)n * n)), dim3(256), 0, s, G, n, (const double*)t_dev);
+void trace_xxyy(const double* T, i64 bs, int X, int Y, int nb, double* out_dev, i64 out_bs, hipStream_t s) {
+    hipLaunchKernelGGL(trace_xxyy_kernel, dim3(nb), dim3(256), 0, s, T, bs, X, Y, out_dev, out_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void accum_log(const double* x_dev, double weight, double* L_dev, double* inv_dev, int* flag_dev, hipStream_t s) {
-    hipLaunchKernelGGL(accum_log_kernel, dim3(1), dim3(1), 0, s, x_dev, weight, L_dev, inv_dev, flag_dev);
+void sym_normalise(double* G, i64 bs, int n, int nb, double* t_dev, i64 t_bs, int* flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(diag_sum_kernel, dim3(nb), dim3(256), 0, s, (const double*)G, bs, n, t_dev, t_bs, flag_dev);
+    hipLaunchKernelGGL(sym_norm_kernel, grid2((i64)n * n, nb), dim3(256), 0, s, G, bs, n, (const double*)t_dev, t_bs);
+    DTRG_HIP(hipGetLastError());
+}
+
+void accum_log(const double* x_dev, double weight, double* L_dev, double* inv_dev, i64 sc_bs, int nb, int* flag_dev,
+               hipStream_t s) {
+    hipLaunchKernelGGL(accum_log_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, x_dev, weight, L_dev, inv_dev, sc_bs,
+                       nb, flag_dev);
     DTRG_HIP(hipGetLastError());
 }
 
 void fill_int(int* p, i64 n, int v, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(fill_int_kernel, grid2(n, 1), dim3(256), 0, s, p, n, v);
     DTRG_HIP(hipGetLastError());
 }
 
-void seed_trace_grad(double* T, int X, int Y, double gbar_weight, const double* tr_dev, hipStream_t s) {
-    hipLaunchKernelGGL(seed_kernel, dim3(grid_for((i64)X * X * Y * Y)), dim3(256), 0, s, T, X, Y, gbar_weight, tr_dev);
+void seed_trace_grad(double* T, i64 bs, int X, int Y, int nb, double gbar_weight, const double* tr_dev, i64 tr_bs,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(seed_kernel, grid2((i64)X * X * Y * Y, nb), dim3(256), 0, s, T, bs, X, Y, gbar_weight, tr_dev,
+                       tr_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void hash_fill(double* p, i64 n, uint64_t seed, hipStream_t s) {
-    hipLaunchKernelGGL(hash_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, seed);
+void hash_fill(double* p, i64 bs, i64 n, int nb, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(hash_fill_kernel, grid2(n, nb), dim3(256), 0, s, p, bs, n, seed);
     DTRG_HIP(hipGetLastError());
 }
 
-void copy2d(const double* src, i64 lds, double* dst, i64 ldd, int rows, int cols, hipStream_t s) {
-    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((i64)rows * cols)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+void copy2d(const double* src, i64 lds, i64 src_bs, double* dst, i64 ldd, i64 dst_bs, int rows, int cols, int nb,
+            hipStream_t s) {
+    if ((i64)rows * cols <= 0) return;
+    hipLaunchKernelGGL(copy2d_kernel, grid2((i64)rows * cols, nb), dim3(256), 0, s, src, lds, src_bs, dst, ldd, dst_bs,
+                       rows, cols);
+    DTRG_HIP(hipGetLastError());
+}
+
+void gather_rows(const double* src, i64 src_bs, const int* idx_dev, double* dst, i64 dst_bs, i64 len, int nb,
+                 bool scatter, hipStream_t s) {
+    if (len <= 0 || nb <= 0) return;
+    hipLaunchKernelGGL(gather_kernel, grid2(len, nb), dim3(256), 0, s, src, src_bs, idx_dev, dst, dst_bs, len,
+                       scatter ? 1 : 0);
+    DTRG_HIP(hipGetLastError());
+}
+
+void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_dev, i64 mx_bs, int* flag_dev,
+               int bit, hipStream_t s) {
+    hipLaunchKernelGGL(max_check_kernel, dim3(nb), dim3(64), 0, s, v, v_bs, k, thr, mx_dev, mx_bs, flag_dev, bit);
     DTRG_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,102 @@
+// Tile autotuner of the MFMA contraction kernel.
+//
+// The first time a contraction shape (precision, output type, M, N, K, both batch levels, operand
+// layouts) is met in an adaptive pass with tuning enabled, every admissible configuration
+// {64 x 64, 128 x 128 tiles} x {split-K 1, 2, 4, ..., 32} is run on a scratch output (beta = 0, so
+// the real output is untouched), timed with HIP events on the caller's stream, and the fastest is
+// kept in a process-wide table.  Later contractions of that shape (including fixed passes that
+// are being captured into a graph) take the table entry without timing anything.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace dtrg {
+
+namespace {
+
+typedef std::tuple<int, int, int, int, int, int, int, int, int> TuneKey;
+
+std::mutex g_mu;
+std::map<TuneKey, GemmCfg> g_table;
+
+TuneKey key_of(Prec prec, bool out_f64, const GemmOp& op) {
+    return TuneKey((int)prec, out_f64 ? 1 : 0, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
+                   op.b_kmajor ? 1 : 0);
+}
+
+// largest split-K workspace a trial may claim (elements)
+constexpr i64 kMaxTrialPartials = 1LL << 26;
+
+}  // namespace
+
+int tuned_count() {
+    std::lock_guard<std::mutex> g(g_mu);
+    return (int)g_table.size();
+}
+
+GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
+                  DevBuf<double>& scratch) {
+    const TuneKey key = key_of(prec, out_f64, op);
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        auto it = g_table.find(key);
+        if (it != g_table.end()) return it->second;
+    }
+    if (!allow_tune || op.M == 0 || op.N == 0 || op.K == 0) return op.cfg;
+
+    const int BK = prec == Prec::BF16X3 ? 32 : 16;
+    const i64 nz = (i64)op.batch * op.batch2;
+    std::vector<GemmCfg> cands;
+    for (int tile = 1; tile <= 2; ++tile) {
+        if (tile == 2 && std::max(op.M, op.N) < 128) continue;
+        for (int sp = 1; sp <= 32; sp *= 2) {
+            if (sp > 1 && op.K < sp * BK * 2) break;
+            if (nz * sp >= 65536) break;
+            if (sp > 1 && nz * sp * op.M * op.N > kMaxTrialPartials) break;
+            GemmCfg c;
+            c.tile = tile;
+            c.splits = sp;
+            cands.push_back(c);
+        }
+    }
+    const i64 ext = gemm_c_extent(op);
+    scratch.ensure((size_t)ext);
+    hipEvent_t e0, e1;
+    DTRG_HIP(hipEventCreate(&e0));
+    DTRG_HIP(hipEventCreate(&e1));
+    GemmCfg best = gemm_resolve(prec, op);
+    float best_ms = 1e30f;
+    try {
+        for (const GemmCfg& c : cands) {
+            GemmOp t = op;
+            t.cfg = c;
+            t.C = scratch.p;
+            t.c_cap = (i64)scratch.n * (out_f64 ? 1 : 2);
+            t.beta = 0.0;
+            t.tag = 0;
+            gemm(prec, out_f64, t, s, ws);   // warm-up (and workspace growth)
+            DTRG_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 2; ++r) gemm(prec, out_f64, t, s, ws);
+            DTRG_HIP(hipEventRecord(e1, s));
+            DTRG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DTRG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table[key] = best;
+    return best;
+}
+
+}  // namespace dtrg

@@ -81,9 +81,32 @@ def test_default_options():
     class Options(ctypes.Structure):
         _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
                     ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("keep_projections", ctypes.c_int), ("profile", ctypes.c_int),
+                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int),
                     ("bf16x3_mask", ctypes.c_int)]
 
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))
     assert o.contract == 0 and o.eig_broadening == 1e-12 and o.max_subspace_iters == 60
+    assert o.autotune == 0 and o.profile == 0 and o.bf16x3_mask == 15 and o.gram_fp64 == 1
+
+
+def test_batch_argument_validation_without_device_work():
+    lib = _lib()
+    lib.dtrg_batch_create.restype = ctypes.c_int
+    lib.dtrg_batch_run.restype = ctypes.c_int
+    lib.dtrg_batch_step_info.restype = ctypes.c_int
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    b = ctypes.c_void_p()
+    chis = (ctypes.c_int * 3)(16, 24, 0)
+    # a chi out of range anywhere in the batch fails before any allocation
+    assert lib.dtrg_batch_create(3, 2, chis, 30, None, ctypes.byref(b)) == 1 and b.value is None
+    assert b"chi" in lib.dtrg_last_error()
+    assert lib.dtrg_batch_create(0, 2, chis, 30, None, ctypes.byref(b)) == 1
+    assert lib.dtrg_batch_create(2, 2, None, 30, None, ctypes.byref(b)) == 1
+    assert lib.dtrg_batch_create(2, 2, chis, 0, None, ctypes.byref(b)) == 1
+    out = (ctypes.c_double * 3)()
+    assert lib.dtrg_batch_run(None, ctypes.c_void_p(8), None, ctypes.c_double(1.0), out, None, None, 0, None) == 1
+    assert lib.dtrg_batch_step_info(None, 0, 1, None) == 1
+    lib.dtrg_batch_destroy(None)
+    lib.dtrg_batch_device_bytes.restype = ctypes.c_size_t
+    assert lib.dtrg_batch_device_bytes(None) == 0
