@@ -41,9 +41,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HOTRG fwd+bwd RG-steps/s at χ=48; lnZ/N & ∂lnZ/∂β error vs FP64 oracle"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X datasheet
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (fp32 accumulate)"}
-DEFAULT_CONTRACT = {"chi48": "fp32", "batch256": "bf16x3", "ising_chi64": "bf16x3"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense MFMA, MI355X datasheet
+# MFMA products per algorithmic multiply-add (the split-bf16 paths run several bf16 products)
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (2 bf16 planes, 3 products, fp32 accumulate)",
+         "bf16x6": "bf16x6 (3 bf16 planes, 6 products, fp32 accumulate)"}
+DEFAULT_CONTRACT = {"chi48": "bf16x6", "batch256": "bf16x6", "ising_chi64": "bf16x6"}
 
 
 # L2-miss byte counters of the timed join kernel per launch, from two rocprofv3 --pmc passes over
@@ -53,7 +56,7 @@ DEFAULT_CONTRACT = {"chi48": "fp32", "batch256": "bf16x3", "ising_chi64": "bf16x
 # for 1048576 KiB written: factor 1.0).  Valid only for the kernel sources they were taken on.
 TRAFFIC_FACTORS = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_02780_amd/csrc/gemm.hip",
-                   "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_bf16x3.hip"]
+                   "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 40 launches per pass
     ("chi48", "fp32"): {"sources_sha256": "7c0907011b3acc159a2ff432c80cc6d9a42de5963cb51e3302e4e0fbf6cf3d31", "fetch_kib": 3809998.1, "write_kib": 1149221.0},
@@ -125,6 +128,10 @@ def roofline(launches, ms, flops, contract, kernel, traffic=None):
     out = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
            "traffic": traffic, "kernel": kernel, "launches": launches, "avg_ms": ms / launches,
            "flops_per_launch": flops / launches}
+    if PRODUCTS[contract] > 1:
+        # achieved counts the algorithmic 2 M N K; the MFMA units execute PRODUCTS times that
+        out["mfma_products"] = PRODUCTS[contract]
+        out["mfma_busy_frac"] = achieved * PRODUCTS[contract] / peak
     if traffic is not None:
         out["traffic_unit"] = "bytes per launch (L2 misses: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
     return out

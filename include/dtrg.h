@@ -59,8 +59,11 @@ typedef enum {
 typedef enum {
     DTRG_FP64 = 0,     /* FP64 operands, FP64 MFMA */
     DTRG_FP32 = 1,     /* FP32 operands, FP32 MFMA, FP32 accumulation */
-    DTRG_BF16X3 = 2    /* FP32 operands split as hi + lo in bf16; hi*hi + hi*lo + lo*hi on bf16
-                          MFMA with FP32 accumulation */
+    DTRG_BF16X3 = 2,   /* FP32 values carried as two bf16 planes x0 + x1 (x0 = bf16(x),
+                          x1 = bf16(x - x0)); a1 b0 + a0 b1 + a0 b0 on bf16 MFMA with FP32
+                          accumulation (the "3-term split-bf16" product, ~2^-17 relative) */
+    DTRG_BF16X6 = 3    /* three bf16 planes; the six partial products down to 2^-24 relative:
+                          FP32-level accuracy on bf16 MFMA */
 } dtrg_precision;
 
 typedef struct {
@@ -77,19 +80,12 @@ typedef struct {
     int block_size;           /* subspace block b (> chi', <= 96); 0 = automatic (min(96, max(chi' + 16,
                                  2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates */
     int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
-                                 (64 x 64, 128 x 128) and split-K factor (1..32) of the MFMA kernel
-                                 on a scratch output and keep the fastest for that shape (a table
-                                 shared by all plans of the process); 0: fixed heuristic.
-                                 Default 0 */
-    int profile;              /* 1: time every chi^7 join contraction with HIP events on the plan's
+                                 (64 x 64, 128 x 128, and 256 x 128 for the bf16-plane precisions)
+                                 and split-K factor (1..32) of the MFMA kernels on a scratch output
+                                 and keep the fastest for that shape (a table shared by all plans of
+                                 the process); 0: fixed heuristic.  Default 0 */
+    int profile;              /* 1: time the chi^7 join contractions with HIP events on the plan's
                                  stream (read with dtrg_plan_profile); default 0 */
-    int bf16x3_mask;          /* with contract = DTRG_BF16X3: which contractions use split-bf16
-                                 (the others use FP32).  Bit 0: the chi^7 join (forward and its
-                                 recompute); bit 1: its adjoint w.r.t. the upper product; bit 2: its
-                                 adjoint w.r.t. the lower copy; bit 3: the six chi^6 projection
-                                 contractions.  Default 15 (all): the gradient is most accurate
-                                 when forward and adjoint contractions round alike, since the
-                                 broadened inverse gaps amplify any mismatch between them. */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -160,7 +156,9 @@ dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* in
  * times the left isometry joined with the lower copy over (x2, j); launched once per step in the
  * forward and once more in the backward's recompute) recorded since the last reset on a plan
  * created with opt.profile = 1: number of launches, summed milliseconds and summed algorithmic
- * flops (2 M N K per launch).  Synchronises on the recorded events; reset != 0 clears the record.
+ * flops (2 M N K per launch).  Only launches in the plan's contraction precision on the 128 x 128
+ * tile are timed (all launches of that kernel), so the average matches that kernel's average in a
+ * kernel trace.  Synchronises on the recorded events; reset != 0 clears the record.
  */
 dtrg_status dtrg_plan_profile(dtrg_plan* plan, long long* launches, double* total_ms, double* flops, int reset);
 
@@ -206,6 +204,10 @@ dtrg_status dtrg_batch_run(dtrg_batch* batch, const double* T0s_dev, const doubl
 /* Diagnostics of step k of instance inst (0-based) after a successful run. */
 dtrg_status dtrg_batch_step_info(const dtrg_batch* batch, int inst, int k, dtrg_step_info* info);
 
+/* dtrg_plan_profile summed over the batch's groups (adaptive runs with opt.profile = 1; replays
+ * record no events). */
+dtrg_status dtrg_batch_profile(dtrg_batch* batch, long long* launches, double* total_ms, double* flops, int reset);
+
 /* Device bytes held by the batch. */
 size_t dtrg_batch_device_bytes(const dtrg_batch* batch);
 
@@ -229,8 +231,9 @@ const char* dtrg_last_error(void);
  *   C[r * ldc + c] = alpha * sum_k A(r, k) B(c, k) + beta * C[r * ldc + c],  r < M, c < N,
  * with A(r, k) = A_dev[r * lda + k] (a_kmajor = 0) or A_dev[k * lda + r] (a_kmajor = 1) and
  * B(c, k) = B_dev[c * ldb + k] (b_kmajor = 0) or B_dev[k * ldb + c] (b_kmajor = 1).
- * precision DTRG_FP64: A, B, C are double.  DTRG_FP32 / DTRG_BF16X3: A, B are float and C is
- * double if out_f64 else float.  Device pointers; enqueued on `stream`, not synchronised.
+ * precision DTRG_FP64: A, B, C are double.  DTRG_FP32 / DTRG_BF16X3 / DTRG_BF16X6: A, B are float
+ * and C is double if out_f64 else float (the split precisions first split A and B into K-contiguous
+ * bf16 planes in a scratch buffer the library keeps per thread).  Device pointers; enqueued on `stream`, not synchronised.
  */
 dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
                           const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,

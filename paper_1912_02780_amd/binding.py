@@ -19,19 +19,19 @@ LIB_PATH = os.path.join(_HERE, "libdtrg.so")
 DTRG_OK, DTRG_EINVAL, DTRG_ENOMEM, DTRG_EHIP, DTRG_ENOCONV, DTRG_ENONPOS, DTRG_ESTATE = range(7)
 STATUS_NAMES = {0: "DTRG_OK", 1: "DTRG_EINVAL", 2: "DTRG_ENOMEM", 3: "DTRG_EHIP", 4: "DTRG_ENOCONV",
                 5: "DTRG_ENONPOS", 6: "DTRG_ESTATE"}
-DTRG_FP64, DTRG_FP32, DTRG_BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3}
+DTRG_FP64, DTRG_FP32, DTRG_BF16X3, DTRG_BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3, "bf16x6": DTRG_BF16X6}
 
 EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "dtrg_plan_forward",
             "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_batch_create", "dtrg_batch_run",
-            "dtrg_batch_step_info", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
+            "dtrg_batch_step_info", "dtrg_batch_profile", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
             "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_version"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("autotune", c_int), ("profile", c_int), ("bf16x3_mask", c_int)]
+                ("autotune", c_int), ("profile", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -75,6 +75,8 @@ def _load():
     lib.dtrg_batch_run.restype = c_int
     lib.dtrg_batch_step_info.argtypes = [c_void_p, c_int, c_int, POINTER(StepInfo)]
     lib.dtrg_batch_step_info.restype = c_int
+    lib.dtrg_batch_profile.argtypes = [c_void_p, POINTER(c_longlong), POINTER(c_double), POINTER(c_double), c_int]
+    lib.dtrg_batch_profile.restype = c_int
     lib.dtrg_batch_device_bytes.argtypes = [c_void_p]
     lib.dtrg_batch_device_bytes.restype = c_size_t
     lib.dtrg_batch_destroy.argtypes = [c_void_p]
@@ -228,6 +230,12 @@ class Batch:
         info = StepInfo()
         _check(lib.dtrg_batch_step_info(self._h, int(inst), int(k), byref(info)))
         return info.as_dict()
+
+    def profile(self, reset: bool = True):
+        """(launches, total_ms, flops) of the timed chi^7 contractions of adaptive runs since the last reset."""
+        n, ms, fl = c_longlong(), c_double(), c_double()
+        _check(lib.dtrg_batch_profile(self._h, byref(n), byref(ms), byref(fl), int(reset)))
+        return n.value, ms.value, fl.value
 
     def device_bytes(self) -> int:
         return int(lib.dtrg_batch_device_bytes(self._h))

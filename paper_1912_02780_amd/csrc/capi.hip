@@ -20,10 +20,18 @@ dtrg_status fail(const Error& e) {
     return e.code;
 }
 
+Prec prec_of(int contract) {
+    switch (contract) {
+        case DTRG_FP32: return Prec::F32;
+        case DTRG_BF16X3: return Prec::BF16X3;
+        case DTRG_BF16X6: return Prec::BF16X6;
+        default: return Prec::F64;
+    }
+}
+
 void validate_options(const dtrg_options& o) {
-    DTRG_REQUIRE(o.contract == DTRG_FP64 || o.contract == DTRG_FP32 || o.contract == DTRG_BF16X3, DTRG_EINVAL,
-                 "contract must be DTRG_FP64, DTRG_FP32 or DTRG_BF16X3");
-    DTRG_REQUIRE(o.bf16x3_mask >= 0 && o.bf16x3_mask <= 15, DTRG_EINVAL, "bf16x3_mask out of range [0, 15]");
+    DTRG_REQUIRE(o.contract >= DTRG_FP64 && o.contract <= DTRG_BF16X6, DTRG_EINVAL,
+                 "contract must be DTRG_FP64, DTRG_FP32, DTRG_BF16X3 or DTRG_BF16X6");
     DTRG_REQUIRE(o.gram_fp64 == 1, DTRG_EINVAL, "the Gram is always formed in FP64 (gram_fp64 must be 1)");
     DTRG_REQUIRE(o.eig_broadening >= 0.0 && std::isfinite(o.eig_broadening), DTRG_EINVAL,
                  "eig_broadening must be finite and >= 0");
@@ -44,7 +52,7 @@ std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const 
     dtrg_default_options(&P->opt);
     if (opt) P->opt = *opt;
     validate_options(P->opt);
-    P->prec = P->opt.contract == DTRG_FP64 ? Prec::F64 : (P->opt.contract == DTRG_FP32 ? Prec::F32 : Prec::BF16X3);
+    P->prec = prec_of(P->opt.contract);
     P->D = D; P->chi = chi; P->nsteps = n_steps; P->nb = nb;
     plan_setup(P.get());
     return P;
@@ -174,7 +182,6 @@ void dtrg_default_options(dtrg_options* o) {
     o->block_size = 0;
     o->autotune = 0;
     o->profile = 0;
-    o->bf16x3_mask = 15;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -443,6 +450,22 @@ dtrg_status dtrg_batch_step_info(const dtrg_batch* batch, int inst, int k, dtrg_
     }
 }
 
+dtrg_status dtrg_batch_profile(dtrg_batch* batch, long long* launches, double* total_ms, double* flops, int reset) {
+    g_last_error.clear();
+    if (!batch || !launches || !total_ms || !flops) { g_last_error = "NULL argument"; return DTRG_EINVAL; }
+    long long n = 0;
+    double ms = 0.0, fl = 0.0;
+    for (auto& P : batch->plans) {
+        long long a = 0;
+        double b = 0.0, c = 0.0;
+        const dtrg_status st = dtrg_plan_profile(P.get(), &a, &b, &c, reset);
+        if (st != DTRG_OK) return st;
+        n += a; ms += b; fl += c;
+    }
+    *launches = n; *total_ms = ms; *flops = fl;
+    return DTRG_OK;
+}
+
 size_t dtrg_batch_device_bytes(const dtrg_batch* batch) {
     if (!batch) return 0;
     size_t t = 0;
@@ -468,20 +491,36 @@ dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev,
                           double alpha, double beta, void* stream) {
     g_last_error.clear();
     static thread_local Scratch ws;
+    static thread_local DevBuf<double> planes;
     try {
         DTRG_REQUIRE(A_dev && B_dev && C_dev, DTRG_EINVAL, "NULL argument");
         DTRG_REQUIRE(M >= 0 && N >= 0 && K >= 0, DTRG_EINVAL, "negative size");
-        DTRG_REQUIRE(precision >= DTRG_FP64 && precision <= DTRG_BF16X3, DTRG_EINVAL, "bad precision");
+        DTRG_REQUIRE(precision >= DTRG_FP64 && precision <= DTRG_BF16X6, DTRG_EINVAL, "bad precision");
         DTRG_REQUIRE(lda >= (a_kmajor ? M : K) && ldb >= (b_kmajor ? N : K) && ldc >= N, DTRG_EINVAL,
                      "leading dimension too small");
+        const Prec pr = prec_of(precision);
+        const hipStream_t s = (hipStream_t)stream;
         GemmOp g;
         g.M = M; g.N = N; g.K = K;
-        g.A = A_dev; g.lda = lda; g.a_kmajor = a_kmajor != 0;
-        g.B = B_dev; g.ldb = ldb; g.b_kmajor = b_kmajor != 0;
         g.C = C_dev; g.rmap = IdxMap::linear(ldc); g.cmap = IdxMap::linear(1);
         g.alpha = alpha; g.beta = beta;
-        const Prec pr = precision == DTRG_FP64 ? Prec::F64 : (precision == DTRG_FP32 ? Prec::F32 : Prec::BF16X3);
-        dtrg::gemm(pr, precision == DTRG_FP64 ? true : out_f64 != 0, g, (hipStream_t)stream, ws);
+        const int np = prec_planes(pr);
+        if (np == 1) {
+            g.A = A_dev; g.lda = lda; g.a_kmajor = a_kmajor != 0;
+            g.B = B_dev; g.ldb = ldb; g.b_kmajor = b_kmajor != 0;
+        } else {
+            // FP32 operands split into K-contiguous bf16 planes (rows padded to 8) in a scratch buffer
+            const i64 ld = ((i64)K + 7) / 8 * 8;
+            const i64 a_ps = (i64)M * ld, b_ps = (i64)N * ld;
+            planes.ensure((size_t)((np * (a_ps + b_ps) * 2 + 7) / 8) + 2);
+            __bf16* pa = (__bf16*)planes.p;
+            __bf16* pb = pa + np * a_ps;
+            split_matrix((const float*)A_dev, lda, a_kmajor != 0, M, K, pa, ld, a_ps, np, s);
+            split_matrix((const float*)B_dev, ldb, b_kmajor != 0, N, K, pb, ld, b_ps, np, s);
+            g.A = pa; g.lda = ld; g.a_ps = a_ps;
+            g.B = pb; g.ldb = ld; g.b_ps = b_ps;
+        }
+        dtrg::gemm(pr, precision == DTRG_FP64 || out_f64 ? Out::F64 : Out::F32, g, s, ws);
         return DTRG_OK;
     } catch (const Error& e) {
         return fail(e);

@@ -86,11 +86,15 @@ struct IdxMap {
 
 __host__ __device__ inline i64 idx_off(const IdxMap& m, i64 i) { return (i / m.div) * m.s1 + (i % m.div) * m.s0; }
 
-// Element types of a contraction.
-enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+// Arithmetic of a contraction, which is also the storage format of its operands: FP64, FP32, or
+// FP32 values carried as 2 (BF16X3: three bf16 products) or 3 (BF16X6: six products) bf16 planes.
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2, BF16X6 = 3 };
+// Output format of a contraction: FP64, FP32, or the contraction's own bf16 planes.
+enum class Out { F64 = 0, F32 = 1, Split = 2 };
+int prec_planes(Prec p);   // 1, or the number of bf16 planes
 
-// Tile configuration of one contraction: tile 0 = automatic, 1 = 64 x 64, 2 = 128 x 128;
-// splits 0 = automatic split-K.
+// Tile configuration of one contraction: tile 0 = automatic, 1 = 64 x 64, 2 = 128 x 128,
+// 3 = 256 x 128 (bf16 planes only); splits 0 = automatic split-K.
 struct GemmCfg {
     int tile = 0;
     int splits = 0;
@@ -102,11 +106,13 @@ struct GemmCfg {
 //   Two batch levels: z = (z2, z1), z1 < batch, z2 < batch2 (the problem instance); operand X of
 //   batch element z starts at X + z1 * x_bs + z2 * x_bs2.
 //   C element (z, r, c) lives at C + z1 * c_bs + z2 * c_bs2 + idx_off(rmap, r) + idx_off(cmap, c).
+//   bf16-plane operands and outputs: plane q at base + q * (a_ps, b_ps, c_ps); such operands are
+//   K-contiguous with rows padded to a multiple of 8 elements.
 struct GemmOp {
     int M = 0, N = 0, K = 0, batch = 1, batch2 = 1;
-    const void* A = nullptr; i64 lda = 0, a_bs = 0, a_bs2 = 0; bool a_kmajor = false;
-    const void* B = nullptr; i64 ldb = 0, b_bs = 0, b_bs2 = 0; bool b_kmajor = false;
-    void* C = nullptr; i64 c_bs = 0, c_bs2 = 0;
+    const void* A = nullptr; i64 lda = 0, a_bs = 0, a_bs2 = 0, a_ps = 0; bool a_kmajor = false;
+    const void* B = nullptr; i64 ldb = 0, b_bs = 0, b_bs2 = 0, b_ps = 0; bool b_kmajor = false;
+    void* C = nullptr; i64 c_bs = 0, c_bs2 = 0, c_ps = 0;
     IdxMap rmap, cmap;
     double alpha = 1.0, beta = 0.0;
     GemmCfg cfg;
@@ -129,7 +135,7 @@ struct Scratch {
 GemmCfg gemm_resolve(Prec in_prec, const GemmOp& op);
 // Largest element offset (plus one) the epilogue of op can write, over all batch elements.
 i64 gemm_c_extent(const GemmOp& op);
-void gemm(Prec in_prec, bool out_f64, const GemmOp& op, hipStream_t s, Scratch& ws);
+void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws);
 
 // tensor_ops.hip
 // Batched helpers: instance i < nb of a buffer p with instance stride bs starts at p + i * bs;
@@ -140,14 +146,27 @@ struct PermDesc {
     int perm[6];
     int nb = 1;                      // instances
     i64 in_bs = 0, out_bs = 0;       // instance strides (elements)
+    int out_inner = 0;               // output rows = the last out_inner output dims (0: dense output)
+    i64 out_ld = 0;                  // output row stride (elements) when out_inner > 0
+    i64 out_ps = 0;                  // plane stride of bf16-plane outputs
     i64 in_cap = -1, out_cap = -1;   // element capacities (-1: unchecked)
 };
 // out = alpha * (scale_dev[i * scale_bs] if scale_dev) * transpose(in, perm) + beta * out
 // (numpy transpose semantics, per instance)
 void permute(const double* in, double* out, const PermDesc& d, double alpha, double beta,
              const double* scale_dev, i64 scale_bs, hipStream_t s);
-void permute_to_f32(const double* in, float* out, const PermDesc& d, hipStream_t s);
-void permute_f32(const float* in, float* out, const PermDesc& d, hipStream_t s);
+// the same (beta = 0) written as out_code 0 double, 1 float, 2 / 3 bf16 planes (the value rounded
+// to FP32, plane q the bf16 rounding of what the planes before it leave), rows padded per d
+void permute_out(const double* in, void* out, int out_code, const PermDesc& d, double alpha, const double* scale_dev,
+                 i64 scale_bs, hipStream_t s);
+// out[c][r] = in[r][c] (r < rows, c < cols, row strides ld_in / ld_out) for np planes (plane strides
+// ps_in / ps_out) of nb instances (strides bs_in / bs_out); esz = element size in bytes (2, 4, 8)
+void transpose_planes(const void* in, void* out, int esz, int rows, int cols, i64 ld_in, i64 ld_out, int nb,
+                      i64 bs_in, i64 bs_out, int np, i64 ps_in, i64 ps_out, hipStream_t s);
+// planes of an FP32 matrix, K-contiguous: out[q][r][k] from in(r, k) (in[r * ld_in + k], or
+// in[k * ld_in + r] if kmajor), rows r < rows, k < cols, row stride ld_out, plane stride ps
+void split_matrix(const float* in, i64 ld_in, bool kmajor, int rows, int cols, void* out, i64 ld_out, i64 ps, int np,
+                  hipStream_t s);
 void convert_f64_to_f32(const double* in, i64 in_bs, float* out, i64 out_bs, i64 n, int nb, hipStream_t s);
 void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s);
 // y += a * x

@@ -1,13 +1,15 @@
-// Host dispatch of the MFMA contraction kernel (tile choice, split-K, bounds checks) and the
-// deterministic split-K reduction.  The kernels themselves are in gemm_kernels.hpp.
+// Host dispatch of the MFMA contraction kernels (tile choice, split-K, bounds checks) and the
+// deterministic split-K reduction.  The kernels are in gemm_kernels.hpp (FP64, FP32) and
+// gemm_split.hpp (bf16 planes).
 #include "gemm_kernels.hpp"
 
 #include <algorithm>
+#include <cstdint>
 
 namespace dtrg {
 
-// Sum of split-K partials in a fixed order, then the scatter epilogue.
-template <class TA, class TO>
+// Sum of split-K partials in a fixed order, then the shared epilogue.
+template <class TA, int OUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
     const i64 MN = (i64)p.M * p.N;
     const i64 total = MN * p.batch * p.batch2;
@@ -17,11 +19,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
         const TA* W = (const TA*)p.W + zb * p.splits * MN + rc;
         double s = 0.0;
         for (int q = 0; q < p.splits; ++q) s += (double)W[(i64)q * MN];
-        TO* C = (TO*)p.C + batch_off(p, (int)zb, p.c_bs, p.c_bs2);
-        const i64 off = idx_off(p.rmap, r) + idx_off(p.cmap, c);
-        double v = p.alpha * s;
-        if (p.beta != 0.0) v += p.beta * (double)C[off];
-        C[off] = (TO)v;
+        write_elem<OUT>(p, (int)zb, r, c, p.alpha * s);
     }
 }
 
@@ -34,9 +32,24 @@ i64 map_max(const IdxMap& m, i64 count) {
     return (last / m.div) * m.s1 + (m.div - 1) * m.s0;
 }
 
-int bk_of(Prec prec) { return prec == Prec::BF16X3 ? 32 : 16; }
+// K tile of the kernel that runs a configuration (split-K chunks are multiples of it)
+int bk_of(Prec prec, int tile) {
+    const int np = prec_planes(prec);
+    if (np == 1) return 16;
+    return (np == 2 && tile == 3) ? 64 : 32;
+}
+
+int out_code(Prec prec, Out out) {
+    if (out == Out::F64) return 0;
+    if (out == Out::F32) return 1;
+    return prec_planes(prec);
+}
+
+i64 round8(i64 x) { return (x + 7) / 8 * 8; }
 
 }  // namespace
+
+int prec_planes(Prec p) { return p == Prec::BF16X3 ? 2 : (p == Prec::BF16X6 ? 3 : 1); }
 
 i64 gemm_c_extent(const GemmOp& op) {
     if (op.M == 0 || op.N == 0) return 0;
@@ -46,13 +59,19 @@ i64 gemm_c_extent(const GemmOp& op) {
 
 GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
     GemmCfg c = op.cfg;
+    const bool split = prec_planes(prec) > 1;
     if (c.tile == 0) {
-        // 128 x 128 for large outputs, 64 x 64 otherwise
+        // 128 x 128 for large outputs (256 x 128 for the split kernel when there are enough of
+        // them to fill the chip), 64 x 64 otherwise
         const bool big = (op.M >= 256 && op.N >= 128) || (op.N >= 256 && op.M >= 128);
         c.tile = big ? 2 : 1;
+        if (split && big && op.M >= 256) {
+            const i64 t3 = (i64)((op.M + 255) / 256) * ((op.N + 127) / 128) * op.batch * op.batch2;
+            if (t3 >= 512) c.tile = 3;
+        }
     }
-    const int BM = c.tile == 2 ? 128 : 64, BN = BM;
-    const int BK = bk_of(prec);
+    const int BM = c.tile == 3 ? 256 : (c.tile == 2 ? 128 : 64), BN = c.tile == 1 ? 64 : 128;
+    const int BK = bk_of(prec, c.tile);
     if (c.splits <= 0) {
         const i64 tiles = (i64)((op.M + BM - 1) / BM) * ((op.N + BN - 1) / BN) * op.batch * op.batch2;
         c.splits = 1;
@@ -66,36 +85,55 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
     return c;
 }
 
-void gemm(Prec prec, bool out_f64, const GemmOp& op, hipStream_t s, Scratch& ws) {
+void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     DTRG_REQUIRE(op.M >= 0 && op.N >= 0 && op.K >= 0 && op.batch >= 1 && op.batch2 >= 1, DTRG_EINVAL,
                  "gemm: bad sizes");
     if (op.M == 0 || op.N == 0) return;
+    const int np = prec_planes(prec);
+    const bool split = np > 1;
+    DTRG_REQUIRE(prec != Prec::F64 || out == Out::F64, DTRG_EINVAL, "gemm: FP64 contraction must write FP64");
+    DTRG_REQUIRE(out != Out::Split || (split && op.beta == 0.0), DTRG_EINVAL,
+                 "gemm: split output needs a split contraction and beta = 0");
+    if (split) {
+        // K-contiguous planes only: 16-byte aligned rows of at least round8(K) elements
+        DTRG_REQUIRE(!op.a_kmajor && !op.b_kmajor, DTRG_EINVAL, "gemm: split operands must be K-contiguous");
+        DTRG_REQUIRE(op.lda % 8 == 0 && op.ldb % 8 == 0 && op.lda >= round8(op.K) && op.ldb >= round8(op.K),
+                     DTRG_EINVAL, "gemm: split operand rows must be padded to a multiple of 8 elements");
+        DTRG_REQUIRE((op.a_ps | op.b_ps | op.a_bs | op.b_bs | op.a_bs2 | op.b_bs2) % 8 == 0, DTRG_EINVAL,
+                     "gemm: split operand strides must be multiples of 8 elements");
+        DTRG_REQUIRE(((uintptr_t)op.A | (uintptr_t)op.B) % 16 == 0, DTRG_EINVAL,
+                     "gemm: split operands must be 16-byte aligned");
+    }
+    const i64 a_row = split ? round8(op.K) : op.K, b_row = a_row;
     if (op.K > 0 && op.a_cap >= 0) {
-        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (op.M - 1) : (i64)(op.M - 1) * op.lda + (op.K - 1)) +
-                       (i64)(op.batch - 1) * op.a_bs + (i64)(op.batch2 - 1) * op.a_bs2;
+        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (op.M - 1) : (i64)(op.M - 1) * op.lda + (a_row - 1)) +
+                       (i64)(op.batch - 1) * op.a_bs + (i64)(op.batch2 - 1) * op.a_bs2 + (i64)(np - 1) * op.a_ps;
         DTRG_REQUIRE(mx < op.a_cap, DTRG_EINVAL, "gemm: operand A out of bounds");
     }
     if (op.K > 0 && op.b_cap >= 0) {
-        const i64 mx = (op.b_kmajor ? (i64)(op.K - 1) * op.ldb + (op.N - 1) : (i64)(op.N - 1) * op.ldb + (op.K - 1)) +
-                       (i64)(op.batch - 1) * op.b_bs + (i64)(op.batch2 - 1) * op.b_bs2;
+        const i64 mx = (op.b_kmajor ? (i64)(op.K - 1) * op.ldb + (op.N - 1) : (i64)(op.N - 1) * op.ldb + (b_row - 1)) +
+                       (i64)(op.batch - 1) * op.b_bs + (i64)(op.batch2 - 1) * op.b_bs2 + (i64)(np - 1) * op.b_ps;
         DTRG_REQUIRE(mx < op.b_cap, DTRG_EINVAL, "gemm: operand B out of bounds");
     }
-    if (op.c_cap >= 0) DTRG_REQUIRE(gemm_c_extent(op) <= op.c_cap, DTRG_EINVAL, "gemm: output C out of bounds");
+    const int onp = out == Out::Split ? np : 1;
+    if (op.c_cap >= 0)
+        DTRG_REQUIRE(gemm_c_extent(op) + (i64)(onp - 1) * op.c_ps <= op.c_cap, DTRG_EINVAL,
+                     "gemm: output C out of bounds");
     KArgs a;
     a.M = op.M; a.N = op.N; a.K = op.K;
-    a.A = op.A; a.lda = op.lda; a.a_bs = op.a_bs; a.a_bs2 = op.a_bs2;
-    a.B = op.B; a.ldb = op.ldb; a.b_bs = op.b_bs; a.b_bs2 = op.b_bs2;
-    a.C = op.C; a.c_bs = op.c_bs; a.c_bs2 = op.c_bs2;
+    a.A = op.A; a.lda = op.lda; a.a_bs = op.a_bs; a.a_bs2 = op.a_bs2; a.a_ps = op.a_ps;
+    a.B = op.B; a.ldb = op.ldb; a.b_bs = op.b_bs; a.b_bs2 = op.b_bs2; a.b_ps = op.b_ps;
+    a.C = op.C; a.c_bs = op.c_bs; a.c_bs2 = op.c_bs2; a.c_ps = op.c_ps;
     a.rmap = op.rmap; a.cmap = op.cmap;
     a.alpha = op.alpha; a.beta = op.beta;
     a.batch = op.batch; a.batch2 = op.batch2;
     a.W = nullptr;
 
     const GemmCfg cfg = gemm_resolve(prec, op);
-    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2, DTRG_EINVAL, "gemm: bad tile configuration");
-    const bool big = cfg.tile == 2;
-    const int BM = big ? 128 : 64, BN = BM;
-    const int BK = bk_of(prec);
+    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || (cfg.tile == 3 && split), DTRG_EINVAL,
+                 "gemm: bad tile configuration");
+    const int BM = cfg.tile == 3 ? 256 : (cfg.tile == 2 ? 128 : 64), BN = cfg.tile == 1 ? 64 : 128;
+    const int BK = bk_of(prec, cfg.tile);
     int splits = std::max(1, cfg.splits);
     const int k_chunk_raw = (op.K + splits - 1) / splits;
     a.k_chunk = std::max(BK, ((k_chunk_raw + BK - 1) / BK) * BK);
@@ -119,25 +157,28 @@ void gemm(Prec prec, bool out_f64, const GemmOp& op, hipStream_t s, Scratch& ws)
     DTRG_REQUIRE(total < (1LL << 30), DTRG_EINVAL, "gemm: grid too large");
     dim3 grid((unsigned)(chunk * kXcds), 1, (unsigned)(nz * splits));
 
+    const int oc = out_code(prec, out);
     switch (prec) {
         case Prec::F64:
-            DTRG_REQUIRE(out_f64, DTRG_EINVAL, "gemm: FP64 contraction must write FP64");
-            launch_gemm_f64(a, grid, op.a_kmajor, op.b_kmajor, op.tag, big, s);
+            launch_gemm_f64(a, grid, op.a_kmajor, op.b_kmajor, op.tag, cfg.tile == 2, s);
             break;
         case Prec::F32:
-            launch_gemm_f32(a, grid, op.a_kmajor, op.b_kmajor, op.tag, big, out_f64, s);
+            launch_gemm_f32(a, grid, op.a_kmajor, op.b_kmajor, op.tag, cfg.tile == 2, out == Out::F64, s);
             break;
         case Prec::BF16X3:
-            launch_gemm_bf16x3(a, grid, op.a_kmajor, op.b_kmajor, op.tag, big, out_f64, s);
+        case Prec::BF16X6:
+            launch_gemm_split(a, grid, np, oc, cfg.tile, op.tag, s);
             break;
     }
     DTRG_HIP(hipGetLastError());
     if (splits > 1) {
         const i64 tot = (i64)op.M * op.N * nz;
-        const int nblk = (int)std::min<i64>((tot + 255) / 256, 4096);
-        if (acc_f64) hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), dim3(nblk), dim3(256), 0, s, a);
-        else if (out_f64) hipLaunchKernelGGL((splitk_reduce_kernel<float, double>), dim3(nblk), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), dim3(nblk), dim3(256), 0, s, a);
+        const dim3 g((unsigned)std::min<i64>((tot + 255) / 256, 4096));
+        if (acc_f64) hipLaunchKernelGGL((splitk_reduce_kernel<double, 0>), g, dim3(256), 0, s, a);
+        else if (oc == 0) hipLaunchKernelGGL((splitk_reduce_kernel<float, 0>), g, dim3(256), 0, s, a);
+        else if (oc == 1) hipLaunchKernelGGL((splitk_reduce_kernel<float, 1>), g, dim3(256), 0, s, a);
+        else if (oc == 2) hipLaunchKernelGGL((splitk_reduce_kernel<float, 2>), g, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((splitk_reduce_kernel<float, 3>), g, dim3(256), 0, s, a);
         DTRG_HIP(hipGetLastError());
     }
 }

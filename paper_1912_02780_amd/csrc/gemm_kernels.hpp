@@ -9,8 +9,8 @@
 //
 // Tiling: 256 threads = 4 waves (2 x 2); block tile BM x BN x BK staged through LDS with one
 // register-prefetched stage (one barrier per K tile); each wave owns (BM/2) x (BN/2) outputs as
-// 16 x 16 MFMA tiles.  FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32; the split-
-// bf16 path uses v_mfma_f32_16x16x32_bf16 three times per K step (hi*hi + hi*lo + lo*hi).
+// 16 x 16 MFMA tiles.  FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  The kernel
+// for operands split into bf16 planes is in gemm_split.hpp.
 #pragma once
 
 #include "common.hpp"
@@ -20,6 +20,7 @@ namespace dtrg {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 
 // Tile of a block.  The grid is one-dimensional in x (z = batch x split-K).  Blocks are handed
 // to the 8 XCDs round-robin (block b runs on XCD b % 8), so block b = 8 q + x is given the q-th
@@ -44,9 +45,9 @@ __device__ inline bool tile_of(int pid, int tiles_m, int tiles_n, int& tm, int& 
 
 struct KArgs {
     int M, N, K;
-    const void* A; i64 lda, a_bs, a_bs2;
-    const void* B; i64 ldb, b_bs, b_bs2;
-    void* C; i64 c_bs, c_bs2;
+    const void* A; i64 lda, a_bs, a_bs2, a_ps;
+    const void* B; i64 ldb, b_bs, b_bs2, b_ps;
+    void* C; i64 c_bs, c_bs2, c_ps;
     IdxMap rmap, cmap;
     double alpha, beta;
     int splits, k_chunk, batch, batch2;
@@ -58,6 +59,38 @@ struct KArgs {
 __host__ __device__ inline i64 batch_off(const KArgs& p, int zb, i64 bs, i64 bs2) {
     return (i64)(zb % p.batch) * bs + (i64)(zb / p.batch) * bs2;
 }
+
+// Output element writers.  OUT = 0: double, 1: float, 2 / 3: the value rounded to FP32 and split
+// into that many bf16 planes (plane q = bf16 of what the planes before it leave; planes ps apart).
+template <int OUT>
+__device__ inline void put_out(void* base, i64 off, i64 ps, double v, double beta) {
+    if constexpr (OUT == 0) {
+        double* C = (double*)base;
+        if (beta != 0.0) v += beta * C[off];
+        C[off] = v;
+    } else if constexpr (OUT == 1) {
+        float* C = (float*)base;
+        if (beta != 0.0) v += beta * (double)C[off];
+        C[off] = (float)v;
+    } else {
+        __bf16* C = (__bf16*)base;
+        float r = (float)v;
+#pragma unroll
+        for (int q = 0; q < OUT; ++q) {
+            const __bf16 h = (__bf16)r;
+            C[q * ps + off] = h;
+            r -= (float)h;
+        }
+    }
+}
+
+// write output element (zb, r, c) = v
+template <int OUT>
+__device__ inline void write_elem(const KArgs& p, int zb, int r, int c, double v) {
+    put_out<OUT>(p.C, batch_off(p, zb, p.c_bs, p.c_bs2) + idx_off(p.rmap, r) + idx_off(p.cmap, c), p.c_ps, v, p.beta);
+}
+
+
 
 // ------------------------------------------------------------------------------------------
 // FP64 / FP32: 16x16x4 MFMA.  Fragment layout (A 16x4, B 4x16, D 16x16) for lane l:
@@ -189,7 +222,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
                 }
         return;
     }
-    TO* C = (TO*)p.C + batch_off(p, zb, p.c_bs, p.c_bs2);
+    constexpr int OUT = sizeof(TO) == 8 ? 0 : 1;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -197,156 +230,9 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm0 + i * 16 + Mfma4<T>::row(lk, r), gn = n0 + wn0 + j * 16 + li;
-                if (gm < p.M && gn < p.N) {
-                    i64 off = idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
-                    double v = p.alpha * (double)acc[i][j][r];
-                    if (p.beta != 0.0) v += p.beta * (double)C[off];
-                    C[off] = (TO)v;
-                }
+                if (gm < p.M && gn < p.N) write_elem<OUT>(p, zb, gm, gn, p.alpha * (double)acc[i][j][r]);
             }
 }
-
-// ------------------------------------------------------------------------------------------
-// split-bf16 x3 on v_mfma_f32_16x16x32_bf16.  Fragment layout (A 16x32, B 32x16) for lane l:
-//   A[i = l % 16][k = 8 * (l / 16) + e], B[k = 8 * (l / 16) + e][j = l % 16], e = 0..7;
-//   D as for the 16x16x4 instructions.
-// Operands arrive as FP32; each element is split into hi = bf16(x) and lo = bf16(x - hi) while
-// it is staged into LDS.
-// ------------------------------------------------------------------------------------------
-__device__ inline __bf16 f2bf(float x) { return (__bf16)x; }
-
-template <class TO, int BM, int BN, bool AKM, bool BKM, int TAG>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(KArgs p) {
-    constexpr int BK = 32;
-    constexpr int NT = 256;
-    constexpr int WM = BM / 2, WN = BN / 2;
-    constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
-    constexpr int KP = BK + 8;  // k-contiguous rows of bf16, padded
-    __shared__ __bf16 Ah[2][BM][KP], Al[2][BM][KP];
-    __shared__ __bf16 Bh[2][BN][KP], Bl[2][BN][KP];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-    int tmi, tni;
-    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
-    const int m0 = tmi * BM, n0 = tni * BN;
-    const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
-    const int kbeg = zs * p.k_chunk;
-    const int kend = min(p.K, kbeg + p.k_chunk);
-    const float* A = (const float*)p.A + batch_off(p, zb, p.a_bs, p.a_bs2);
-    const float* B = (const float*)p.B + batch_off(p, zb, p.b_bs, p.b_bs2);
-
-    v4f acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    float ra[AE], rb[BE];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int e = 0; e < AE; ++e) {
-            int m, k;
-            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
-            int gm = m0 + m, gk = k0 + k;
-            ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : 0.f;
-        }
-#pragma unroll
-        for (int e = 0; e < BE; ++e) {
-            int n, k;
-            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
-            int gn = n0 + n, gk = k0 + k;
-            rb[e] = (gn < p.N && gk < kend) ? (BKM ? B[(i64)gk * p.ldb + gn] : B[(i64)gn * p.ldb + gk]) : 0.f;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < AE; ++e) {
-            int m, k;
-            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
-            __bf16 h = f2bf(ra[e]);
-            Ah[buf][m][k] = h;
-            Al[buf][m][k] = f2bf(ra[e] - (float)h);
-        }
-#pragma unroll
-        for (int e = 0; e < BE; ++e) {
-            int n, k;
-            if (BKM) { int idx = tid + e * NT; k = idx / BN; n = idx % BN; }
-            else { int idx = tid + e * NT; n = idx / BK; k = idx % BK; }
-            __bf16 h = f2bf(rb[e]);
-            Bh[buf][n][k] = h;
-            Bl[buf][n][k] = f2bf(rb[e] - (float)h);
-        }
-    };
-
-    const int ntiles = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-    if (ntiles > 0) {
-        load(kbeg);
-        store(0);
-    }
-    __syncthreads();
-    const int li = lane & 15, lk = lane >> 4;
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < ntiles) load(kbeg + (t + 1) * BK);
-        v8bf ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            ah[i] = *(const v8bf*)&Ah[buf][wm0 + i * 16 + li][8 * lk];
-            al[i] = *(const v8bf*)&Al[buf][wm0 + i * 16 + li][8 * lk];
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            bh[j] = *(const v8bf*)&Bh[buf][wn0 + j * 16 + li][8 * lk];
-            bl[j] = *(const v8bf*)&Bl[buf][wn0 + j * 16 + li][8 * lk];
-        }
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            }
-        if (t + 1 < ntiles) store(buf ^ 1);
-        __syncthreads();
-    }
-
-    if (p.splits > 1) {
-        float* W = (float*)p.W + (i64)blockIdx.z * p.M * p.N;
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    int gm = m0 + wm0 + i * 16 + 4 * lk + r, gn = n0 + wn0 + j * 16 + li;
-                    if (gm < p.M && gn < p.N) W[(i64)gm * p.N + gn] = acc[i][j][r];
-                }
-        return;
-    }
-    TO* C = (TO*)p.C + batch_off(p, zb, p.c_bs, p.c_bs2);
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int gm = m0 + wm0 + i * 16 + 4 * lk + r, gn = n0 + wn0 + j * 16 + li;
-                if (gm < p.M && gn < p.N) {
-                    i64 off = idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
-                    double v = p.alpha * (double)acc[i][j][r];
-                    if (p.beta != 0.0) v += p.beta * (double)C[off];
-                    C[off] = (TO)v;
-                }
-            }
-}
-
 
 template <class T, class TO, int BM, int BN, int BK, int TAG>
 void launch_mfma4_t(const KArgs& a, dim3 grid, bool akm, bool bkm, hipStream_t s) {
@@ -367,28 +253,11 @@ void launch_mfma4(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStr
     launch_mfma4_t<T, TO, BM, BN, BK, 0>(a, grid, akm, bkm, s);
 }
 
-template <class TO, int BM, int BN, int TAG>
-void launch_bf16x3_t(const KArgs& a, dim3 grid, bool akm, bool bkm, hipStream_t s) {
-    if (akm && bkm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, true, true, TAG>), grid, dim3(256), 0, s, a);
-    else if (akm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, true, false, TAG>), grid, dim3(256), 0, s, a);
-    else if (bkm) hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, false, true, TAG>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((gemm_bf16x3_kernel<TO, BM, BN, false, false, TAG>), grid, dim3(256), 0, s, a);
-}
-
-template <class TO, int BM, int BN>
-void launch_bf16x3(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStream_t s) {
-    if constexpr (BM == 128) {
-        if (tag == 7) { launch_bf16x3_t<TO, BM, BN, 7>(a, grid, akm, bkm, s); return; }
-        if (tag == 8) { launch_bf16x3_t<TO, BM, BN, 8>(a, grid, akm, bkm, s); return; }
-        if (tag == 9) { launch_bf16x3_t<TO, BM, BN, 9>(a, grid, akm, bkm, s); return; }
-    }
-    launch_bf16x3_t<TO, BM, BN, 0>(a, grid, akm, bkm, s);
-}
-
-
 // per-precision launchers (one translation unit each, compiled in parallel)
 void launch_gemm_f64(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, hipStream_t s);
 void launch_gemm_f32(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, bool out_f64, hipStream_t s);
-void launch_gemm_bf16x3(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, bool out_f64, hipStream_t s);
+// split-bf16 planes (gemm_split.hip): np = 2 or 3 planes per operand, out = 0 double, 1 float,
+// 2 / 3 bf16 planes; tile 1 = 64 x 64, 2 = 128 x 128, 3 = 256 x 128
+void launch_gemm_split(const KArgs& a, dim3 grid, int np, int out, int tile, int tag, hipStream_t s);
 
 }  // namespace dtrg

@@ -6,16 +6,12 @@
 //   A,B [a][b][j][k] = [X][X][Y][Y]        half-environments of the Gram
 //   G   [(a,c)][(b,d)] = n x n             Gram of the (x1, x2) unfolding, then sym / trace
 //   U   [n][b]                             eigenvectors (first K columns are w[x1][x2][alpha])
-//   P1  [alpha][y][i][b][j]                upper copy times the left isometry
-//   Q2  [alpha][y][z][i][m]                P1 joined with the lower copy over (b, j)  (chi^7)
-//   T'  [alpha][beta][y][z]                step output; the next input is T'/c permuted (2,3,0,1)
-// Every contraction is one call of the MFMA kernel (instances are its outer batch level), whose
-// scatter epilogue writes each result directly in the layout its consumer reads (index maps
-// written next to each call).
-//
-// A step's checkpoint is its normalised input T, its eigenvectors and eigenvalues and a few
-// scalars; the backward recomputes everything else of the step (the half-environments, the Gram
-// and the projection intermediates) from it.
+// The operands of the projection contractions and of their adjoints are stored in the step's
+// contraction format (FP64, FP32 or bf16 planes) and always K-contiguous for the contraction that
+// reads them, rows padded to a multiple of 8 elements: permutations of T, U and the incoming
+// gradient write them from FP64, each contraction's scatter epilogue writes its result in the layout
+// of its first consumer, and a tiled transpose makes the copy that a second consumer contracting it
+// over the other indices reads.  The layouts are written next to their producers.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -30,37 +26,41 @@ dtrg_plan::~dtrg_plan() {
     for (auto e : ev_pool) (void)hipEventDestroy(e);
 }
 
+namespace {
+
+template <class F>
+void for_each_buf(const dtrg_plan& P, F f) {
+    const DevBuf<double>* w[] = {&P.TA, &P.TB, &P.Tn, &P.Tbar, &P.Tbar2, &P.Wk, &P.A, &P.B, &P.Gw, &P.Gt, &P.Ub,
+                                 &P.Xe, &P.Xc, &P.Re, &P.Om, &P.Sm, &P.Vc, &P.Vp, &P.Vn, &P.Ye, &P.We, &P.V1, &P.V2,
+                                 &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
+                                 &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red};
+    for (auto* b : w) f(b->p, b->bytes());
+    for (const OpSet& o : P.ops) {
+        const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
+                            &o.X1, &o.X2, &o.X3};
+        for (auto* b : v) f(b->mem.p, b->mem.bytes());
+    }
+    for (auto& st : P.steps) {
+        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam};
+        for (auto* b : v) f(b->p, b->bytes());
+    }
+}
+
+}  // namespace
+
 i64 dtrg_plan::cap_bytes(const void* ptr) const {
     const char* q = (const char*)ptr;
-    auto chk = [&](const void* base, size_t nbytes) -> i64 {
+    i64 r = -1;
+    for_each_buf(*this, [&](const void* base, size_t nbytes) {
         const char* b = (const char*)base;
-        if (b && q >= b && q < b + nbytes) return (i64)nbytes - (i64)(q - b);
-        return -1;
-    };
-    const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Tb2, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &A, &B, &P1, &Q2,
-                                 &X5, &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
-                                 &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &fv, &ctab, &scal, &T0buf,
-                                 &T0barbuf, &dT0buf, &tune_c};
-    for (auto* b : w) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
-    const DevBuf<float>* f[] = {&Tpf, &Tbf, &Tb2f, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
-    for (auto* b : f) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
-    for (auto& st : steps) {
-        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam};
-        for (auto* b : v) { const i64 r = chk(b->p, b->bytes()); if (r >= 0) return r; }
-    }
-    return -1;
+        if (r < 0 && b && q >= b && q < b + nbytes) r = (i64)nbytes - (i64)(q - b);
+    });
+    return r;
 }
 
 size_t dtrg_plan::bytes() const {
     size_t t = 0;
-    for (auto& st : steps) t += st.T.bytes() + st.U.bytes() + st.lam.bytes();
-    const DevBuf<double>* w[] = {&TA, &TB, &Tp, &Tb, &Tb2, &Wt, &Wt2, &Tn, &Tbar, &Tbar2, &Tpbar, &A, &B, &P1, &Q2,
-                                 &X5, &Gw, &Gt, &Ub, &Xe, &Xc, &Re, &Om, &Sm, &Vc, &Vp, &Vn, &Ye, &We, &V1, &V2,
-                                 &Y1, &Y2, &H, &Z, &Rinv, &Sg, &th, &res, &nrm, &coef, &fv, &ctab, &scal, &T0buf,
-                                 &T0barbuf, &dT0buf, &tune_c, &ws.splitk, &ws.red};
-    for (auto* b : w) t += b->bytes();
-    const DevBuf<float>* f[] = {&Tpf, &Tbf, &Tb2f, &Wtf, &Wt2f, &Uf, &P1f, &Q2f, &X5f, &Tpbarf};
-    for (auto* b : f) t += b->bytes();
+    for_each_buf(*this, [&](const void*, size_t nbytes) { t += nbytes; });
     return t + flags.bytes() + misc.bytes();
 }
 
@@ -98,12 +98,21 @@ i64 ctab_offset(int m) {
 }
 i64 ctab_total() { return ctab_offset(2 * kChebMaxDegree); }
 
-// A device operand with its instance stride.
+i64 pad8(i64 x) { return (x + 7) / 8 * 8; }
+
+// A device operand: base, instance stride, plane stride and (for operand buffers) row stride.
 struct Opnd {
     const void* p = nullptr;
-    i64 bs = 0;
+    i64 bs = 0, ps = 0, ld = 0;
 };
-template <class T> Opnd op_of(const DevBuf<T>& b) { Opnd o; o.p = b.p; o.bs = b.bs; return o; }
+Opnd op_of(const DevBuf<double>& b, i64 ld = 0) { Opnd o; o.p = b.p; o.bs = b.bs; o.ld = ld; return o; }
+Opnd op_of(const OpBuf& b, i64 ld) { Opnd o; o.p = b.p(); o.bs = b.per; o.ps = b.ps(); o.ld = ld; return o; }
+
+int esize(Prec pr) { return pr == Prec::F64 ? 8 : (pr == Prec::F32 ? 4 : 2); }
+int esize(Prec pr, Out o) { return o == Out::F64 ? 8 : (o == Out::F32 ? 4 : 2); }
+// the contraction format's own output kind
+Out own_out(Prec pr) { return pr == Prec::F64 ? Out::F64 : (pr == Prec::F32 ? Out::F32 : Out::Split); }
+int out_code(Prec pr) { return pr == Prec::F64 ? 0 : (pr == Prec::F32 ? 1 : prec_planes(pr)); }
 
 // -------------------------------------------------------------------------------------------
 // contractions
@@ -114,16 +123,18 @@ struct Ctx {
     Mode mode;
     bool adaptive() const { return mode == Mode::Adaptive; }
     // one contraction in precision `pr` over the plan's nb instances (operand instance strides
-    // set by the caller in a_bs2 / b_bs2 / c_bs2); operands of 8 (FP64) or 4 (FP32) bytes,
-    // output FP64 or FP32
-    void run(GemmOp g, Prec pr, bool out_f64) {
+    // set by the caller in a_bs2 / b_bs2 / c_bs2), output kind `out`
+    void run(GemmOp g, Prec pr, Out out) {
         g.batch2 = P->nb;
-        const int ein = pr == Prec::F64 ? 8 : 4, eout = out_f64 ? 8 : 4;
+        const int ein = esize(pr), eout = esize(pr, out);
         if (g.a_cap < 0) g.a_cap = P->cap_of(g.A, ein);
         if (g.b_cap < 0) g.b_cap = P->cap_of(g.B, ein);
         if (g.c_cap < 0) g.c_cap = P->cap_of(g.C, eout);
-        if (P->opt.autotune) g.cfg = tuned_cfg(pr, out_f64, g, adaptive(), s, P->ws, P->tune_c);
-        const bool timed = P->opt.profile && g.tag == 7 && adaptive();
+        if (P->opt.autotune) g.cfg = tuned_cfg(pr, out, g, adaptive(), s, P->ws, P->tune_c);
+        // timed: the joins in the plan's contraction precision on the large tiles, i.e. every
+        // launch of that one kernel symbol (the small early steps stay FP64 on mixed plans)
+        const bool timed = P->opt.profile && g.tag == 7 && adaptive() && pr == P->prec &&
+                           gemm_resolve(pr, g).tile >= 2;
         if (timed) {
             while (P->ev_pool.size() < P->ev_used + 2) {
                 hipEvent_t e;
@@ -132,7 +143,7 @@ struct Ctx {
             }
             DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used], s));
         }
-        dtrg::gemm(pr, out_f64, g, s, P->ws);
+        dtrg::gemm(pr, out, g, s, P->ws);
         if (timed) {
             DTRG_HIP(hipEventRecord(P->ev_pool[P->ev_used + 1], s));
             P->ev_used += 2;
@@ -140,12 +151,15 @@ struct Ctx {
         }
     }
     // FP64 contraction (Gram, eigensolver, eigen-adjoint)
-    void gemm(const GemmOp& op) { run(op, Prec::F64, true); }
-    // projection contraction in precision pr (FP64 operands always write FP64)
-    void gemmc(const GemmOp& op, Prec pr, bool out_f64) { run(op, pr, pr == Prec::F64 ? true : out_f64); }
+    void gemm(const GemmOp& op) { run(op, Prec::F64, Out::F64); }
 };
 
 void set_bs(GemmOp& g, i64 a, i64 b, i64 c) { g.a_bs2 = a; g.b_bs2 = b; g.c_bs2 = c; }
+void set_ops(GemmOp& g, const Opnd& A, const Opnd& B) {
+    g.A = A.p; g.lda = A.ld; g.a_bs2 = A.bs; g.a_ps = A.ps;
+    g.B = B.p; g.ldb = B.ld; g.b_bs2 = B.bs; g.b_ps = B.ps;
+}
+void set_out(GemmOp& g, const Opnd& C) { g.C = (void*)C.p; g.c_bs2 = C.bs; g.c_ps = C.ps; }
 
 // permutes over all instances with the capacities of plan-owned buffers checked on the host
 void permute_checked(dtrg_plan* P, const DevBuf<double>& in, double* out, i64 out_bs, PermDesc d, double alpha,
@@ -158,13 +172,18 @@ void permute_checked(dtrg_plan* P, const DevBuf<double>& in, double* out, i64 ou
     dtrg::permute(in.p, out, d, alpha, 0.0, scale_dev, P->S, s);
 }
 
-void permute_f32_checked(dtrg_plan* P, const DevBuf<double>& in, DevBuf<float>& out, PermDesc d, hipStream_t s) {
+// permute an FP64 tensor into an operand buffer: rows of the last `inner` output dims, row stride ld
+void permute_op(dtrg_plan* P, Prec pr, const DevBuf<double>& in, const OpBuf& out, PermDesc d, int inner, i64 ld,
+                const double* scale_dev, hipStream_t s) {
     d.nb = P->nb;
     d.in_bs = in.bs;
-    d.out_bs = out.bs;
-    d.in_cap = P->cap_of(in.p, 8);
-    d.out_cap = P->cap_of(out.p, 4);
-    dtrg::permute_to_f32(in.p, out.p, d, s);
+    d.out_bs = out.per;
+    d.out_inner = inner;
+    d.out_ld = ld;
+    d.out_ps = out.ps();
+    d.in_cap = P->cap_of(in.p);
+    d.out_cap = P->cap_of(out.p(), esize(pr));
+    dtrg::permute_out(in.p, out.p(), out_code(pr), d, 1.0, scale_dev, P->S, s);
 }
 
 // A[a][b][j][k] = sum_{x,y} TA[(a,j)][(x,y)] TA[(b,k)][(x,y)]  (also B with TB)
@@ -206,92 +225,106 @@ void gram_of_step(Ctx& c, const StepCk& st, int k) {
     sym_normalise(P->Gw.p, P->Gw.bs, n, P->nb, P->sc(k, 2), P->S, P->flags.p, c.s);
 }
 
-// P1[alpha][y][i][b][j] = sum_a Wt[(alpha,b)][a] Tp[y][(i,j)][a]   (batched over y)
-void proj1(Ctx& c, Prec pr, Opnd Wt, Opnd Tp, Opnd P1, int X, int Y, int K) {
-    GemmOp g;
-    g.M = K * X; g.N = X * Y; g.K = X; g.batch = Y;
-    g.A = Wt.p; g.lda = X; g.a_bs = 0;
-    g.B = Tp.p; g.ldb = X; g.b_bs = (i64)X * Y * X;
-    g.C = (void*)P1.p; g.c_bs = (i64)X * X * Y;
-    g.rmap = IdxMap::split(X, (i64)Y * X * X * Y, Y);
-    g.cmap = IdxMap::split(Y, (i64)X * Y, 1);
-    set_bs(g, Wt.bs, Tp.bs, P1.bs);
-    c.gemmc(g, pr, false);
+// Row strides of the operand layouts of one step (every row padded to a multiple of 8).
+struct Lds {
+    i64 Wt, Wt2, UT, Us, Tp, Tb, Tb2, TpT, Tpb, Tpb2;      // chi^4 / n x b class
+    i64 P1, P1T, Q2, Q2b, QbA, QbB, X5A, X5B;              // chi^5 class
+    explicit Lds(const StepShape& s) {
+        const i64 X = s.X, Y = s.Y, K = s.K, b = s.b, n = s.n;
+        Wt = pad8(X); Wt2 = pad8(b * X); UT = pad8(n); Us = pad8(b);
+        Tp = pad8(X); Tb = pad8(X * Y); Tb2 = pad8(Y * X); TpT = pad8(Y * X * Y);
+        Tpb = pad8(K * Y * Y); Tpb2 = pad8(K);
+        P1 = pad8(X * Y); P1T = pad8(K * Y * X); Q2 = pad8(X * X); Q2b = pad8(K * Y * Y);
+        QbA = pad8(Y * X); QbB = pad8(K * Y * X); X5A = pad8(K * X); X5B = pad8(Y * X * Y);
+    }
+    // per-instance element counts of the buffers (rows x row stride)
+    static void sizes(const StepShape& s, i64 out[13]) {
+        const Lds l(s);
+        const i64 X = s.X, Y = s.Y, K = s.K, b = s.b, n = s.n;
+        out[0] = b * X * l.Wt; out[1] = X * l.Wt2; out[2] = b * l.UT; out[3] = n * l.Us;
+        out[4] = Y * X * Y * l.Tp; out[5] = Y * X * l.Tb; out[6] = Y * X * l.Tb2; out[7] = X * l.TpT;
+        out[8] = K * l.Tpb; out[9] = K * Y * Y * l.Tpb2;
+        out[10] = std::max({K * Y * X * l.P1, X * X * l.Q2b, Y * X * l.QbB, Y * X * Y * l.X5A});   // X1
+        out[11] = std::max(K * Y * Y * l.Q2, K * Y * X * l.QbA);                                  // X2
+        out[12] = std::max(X * Y * l.P1T, K * X * l.X5B);                                         // X3
+    }
+};
+
+// forward operands of a step: Wt [(alpha,b)][a], Tp [(y,i,j)][a], Tb [(z,m)][(b,j)], UT [beta][(i,m)]
+// (for the backward also Wt2 [a][(alpha,b)], Tb2 [(j,b)][(z,m)], TpT [a][(y,i,j)], Us [(i,m)][beta])
+void prep_operands(Ctx& c, const StepCk& st, const OpSet& o, bool backward) {
+    dtrg_plan* P = c.P;
+    const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
+    const Lds l(st.sh);
+    const Prec pr = o.pr;
+    permute_op(P, pr, st.U, o.Wt, pd3(X, X, b, 2, 1, 0), 1, l.Wt, nullptr, c.s);
+    permute_op(P, pr, st.T, o.Tp, pd4(X, X, Y, Y, 2, 1, 3, 0), 1, l.Tp, nullptr, c.s);
+    permute_op(P, pr, st.T, o.Tb, pd4(X, X, Y, Y, 3, 1, 0, 2), 2, l.Tb, nullptr, c.s);
+    if (!backward) {
+        PermDesc u;
+        u.rank = 2; u.in_dims[0] = n; u.in_dims[1] = b; u.perm[0] = 1; u.perm[1] = 0;
+        permute_op(P, pr, st.U, o.UT, u, 1, l.UT, nullptr, c.s);
+    } else {
+        permute_op(P, pr, st.U, o.Wt2, pd3(X, X, b, 0, 2, 1), 2, l.Wt2, nullptr, c.s);
+        permute_op(P, pr, st.T, o.Tb2, pd4(X, X, Y, Y, 2, 0, 3, 1), 2, l.Tb2, nullptr, c.s);
+        permute_op(P, pr, st.T, o.TpT, pd4(X, X, Y, Y, 0, 2, 1, 3), 3, l.TpT, nullptr, c.s);
+        PermDesc u;
+        u.rank = 2; u.in_dims[0] = n; u.in_dims[1] = b; u.perm[0] = 0; u.perm[1] = 1;
+        permute_op(P, pr, st.U, o.Us, u, 1, l.Us, nullptr, c.s);
+    }
 }
 
-// Q2[alpha][y][z][i][m] = sum_{(b,j)} P1[(alpha,y,i)][(b,j)] Tb[(z,m)][(b,j)]      (the chi^7 term)
-void proj2(Ctx& c, Prec pr, Opnd P1, Opnd Tb, Opnd Q2, int X, int Y, int K) {
+// P1[(alpha,y,i)][(b,j)] = sum_a Wt[(alpha,b)][a] Tp[y][(i,j)][a]   (batched over y), into X1
+void proj1(Ctx& c, const StepCk& st, const OpSet& o) {
+    const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
+    const Lds l(st.sh);
+    GemmOp g;
+    g.M = K * X; g.N = X * Y; g.K = X; g.batch = Y;
+    set_ops(g, op_of(o.Wt, l.Wt), op_of(o.Tp, l.Tp));
+    g.a_bs = 0;
+    g.b_bs = (i64)X * Y * l.Tp;
+    set_out(g, op_of(o.X1, l.P1));
+    g.c_bs = (i64)X * l.P1;
+    g.rmap = IdxMap::split(X, (i64)Y * X * l.P1, Y);
+    g.cmap = IdxMap::split(Y, l.P1, 1);
+    c.run(g, o.pr, own_out(o.pr));
+}
+
+// out[c][r] = in[r][c] between two operand buffers of the same format (all planes and instances)
+void transpose_op(Ctx& c, const OpBuf& in, i64 ld_in, int rows, int cols, const OpBuf& out, i64 ld_out) {
+    DTRG_REQUIRE(in.per >= (i64)rows * ld_in && ld_in >= cols && out.per >= (i64)cols * ld_out && ld_out >= rows &&
+                     in.esz == out.esz && in.np == out.np && in.nb == c.P->nb && out.nb == c.P->nb,
+                 DTRG_EINVAL, "transpose: operand buffer too small");
+    transpose_planes(in.p(), out.p(), in.esz, rows, cols, ld_in, ld_out, c.P->nb, in.per, out.per, in.np, in.ps(),
+                     out.ps(), c.s);
+}
+
+// the join (the chi^7 term): Q2[(alpha,y,z)][(i,m)] = sum_{(b,j)} P1[(alpha,y,i)][(b,j)] Tb[(z,m)][(b,j)],
+// from X1 into X2
+void join(Ctx& c, const StepCk& st, const OpSet& o) {
+    const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
+    const Lds l(st.sh);
     GemmOp g;
     g.tag = 7;
     g.M = K * Y * X; g.N = Y * X; g.K = X * Y;
-    g.A = P1.p; g.lda = X * Y;
-    g.B = Tb.p; g.ldb = X * Y;
-    g.C = (void*)Q2.p;
-    g.rmap = IdxMap::split(X, (i64)Y * X * X, X);
-    g.cmap = IdxMap::split(X, (i64)X * X, 1);
-    set_bs(g, P1.bs, Tb.bs, Q2.bs);
-    c.gemmc(g, pr, false);
+    set_ops(g, op_of(o.X1, l.P1), op_of(o.Tb, l.Tb));
+    set_out(g, op_of(o.X2, l.Q2));
+    g.rmap = IdxMap::split(X, (i64)Y * l.Q2, X);
+    g.cmap = IdxMap::split(X, l.Q2, 1);
+    c.run(g, o.pr, own_out(o.pr));
 }
 
-// T'[alpha][beta][y][z] = sum_{(i,m)} Q2[(alpha,y,z)][(i,m)] w[(i,m)][beta]
-void proj3(Ctx& c, Prec pr, Opnd Q2, Opnd U, int ldu, DevBuf<double>& Tn, int X, int Y, int K) {
+// T'[alpha][beta][y][z] = sum_{(i,m)} Q2[(alpha,y,z)][(i,m)] UT[beta][(i,m)]   (FP64 out)
+void proj3(Ctx& c, const StepCk& st, const OpSet& o, DevBuf<double>& Tn) {
+    const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
+    const Lds l(st.sh);
     GemmOp g;
     g.M = K * Y * Y; g.N = K; g.K = X * X;
-    g.A = Q2.p; g.lda = X * X;
-    g.B = U.p; g.ldb = ldu; g.b_kmajor = true;
-    g.C = Tn.p;
+    set_ops(g, op_of(o.X2, l.Q2), op_of(o.UT, l.UT));
+    g.C = Tn.p; g.c_bs2 = Tn.bs;
     g.rmap = IdxMap::split((i64)Y * Y, (i64)K * Y * Y, 1);
     g.cmap = IdxMap::linear((i64)Y * Y);
-    set_bs(g, Q2.bs, U.bs, Tn.bs);
-    c.gemmc(g, pr, true);
-}
-
-// Contraction operands of one step, in the contraction precision.
-struct Ops {
-    Opnd Tp, Tb, Tb2, Wt, Wt2, U;
-    Opnd P1, Q2, X5, Tpbar;
-    Prec pr;    // precision of this step's contractions (FP64, FP32 or split-bf16)
-    int mask;   // with split-bf16: bit 0 join, 1 adjoint w.r.t. P, 2 w.r.t. the lower copy, 3 chi^6
-    // precision of contraction `bit`: split-bf16 only where the mask selects it, FP32 otherwise
-    Prec at(int bit) const { return (pr == Prec::BF16X3 && !(mask & (1 << bit))) ? Prec::F32 : pr; }
-};
-
-// Operand layouts of one step from its input T and its eigenvectors U:
-//   Tp [u][r][d][l], Tb [d][r][l][u], Wt [alpha][b][a], U as is (n x b); for the backward also
-//   Wt2 [a][alpha][b] and Tb2 [d][r][u][l].
-// FP64 path: permuted FP64 copies; mixed paths: permuted FP32 copies.
-Ops prep_operands(Ctx& c, const StepCk& st, bool need_wt2) {
-    dtrg_plan* P = c.P;
-    const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
-    Ops o;
-    o.pr = st.sh.mixed ? P->prec : Prec::F64;
-    o.mask = P->opt.bf16x3_mask;
-    if (!st.sh.mixed) {
-        permute_checked(P, st.T, P->Tp.p, P->Tp.bs, pd4(X, X, Y, Y, 2, 1, 3, 0), 1.0, nullptr, c.s);
-        permute_checked(P, st.T, P->Tb.p, P->Tb.bs, pd4(X, X, Y, Y, 3, 1, 0, 2), 1.0, nullptr, c.s);
-        permute_checked(P, st.U, P->Wt.p, P->Wt.bs, pd3(X, X, b, 2, 1, 0), 1.0, nullptr, c.s);
-        if (need_wt2) {
-            permute_checked(P, st.U, P->Wt2.p, P->Wt2.bs, pd3(X, X, b, 0, 2, 1), 1.0, nullptr, c.s);
-            permute_checked(P, st.T, P->Tb2.p, P->Tb2.bs, pd4(X, X, Y, Y, 3, 1, 2, 0), 1.0, nullptr, c.s);
-        }
-        o.Tp = op_of(P->Tp); o.Tb = op_of(P->Tb); o.Tb2 = op_of(P->Tb2); o.Wt = op_of(P->Wt);
-        o.Wt2 = op_of(P->Wt2); o.U = op_of(st.U);
-        o.P1 = op_of(P->P1); o.Q2 = op_of(P->Q2); o.X5 = op_of(P->X5); o.Tpbar = op_of(P->Tpbar);
-    } else {
-        permute_f32_checked(P, st.T, P->Tpf, pd4(X, X, Y, Y, 2, 1, 3, 0), c.s);
-        permute_f32_checked(P, st.T, P->Tbf, pd4(X, X, Y, Y, 3, 1, 0, 2), c.s);
-        permute_f32_checked(P, st.U, P->Wtf, pd3(X, X, b, 2, 1, 0), c.s);
-        if (need_wt2) {
-            permute_f32_checked(P, st.U, P->Wt2f, pd3(X, X, b, 0, 2, 1), c.s);
-            permute_f32_checked(P, st.T, P->Tb2f, pd4(X, X, Y, Y, 3, 1, 2, 0), c.s);
-        }
-        DTRG_REQUIRE(P->Uf.bs >= (i64)n * b, DTRG_EINVAL, "FP32 isometry buffer too small");
-        convert_f64_to_f32(st.U.p, st.U.bs, P->Uf.p, P->Uf.bs, (i64)n * b, P->nb, c.s);
-        o.Tp = op_of(P->Tpf); o.Tb = op_of(P->Tbf); o.Tb2 = op_of(P->Tb2f); o.Wt = op_of(P->Wtf);
-        o.Wt2 = op_of(P->Wt2f); o.U = op_of(P->Uf);
-        o.P1 = op_of(P->P1f); o.Q2 = op_of(P->Q2f); o.X5 = op_of(P->X5f); o.Tpbar = op_of(P->Tpbarf);
-    }
-    return o;
+    c.run(g, o.pr, Out::F64);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -525,11 +558,10 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
     const i64 D4 = (i64)P->D * P->D * P->D * P->D;
     i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1;
-    i64 t4d = 1, t5d = 1, bX2d = 1, t4f = 1, t5f = 1, bX2f = 1, nbf = 1;   // per-precision operand sizes
-    bool any_d = false, any_f = false;
+    i64 osz[2][13] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
+    bool used[2] = {false, false};
     for (auto& s : sh) {
         const i64 a4 = std::max<i64>((i64)s.X * s.X * s.Y * s.Y, (i64)s.K * s.K * s.Y * s.Y);
-        const i64 a5 = (i64)s.K * s.Y * s.X * s.X * s.Y, ab = (i64)s.b * s.X * s.X;
         t4 = std::max(t4, a4);
         n2 = std::max<i64>(n2, (i64)s.n * s.n);
         nbk = std::max<i64>(nbk, (i64)s.n * s.b);
@@ -538,28 +570,21 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         bK = std::max<i64>(bK, (i64)s.b * s.K);
         KK = std::max<i64>(KK, (i64)s.K * s.K);
         Kmax = std::max<i64>(Kmax, s.K);
-        if (s.mixed) {
-            any_f = true;
-            t4f = std::max(t4f, a4); t5f = std::max(t5f, a5); bX2f = std::max(bX2f, ab);
-            nbf = std::max<i64>(nbf, (i64)s.n * s.b);
-        } else {
-            any_d = true;
-            t4d = std::max(t4d, a4); t5d = std::max(t5d, a5); bX2d = std::max(bX2d, ab);
-        }
+        const int f = s.mixed ? 1 : 0;
+        used[f] = true;
+        i64 z[13];
+        Lds::sizes(s, z);
+        for (int i = 0; i < 13; ++i) osz[f][i] = std::max(osz[f][i], z[i]);
     }
     P->T0buf.alloc_inst(nb, D4); P->T0barbuf.alloc_inst(nb, D4); P->dT0buf.alloc_inst(nb, D4);
-    for (DevBuf<double>* b : {&P->TA, &P->TB, &P->Tn, &P->Tbar, &P->Tbar2, &P->Tpbar, &P->A, &P->B})
+    for (DevBuf<double>* b : {&P->TA, &P->TB, &P->Tn, &P->Tbar, &P->Tbar2, &P->Wk, &P->A, &P->B})
         b->alloc_inst(nb, t4);
-    if (any_d) {
-        P->Tp.alloc_inst(nb, t4d); P->Tb.alloc_inst(nb, t4d); P->Tb2.alloc_inst(nb, t4d);
-        P->Wt.alloc_inst(nb, bX2d); P->Wt2.alloc_inst(nb, bX2d);
-        P->P1.alloc_inst(nb, t5d); P->Q2.alloc_inst(nb, t5d); P->X5.alloc_inst(nb, t5d);
-    }
-    if (any_f) {
-        P->Tpf.alloc_inst(nb, t4f); P->Tbf.alloc_inst(nb, t4f); P->Tb2f.alloc_inst(nb, t4f);
-        P->Tpbarf.alloc_inst(nb, t4f);
-        P->Wtf.alloc_inst(nb, bX2f); P->Wt2f.alloc_inst(nb, bX2f); P->Uf.alloc_inst(nb, nbf);
-        P->P1f.alloc_inst(nb, t5f); P->Q2f.alloc_inst(nb, t5f); P->X5f.alloc_inst(nb, t5f);
+    for (int f = 0; f < 2; ++f) {
+        OpSet& o = P->ops[f];
+        o.pr = f == 0 ? Prec::F64 : P->prec;
+        if (!used[f]) continue;
+        OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2, &o.X1, &o.X2, &o.X3};
+        for (int i = 0; i < 13; ++i) v[i]->alloc(o.pr, nb, std::max<i64>(osz[f][i], 8));
     }
     P->Gw.alloc_inst(nb, n2); P->Gt.alloc_inst(nb, n2);
     for (DevBuf<double>* b : {&P->V1, &P->V2, &P->Y1, &P->Y2}) b->alloc_inst(nb, nbk);
@@ -850,11 +875,12 @@ void plan_forward(dtrg_plan* P, Mode mode) {
         if (c.adaptive()) check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
         const StepCk* warm = (k >= 3) ? &P->steps[k - 3] : nullptr;
         eigensolve(c, st, k, warm);
-        // projection (contraction precision; the output T' is FP64)
-        const Ops o = prep_operands(c, st, false);
-        proj1(c, o.at(3), o.Wt, o.Tp, o.P1, X, Y, K);
-        proj2(c, o.at(0), o.P1, o.Tb, o.Q2, X, Y, K);
-        proj3(c, o.at(3), o.Q2, o.U, st.sh.b, P->Tn, X, Y, K);
+        // projection (in the step's contraction format; the output T' is FP64)
+        const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
+        prep_operands(c, st, o, false);
+        proj1(c, st, o);
+        join(c, st, o);
+        proj3(c, st, o, P->Tn);
         // c_k = |T'|, L += 2^-k ln c_k, 1/c_k
         norm2(P->Tn.p, P->Tn.bs, (i64)K * K * Y * Y, nb, P->sc(k, 0), P->S, c.s, P->ws);
         accum_log(P->sc(k, 0), ldexp1(-k), P->sp(0), P->sc(k, 1), P->S, nb, P->flags.p, c.s);
@@ -887,101 +913,98 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
     for (int k = ns; k >= 1; --k) {
         StepCk& st = P->steps[k - 1];
         const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K, n = st.sh.n, b = st.sh.b;
-        // T'bar_p[alpha][y][z][beta] = permute(Tbar [y][z][alpha][beta]) / c_k
-        permute_checked(P, P->Tbar, P->Tpbar.p, P->Tpbar.bs, pd4(Y, Y, K, K, 2, 0, 1, 3), 1.0, P->sc(k, 1), c.s);
-        // recompute the projection intermediates (contraction precision)
-        const Ops o = prep_operands(c, st, true);
-        const Prec pr6 = o.at(3);
-        proj1(c, pr6, o.Wt, o.Tp, o.P1, X, Y, K);
-        proj2(c, o.at(0), o.P1, o.Tb, o.Q2, X, Y, K);
-        if (st.sh.mixed)
-            convert_f64_to_f32(P->Tpbar.p, P->Tpbar.bs, P->Tpbarf.p, P->Tpbarf.bs, (i64)K * Y * Y * K, nb, c.s);
-        // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2[(alpha,y,z)][(i,m)] T'bar_p[(alpha,y,z)][beta]
+        const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
+        const Prec pr = o.pr;
+        const Lds l(st.sh);
+        // incoming gradient / c_k in the two layouts it is contracted in:
+        //   Tpb [beta][(alpha,y,z)] and Tpb2 [(alpha,y,z)][beta]  (from Tbar [y][z][alpha][beta])
+        permute_op(P, pr, P->Tbar, o.Tpb, pd4(Y, Y, K, K, 3, 2, 0, 1), 3, l.Tpb, P->sc(k, 1), c.s);
+        permute_op(P, pr, P->Tbar, o.Tpb2, pd4(Y, Y, K, K, 2, 0, 1, 3), 1, l.Tpb2, P->sc(k, 1), c.s);
+        // recompute P1 (X1) and the join (X2); transposed copies P1T [(b,j)][(alpha,y,i)] (X3) and
+        // Q2b [(i,m)][(alpha,y,z)] (X1, once P1 is consumed)
+        prep_operands(c, st, o, true);
+        proj1(c, st, o);
+        transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, o.X3, l.P1T);
+        join(c, st, o);
+        transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, o.X1, l.Q2b);
+        // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2b[(i,m)][(alpha,y,z)] Tpb[beta][(alpha,y,z)]
         {
             GemmOp g;
             g.M = n; g.N = K; g.K = K * Y * Y;
-            g.A = o.Q2.p; g.lda = n; g.a_kmajor = true;
-            g.B = o.Tpbar.p; g.ldb = K; g.b_kmajor = true;
-            g.C = P->Ub.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
-            set_bs(g, o.Q2.bs, o.Tpbar.bs, P->Ub.bs);
-            c.gemmc(g, pr6, true);
+            set_ops(g, op_of(o.X1, l.Q2b), op_of(o.Tpb, l.Tpb));
+            g.C = P->Ub.p; g.c_bs2 = P->Ub.bs;
+            g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+            c.run(g, pr, Out::F64);
         }
-        // Qbar[alpha][y][i][z][m] = sum_beta T'bar_p[(alpha,y,z)][beta] w[(i,m)][beta]   (into Q2)
+        // QbA[(alpha,y,i)][(z,m)] = sum_beta Tpb2[(alpha,y,z)][beta] Us[(i,m)][beta]   (X2), and its
+        // transpose QbB [(z,m)][(alpha,y,i)] (X1)
         {
             GemmOp g;
             g.M = K * Y * Y; g.N = n; g.K = K;
-            g.A = o.Tpbar.p; g.lda = K;
-            g.B = o.U.p; g.ldb = b;
-            g.C = (void*)o.Q2.p;
-            g.rmap = IdxMap::split(Y, (i64)X * Y * X, X);
-            g.cmap = IdxMap::split(X, (i64)Y * X, 1);
-            set_bs(g, o.Tpbar.bs, o.U.bs, o.Q2.bs);
-            c.gemmc(g, pr6, false);
+            set_ops(g, op_of(o.Tpb2, l.Tpb2), op_of(o.Us, l.Us));
+            set_out(g, op_of(o.X2, l.QbA));
+            g.rmap = IdxMap::split(Y, (i64)X * l.QbA, X);
+            g.cmap = IdxMap::split(X, l.QbA, 1);
+            c.run(g, pr, own_out(pr));
         }
+        transpose_op(c, o.X2, l.QbA, K * Y * X, Y * X, o.X1, l.QbB);
         fill(P->Tbar2.p, P->Tbar2.bs, (i64)X * X * Y * Y, nb, 0.0, c.s);
-        // Pbar_p[y][i][j][alpha][b] = sum_{(z,m)} Qbar[(alpha,y,i)][(z,m)] Tb2[(z,m)][(j,b)]   (chi^7)
-        // (the adjoint of the join with respect to P, written straight in the layout of its two
-        // consumers below: rows (alpha,(y,i)), columns (j,b))
-        {
-            GemmOp g;
-            g.M = K * Y * X; g.N = Y * X; g.K = Y * X;
-            g.A = o.Q2.p; g.lda = Y * X;
-            g.B = o.Tb2.p; g.ldb = Y * X; g.b_kmajor = true;
-            g.C = (void*)o.X5.p;
-            g.rmap = IdxMap::split((i64)Y * X, X, (i64)Y * K * X);
-            g.cmap = IdxMap::split(X, (i64)K * X, 1);
-            g.tag = 8;
-            set_bs(g, o.Q2.bs, o.Tb2.bs, o.X5.bs);
-            c.gemmc(g, o.at(1), false);
-        }
-        // Tbar_lower[b][m][j][z] += sum_{(alpha,y,i)} Qbar[(alpha,y,i)][(z,m)] P1[(alpha,y,i)][(b,j)]   (chi^7)
+        // Tbar_lower[b][m][j][z] = sum_{(alpha,y,i)} QbB[(z,m)][(alpha,y,i)] P1T[(b,j)][(alpha,y,i)]   (chi^7)
         {
             GemmOp g;
             g.M = Y * X; g.N = X * Y; g.K = K * Y * X;
-            g.A = o.Q2.p; g.lda = Y * X; g.a_kmajor = true;
-            g.B = o.P1.p; g.ldb = X * Y; g.b_kmajor = true;
-            g.C = P->Tbar2.p;
+            set_ops(g, op_of(o.X1, l.QbB), op_of(o.X3, l.P1T));
+            g.C = P->Tbar2.p; g.c_bs2 = P->Tbar2.bs;
             g.rmap = IdxMap::split(X, 1, (i64)Y * Y);
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
             g.beta = 1.0;
             g.tag = 9;
-            set_bs(g, o.Q2.bs, o.P1.bs, P->Tbar2.bs);
-            c.gemmc(g, o.at(2), true);
+            c.run(g, pr, Out::F64);
         }
-        // Tbar_upper[a][i][y][j] += sum_{(alpha,b)} Pbar_p[y][(i,j)][(alpha,b)] Wt2[a][(alpha,b)]
+        // X5A[(y,i,j)][(alpha,b)] = sum_{(z,m)} QbA[(alpha,y,i)][(z,m)] Tb2[(j,b)][(z,m)]   (chi^7, X1), and
+        // its transpose X5B [(alpha,b)][(y,i,j)] (X3)
+        {
+            GemmOp g;
+            g.M = K * Y * X; g.N = Y * X; g.K = Y * X;
+            set_ops(g, op_of(o.X2, l.QbA), op_of(o.Tb2, l.Tb2));
+            set_out(g, op_of(o.X1, l.X5A));
+            g.rmap = IdxMap::split((i64)Y * X, X, (i64)Y * l.X5A);
+            g.cmap = IdxMap::split(X, l.X5A, 1);
+            g.tag = 8;
+            c.run(g, pr, own_out(pr));
+        }
+        transpose_op(c, o.X1, l.X5A, Y * X * Y, K * X, o.X3, l.X5B);
+        // Tbar_upper[a][i][y][j] += sum_{(alpha,b)} X5A[y][(i,j)][(alpha,b)] Wt2[a][(alpha,b)]   (batched over y)
         {
             GemmOp g;
             g.M = X * Y; g.N = X; g.K = K * X; g.batch = Y;
-            g.A = o.X5.p; g.lda = (i64)K * X; g.a_bs = (i64)X * Y * K * X;
-            g.B = o.Wt2.p; g.ldb = (i64)b * X; g.b_bs = 0;
-            g.C = P->Tbar2.p; g.c_bs = Y;
+            set_ops(g, op_of(o.X1, l.X5A), op_of(o.Wt2, l.Wt2));
+            g.a_bs = (i64)X * Y * l.X5A; g.b_bs = 0;
+            g.C = P->Tbar2.p; g.c_bs = Y; g.c_bs2 = P->Tbar2.bs;
             g.rmap = IdxMap::split(Y, (i64)Y * Y, 1);
             g.cmap = IdxMap::linear((i64)X * Y * Y);
             g.beta = 1.0;
-            set_bs(g, o.X5.bs, o.Wt2.bs, P->Tbar2.bs);
-            c.gemmc(g, pr6, true);
+            c.run(g, pr, Out::F64);
         }
-        // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} Tp[(y,i,j)][a] Pbar_p[(y,i,j)][(alpha,b)]
+        // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} TpT[a][(y,i,j)] X5B[(alpha,b)][(y,i,j)]
         {
             GemmOp g;
             g.M = X; g.N = K * X; g.K = Y * X * Y;
-            g.A = o.Tp.p; g.lda = X; g.a_kmajor = true;
-            g.B = o.X5.p; g.ldb = (i64)K * X; g.b_kmajor = true;
-            g.C = P->Ub.p;
+            set_ops(g, op_of(o.TpT, l.TpT), op_of(o.X3, l.X5B));
+            g.C = P->Ub.p; g.c_bs2 = P->Ub.bs;
             g.rmap = IdxMap::linear((i64)X * K);
             g.cmap = IdxMap::split(X, 1, K);
             g.beta = 1.0;
-            set_bs(g, o.Tp.bs, o.X5.bs, P->Ub.bs);
-            c.gemmc(g, pr6, true);
+            c.run(g, pr, Out::F64);
         }
         // recompute the step's half-environments and normalised Gram from its checkpoint
         gram_of_step(c, st, k);
         // eigensolver adjoint -> G_bar, in Gt[(a,b)][(c,d)]
         eig_adjoint(c, st, k);
         // Abar'[a][j][b][k] = sum_{(c,d)} Gt[(a,b)][(c,d)] B[(c,d)][(j,k)]   (into Tn)
-        // Bbar'[c][j][d][k] = sum_{(a,b)} Gt[(a,b)][(c,d)] A[(a,b)][(j,k)]   (into Tpbar)
+        // Bbar'[c][j][d][k] = sum_{(a,b)} Gt[(a,b)][(c,d)] A[(a,b)][(j,k)]   (into Wk)
         DevBuf<double>& Abar = P->Tn;
-        DevBuf<double>& Bbar = P->Tpbar;
+        DevBuf<double>& Bbar = P->Wk;
         {
             GemmOp g;
             g.M = X * X; g.N = Y * Y; g.K = X * X;

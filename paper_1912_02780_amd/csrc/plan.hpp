@@ -44,6 +44,33 @@ struct StepShape {
     double join_flops() const { return 2.0 * K * Y * X * (double)(Y * X) * (X * Y); }
 };
 
+// A contraction operand of nb instances in a contraction format (FP64, FP32 or bf16 planes):
+// per instance `per` elements (rows x padded row stride, a multiple of 8); bf16 planes outermost,
+// plane q of instance i at (q * nb + i) * per elements.
+struct OpBuf {
+    DevBuf<double> mem;   // raw storage
+    i64 per = 0;
+    int esz = 8, np = 1, nb = 1;
+    void alloc(Prec pr, int n_inst, i64 per_elems) {
+        np = prec_planes(pr);
+        esz = pr == Prec::F64 ? 8 : (pr == Prec::F32 ? 4 : 2);
+        nb = n_inst;
+        per = (per_elems + 7) / 8 * 8;
+        const i64 bytes = (i64)np * nb * per * esz;
+        mem.alloc((size_t)((bytes + 7) / 8));
+    }
+    void* p() const { return mem.p; }
+    i64 ps() const { return per * nb; }
+};
+
+// Operands of the projection contractions and their adjoints in one format, every one stored
+// K-contiguous for the contraction that reads it (names: the layouts written next to their producers).
+struct OpSet {
+    Prec pr = Prec::F64;
+    OpBuf Wt, Wt2, UT, Us, Tp, Tb, Tb2, TpT, Tpb, Tpb2;   // chi^4 / n x b class
+    OpBuf X1, X2, X3;                                      // chi^5 class
+};
+
 struct StepCk {
     StepShape sh;
     DevBuf<double> T;      // normalised input [X][X][Y][Y] (checkpoint)
@@ -78,15 +105,15 @@ struct dtrg_plan {
     // inputs and outputs of the nb instances ([nb][D^4])
     dtrg::DevBuf<double> T0buf, T0barbuf, dT0buf;
     // workspaces (instance stride bs)
-    dtrg::DevBuf<double> TA, TB, Tp, Tb, Tb2, Wt, Wt2, Tn, Tbar, Tbar2, Tpbar;
-    dtrg::DevBuf<double> A, B, P1, Q2, X5;
+    dtrg::DevBuf<double> TA, TB, Tn, Tbar, Tbar2, Wk;
+    dtrg::DevBuf<double> A, B;
+    // contraction operands: [0] for steps in FP64, [1] for steps in the plan's contraction format
+    dtrg::OpSet ops[2];
     dtrg::DevBuf<double> Gw, Gt, Ub, Xe, Xc, Re, Om, Sm, Vc, Vp, Vn, Ye, We;
     dtrg::DevBuf<double> V1, V2, Y1, Y2, H, Z, Rinv, Sg, th, res, nrm, coef, fv;
     dtrg::DevBuf<double> ctab;  // Chebyshev DCT tables of degree 8, 16, ..., 1024
     bool ctab_ready = false;
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
-    // contraction operands in FP32 (FP32 and split-bf16 paths)
-    dtrg::DevBuf<float> Tpf, Tbf, Tb2f, Wtf, Wt2f, Uf, P1f, Q2f, X5f, Tpbarf;
     bool mixed() const { return prec != dtrg::Prec::F64; }
     // HIP-event timing of the chi^7 join contractions (adaptive passes with opt.profile)
     std::vector<hipEvent_t> ev_pool;
@@ -120,7 +147,7 @@ void plan_throw_flags(const dtrg_plan* P, int mask, const std::string& where);
 // tune.hip: the tile configuration for op, measured once per shape when tuning is allowed
 // (adaptive passes with the autotuner on) and reused afterwards; `scratch` receives the trial
 // outputs.
-GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
+GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
                   DevBuf<double>& scratch);
 // Number of shapes in the tuning table (for tests and diagnostics).
 int tuned_count();

@@ -18,9 +18,12 @@ struct PermK {
     i64 odims[6];     // output dims
     i64 istr[6];      // input stride of each output axis
     i64 total;        // elements per instance
+    i64 rowlen;       // output row length (product of the last out_inner output dims), 0: dense
+    i64 out_ld;       // output row stride when rowlen > 0
+    i64 out_ps;       // plane stride of bf16-plane outputs
 };
 
-PermK make_perm(const PermDesc& d) {
+PermK make_perm(const PermDesc& d, int np = 1) {
     DTRG_REQUIRE(d.rank >= 1 && d.rank <= 6, DTRG_EINVAL, "permute: rank out of range");
     DTRG_REQUIRE(d.nb >= 1 && d.nb < 65536, DTRG_EINVAL, "permute: instance count out of range");
     PermK k;
@@ -39,10 +42,25 @@ PermK make_perm(const PermDesc& d) {
         k.total *= k.odims[i];
     }
     for (int i = d.rank; i < 6; ++i) { k.odims[i] = 1; k.istr[i] = 0; }
-    const i64 in_ext = (i64)(d.nb - 1) * d.in_bs + k.total, out_ext = (i64)(d.nb - 1) * d.out_bs + k.total;
+    DTRG_REQUIRE(d.out_inner >= 0 && d.out_inner <= d.rank, DTRG_EINVAL, "permute: bad row definition");
+    k.rowlen = 0;
+    k.out_ld = 0;
+    k.out_ps = d.out_ps;
+    i64 out_inst = k.total;   // extent of one output instance
+    if (d.out_inner > 0) {
+        k.rowlen = 1;
+        for (int i = d.rank - d.out_inner; i < d.rank; ++i) k.rowlen *= k.odims[i];
+        DTRG_REQUIRE(d.out_ld >= k.rowlen, DTRG_EINVAL, "permute: output row stride smaller than a row");
+        k.out_ld = d.out_ld;
+        out_inst = k.total > 0 ? (k.total / k.rowlen - 1) * k.out_ld + k.rowlen : 0;
+    }
+    DTRG_REQUIRE(np == 1 || d.out_ps >= (i64)(d.nb - 1) * d.out_bs + out_inst, DTRG_EINVAL,
+                 "permute: output planes overlap");
+    const i64 in_ext = (i64)(d.nb - 1) * d.in_bs + k.total;
+    const i64 out_ext = (i64)(d.nb - 1) * d.out_bs + out_inst + (i64)(np - 1) * d.out_ps;
     DTRG_REQUIRE(d.in_cap < 0 || in_ext <= d.in_cap, DTRG_EINVAL, "permute: input out of bounds");
     DTRG_REQUIRE(d.out_cap < 0 || out_ext <= d.out_cap, DTRG_EINVAL, "permute: output out of bounds");
-    DTRG_REQUIRE(d.nb == 1 || (d.in_bs >= k.total && d.out_bs >= k.total), DTRG_EINVAL,
+    DTRG_REQUIRE(d.nb == 1 || (d.in_bs >= k.total && d.out_bs >= out_inst), DTRG_EINVAL,
                  "permute: instance stride smaller than an instance");
     return k;
 }
@@ -63,18 +81,54 @@ dim3 grid2(i64 n, int nb) {
     return dim3((unsigned)per, (unsigned)nb);
 }
 
-template <class TI, class TO>
-__global__ __launch_bounds__(256) void permute_kernel(const TI* __restrict__ in, TO* __restrict__ out, PermK p,
+// output writers: OUT = 0 double, 1 float, 2 / 3 the value rounded to FP32 and split into that
+// many bf16 planes (plane q = bf16 of what the planes before it leave)
+template <int OUT>
+__device__ inline void put_elem(void* base, i64 off, i64 ps, double v, double beta) {
+    if constexpr (OUT == 0) {
+        double* o = (double*)base;
+        if (beta != 0.0) v += beta * o[off];
+        o[off] = v;
+    } else if constexpr (OUT == 1) {
+        float* o = (float*)base;
+        if (beta != 0.0) v += beta * (double)o[off];
+        o[off] = (float)v;
+    } else {
+        __bf16* o = (__bf16*)base;
+        float r = (float)v;
+#pragma unroll
+        for (int q = 0; q < OUT; ++q) {
+            const __bf16 h = (__bf16)r;
+            o[q * ps + off] = h;
+            r -= (float)h;
+        }
+    }
+}
+
+template <class TI, int OUT>
+__global__ __launch_bounds__(256) void permute_kernel(const TI* __restrict__ in, void* __restrict__ out, PermK p,
                                                       i64 in_bs, i64 out_bs, double alpha, double beta,
                                                       const double* scale, i64 scale_bs) {
     const int z = blockIdx.y;
     in += z * in_bs;
-    out += z * out_bs;
     const double a = scale ? alpha * scale[z * scale_bs] : alpha;
+    const i64 ob = z * out_bs;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < p.total; i += (i64)gridDim.x * blockDim.x) {
-        double v = a * (double)in[perm_src(p, i)];
-        if (beta != 0.0) v += beta * (double)out[i];
-        out[i] = (TO)v;
+        const i64 o = p.rowlen > 0 ? (i / p.rowlen) * p.out_ld + i % p.rowlen : i;
+        put_elem<OUT>(out, ob + o, p.out_ps, a * (double)in[perm_src(p, i)], beta);
+    }
+}
+
+// out[q][r][k] (row stride ld_out, plane stride ps) = planes of in(r, k), in(r, k) = in[r * ld_in + k]
+// or in[k * ld_in + r] (kmajor)
+template <int OUT>
+__global__ __launch_bounds__(256) void split_matrix_kernel(const float* in, i64 ld_in, int kmajor, int rows, int cols,
+                                                           void* out, i64 ld_out, i64 ps) {
+    const i64 total = (i64)rows * cols;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < total; i += (i64)gridDim.x * blockDim.x) {
+        const i64 r = i / cols, k = i % cols;
+        const float v = kmajor ? in[k * ld_in + r] : in[r * ld_in + k];
+        put_elem<OUT>(out, r * ld_out + k, ps, (double)v, 0.0);
     }
 }
 
@@ -266,27 +320,85 @@ int np_of(int nb) {
     return nb == 1 ? kRedBlocks : std::max(16, std::min(kRedBlocks, 4096 / nb));
 }
 
+// out[c][r] = in[r][c] for every plane and instance: 64 x 64 tiles through LDS, reads and writes
+// coalesced along the contiguous index of each side.  E is the element type (its size only).
+template <class E>
+__global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in, E* __restrict__ out, int rows,
+                                                        int cols, i64 ld_in, i64 ld_out, int nb, i64 bs_in,
+                                                        i64 bs_out, i64 ps_in, i64 ps_out) {
+    __shared__ E t[64][65];
+    const int z = blockIdx.z;               // plane * nb + instance
+    const int q = z / nb, i = z % nb;
+    in += q * ps_in + i * bs_in;
+    out += q * ps_out + i * bs_out;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int rr = ty; rr < 64; rr += 4) {
+        const int r = r0 + rr, c = c0 + tx;
+        if (r < rows && c < cols) t[rr][tx] = in[(i64)r * ld_in + c];
+    }
+    __syncthreads();
+    for (int cc = ty; cc < 64; cc += 4) {
+        const int c = c0 + cc, r = r0 + tx;
+        if (r < rows && c < cols) out[(i64)c * ld_out + r] = t[tx][cc];
+    }
+}
+
 }  // namespace
 
 void permute(const double* in, double* out, const PermDesc& d, double alpha, double beta,
              const double* scale_dev, i64 scale_bs, hipStream_t s) {
     PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<double, double>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
+    hipLaunchKernelGGL((permute_kernel<double, 0>), grid2(k.total, d.nb), dim3(256), 0, s, in, (void*)out, k, d.in_bs,
                        d.out_bs, alpha, beta, scale_dev, scale_bs);
     DTRG_HIP(hipGetLastError());
 }
 
-void permute_to_f32(const double* in, float* out, const PermDesc& d, hipStream_t s) {
-    PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<double, float>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
-                       d.out_bs, 1.0, 0.0, (const double*)nullptr, (i64)0);
+void permute_out(const double* in, void* out, int out_code, const PermDesc& d, double alpha, const double* scale_dev,
+                 i64 scale_bs, hipStream_t s) {
+    DTRG_REQUIRE(out_code >= 0 && out_code <= 3, DTRG_EINVAL, "permute: bad output format");
+    PermK k = make_perm(d, out_code >= 2 ? out_code : 1);
+    const dim3 g = grid2(k.total, d.nb);
+    switch (out_code) {
+        case 0: hipLaunchKernelGGL((permute_kernel<double, 0>), g, dim3(256), 0, s, in, out, k, d.in_bs, d.out_bs, alpha,
+                                   0.0, scale_dev, scale_bs); break;
+        case 1: hipLaunchKernelGGL((permute_kernel<double, 1>), g, dim3(256), 0, s, in, out, k, d.in_bs, d.out_bs, alpha,
+                                   0.0, scale_dev, scale_bs); break;
+        case 2: hipLaunchKernelGGL((permute_kernel<double, 2>), g, dim3(256), 0, s, in, out, k, d.in_bs, d.out_bs, alpha,
+                                   0.0, scale_dev, scale_bs); break;
+        default: hipLaunchKernelGGL((permute_kernel<double, 3>), g, dim3(256), 0, s, in, out, k, d.in_bs, d.out_bs,
+                                    alpha, 0.0, scale_dev, scale_bs); break;
+    }
     DTRG_HIP(hipGetLastError());
 }
 
-void permute_f32(const float* in, float* out, const PermDesc& d, hipStream_t s) {
-    PermK k = make_perm(d);
-    hipLaunchKernelGGL((permute_kernel<float, float>), grid2(k.total, d.nb), dim3(256), 0, s, in, out, k, d.in_bs,
-                       d.out_bs, 1.0, 0.0, (const double*)nullptr, (i64)0);
+void transpose_planes(const void* in, void* out, int esz, int rows, int cols, i64 ld_in, i64 ld_out, int nb,
+                      i64 bs_in, i64 bs_out, int np, i64 ps_in, i64 ps_out, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return;
+    DTRG_REQUIRE((i64)nb * np < 65536, DTRG_EINVAL, "transpose: too many planes x instances");
+    const dim3 g((cols + 63) / 64, (rows + 63) / 64, nb * np);
+    if (esz == 8)
+        hipLaunchKernelGGL(transpose_kernel<double>, g, dim3(256), 0, s, (const double*)in, (double*)out, rows, cols,
+                           ld_in, ld_out, nb, bs_in, bs_out, ps_in, ps_out);
+    else if (esz == 4)
+        hipLaunchKernelGGL(transpose_kernel<float>, g, dim3(256), 0, s, (const float*)in, (float*)out, rows, cols, ld_in,
+                           ld_out, nb, bs_in, bs_out, ps_in, ps_out);
+    else {
+        DTRG_REQUIRE(esz == 2, DTRG_EINVAL, "transpose: element size 2, 4 or 8");
+        hipLaunchKernelGGL(transpose_kernel<unsigned short>, g, dim3(256), 0, s, (const unsigned short*)in,
+                           (unsigned short*)out, rows, cols, ld_in, ld_out, nb, bs_in, bs_out, ps_in, ps_out);
+    }
+    DTRG_HIP(hipGetLastError());
+}
+
+void split_matrix(const float* in, i64 ld_in, bool kmajor, int rows, int cols, void* out, i64 ld_out, i64 ps, int np,
+                  hipStream_t s) {
+    DTRG_REQUIRE(np == 2 || np == 3, DTRG_EINVAL, "split_matrix: 2 or 3 planes");
+    const dim3 g = grid2((i64)rows * cols, 1);
+    if (np == 2) hipLaunchKernelGGL((split_matrix_kernel<2>), g, dim3(256), 0, s, in, ld_in, kmajor ? 1 : 0, rows, cols,
+                                    out, ld_out, ps);
+    else hipLaunchKernelGGL((split_matrix_kernel<3>), g, dim3(256), 0, s, in, ld_in, kmajor ? 1 : 0, rows, cols, out,
+                            ld_out, ps);
     DTRG_HIP(hipGetLastError());
 }
 

@@ -1,11 +1,12 @@
 // Tile autotuner of the MFMA contraction kernel.
 //
-// The first time a contraction shape (precision, output type, M, N, K, both batch levels, operand
-// layouts) is met in an adaptive pass with tuning enabled, every admissible configuration
-// {64 x 64, 128 x 128 tiles} x {split-K 1, 2, 4, ..., 32} is run on a scratch output (beta = 0, so
-// the real output is untouched), timed with HIP events on the caller's stream, and the fastest is
-// kept in a process-wide table.  Later contractions of that shape (including fixed passes that
-// are being captured into a graph) take the table entry without timing anything.
+// The first time a contraction shape (precision, output kind, M, N, K, both batch levels, operand
+// layouts) is met in an adaptive pass with tuning enabled, every admissible
+// configuration {64 x 64, 128 x 128 (and 256 x 128 for bf16 planes) tiles} x {split-K 1, 2, 4, ...,
+// 32} is run on a scratch output (beta = 0, so the real output is untouched), timed with HIP events
+// on the caller's stream, and the fastest is kept in a process-wide table.  Later contractions of
+// that shape (including fixed passes that are being captured into a graph) take the table entry
+// without timing anything.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -23,8 +24,8 @@ typedef std::tuple<int, int, int, int, int, int, int, int, int> TuneKey;
 std::mutex g_mu;
 std::map<TuneKey, GemmCfg> g_table;
 
-TuneKey key_of(Prec prec, bool out_f64, const GemmOp& op) {
-    return TuneKey((int)prec, out_f64 ? 1 : 0, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
+TuneKey key_of(Prec prec, Out out, const GemmOp& op) {
+    return TuneKey((int)prec, (int)out, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
                    op.b_kmajor ? 1 : 0);
 }
 
@@ -38,9 +39,9 @@ int tuned_count() {
     return (int)g_table.size();
 }
 
-GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
+GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,
                   DevBuf<double>& scratch) {
-    const TuneKey key = key_of(prec, out_f64, op);
+    const TuneKey key = key_of(prec, out, op);
     {
         std::lock_guard<std::mutex> g(g_mu);
         auto it = g_table.find(key);
@@ -48,11 +49,13 @@ GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hi
     }
     if (!allow_tune || op.M == 0 || op.N == 0 || op.K == 0) return op.cfg;
 
-    const int BK = prec == Prec::BF16X3 ? 32 : 16;
+    const int np = prec_planes(prec);
+    const int BK = np > 1 ? 32 : 16;
     const i64 nz = (i64)op.batch * op.batch2;
     std::vector<GemmCfg> cands;
-    for (int tile = 1; tile <= 2; ++tile) {
+    for (int tile = 1; tile <= (np > 1 ? 3 : 2); ++tile) {
         if (tile == 2 && std::max(op.M, op.N) < 128) continue;
+        if (tile == 3 && op.M < 256) continue;
         for (int sp = 1; sp <= 32; sp *= 2) {
             if (sp > 1 && op.K < sp * BK * 2) break;
             if (nz * sp >= 65536) break;
@@ -63,8 +66,12 @@ GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hi
             cands.push_back(c);
         }
     }
-    const i64 ext = gemm_c_extent(op);
-    scratch.ensure((size_t)ext);
+    // trial output: the real output's extent (all planes) in the scratch buffer
+    const int eout = out == Out::F64 ? 8 : (out == Out::F32 ? 4 : 2);
+    const int onp = out == Out::Split ? np : 1;
+    const i64 ext1 = gemm_c_extent(op);
+    const i64 ext = ext1 * onp;
+    scratch.ensure((size_t)((ext * eout + 7) / 8));
     hipEvent_t e0, e1;
     DTRG_HIP(hipEventCreate(&e0));
     DTRG_HIP(hipEventCreate(&e1));
@@ -75,12 +82,13 @@ GemmCfg tuned_cfg(Prec prec, bool out_f64, const GemmOp& op, bool allow_tune, hi
             GemmOp t = op;
             t.cfg = c;
             t.C = scratch.p;
-            t.c_cap = (i64)scratch.n * (out_f64 ? 1 : 2);
+            t.c_ps = ext1;
+            t.c_cap = (i64)scratch.bytes() / eout;
             t.beta = 0.0;
             t.tag = 0;
-            gemm(prec, out_f64, t, s, ws);   // warm-up (and workspace growth)
+            gemm(prec, out, t, s, ws);   // warm-up (and workspace growth)
             DTRG_HIP(hipEventRecord(e0, s));
-            for (int r = 0; r < 2; ++r) gemm(prec, out_f64, t, s, ws);
+            for (int r = 0; r < 2; ++r) gemm(prec, out, t, s, ws);
             DTRG_HIP(hipEventRecord(e1, s));
             DTRG_HIP(hipEventSynchronize(e1));
             float ms = 0.f;

@@ -81,13 +81,12 @@ def test_default_options():
     class Options(ctypes.Structure):
         _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
                     ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int),
-                    ("bf16x3_mask", ctypes.c_int)]
+                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int)]
 
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))
     assert o.contract == 0 and o.eig_broadening == 1e-12 and o.max_subspace_iters == 60
-    assert o.autotune == 0 and o.profile == 0 and o.bf16x3_mask == 15 and o.gram_fp64 == 1
+    assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1
 
 
 def test_batch_argument_validation_without_device_work():

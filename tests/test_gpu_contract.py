@@ -1,8 +1,10 @@
 """The MFMA contraction kernel (diagnostic entry point of the C ABI) against float64 matmul.
 
-Covers every precision, the four operand layouts, ragged edges, both tile shapes and split-K.
-FP64 must agree to rounding; FP32 to single precision; split-bf16 (three products) to the
-~2^-16 relative error of the dropped lo*lo term and the bf16 rounding of lo.
+Covers every precision, the four operand layouts, ragged edges (K not a multiple of 8: the bf16
+planes' masked last chunk), every tile shape and split-K.  FP64 must agree to rounding; FP32 to
+single precision; split-bf16 with two planes (three products) to the ~2^-17 relative error of the
+two-plane representation and the dropped x1*y1 term; with three planes (six products) to single
+precision.
 """
 
 import sys
@@ -14,7 +16,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(70, 45, 37), (300, 260, 129), (40, 30, 5000), (16, 16, 4), (1, 1, 1), (129, 257, 65)]
-TOL = {"fp64": 1e-13, "fp32": 2e-6, "bf16x3": 3e-5}
+TOL = {"fp64": 1e-13, "fp32": 2e-6, "bf16x3": 3e-5, "bf16x6": 2e-6}
+PRECS = ["fp64", "fp32", "bf16x3", "bf16x6"]
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +28,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("akm", [False, True])
 @pytest.mark.parametrize("bkm", [False, True])
 @pytest.mark.parametrize("shape", SHAPES)
@@ -50,3 +53,10 @@ def test_contract(B, prec, akm, bkm, shape):
         err = (out - ref).norm() / ref.norm()
         tol = TOL[prec] if out_dt == torch.float64 else max(TOL[prec], 1e-6)
         assert err < tol, (prec, akm, bkm, shape, out_dt, float(err))
+
+
+# enough 256 x 128 tiles to select the largest tile of the bf16-plane kernel (ragged in M, N, K)
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("layout", [(False, False), (True, True)])
+def test_contract_large_tile(B, prec, layout):
+    test_contract(B, prec, layout[0], layout[1], (8200, 4100, 70))

@@ -233,14 +233,18 @@ MIXED = [
 ]
 
 
-# Gradient tolerance per contraction precision.  FP32 meets the 1e-5 target with margin.  Split-bf16
-# x3 sits at it: perturbing every step output of the FP64 oracle by a relative 7.6e-6 (the bf16x3
-# product error) moves its T0bar by 1e-5 to 3e-5 on these random tensors, so 3e-5 is the bound
-# that the method's conditioning allows at that precision.
-GRAD_TOL = {"fp32": 1e-5, "bf16x3": 3e-5}
+# (On the random tensors, perturbing every step output of the FP64 oracle by a relative 7.6e-6, the
+# two-plane product error, moves its T0bar by 1e-5 to 3e-5: the same conditioning.)
+# Gradient tolerance per contraction format.  FP32 and three-plane split-bf16 (six products) meet the
+# 1e-5 target.  Two-plane split-bf16 (three products) carries ~2^-17 relative error per product (the
+# two-plane representation and the dropped x1*y1 term); the broadened eigen-adjoint amplifies it:
+# over the 256-temperature Ising sweep (chi <= 32, 30 steps) its d(lnZ/N)/dbeta differs from the
+# FP64 path by 3e-5 at the median and 2.5e-4 at worst, so that format is bounded by 3e-4 and does not
+# meet the target.
+GRAD_TOL = {"fp32": 1e-5, "bf16x3": 3e-4, "bf16x6": 1e-5}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("case", MIXED, ids=[c[0] for c in MIXED])
 def test_gpu_mixed_vs_oracle_small(B, prec, case):
     """Ising inputs: the gradient that matters is d(lnZ/N)/dbeta; their full T0bar is ill-conditioned
@@ -263,7 +267,7 @@ def test_gpu_mixed_vs_oracle_small(B, prec, case):
         assert _rel(g, go) < GRAD_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 def test_gpu_mixed_vs_golden_chi48(B, prec):
     from paper_1912_02780_amd import inputs as I
     gd = _golden("random_d4_seed0_chi48_n24")
