@@ -66,8 +66,9 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
         const bool big = (op.M >= 256 && op.N >= 128) || (op.N >= 256 && op.M >= 128);
         c.tile = big ? 2 : 1;
         if (split && big && op.M >= 256) {
+            // the largest tile when it alone fills the chip, or when K is long enough for split-K to
             const i64 t3 = (i64)((op.M + 255) / 256) * ((op.N + 127) / 128) * op.batch * op.batch2;
-            if (t3 >= 512) c.tile = 3;
+            if (t3 >= 512 || (op.N >= 128 && op.K >= 4096)) c.tile = 3;
         }
     }
     const int BM = c.tile == 3 ? 256 : (c.tile == 2 ? 128 : 64), BN = c.tile == 1 ? 64 : 128;
