@@ -79,6 +79,11 @@ def traffic_bytes(workload, contract):
     return (m["fetch_kib"] * TRAFFIC_FACTORS["fetch"] + m["write_kib"] * TRAFFIC_FACTORS["write"]) * 1024.0
 
 
+def _progress(msg):
+    # progress lines on stderr (the JSON result line is the only stdout output)
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _threads():
     try:
         from threadpoolctl import threadpool_info
@@ -180,6 +185,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         **err,
     }
     if not args.no_cpu_baseline:
+        _progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(chi, n, D)
     return out
 
@@ -200,12 +206,14 @@ def bench_batch256(args, B, I, torch, np, dev):
     B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=False, T0bar=T0bar)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
+    _progress(f"first adaptive run (with tuning) {t_first:.1f} s")
     batch.profile(reset=True)
     t0 = time.perf_counter()
     L, _, d = B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=False, T0bar=T0bar)
     torch.cuda.synchronize()
     t_adaptive = time.perf_counter() - t0
     launches, ms, flops = batch.profile(reset=True)
+    _progress(f"second adaptive run {t_adaptive:.1f} s")
     for _ in range(max(1, args.warmup)):   # the first replay captures the graph
         B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=True, T0bar=T0bar)
     torch.cuda.synchronize()
@@ -215,6 +223,7 @@ def bench_batch256(args, B, I, torch, np, dev):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = n_inst * n * args.steps / wall
+    _progress(f"{args.steps} replays {wall:.1f} s")
     # every instance against Onsager
     L, d = np.array(L), np.array(d)
     f_ex = np.array([float(E.onsager_lnZ_per_site(b)) for b in betas])
@@ -242,6 +251,7 @@ def bench_batch256(args, B, I, torch, np, dev):
             if j > 0:   # the first run of a plan is a warm-up
                 ts.append(time.perf_counter() - t0)
         plan.close()
+        _progress(f"sequential FP64 sample chi={c}")
         per = float(np.mean(ts))
         sample[f"chi{c}"] = per
         seq_s += per * int((chis == c).sum())
@@ -285,6 +295,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     for _ in range(args.warmup):
         one_step()
         free_min = min(free_min, torch.cuda.mem_get_info(dev)[0])
+    _progress("warm-up done")
     torch.cuda.synchronize()
     plan.profile(reset=True)
     t0 = time.perf_counter()
@@ -305,6 +316,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     def lnZ64(b):
         return B.dtrg_plan_forward(p64, torch.from_numpy(I.ising_T0(b)).to(dev))
 
+    _progress("FP64 gradient done")
     fd = (lnZ64(beta + h) - lnZ64(beta - h)) / (2 * h)
     fd2 = (lnZ64(beta + h / 2) - lnZ64(beta - h / 2)) / h
     rich = (4 * fd2 - fd) / 3

@@ -21,7 +21,7 @@ namespace {
 
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
-constexpr int JT = 512;    // Jacobi: 8 waves
+constexpr int JT = 512;    // Jacobi: 8 waves (one wave is slower: the row and column updates need the width)
 constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,

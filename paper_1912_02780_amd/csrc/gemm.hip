@@ -47,6 +47,11 @@ int out_code(Prec prec, Out out) {
 
 i64 round8(i64 x) { return (x + 7) / 8 * 8; }
 
+// longest FP32 accumulation chain of a contraction in FP32 or bf16 planes, and the largest split-K
+// workspace (elements) spent on keeping to it
+constexpr i64 kMaxFp32Chain = 4096;
+constexpr i64 kMaxChainPartials = 1LL << 30;
+
 }  // namespace
 
 int prec_planes(Prec p) { return p == Prec::BF16X3 ? 2 : (p == Prec::BF16X6 ? 3 : 1); }
@@ -74,13 +79,21 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
     const int BM = c.tile == 3 ? 256 : (c.tile == 2 ? 128 : 64), BN = c.tile == 1 ? 64 : 128;
     const int BK = bk_of(prec, c.tile);
     if (c.splits <= 0) {
-        const i64 tiles = (i64)((op.M + BM - 1) / BM) * ((op.N + BN - 1) / BN) * op.batch * op.batch2;
+        const i64 nz = (i64)op.batch * op.batch2;
+        const i64 tiles = (i64)((op.M + BM - 1) / BM) * ((op.N + BN - 1) / BN) * nz;
         c.splits = 1;
         // fill the 256 CUs (several blocks each) when the output is small and K is long
         if (tiles < 512) {
             const i64 want = (1024 + tiles - 1) / tiles;
             const i64 maxs = std::max<i64>(1, op.K / (BK * 8));
             c.splits = (int)std::min<i64>({want, maxs, 64});
+        }
+        // FP32 accumulation: no chain longer than kMaxFp32Chain products per output (the partials
+        // are summed in FP64), where the partials fit in kMaxChainPartials elements
+        if (prec != Prec::F64 && op.K > kMaxFp32Chain) {
+            const i64 need = std::min<i64>(64, (op.K + kMaxFp32Chain - 1) / kMaxFp32Chain);
+            if (need > c.splits && nz * need * op.M * op.N <= kMaxChainPartials && nz * need < 65536)
+                c.splits = (int)need;
         }
     }
     return c;

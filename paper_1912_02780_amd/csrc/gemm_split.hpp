@@ -15,7 +15,7 @@
 //
 // Tiles: BM x BN per block, WGM x WGN waves of (BM / WGM) x (BN / WGN) outputs each, BK per K tile,
 // one or two LDS stages (with one stage the next tile waits in registers).  The epilogue is the
-// shared one: alpha scaling, optional beta, two-level scatter, optional second copy, and output as
+// shared one: alpha scaling, optional beta, two-level scatter, and output as
 // FP64, FP32 or NP bf16 planes.
 #pragma once
 

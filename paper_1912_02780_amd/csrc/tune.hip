@@ -31,6 +31,10 @@ TuneKey key_of(Prec prec, Out out, const GemmOp& op) {
 
 // largest split-K workspace a trial may claim (elements)
 constexpr i64 kMaxTrialPartials = 1LL << 26;
+// contractions below this many flops are launch-bound: the heuristic is kept, nothing is timed
+constexpr double kMinTunedFlops = 1e8;
+// split-K is only tried up to this many blocks in the grid
+constexpr i64 kMaxTrialBlocks = 2048;
 
 }  // namespace
 
@@ -48,6 +52,11 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
         if (it != g_table.end()) return it->second;
     }
     if (!allow_tune || op.M == 0 || op.N == 0 || op.K == 0) return op.cfg;
+    if (2.0 * op.M * (double)op.N * op.K * op.batch * op.batch2 < kMinTunedFlops) {
+        std::lock_guard<std::mutex> g(g_mu);
+        g_table[key] = op.cfg;
+        return op.cfg;
+    }
 
     const int np = prec_planes(prec);
     const int BK = np > 1 ? 32 : 16;
@@ -56,9 +65,12 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
     for (int tile = 1; tile <= (np > 1 ? 3 : 2); ++tile) {
         if (tile == 2 && std::max(op.M, op.N) < 128) continue;
         if (tile == 3 && op.M < 256) continue;
+        const int BMt = tile == 3 ? 256 : (tile == 2 ? 128 : 64), BNt = tile == 1 ? 64 : 128;
+        const i64 tiles = (i64)((op.M + BMt - 1) / BMt) * ((op.N + BNt - 1) / BNt) * nz;
         for (int sp = 1; sp <= 32; sp *= 2) {
             if (sp > 1 && op.K < sp * BK * 2) break;
             if (nz * sp >= 65536) break;
+            if (sp > 1 && tiles * sp > kMaxTrialBlocks) break;
             if (sp > 1 && nz * sp * op.M * op.N > kMaxTrialPartials) break;
             GemmCfg c;
             c.tile = tile;
@@ -88,7 +100,7 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
             t.tag = 0;
             gemm(prec, out, t, s, ws);   // warm-up (and workspace growth)
             DTRG_HIP(hipEventRecord(e0, s));
-            for (int r = 0; r < 2; ++r) gemm(prec, out, t, s, ws);
+            gemm(prec, out, t, s, ws);
             DTRG_HIP(hipEventRecord(e1, s));
             DTRG_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
