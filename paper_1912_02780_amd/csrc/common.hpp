@@ -133,6 +133,9 @@ struct Scratch {
 // gemm.hip
 // Tile configuration gemm() would pick for op (after the automatic choices are resolved).
 GemmCfg gemm_resolve(Prec in_prec, const GemmOp& op);
+// smallest split-K count that keeps every FP32 accumulation chain of the contraction short (1 for
+// FP64 and short K); gemm_resolve never picks fewer, and the autotuner tries no fewer
+int gemm_chain_splits(Prec prec, const GemmOp& op);
 // Largest element offset (plus one) the epilogue of op can write, over all batch elements.
 i64 gemm_c_extent(const GemmOp& op);
 void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws);

@@ -88,15 +88,18 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
             const i64 maxs = std::max<i64>(1, op.K / (BK * 8));
             c.splits = (int)std::min<i64>({want, maxs, 64});
         }
-        // FP32 accumulation: no chain longer than kMaxFp32Chain products per output (the partials
-        // are summed in FP64), where the partials fit in kMaxChainPartials elements
-        if (prec != Prec::F64 && op.K > kMaxFp32Chain) {
-            const i64 need = std::min<i64>(64, (op.K + kMaxFp32Chain - 1) / kMaxFp32Chain);
-            if (need > c.splits && nz * need * op.M * op.N <= kMaxChainPartials && nz * need < 65536)
-                c.splits = (int)need;
-        }
+        c.splits = std::max(c.splits, gemm_chain_splits(prec, op));
     }
     return c;
+}
+
+int gemm_chain_splits(Prec prec, const GemmOp& op) {
+    // FP32 accumulation: no chain longer than kMaxFp32Chain products per output (the partials are
+    // summed in FP64), where the partials fit in kMaxChainPartials elements
+    if (prec == Prec::F64 || op.K <= kMaxFp32Chain) return 1;
+    const i64 nz = (i64)op.batch * op.batch2;
+    const i64 need = std::min<i64>(64, (op.K + kMaxFp32Chain - 1) / kMaxFp32Chain);
+    return nz * need * op.M * op.N <= kMaxChainPartials && nz * need < 65536 ? (int)need : 1;
 }
 
 void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {

@@ -1,12 +1,13 @@
 // Tile autotuner of the MFMA contraction kernel.
 //
 // The first time a contraction shape (precision, output kind, M, N, K, both batch levels, operand
-// layouts) is met in an adaptive pass with tuning enabled, every admissible
-// configuration {64 x 64, 128 x 128 (and 256 x 128 for bf16 planes) tiles} x {split-K 1, 2, 4, ...,
-// 32} is run on a scratch output (beta = 0, so the real output is untouched), timed with HIP events
-// on the caller's stream, and the fastest is kept in a process-wide table.  Later contractions of
-// that shape (including fixed passes that are being captured into a graph) take the table entry
-// without timing anything.
+// layouts) is met in an adaptive pass with tuning enabled, every admissible configuration is run
+// on a scratch output (beta = 0, so the real output is untouched), timed with HIP events on the
+// caller's stream, and the fastest is kept in a process-wide table.  The configurations are the
+// tiles {64 x 64, 128 x 128, and 256 x 128 for bf16 planes} times the split-K counts {s0, then the
+// powers of two above it up to 32}, s0 being the least count that keeps FP32 accumulation chains
+// short (1 for FP64 and for short K).  Later contractions of that shape (including fixed passes
+// that are being captured into a graph) take the table entry without timing anything.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -36,6 +37,12 @@ constexpr double kMinTunedFlops = 1e8;
 // split-K is only tried up to this many blocks in the grid
 constexpr i64 kMaxTrialBlocks = 2048;
 
+int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
+}
+
 }  // namespace
 
 int tuned_count() {
@@ -61,17 +68,22 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
     const int np = prec_planes(prec);
     const int BK = np > 1 ? 32 : 16;
     const i64 nz = (i64)op.batch * op.batch2;
+    const int minsp = gemm_chain_splits(prec, op);
     std::vector<GemmCfg> cands;
     for (int tile = 1; tile <= (np > 1 ? 3 : 2); ++tile) {
         if (tile == 2 && std::max(op.M, op.N) < 128) continue;
         if (tile == 3 && op.M < 256) continue;
         const int BMt = tile == 3 ? 256 : (tile == 2 ? 128 : 64), BNt = tile == 1 ? 64 : 128;
         const i64 tiles = (i64)((op.M + BMt - 1) / BMt) * ((op.N + BNt - 1) / BNt) * nz;
-        for (int sp = 1; sp <= 32; sp *= 2) {
-            if (sp > 1 && op.K < sp * BK * 2) break;
-            if (nz * sp >= 65536) break;
-            if (sp > 1 && tiles * sp > kMaxTrialBlocks) break;
-            if (sp > 1 && nz * sp * op.M * op.N > kMaxTrialPartials) break;
+        // the chain floor is always a candidate (the untuned path would take it too); larger
+        // split counts only within the trial limits
+        for (int sp = minsp; sp <= std::max(32, minsp); sp = sp == minsp ? next_pow2(minsp + 1) : sp * 2) {
+            if (sp > minsp) {
+                if (op.K < sp * BK * 2) break;
+                if (nz * sp >= 65536) break;
+                if (tiles * sp > kMaxTrialBlocks) break;
+                if (nz * sp * op.M * op.N > kMaxTrialPartials) break;
+            }
             GemmCfg c;
             c.tile = tile;
             c.splits = sp;

@@ -278,3 +278,79 @@ def test_gpu_mixed_vs_golden_chi48(B, prec):
     _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.2e}  T0bar rel {_rel(g, go):.2e}")
     assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-6
     assert _rel(g, go) < GRAD_TOL[prec]
+
+
+# ---------------------------------------------------------------------------------------------
+# finite differences in beta at full size (FP64 path), and the chi = 64 critical run
+# ---------------------------------------------------------------------------------------------
+
+def _lnZ_gpu(B, beta, chi, n, plan=None, contract=None):
+    from paper_1912_02780_amd import inputs as I
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(I.ising_T0(beta)).to(dev)
+    if plan is None:
+        plan = B.dtrg_plan_create(2, chi, n, B.default_options(contract=contract) if contract else None, dev)
+    return B.dtrg_plan_forward(plan, t), plan
+
+
+# Central differences with h = 1e-5 carry an O(h^2) error that is largest at the critical point: at
+# chi = 32 it is 1.8e-6 relative there and below 1e-8 away from it; the Richardson combination of h and
+# h/2 removes the h^2 term.
+@pytest.mark.parametrize("beta,tol_fd", [(0.30, 1e-8), (0.4406868, 5e-6), (0.50, 1e-8)])
+def test_gpu_dbeta_vs_finite_differences_chi32(B, beta, tol_fd):
+    from paper_1912_02780_amd import inputs as I
+    chi, n, h = 32, 30, 1e-5
+    _say(f"[gpu] finite differences beta={beta} chi={chi} n={n}")
+    dev = torch.device("cuda:0")
+    plan, L = B.dtrg_hotrg_forward(torch.from_numpy(I.ising_T0(beta)).to(dev), chi, n)
+    _, d = B.dtrg_hotrg_backward(plan, 1.0, torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev))
+    f = {}
+    p2 = None
+    for s in (-1.0, -0.5, 0.5, 1.0):
+        f[s], p2 = _lnZ_gpu(B, beta + s * h, chi, n, p2)
+    fd = (f[1.0] - f[-1.0]) / (2 * h)
+    fd2 = (f[0.5] - f[-0.5]) / h
+    rich = (4 * fd2 - fd) / 3
+    _say(f"    AD {d:.15f}  FD {fd:.15f} (rel {abs(d / fd - 1):.1e})  Richardson rel {abs(d / rich - 1):.1e}")
+    assert abs(d / fd - 1) < tol_fd
+    assert abs(d / rich - 1) < max(tol_fd / 10, 2e-7)
+
+
+def test_gpu_chi64_critical_dbeta(B):
+    """Ising at beta_c, chi = 64, 30 steps: the FP64 gradient against Richardson-extrapolated central
+    differences of the FP64 forward, and the three-plane split-bf16 gradient against the FP64 one.
+    The second bound needs the 4096-product cap on FP32 accumulation chains (without it: 1.4e-4)."""
+    from paper_1912_02780_amd import inputs as I
+    beta, chi, n, h = 0.4406868, 64, 30, 1e-5
+    _say(f"[gpu] chi={chi} critical: FP64 gradient and finite differences")
+    dev = torch.device("cuda:0")
+    T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
+    dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
+    plan, L64 = B.dtrg_hotrg_forward(T0, chi, n)
+    _, d64 = B.dtrg_hotrg_backward(plan, 1.0, dT0)
+    f = {}
+    for s in (-1.0, -0.5, 0.5, 1.0):
+        f[s], _ = _lnZ_gpu(B, beta + s * h, chi, n, plan)
+    rich = (4 * (f[0.5] - f[-0.5]) / h - (f[1.0] - f[-1.0]) / (2 * h)) / 3
+    plan.close()
+    _say(f"    FP64 AD {d64:.12f}  Richardson FD {rich:.12f}  rel {abs(d64 / rich - 1):.1e}")
+    assert abs(d64 / rich - 1) < 2e-6
+    _say("[gpu] chi=64 critical: bf16x6")
+    p6, L6 = B.dtrg_hotrg_forward(T0, chi, n, B.default_options(contract="bf16x6"))
+    _, d6 = B.dtrg_hotrg_backward(p6, 1.0, dT0)
+    _say(f"    bf16x6 lnZ rel {abs(L6 / L64 - 1):.1e}  dbeta rel {abs(d6 / d64 - 1):.1e}")
+    assert abs(L6 / L64 - 1) < 1e-7
+    assert abs(d6 / d64 - 1) < 3e-5
+
+
+def test_gpu_autotuned_plan(B):
+    """A plan with the tile autotuner on gives the untuned result to rounding and fills the table."""
+    from paper_1912_02780_amd import inputs as I
+    T0 = I.random_d4_T0(1)
+    _say("[gpu] autotuned plan")
+    L0, g0, _, _ = _gpu(B, T0, 20, 8, None, contract="bf16x6")
+    L1, g1, _, _ = _gpu(B, T0, 20, 8, None, contract="bf16x6", autotune=1)
+    assert B.tuned_shapes() > 0
+    _say(f"    lnZ rel {abs(L1 / L0 - 1):.1e}  T0bar rel {_rel(g1, g0):.1e}  tuned shapes {B.tuned_shapes()}")
+    assert abs(L1 / L0 - 1) < 1e-9
+    assert _rel(g1, g0) < 1e-5
