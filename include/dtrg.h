@@ -81,11 +81,22 @@ typedef struct {
                                  2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates */
     int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
                                  (64 x 64, 128 x 128, and 256 x 128 for the bf16-plane precisions)
-                                 and split-K factor (1..32) of the MFMA kernels on a scratch output
-                                 and keep the fastest for that shape (a table shared by all plans of
-                                 the process); 0: fixed heuristic.  Default 0 */
+                                 and split-K factor (the least one that keeps every FP32
+                                 accumulation chain at 4096 products or fewer, then the powers of two
+                                 above it up to 32) of the MFMA kernels on a scratch output and keep
+                                 the fastest for that shape (a table shared by all plans of the
+                                 process); 0: fixed heuristic.  Default 0 */
     int profile;              /* 1: time the chi^7 join contractions with HIP events on the plan's
                                  stream (read with dtrg_plan_profile); default 0 */
+    double checkpoint_gib;    /* device memory (GiB) the plan may spend keeping forward-pass
+                                 intermediates that the backward pass would otherwise recompute:
+                                 first each step's half-environments and normalised Gram (FP64),
+                                 then, from the last step back, each step's first projection and
+                                 join in the layouts their adjoints read.  What does not fit is
+                                 recomputed in the backward pass (0: recompute everything, the
+                                 least memory).  Results do not depend on it.  A batch divides it
+                                 among its plans in proportion to their instances.  Finite, >= 0;
+                                 default 64 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */

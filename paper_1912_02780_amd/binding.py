@@ -31,7 +31,7 @@ EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "d
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("autotune", c_int), ("profile", c_int)]
+                ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double)]
 
 
 class StepInfo(ctypes.Structure):

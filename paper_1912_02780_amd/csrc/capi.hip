@@ -38,6 +38,8 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE(o.max_subspace_iters >= 1, DTRG_EINVAL, "max_subspace_iters must be >= 1");
     DTRG_REQUIRE(o.block_size >= 0 && o.block_size <= kJacobiMax, DTRG_EINVAL, "block_size out of range [0, 96]");
     DTRG_REQUIRE(o.autotune == 0 || o.autotune == 1, DTRG_EINVAL, "autotune must be 0 or 1");
+    DTRG_REQUIRE(o.checkpoint_gib >= 0.0 && std::isfinite(o.checkpoint_gib), DTRG_EINVAL,
+                 "checkpoint_gib must be finite and >= 0");
 }
 
 void validate_sizes(int D, int chi, int n_steps) {
@@ -46,12 +48,15 @@ void validate_sizes(int D, int chi, int n_steps) {
     DTRG_REQUIRE(n_steps >= 1 && n_steps <= 62, DTRG_EINVAL, "n_steps out of range [1, 62]");
 }
 
-std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const dtrg_options* opt) {
+// share: the fraction of the checkpoint budget this plan may use (a batch divides it)
+std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const dtrg_options* opt,
+                                     double share = 1.0) {
     validate_sizes(D, chi, n_steps);
     std::unique_ptr<dtrg_plan> P(new dtrg_plan());
     dtrg_default_options(&P->opt);
     if (opt) P->opt = *opt;
     validate_options(P->opt);
+    P->ck_budget = (dtrg::i64)std::min(P->opt.checkpoint_gib * share * 1073741824.0, 9.0e18);
     P->prec = prec_of(P->opt.contract);
     P->D = D; P->chi = chi; P->nsteps = n_steps; P->nb = nb;
     plan_setup(P.get());
@@ -182,6 +187,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->block_size = 0;
     o->autotune = 0;
     o->profile = 0;
+    o->checkpoint_gib = 64.0;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -337,7 +343,8 @@ dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_step
             Bt->members[group_of[chi_host[i]]].push_back(i);
         }
         for (size_t g = 0; g < order.size(); ++g) {
-            Bt->plans.push_back(make_plan(D, order[g], n_steps, (int)Bt->members[g].size(), opt));
+            Bt->plans.push_back(make_plan(D, order[g], n_steps, (int)Bt->members[g].size(), opt,
+                                          (double)Bt->members[g].size() / n_inst));
             Bt->idx.emplace_back();
             Bt->idx.back().alloc(Bt->members[g].size());
             DTRG_HIP(hipMemcpy(Bt->idx.back().p, Bt->members[g].data(), Bt->members[g].size() * sizeof(int),

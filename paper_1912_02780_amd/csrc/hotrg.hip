@@ -41,8 +41,10 @@ void for_each_buf(const dtrg_plan& P, F f) {
         for (auto* b : v) f(b->mem.p, b->mem.bytes());
     }
     for (auto& st : P.steps) {
-        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam};
+        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam, &st.Ak, &st.Bk, &st.Gk};
         for (auto* b : v) f(b->p, b->bytes());
+        f(st.P1Tk.mem.p, st.P1Tk.mem.bytes());
+        f(st.Q2bk.mem.p, st.Q2bk.mem.bytes());
     }
 }
 
@@ -214,11 +216,32 @@ void gram(Ctx& c, const DevBuf<double>& A, const DevBuf<double>& B, DevBuf<doubl
 
 // Gram of step input T (checkpoint), normalised: TA, TB, A, B, then G in Gw with its trace in
 // sc(k, 2).  Shared by the forward pass and the backward recompute.
+// TA and TB, the two layouts of the step input that the half-environments contract
+void step_operands_TA_TB(Ctx& c, const StepCk& st) {
+    dtrg_plan* P = c.P;
+    const int X = st.sh.X, Y = st.sh.Y;
+    permute_checked(P, st.T, P->TA.p, P->TA.bs, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, nullptr, c.s);
+    permute_checked(P, st.T, P->TB.p, P->TB.bs, pd4(X, X, Y, Y, 0, 2, 1, 3), 1.0, nullptr, c.s);
+}
+
+// copy A, B and the normalised Gram of a step into its kept buffers (save) or back (!save)
+void keep_gram(Ctx& c, const StepCk& st, bool save) {
+    dtrg_plan* P = c.P;
+    const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n;
+    const DevBuf<double>* w[3] = {&P->A, &P->B, &P->Gw};
+    const DevBuf<double>* k[3] = {&st.Ak, &st.Bk, &st.Gk};
+    const int rows[3] = {X * X, X * X, n}, cols[3] = {Y * Y, Y * Y, n};
+    for (int i = 0; i < 3; ++i) {
+        const DevBuf<double>& src = save ? *w[i] : *k[i];
+        const DevBuf<double>& dst = save ? *k[i] : *w[i];
+        copy2d(src.p, cols[i], src.bs, dst.p, cols[i], dst.bs, rows[i], cols[i], P->nb, c.s);
+    }
+}
+
 void gram_of_step(Ctx& c, const StepCk& st, int k) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n;
-    permute_checked(P, st.T, P->TA.p, P->TA.bs, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, nullptr, c.s);
-    permute_checked(P, st.T, P->TB.p, P->TB.bs, pd4(X, X, Y, Y, 0, 2, 1, 3), 1.0, nullptr, c.s);
+    step_operands_TA_TB(c, st);
     half_env(c, P->TA, P->A, X, Y);
     half_env(c, P->TB, P->B, X, Y);
     gram(c, P->A, P->B, P->Gw, X, Y);
@@ -251,15 +274,18 @@ struct Lds {
 };
 
 // forward operands of a step: Wt [(alpha,b)][a], Tp [(y,i,j)][a], Tb [(z,m)][(b,j)], UT [beta][(i,m)]
-// (for the backward also Wt2 [a][(alpha,b)], Tb2 [(j,b)][(z,m)], TpT [a][(y,i,j)], Us [(i,m)][beta])
-void prep_operands(Ctx& c, const StepCk& st, const OpSet& o, bool backward) {
+// (for the backward also Wt2 [a][(alpha,b)], Tb2 [(j,b)][(z,m)], TpT [a][(y,i,j)], Us [(i,m)][beta];
+// a backward that does not recompute the first projection and the join skips Wt, Tp and Tb)
+void prep_operands(Ctx& c, const StepCk& st, const OpSet& o, bool backward, bool forward_ops = true) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n, b = st.sh.b;
     const Lds l(st.sh);
     const Prec pr = o.pr;
-    permute_op(P, pr, st.U, o.Wt, pd3(X, X, b, 2, 1, 0), 1, l.Wt, nullptr, c.s);
-    permute_op(P, pr, st.T, o.Tp, pd4(X, X, Y, Y, 2, 1, 3, 0), 1, l.Tp, nullptr, c.s);
-    permute_op(P, pr, st.T, o.Tb, pd4(X, X, Y, Y, 3, 1, 0, 2), 2, l.Tb, nullptr, c.s);
+    if (forward_ops) {
+        permute_op(P, pr, st.U, o.Wt, pd3(X, X, b, 2, 1, 0), 1, l.Wt, nullptr, c.s);
+        permute_op(P, pr, st.T, o.Tp, pd4(X, X, Y, Y, 2, 1, 3, 0), 1, l.Tp, nullptr, c.s);
+        permute_op(P, pr, st.T, o.Tb, pd4(X, X, Y, Y, 3, 1, 0, 2), 2, l.Tb, nullptr, c.s);
+    }
     if (!backward) {
         PermDesc u;
         u.rank = 2; u.in_dims[0] = n; u.in_dims[1] = b; u.perm[0] = 1; u.perm[1] = 0;
@@ -554,6 +580,41 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, bool mixed)
     return v;
 }
 
+// Forward intermediates kept for the backward pass, within P->ck_budget bytes: first the FP64
+// half-environments and Gram of every step (from the last step back), then the transposed first
+// projection and join of each step (from the last step back).  Steps that do not fit recompute
+// them in the backward pass.
+void alloc_kept(dtrg_plan* P) {
+    const int nb = P->nb;
+    i64 left = P->ck_budget;
+    const int ns = (int)P->steps.size();
+    for (int k = ns - 1; k >= 0; --k) {
+        StepCk& st = P->steps[k];
+        const i64 X = st.sh.X, Y = st.sh.Y, n = st.sh.n;
+        const i64 bytes = (i64)nb * (2 * X * X * Y * Y + n * n) * 8;
+        if (bytes > left) continue;
+        st.Ak.alloc_inst(nb, X * X * Y * Y);
+        st.Bk.alloc_inst(nb, X * X * Y * Y);
+        st.Gk.alloc_inst(nb, n * n);
+        st.keep_gram = true;
+        left -= bytes;
+    }
+    for (int k = ns - 1; k >= 0; --k) {
+        StepCk& st = P->steps[k];
+        const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
+        const Lds l(st.sh);
+        const i64 X = st.sh.X, Y = st.sh.Y;
+        const int np = prec_planes(o.pr), esz = o.pr == Prec::F64 ? 8 : (o.pr == Prec::F32 ? 4 : 2);
+        const i64 e1 = X * Y * l.P1T, e2 = X * X * l.Q2b;
+        const i64 bytes = (i64)np * nb * (pad8(e1) + pad8(e2)) * esz;
+        if (bytes > left) continue;
+        st.P1Tk.alloc(o.pr, nb, e1);
+        st.Q2bk.alloc(o.pr, nb, e2);
+        st.keep_join = true;
+        left -= bytes;
+    }
+}
+
 void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
     const i64 D4 = (i64)P->D * P->D * P->D * P->D;
@@ -614,6 +675,7 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         st.U.alloc_inst(nb, (i64)n * b);
         st.lam.alloc_inst(nb, b);
     }
+    alloc_kept(P);
 }
 
 // -------------------------------------------------------------------------------------------
@@ -872,14 +934,18 @@ void plan_forward(dtrg_plan* P, Mode mode) {
                             P->sc(k - 1, 1), c.s);
         }
         gram_of_step(c, st, k);
+        if (st.keep_gram) keep_gram(c, st, true);
         if (c.adaptive()) check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
         const StepCk* warm = (k >= 3) ? &P->steps[k - 3] : nullptr;
         eigensolve(c, st, k, warm);
         // projection (in the step's contraction format; the output T' is FP64)
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
+        const Lds l(st.sh);
         prep_operands(c, st, o, false);
         proj1(c, st, o);
+        if (st.keep_join) transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, st.P1Tk, l.P1T);
         join(c, st, o);
+        if (st.keep_join) transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, st.Q2bk, l.Q2b);
         proj3(c, st, o, P->Tn);
         // c_k = |T'|, L += 2^-k ln c_k, 1/c_k
         norm2(P->Tn.p, P->Tn.bs, (i64)K * K * Y * Y, nb, P->sc(k, 0), P->S, c.s, P->ws);
@@ -920,18 +986,22 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         //   Tpb [beta][(alpha,y,z)] and Tpb2 [(alpha,y,z)][beta]  (from Tbar [y][z][alpha][beta])
         permute_op(P, pr, P->Tbar, o.Tpb, pd4(Y, Y, K, K, 3, 2, 0, 1), 3, l.Tpb, P->sc(k, 1), c.s);
         permute_op(P, pr, P->Tbar, o.Tpb2, pd4(Y, Y, K, K, 2, 0, 1, 3), 1, l.Tpb2, P->sc(k, 1), c.s);
-        // recompute P1 (X1) and the join (X2); transposed copies P1T [(b,j)][(alpha,y,i)] (X3) and
-        // Q2b [(i,m)][(alpha,y,z)] (X1, once P1 is consumed)
-        prep_operands(c, st, o, true);
-        proj1(c, st, o);
-        transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, o.X3, l.P1T);
-        join(c, st, o);
-        transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, o.X1, l.Q2b);
+        // P1T [(b,j)][(alpha,y,i)] and Q2b [(i,m)][(alpha,y,z)]: kept by the forward pass, or
+        // recomputed: P1 (X1) and the join (X2), transposed into X3 and X1 (once P1 is consumed)
+        prep_operands(c, st, o, true, !st.keep_join);
+        const OpBuf& P1T = st.keep_join ? st.P1Tk : o.X3;
+        const OpBuf& Q2b = st.keep_join ? st.Q2bk : o.X1;
+        if (!st.keep_join) {
+            proj1(c, st, o);
+            transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, o.X3, l.P1T);
+            join(c, st, o);
+            transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, o.X1, l.Q2b);
+        }
         // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2b[(i,m)][(alpha,y,z)] Tpb[beta][(alpha,y,z)]
         {
             GemmOp g;
             g.M = n; g.N = K; g.K = K * Y * Y;
-            set_ops(g, op_of(o.X1, l.Q2b), op_of(o.Tpb, l.Tpb));
+            set_ops(g, op_of(Q2b, l.Q2b), op_of(o.Tpb, l.Tpb));
             g.C = P->Ub.p; g.c_bs2 = P->Ub.bs;
             g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
             c.run(g, pr, Out::F64);
@@ -953,7 +1023,7 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         {
             GemmOp g;
             g.M = Y * X; g.N = X * Y; g.K = K * Y * X;
-            set_ops(g, op_of(o.X1, l.QbB), op_of(o.X3, l.P1T));
+            set_ops(g, op_of(o.X1, l.QbB), op_of(P1T, l.P1T));
             g.C = P->Tbar2.p; g.c_bs2 = P->Tbar2.bs;
             g.rmap = IdxMap::split(X, 1, (i64)Y * Y);
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
@@ -997,8 +1067,13 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.beta = 1.0;
             c.run(g, pr, Out::F64);
         }
-        // recompute the step's half-environments and normalised Gram from its checkpoint
-        gram_of_step(c, st, k);
+        // the step's half-environments and normalised Gram: kept, or recomputed from its checkpoint
+        if (st.keep_gram) {
+            step_operands_TA_TB(c, st);
+            keep_gram(c, st, false);
+        } else {
+            gram_of_step(c, st, k);
+        }
         // eigensolver adjoint -> G_bar, in Gt[(a,b)][(c,d)]
         eig_adjoint(c, st, k);
         // Abar'[a][j][b][k] = sum_{(c,d)} Gt[(a,b)][(c,d)] B[(c,d)][(j,k)]   (into Tn)

@@ -76,6 +76,11 @@ struct StepCk {
     DevBuf<double> T;      // normalised input [X][X][Y][Y] (checkpoint)
     DevBuf<double> U;      // [n][b] eigenvectors / Ritz vectors (first K columns: w)
     DevBuf<double> lam;    // b eigenvalues / Ritz values, descending
+    // forward intermediates kept for the backward pass (within the plan's checkpoint budget)
+    bool keep_gram = false;          // Ak, Bk, Gk: half-environments and normalised Gram
+    bool keep_join = false;          // P1Tk, Q2bk: first projection and join, transposed
+    DevBuf<double> Ak, Bk, Gk;
+    OpBuf P1Tk, Q2bk;
     // schedule (written by adaptive passes, replayed by fixed passes)
     int iters = 0;         // subspace iterations
     int cheb = 0;          // degree of the complement expansion (0: none)
@@ -114,6 +119,7 @@ struct dtrg_plan {
     dtrg::DevBuf<double> ctab;  // Chebyshev DCT tables of degree 8, 16, ..., 1024
     bool ctab_ready = false;
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
+    dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     bool mixed() const { return prec != dtrg::Prec::F64; }
     // HIP-event timing of the chi^7 join contractions (adaptive passes with opt.profile)
     std::vector<hipEvent_t> ev_pool;

@@ -81,12 +81,21 @@ def test_default_options():
     class Options(ctypes.Structure):
         _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
                     ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int)]
+                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int),
+                    ("checkpoint_gib", ctypes.c_double)]
 
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))
     assert o.contract == 0 and o.eig_broadening == 1e-12 and o.max_subspace_iters == 60
-    assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1
+    assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1 and o.checkpoint_gib == 64.0
+    # a checkpoint budget that is negative or not finite is rejected before any allocation
+    lib.dtrg_plan_create.restype = ctypes.c_int
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    plan = ctypes.c_void_p()
+    for bad in (-1.0, float("nan"), float("inf")):
+        o.checkpoint_gib = bad
+        assert lib.dtrg_plan_create(2, 4, 3, ctypes.byref(o), ctypes.byref(plan)) == 1 and plan.value is None
+        assert b"checkpoint_gib" in lib.dtrg_last_error()
 
 
 def test_batch_argument_validation_without_device_work():

@@ -354,3 +354,21 @@ def test_gpu_autotuned_plan(B):
     _say(f"    lnZ rel {abs(L1 / L0 - 1):.1e}  T0bar rel {_rel(g1, g0):.1e}  tuned shapes {B.tuned_shapes()}")
     assert abs(L1 / L0 - 1) < 1e-9
     assert _rel(g1, g0) < 1e-5
+
+
+@pytest.mark.parametrize("contract", ["fp64", "bf16x6"])
+def test_gpu_checkpoint_budget_does_not_change_results(B, contract):
+    """Keeping the forward intermediates (Gram, first projection, join) for the backward pass, for
+    every step, for some steps or for none, gives bit-identical ln Z and gradients."""
+    from paper_1912_02780_amd import inputs as I
+    T0 = I.random_d4_T0(3)
+    dT0 = I.random_d4_T0(4)
+    _say(f"[gpu] checkpoint budget {contract}")
+    L0, g0, d0, p0 = _gpu(B, T0, 20, 8, dT0, contract=contract, checkpoint_gib=0.0)
+    b0 = p0.device_bytes()
+    for gib in (64.0, 0.05):
+        L1, g1, d1, p1 = _gpu(B, T0, 20, 8, dT0, contract=contract, checkpoint_gib=gib)
+        _say(f"    budget {gib} GiB: plan {p1.device_bytes() / 2**20:.1f} MiB (none kept: {b0 / 2**20:.1f} MiB)")
+        assert p1.device_bytes() > b0
+        assert L1 == L0 and d1 == d0
+        assert np.array_equal(g1, g0)
