@@ -33,11 +33,7 @@ i64 map_max(const IdxMap& m, i64 count) {
 }
 
 // K tile of the kernel that runs a configuration (split-K chunks are multiples of it)
-int bk_of(Prec prec, int tile) {
-    const int np = prec_planes(prec);
-    if (np == 1) return 16;
-    return (np == 2 && tile == 3) ? 64 : 32;
-}
+int bk_of(Prec prec, int) { return prec_planes(prec) == 1 ? 16 : 32; }
 
 int out_code(Prec prec, Out out) {
     if (out == Out::F64) return 0;
@@ -145,6 +141,15 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     a.alpha = op.alpha; a.beta = op.beta;
     a.batch = op.batch; a.batch2 = op.batch2;
     a.W = nullptr;
+    {
+        // 16-byte epilogue stores of bf16 planes: every aligned group of 8 output columns must be
+        // contiguous and start on a multiple of 8 elements in every plane and batch element
+        auto al8 = [](i64 x) { return x % 8 == 0; };
+        const bool cols = op.cmap.s0 == 1 && (op.cmap.div >= (1LL << 62) || al8(op.cmap.div)) && al8(op.cmap.s1);
+        const bool rows = al8(op.rmap.s0) && al8(op.rmap.s1);
+        a.vec_out = out == Out::Split && cols && rows && al8(op.c_bs) && al8(op.c_bs2) && al8(op.c_ps) &&
+                    (uintptr_t)op.C % 16 == 0;
+    }
 
     const GemmCfg cfg = gemm_resolve(prec, op);
     DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || (cfg.tile == 3 && split), DTRG_EINVAL,

@@ -53,6 +53,8 @@ struct KArgs {
     int splits, k_chunk, batch, batch2;
     int tiles_m, tiles_n;
     void* W;  // split-K partials [batch2 * batch * splits][M][N], accumulator type
+    int vec_out;  // bf16-plane output whose aligned groups of 8 columns are 16-byte aligned and
+                  // contiguous in every plane (the epilogue then stores 16 bytes per lane)
 };
 
 // offset of batch element zb = z2 * batch + z1 in an operand with strides (bs, bs2)

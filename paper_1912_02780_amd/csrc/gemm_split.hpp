@@ -8,32 +8,90 @@
 //   NP = 3 (6 products):  a2 b0 + a1 b1 + a0 b2 + a1 b0 + a0 b1 + a0 b0   (below FP32 rounding)
 //
 // Both operands are stored K-contiguous (row r of plane q at base + q * ps + r * ld, ld a multiple
-// of 8 elements, 16-byte aligned), so every global load and every LDS store moves 16 bytes
-// (8 bf16 along K) and the MFMA fragments (8 consecutive K values per lane) are single 16-byte LDS
-// reads; there is no conversion work in the K loop.  K beyond the operand's extent is masked to
-// zero in the last tile, so row padding is never read as data.
+// of 8 elements, 16-byte aligned), so the K tiles (32 bf16 = 64 bytes per row and plane) go from
+// global memory straight into LDS with 16-byte direct-to-LDS loads (no registers, no LDS store
+// instructions), double-buffered so that the next tile is in flight while the current one is
+// multiplied, and the MFMA fragments (8 consecutive K values per lane) are single 16-byte LDS
+// reads; there is no conversion work in the K loop.  Elements at or beyond the end of K in the
+// last tile are zeroed in LDS, so row padding is never read as data.
 //
-// Tiles: BM x BN per block, WGM x WGN waves of (BM / WGM) x (BN / WGN) outputs each, BK per K tile,
-// one or two LDS stages (with one stage the next tile waits in registers).  The epilogue is the
-// shared one: alpha scaling, optional beta, two-level scatter, and output as
-// FP64, FP32 or NP bf16 planes.
+// Tiles: BM x BN per block, WGM x WGN waves of (BM / WGM) x (BN / WGN) outputs each.  The epilogue
+// applies alpha (and beta), scatters through the two-level index maps and writes FP64, FP32 or NP
+// bf16 planes; bf16 planes whose aligned groups of 8 columns are contiguous go out as 16-byte
+// stores through a per-wave LDS slab.
 #pragma once
 
 #include "gemm_kernels.hpp"
 
 namespace dtrg {
 
-template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int BK, int STAGES, int TAG>
+// Epilogue of a bf16-plane output with 16-byte stores.  A wave passes its WM x WN accumulator
+// tile through its own LDS slab of 16 rows (stride WN + 4 floats) one row of MFMA tiles at a time;
+// each lane then reads 8 consecutive columns of a row, splits them into the OUT planes and stores
+// 16 bytes per plane (element by element at the ragged right edge).  Only the wave's own lanes
+// touch its slab, and LDS instructions of a wave complete in order, so no barrier is needed.
+template <int OUT, int TM, int TN>
+__device__ inline void store_planes_vec(const KArgs& p, int zb, const v4f (&acc)[TM][TN], int r0, int c0, float* slab) {
+    constexpr int WN = TN * 16, SLD = WN + 4, GPR = WN / 8;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const i64 cbase = batch_off(p, zb, p.c_bs, p.c_bs2);
+    __bf16* C = (__bf16*)p.C;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) slab[(4 * lk + r) * SLD + j * 16 + li] = acc[i][j][r];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int g = lane; g < 16 * GPR; g += 64) {
+            const int row = g / GPR, cg = (g % GPR) * 8;
+            const int gm = r0 + i * 16 + row, gn = c0 + cg;
+            if (gm < p.M && gn < p.N) {
+                float v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = (float)(p.alpha * (double)slab[row * SLD + cg + t]);
+                const i64 off = cbase + idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
+                if (gn + 8 <= p.N) {
+#pragma unroll
+                    for (int q = 0; q < OUT; ++q) {
+                        v8bf h;
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            h[t] = (__bf16)v[t];
+                            v[t] -= (float)h[t];
+                        }
+                        *(v8bf*)(C + q * p.c_ps + off) = h;
+                    }
+                } else {
+                    for (int t = 0; t < 8 && gn + t < p.N; ++t) put_out<OUT>(p.C, off + t, p.c_ps, (double)v[t], 0.0);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
+
+// Position (in bf16 elements) of element k of row r in a 64-byte LDS row: the four 16-byte chunks
+// of row r are permuted by r / 2 mod 4, which spreads the 16 rows x 4 chunks read by one
+// ds_read_b128 of the MFMA fragment loads over all banks (measured on gfx950; a row stride of 80
+// or 72 bytes, or the permutation by r mod 4, leaves two-way conflicts).
+__device__ inline int lds_pos(int r, int k) { return ((((k >> 3) ^ (r >> 1)) & 3) << 3) | (k & 7); }
+
+template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int TAG>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
-    constexpr int NT = 64 * WGM * WGN;
-    constexpr int KP = BK + 8;   // row stride in LDS (bf16), padded
+    constexpr int BK = 32, NW = WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
-    constexpr int CPR = BK / 8;                      // 16-byte chunks per tile row
-    constexpr int ACH = (BM * CPR + NT - 1) / NT;    // chunks per thread per plane
-    constexpr int BCH = (BN * CPR + NT - 1) / NT;
-    static_assert(TM >= 1 && TN >= 1 && BK % 32 == 0, "bad tile");
-    __shared__ __bf16 As[STAGES][NP][BM][KP];
-    __shared__ __bf16 Bs[STAGES][NP][BN][KP];
+    constexpr int AI = NP * BM / 16, BI = NP * BN / 16;   // 1 KiB direct-to-LDS loads per stage
+    static_assert(TM >= 1 && TN >= 1 && AI % NW == 0 && BI % NW == 0, "bad tile");
+    // two stages in distinct arrays, so that the compiler can tell the stage being filled from the
+    // one being read and does not wait for the loads in flight before reading
+    __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM][BK], As1[NP][BM][BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN][BK], Bs1[NP][BN][BK];
+    static_assert(16 * (WN + 4) * 4 * ((NW + 1) / 2) <= (int)sizeof(As0), "epilogue slabs must fit");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
@@ -52,96 +110,120 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    v8bf ra[NP][ACH], rb[NP][BCH];
-    auto chunk = [&](const __bf16* X, i64 ld, i64 ps, int q, int row, int nrows, int gk) -> v8bf {
-        v8bf v = {};
-        if (row < nrows && gk < kend) {
-            v = *(const v8bf*)(X + q * ps + (i64)row * ld + gk);
-            if (gk + 8 > kend) {
+    // Direct-to-LDS loads: one instruction of a wave fills 16 rows x 64 bytes of one plane, lane
+    // l writing the 16 bytes at l * 16, i.e. row l / 4, chunk position l % 4, which holds the
+    // chunk of logical index (l % 4) ^ (row / 2 mod 4).  Rows beyond M (N) are clamped to the last
+    // row (they only feed outputs that are never stored); chunks at or beyond kend load any valid
+    // chunk and are zeroed in LDS afterwards (zero_tail).
+    const int lr = lane >> 2, lp = lane & 3;
+    auto issue = [&](auto& As, auto& Bs, int k0) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    if (gk + t >= kend) v[t] = (__bf16)0.f;
-            }
+        for (int e = 0; e < AI / NW; ++e) {
+            const int g = wave + NW * e, q = g / (BM / 16), rb = g % (BM / 16);
+            const int row = rb * 16 + lr;
+            const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
+            const __bf16* src = A + q * p.a_ps + (i64)min(m0 + row, p.M - 1) * p.lda + (gk < kend ? gk : kbeg);
+            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&As[q][rb * 16][0], 16, 0, 0);
         }
-        return v;
+#pragma unroll
+        for (int e = 0; e < BI / NW; ++e) {
+            const int g = wave + NW * e, q = g / (BN / 16), rb = g % (BN / 16);
+            const int row = rb * 16 + lr;
+            const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
+            const __bf16* src = B + q * p.b_ps + (i64)min(n0 + row, p.N - 1) * p.ldb + (gk < kend ? gk : kbeg);
+            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&Bs[q][rb * 16][0], 16, 0, 0);
+        }
     };
-    auto load = [&](int k0) {
+    // zero the elements k >= kend of a stage holding the last, partial K tile (after its loads landed)
+    auto zero_tail = [&](auto& As, auto& Bs, int k0) {
+        const int kv = kend - k0;
+        for (int idx = tid; idx < NP * (BM + BN) * BK; idx += 64 * NW) {
+            const int k = idx % BK, rr = idx / BK, q = rr / (BM + BN), row = rr % (BM + BN);
+            if (k < kv) continue;
+            if (row < BM) As[q][row][lds_pos(row, k)] = (__bf16)0.f;
+            else Bs[q][row - BM][lds_pos(row - BM, k)] = (__bf16)0.f;
+        }
+    };
+    const int li = lane & 15, lk = lane >> 4;
+    auto compute = [&](auto& As, auto& Bs) {
+        v8bf a[NP][TM], b[NP][TN];
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
 #pragma unroll
-            for (int e = 0; e < ACH; ++e) {
-                const int c = tid + e * NT, m = c / CPR, kc = (c % CPR) * 8;
-                ra[q][e] = m < BM ? chunk(A, p.lda, p.a_ps, q, m0 + m, p.M, k0 + kc) : v8bf{};
+            for (int i = 0; i < TM; ++i) {
+                const int r = wm0 + i * 16 + li;
+                a[q][i] = *(const v8bf*)&As[q][r][lds_pos(r, 8 * lk)];
             }
 #pragma unroll
-            for (int e = 0; e < BCH; ++e) {
-                const int c = tid + e * NT, n = c / CPR, kc = (c % CPR) * 8;
-                rb[q][e] = n < BN ? chunk(B, p.ldb, p.b_ps, q, n0 + n, p.N, k0 + kc) : v8bf{};
+            for (int j = 0; j < TN; ++j) {
+                const int r = wn0 + j * 16 + li;
+                b[q][j] = *(const v8bf*)&Bs[q][r][lds_pos(r, 8 * lk)];
             }
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (NP == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+                } else {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+                }
+            }
     };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-#pragma unroll
-            for (int e = 0; e < ACH; ++e) {
-                const int c = tid + e * NT, m = c / CPR, kc = (c % CPR) * 8;
-                if (m < BM) *(v8bf*)&As[buf][q][m][kc] = ra[q][e];
-            }
-#pragma unroll
-            for (int e = 0; e < BCH; ++e) {
-                const int c = tid + e * NT, n = c / CPR, kc = (c % CPR) * 8;
-                if (n < BN) *(v8bf*)&Bs[buf][q][n][kc] = rb[q][e];
-            }
-        }
+    // every wave's loads have landed and are visible to the block
+    auto landed = [&]() {
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     };
 
-    const int ntiles = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-    if (ntiles > 0) {
-        load(kbeg);
-        store(0);
+    // K tiles t = 0 .. nt-1; tile t in stage t % 2; the loads of tile t + 1 are in flight while
+    // tile t is multiplied
+    const int nt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    const bool ragged = (kend - kbeg) % BK != 0;
+    if (nt > 0) {
+        issue(As0, Bs0, kbeg);
+        landed();
+        if (nt == 1 && ragged) {
+            zero_tail(As0, Bs0, kbeg);
+            __syncthreads();
+        }
     }
-    __syncthreads();
-    const int li = lane & 15, lk = lane >> 4;
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = STAGES == 2 ? (t & 1) : 0;
-        if (t + 1 < ntiles) load(kbeg + (t + 1) * BK);
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 32) {
-            v8bf a[NP][TM], b[NP][TN];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i) a[q][i] = *(const v8bf*)&As[buf][q][wm0 + i * 16 + li][kk + 8 * lk];
-#pragma unroll
-                for (int j = 0; j < TN; ++j) b[q][j] = *(const v8bf*)&Bs[buf][q][wn0 + j * 16 + li][kk + 8 * lk];
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    if constexpr (NP == 2) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-                    } else {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-                    }
-                }
+    for (int t = 0; t < nt; t += 2) {
+        if (t + 1 < nt) issue(As1, Bs1, kbeg + (t + 1) * BK);
+        compute(As0, Bs0);
+        landed();
+        if (t + 1 >= nt) break;
+        if (t + 2 == nt && ragged) {
+            zero_tail(As1, Bs1, kbeg + (t + 1) * BK);
+            __syncthreads();
         }
-        if (t + 1 < ntiles) {
-            if (STAGES == 1) __syncthreads();   // every wave is done reading the stage
-            store(STAGES == 2 ? (buf ^ 1) : 0);
+        if (t + 2 < nt) issue(As0, Bs0, kbeg + (t + 2) * BK);
+        compute(As1, Bs1);
+        landed();
+        if (t + 3 == nt && ragged) {
+            zero_tail(As0, Bs0, kbeg + (t + 2) * BK);
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // epilogue: D row of accumulator register r of lane l is 4 (l / 16) + r, column l % 16
+    if constexpr (OUT >= 2) {
+        if (p.vec_out && p.splits == 1) {
+            float* slab = (wave < (NW + 1) / 2 ? (float*)&As0[0][0][0] : (float*)&As1[0][0][0]) +
+                          (wave % ((NW + 1) / 2)) * 16 * (WN + 4);
+            store_planes_vec<OUT>(p, zb, acc, m0 + wm0, n0 + wn0, slab);
+            return;
+        }
+    }
     if (p.splits > 1) {
         float* W = (float*)p.W + (i64)blockIdx.z * p.M * p.N;
 #pragma unroll
@@ -167,19 +249,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 }
 
 // Tile shapes: 1 = 64 x 64 (4 waves of 32 x 32), 2 = 128 x 128 (4 waves of 64 x 64),
-// 3 = 256 x 128 (8 waves of 64 x 64).  LDS: at most 120 KiB.
+// 3 = 256 x 128 (8 waves of 64 x 64).  LDS: two stages of NP x (BM + BN) x 64 bytes (at most
+// 144 KiB).
 template <int NP, int OUT, int TAG>
 void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
-    if (tile == 3) {
-        if constexpr (NP == 2)
-            hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, 64, 1, TAG>), grid, dim3(512), 0, s, a);
-        else
-            hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, 32, 1, TAG>), grid, dim3(512), 0, s, a);
-    } else if (tile == 2) {
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, 32, 2, TAG>), grid, dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 2, 2, 32, 2, 0>), grid, dim3(256), 0, s, a);
-    }
+    if (tile == 3)
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, TAG>), grid, dim3(512), 0, s, a);
+    else if (tile == 2)
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, TAG>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 2, 2, 0>), grid, dim3(256), 0, s, a);
 }
 
 // tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
