@@ -3,8 +3,11 @@
 // * jacobi_eig: one workgroup holds an n x n symmetric matrix and its eigenvector accumulator in
 //   LDS (n <= 96: 2 x 96 x 97 doubles = 146 KiB of the 160 KiB LDS) and runs cyclic Jacobi in the
 //   round-robin (Berger table) order: in every round n/2 disjoint index pairs are rotated at once,
-//   rows first, then columns.  A pair is rotated while |a_pq| > 1e-16 sqrt(|a_pp a_qq|) (or above
-//   an absolute floor), which keeps small eigenvalues to high relative accuracy.
+//   rows first, then columns, each pass with one thread per row (or column) element of a pair, so
+//   that a wave touches consecutive LDS words.  A pair is rotated while |a_pq| > 1e-16
+//   sqrt(|a_pp a_qq|) (or above an absolute floor), which keeps small eigenvalues to high relative
+//   accuracy.  (One pass over the disjoint 2 x 2 blocks of pair rows and pair columns, with one
+//   barrier less per round, measured 40% slower: its LDS accesses scatter over the banks.)
 // * chol_inverse: Cholesky of a (shifted) b x b Gram in LDS and the inverse of its triangular
 //   factor, for CholeskyQR of the subspace block.
 // * element-wise helpers for Ritz residuals, column normalisation, the broadened inverse gaps of
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
             // need a rotation are compacted into slots 0..nact-1
             if (tid < 64) {
                 int p = 0, q = 0, active = 0;
-                double c = 1.0, s = 0.0;
+                double c = 1.0, sn = 0.0;
                 if (tid < m / 2) {
                     if (tid == 0) { p = m - 1; q = round; }
                     else { p = (round + tid) % (m - 1); q = (round - tid + (m - 1)) % (m - 1); }
@@ -78,40 +81,44 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
                             if (fabs(theta) > 1e150) t = 0.5 / theta;
                             else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
                             c = 1.0 / sqrt(1.0 + t * t);
-                            s = t * c;
+                            sn = t * c;
                             active = 1;
                         }
                     }
                 }
                 const unsigned long long mask = __ballot(active);
                 const int slot = __popcll(mask & ((1ull << tid) - 1ull));
-                if (active) { rp[slot] = p; rq[slot] = q; rc[slot] = c; rs[slot] = s; }
+                if (active) { rp[slot] = p; rq[slot] = q; rc[slot] = c; rs[slot] = sn; }
                 if (tid == 0) { nact = __popcll(mask); nrot += nact; }
             }
             __syncthreads();
             const int na = nact;
             if (na > 0) {
-                // rows:  row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q
-                for (int idx = tid; idx < na * n; idx += JT) {
-                    const int i = idx / n, j = idx % n;
+                // rows: row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q.  Slot i of group g
+                // (128 threads each) covers the row pair, one column per thread
+                const int g = tid >> 7, l = tid & 127;
+                for (int i = g; i < na; i += JT / 128) {
                     const int p = rp[i], q = rq[i];
-                    const double c = rc[i], s = rs[i];
-                    const double ap = A[p * JLD + j], aq = A[q * JLD + j];
-                    A[p * JLD + j] = c * ap - s * aq;
-                    A[q * JLD + j] = s * ap + c * aq;
+                    const double c = rc[i], sn = rs[i];
+                    for (int j = l; j < n; j += 128) {
+                        const double ap = A[p * JLD + j], aq = A[q * JLD + j];
+                        A[p * JLD + j] = c * ap - sn * aq;
+                        A[q * JLD + j] = sn * ap + c * aq;
+                    }
                 }
                 __syncthreads();
-                // columns of A and of V
-                for (int idx = tid; idx < na * n; idx += JT) {
-                    const int i = idx / n, r = idx % n;
+                // columns of A and of V, one row per thread
+                for (int i = g; i < na; i += JT / 128) {
                     const int p = rp[i], q = rq[i];
-                    const double c = rc[i], s = rs[i];
-                    const double ap = A[r * JLD + p], aq = A[r * JLD + q];
-                    A[r * JLD + p] = c * ap - s * aq;
-                    A[r * JLD + q] = s * ap + c * aq;
-                    const double vp = V[r * JLD + p], vq = V[r * JLD + q];
-                    V[r * JLD + p] = c * vp - s * vq;
-                    V[r * JLD + q] = s * vp + c * vq;
+                    const double c = rc[i], sn = rs[i];
+                    for (int r = l; r < n; r += 128) {
+                        const double ap = A[r * JLD + p], aq = A[r * JLD + q];
+                        A[r * JLD + p] = c * ap - sn * aq;
+                        A[r * JLD + q] = sn * ap + c * aq;
+                        const double vp = V[r * JLD + p], vq = V[r * JLD + q];
+                        V[r * JLD + p] = c * vp - sn * vq;
+                        V[r * JLD + q] = sn * vp + c * vq;
+                    }
                 }
             }
             __syncthreads();
@@ -134,10 +141,10 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     if (tid == 0 && sweeps_out) atomicMax(sweeps_out, sweep);
 }
 
-// Lower Cholesky factor L of S + shift I in LDS, then Rinv = (L^T)^{-1} (upper) to global.
 // Lower Cholesky factor L of (S + shift I) in LDS (right-looking, rank-1 trailing updates in
 // parallel), then X = L^{-1} by the same elimination applied to the identity (row k of X is
-// final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.
+// final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.  The
+// updates run on a 16 x 16 thread grid, one barrier per column (or row).
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, i64 s_bs, int b,
                                                        double shift_rel, double* __restrict__ Rinv, i64 r_bs,
                                                        int* flag) {
@@ -163,34 +170,44 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
     const double shift = shift_rel * tr;
     for (int i = tid; i < b; i += CT) L[i * JLD + i] += shift;
     __syncthreads();
-    for (int k = 0; k < b; ++k) {
+    // Cholesky, right-looking, one barrier per column: phase k takes the pivot and column k as phase
+    // k-1 left them, applies the rank-1 update with the scaled column to the trailing lower
+    // triangle, and writes back the scaled column k-1, which phase k no longer reads
+    const int tx = tid & 15, ty = tid >> 4;
+    double dprev = 1.0, rprev = 1.0;
+    for (int k = 0; k <= b; ++k) {
+        if (k > 0) {
+            for (int i = k + tid; i < b; i += CT) L[i * JLD + k - 1] *= rprev;
+            if (tid == 0) L[(k - 1) * JLD + k - 1] = dprev;
+        }
+        if (k == b) break;
         double d = L[k * JLD + k];
         if (!(d > 0.0) || !isfinite(d)) {
             if (tid == 0) flag[0] |= 2;
             d = 1e-300;
         }
-        const double dk = sqrt(d);
-        // column k of L below the diagonal; lanes read L[k][k] before it is overwritten
-        for (int i = k + 1 + tid; i < b; i += CT) L[i * JLD + k] /= dk;
-        __syncthreads();
-        if (tid == 0) L[k * JLD + k] = dk;
-        const int rem = b - k - 1;
-        for (int idx = tid; idx < rem * rem; idx += CT) {
-            const int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
-            if (j <= i) L[i * JLD + j] -= L[i * JLD + k] * L[j * JLD + k];
+        const double dk = sqrt(d), rdk = 1.0 / dk;
+        for (int i = k + 1 + ty; i < b; i += 16) {
+            const double lik = L[i * JLD + k] * rdk;
+            for (int j = k + 1 + tx; j <= i; j += 16) L[i * JLD + j] -= lik * (L[j * JLD + k] * rdk);
         }
+        dprev = dk;
+        rprev = rdk;
         __syncthreads();
     }
-    // X = L^{-1}: for k = 0..b-1, scale row k by 1/L[k][k], then remove it from the rows below
-    for (int k = 0; k < b; ++k) {
+    // X = L^{-1}, one barrier per row: phase k removes row k, scaled by 1 / L[k][k], from the rows
+    // below and writes back the scaled row k-1, which phase k no longer reads
+    double inv_prev = 1.0;
+    for (int k = 0; k <= b; ++k) {
+        if (k > 0)
+            for (int j = tid; j < k; j += CT) Xs[(k - 1) * JLD + j] *= inv_prev;
+        if (k == b) break;
         const double inv = 1.0 / L[k * JLD + k];
-        for (int j = tid; j <= k; j += CT) Xs[k * JLD + j] *= inv;
-        __syncthreads();
-        const int rem = b - k - 1;
-        for (int idx = tid; idx < rem * (k + 1); idx += CT) {
-            const int i = k + 1 + idx / (k + 1), j = idx % (k + 1);
-            Xs[i * JLD + j] -= L[i * JLD + k] * Xs[k * JLD + j];
+        for (int i = k + 1 + ty; i < b; i += 16) {
+            const double lik = L[i * JLD + k];
+            for (int j = tx; j <= k; j += 16) Xs[i * JLD + j] -= lik * (Xs[k * JLD + j] * inv);
         }
+        inv_prev = inv;
         __syncthreads();
     }
     // Rinv = (L^{-1})^T
