@@ -10,7 +10,10 @@ Workloads (--workload):
       Reported beside it: the roofline of the chi^7 join contraction from HIP events the library
       records on its stream inside the timed region, the error of ln Z / N and of the gradient
       against the FP64 oracle's stored result, and the FP64 NumPy oracle timed on this host on a
-      bounded sample of the same workload.
+      bounded sample of the same workload.  The plan keeps the forward intermediates the backward
+      pass would otherwise recompute (the library default, a 64 GiB budget); the same pass with one
+      checkpoint per RG step and the recompute inside the backward step (checkpoint_gib = 0) is
+      timed beside it and reported under "recompute_in_step".
   batch256
       256 Ising temperatures beta_i = 0.30 + 0.30 i / 255 with chi_i = (32, 16, 24)[i mod 3], 30 steps
       each, forward + backward to d(lnZ/N)/dbeta for every instance, replayed from one captured HIP
@@ -23,9 +26,12 @@ Workloads (--workload):
       eigensolver; value = RG-steps per second.  Reported beside it: peak device memory, the
       eigen-adjoint broadening, and d(lnZ/N)/dbeta against central finite differences of the FP64
       path (step 1e-5, and its Richardson extrapolation with step 5e-6) and the FP64 gradient.
+      The backward stores one checkpoint per RG step and recomputes inside the step
+      (checkpoint_gib = 0); the pass with the forward intermediates kept (64 GiB budget) is timed
+      beside it under "with_kept_intermediates".
 
     python bench.py [--workload chi48|batch256|ising_chi64] [--steps K] [--warmup W]
-                    [--contract fp32|fp64|bf16x3] [--no-cpu-baseline]
+                    [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--no-cpu-baseline]
 """
 
 from __future__ import annotations
@@ -142,10 +148,25 @@ def roofline(launches, ms, flops, contract, kernel, traffic=None):
     return out
 
 
+def _time_passes(B, torch, plan, T0, dT0, warmup, steps):
+    """Wall time per forward + backward pass of an existing plan (after `warmup` passes)."""
+    for _ in range(warmup):
+        B.dtrg_plan_forward(plan, T0)
+        B.dtrg_hotrg_backward(plan, 1.0, dT0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.dtrg_plan_forward(plan, T0)
+        B.dtrg_hotrg_backward(plan, 1.0, dT0)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
 def bench_chi48(args, B, I, torch, np, dev):
     D, chi, n = 4, args.chi, args.n_steps
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
-    opts = B.default_options(contract=args.contract, profile=1)
+    ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
+    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -179,11 +200,21 @@ def bench_chi48(args, B, I, torch, np, dev):
         "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
                                 f"{n} RG steps, forward + backward to dlnZ/dT0"),
                    "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64",
-                   "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
+                   "checkpoint_gib": ck, "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
                              traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None),
         **err,
     }
+    plan.close()
+    if ck > 0:
+        # the same pass with one checkpoint per RG step, recomputing inside the backward step
+        _progress("timing the pass with recompute inside the step")
+        opts0 = B.default_options(contract=args.contract, checkpoint_gib=0.0)
+        plan0 = B.dtrg_plan_create(D, chi, n, opts0, dev)
+        sec = _time_passes(B, torch, plan0, T0, None, 1, max(1, min(args.steps, 3)))
+        out["recompute_in_step"] = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
+                                    "plan_device_GB": plan0.device_bytes() / 1e9, "checkpoint_gib": 0.0}
+        plan0.close()
     if not args.no_cpu_baseline:
         _progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(chi, n, D)
@@ -199,7 +230,8 @@ def bench_batch256(args, B, I, torch, np, dev):
     T0s = torch.from_numpy(np.stack([I.ising_T0(b) for b in betas])).to(dev)
     dT0s = torch.from_numpy(np.stack([I.ising_dT0_dbeta(b) for b in betas])).to(dev)
     T0bar = torch.empty_like(T0s)
-    opts = B.default_options(contract=args.contract, autotune=1, profile=1)
+    ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
+    opts = B.default_options(contract=args.contract, autotune=1, profile=1, checkpoint_gib=ck)
     batch = B.dtrg_batch_create(2, [int(c) for c in chis], n, opts, dev)
     # adaptive runs: the first records the schedule and tunes the tiles, the second is profiled
     t0 = time.perf_counter()
@@ -262,7 +294,7 @@ def bench_batch256(args, B, I, torch, np, dev):
         "config": {"workload": ("256 Ising temperatures beta in [0.30, 0.60] (uniform grid), chi (32,16,24)[i mod 3] "
                                 "(86/85/85), 30 RG steps each, forward + backward to dlnZ/dbeta, replayed from one "
                                 "HIP graph"),
-                   "n_inst": n_inst, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": 1,
+                   "n_inst": n_inst, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": 1, "checkpoint_gib": ck,
                    "device_GB": batch.device_bytes() / 1e9},
         "adaptive_run_s": t_adaptive, "first_adaptive_run_s (incl. tuning)": t_first,
         "sequential_fp64_single_instance": {"value": seq_value, "unit": "RG-steps/s",
@@ -283,7 +315,8 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     free0, total = torch.cuda.mem_get_info(dev)
     T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
     dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
-    opts = B.default_options(contract=args.contract, profile=1)
+    ck = 0.0 if args.checkpoint_gib is None else args.checkpoint_gib
+    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -308,6 +341,15 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     plan_bytes = plan.device_bytes()
     peak_torch = torch.cuda.max_memory_allocated(dev)
     plan.close()
+    kept = None
+    if ck == 0.0:
+        # the same pass with the forward intermediates kept for the backward (64 GiB budget)
+        _progress("timing the pass with the forward intermediates kept")
+        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0), dev)
+        sec = _time_passes(B, torch, plan_k, T0, dT0, 1, 1)
+        kept = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
+                "plan_device_GB": plan_k.device_bytes() / 1e9, "checkpoint_gib": 64.0}
+        plan_k.close()
     # FP64 path: gradient and finite differences of ln Z / N in beta
     p64 = B.dtrg_plan_create(D, chi, n, None, dev)
     L64 = B.dtrg_plan_forward(p64, T0)
@@ -326,7 +368,9 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         "metric": "HOTRG fwd+bwd RG-steps/s, Ising at beta_c, chi=64 (split-bf16 contractions, FP64 eigensolver)",
         "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": f"2D Ising at beta={beta}, HOTRG chi={chi}, {n} RG steps, forward + backward to dlnZ/dbeta",
-                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12},
+                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12,
+                   "checkpoint_gib": ck, "checkpoint": ("one checkpoint per RG step, recompute inside the step"
+                                                        if ck == 0.0 else "forward intermediates kept within the budget")},
         "peak_hbm": {"plan_device_GB": plan_bytes / 1e9, "torch_max_allocated_GB": peak_torch / 1e9,
                      "hipMemGetInfo_used_increase_GB": (free0 - free_min) / 1e9, "total_GB": total / 1e9},
         "lnZ_per_site": L, "lnZ_fp64": L64, "lnZ_rel_err_vs_fp64": abs(L / L64 - 1),
@@ -335,6 +379,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         "fp64_ad_rel_err_vs_fd_richardson": abs(db64 / rich - 1), "rel_err_vs_fp64_ad": abs(db / db64 - 1),
         "energy_rel_err_vs_onsager": abs(db / u_ex - 1),
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)"),
+        **({"with_kept_intermediates": kept} if kept else {}),
     }
 
 
@@ -351,6 +396,9 @@ def main():
     ap.add_argument("--n-steps", type=int, default=None, help="chi48: 24 by default; ising_chi64: 30")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--checkpoint-gib", type=float, default=None,
+                    help="device memory for kept forward intermediates (chi48 and batch256: 64 by default; "
+                         "ising_chi64: 0, one checkpoint per RG step)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
