@@ -7,10 +7,11 @@
 //     C + batch * c_bs + (r / rdiv) * rs1 + (r % rdiv) * rs0 + (c / cdiv) * cs1 + (c % cdiv) * cs0,
 // which is enough to emit every intermediate directly in the layout its consumer reads.
 //
-// Tiling: 256 threads = 4 waves (2 x 2); block tile BM x BN x BK staged through LDS with one
-// register-prefetched stage (one barrier per K tile); each wave owns (BM/2) x (BN/2) outputs as
-// 16 x 16 MFMA tiles.  FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  The kernel
-// for operands split into bf16 planes is in gemm_split.hpp.
+// Tiling: WGM x WGN waves (2 x 2 by default; FP64 runs 128 x 128 tiles on 4 x 2 waves so that two
+// waves share each SIMD); block tile BM x BN x BK staged through LDS with one register-prefetched
+// stage (one barrier per K tile); each wave owns (BM/WGM) x (BN/WGN) outputs as 16 x 16 MFMA tiles.
+// FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  The kernel for operands split into
+// bf16 planes is in gemm_split.hpp.
 #pragma once
 
 #include "common.hpp"
@@ -118,11 +119,12 @@ template <> struct Mfma4<float> {
 };
 
 // TAG only distinguishes kernel symbols in profiles (7, 8, 9: the three chi^7 contractions).
-template <class T, class TO, int BM, int BN, int BK, bool AKM, bool BKM, int TAG>
-__global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
+// WGM x WGN waves per block, each owning (BM / WGM) x (BN / WGN) outputs.
+template <class T, class TO, int BM, int BN, int BK, bool AKM, bool BKM, int TAG, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_mfma4_kernel(KArgs p) {
     typedef typename Mfma4<T>::acc_t acc_t;
-    constexpr int NT = 256;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
     constexpr int PAD = 1;   // odd row stride: the transposing LDS stores of K-contiguous tiles spread over banks
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
     int tmi, tni;
     if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
     const int m0 = tmi * BM, n0 = tni * BN;
@@ -236,23 +238,24 @@ __global__ __launch_bounds__(256) void gemm_mfma4_kernel(KArgs p) {
             }
 }
 
-template <class T, class TO, int BM, int BN, int BK, int TAG>
+template <class T, class TO, int BM, int BN, int BK, int TAG, int WGM, int WGN>
 void launch_mfma4_t(const KArgs& a, dim3 grid, bool akm, bool bkm, hipStream_t s) {
-    if (akm && bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, true, TAG>), grid, dim3(256), 0, s, a);
-    else if (akm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, false, TAG>), grid, dim3(256), 0, s, a);
-    else if (bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, true, TAG>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, false, TAG>), grid, dim3(256), 0, s, a);
+    const dim3 blk(64 * WGM * WGN);
+    if (akm && bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, true, TAG, WGM, WGN>), grid, blk, 0, s, a);
+    else if (akm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, true, false, TAG, WGM, WGN>), grid, blk, 0, s, a);
+    else if (bkm) hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, true, TAG, WGM, WGN>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((gemm_mfma4_kernel<T, TO, BM, BN, BK, false, false, TAG, WGM, WGN>), grid, blk, 0, s, a);
 }
 
 // tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
-template <class T, class TO, int BM, int BN, int BK>
+template <class T, class TO, int BM, int BN, int BK, int WGM = 2, int WGN = 2>
 void launch_mfma4(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStream_t s) {
     if constexpr (BM == 128) {
-        if (tag == 7) { launch_mfma4_t<T, TO, BM, BN, BK, 7>(a, grid, akm, bkm, s); return; }
-        if (tag == 8) { launch_mfma4_t<T, TO, BM, BN, BK, 8>(a, grid, akm, bkm, s); return; }
-        if (tag == 9) { launch_mfma4_t<T, TO, BM, BN, BK, 9>(a, grid, akm, bkm, s); return; }
+        if (tag == 7) { launch_mfma4_t<T, TO, BM, BN, BK, 7, WGM, WGN>(a, grid, akm, bkm, s); return; }
+        if (tag == 8) { launch_mfma4_t<T, TO, BM, BN, BK, 8, WGM, WGN>(a, grid, akm, bkm, s); return; }
+        if (tag == 9) { launch_mfma4_t<T, TO, BM, BN, BK, 9, WGM, WGN>(a, grid, akm, bkm, s); return; }
     }
-    launch_mfma4_t<T, TO, BM, BN, BK, 0>(a, grid, akm, bkm, s);
+    launch_mfma4_t<T, TO, BM, BN, BK, 0, WGM, WGN>(a, grid, akm, bkm, s);
 }
 
 // per-precision launchers (one translation unit each, compiled in parallel)
