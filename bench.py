@@ -206,7 +206,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         **err,
     }
     plan.close()
-    if ck > 0:
+    if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
         opts0 = B.default_options(contract=args.contract, checkpoint_gib=0.0)
@@ -342,7 +342,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     peak_torch = torch.cuda.max_memory_allocated(dev)
     plan.close()
     kept = None
-    if ck == 0.0:
+    if ck == 0.0 and not args.no_policy_compare:
         # the same pass with the forward intermediates kept for the backward (64 GiB budget)
         _progress("timing the pass with the forward intermediates kept")
         plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0), dev)
@@ -396,6 +396,8 @@ def main():
     ap.add_argument("--n-steps", type=int, default=None, help="chi48: 24 by default; ising_chi64: 30")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-policy-compare", action="store_true",
+                    help="skip the pass timed with the other checkpoint policy (for profiles of one policy)")
     ap.add_argument("--checkpoint-gib", type=float, default=None,
                     help="device memory for kept forward intermediates (chi48 and batch256: 64 by default; "
                          "ising_chi64: 0, one checkpoint per RG step)")

@@ -94,11 +94,14 @@ enum class Out { F64 = 0, F32 = 1, Split = 2 };
 int prec_planes(Prec p);   // 1, or the number of bf16 planes
 
 // Tile configuration of one contraction: tile 0 = automatic, 1 = 64 x 64, 2 = 128 x 128,
-// 3 = 256 x 128 (bf16 planes only); splits 0 = automatic split-K.
+// 3 = 256 x 128, 4 = 64 x 64 on waves of 16 full-width rows (3 and 4: bf16 planes only);
+// splits 0 = automatic split-K.
 struct GemmCfg {
     int tile = 0;
     int splits = 0;
 };
+inline int tile_rows(int tile) { return tile == 3 ? 256 : (tile == 2 ? 128 : 64); }
+inline int tile_cols(int tile) { return (tile == 2 || tile == 3) ? 128 : 64; }
 
 // One (batched) contraction C[z](r, c) = alpha * sum_k A[z](r, k) B[z](c, k) + beta * C[z](r, c).
 //   A stored as [M][K] (a_kmajor = false: A[m * lda + k]) or [K][M] (a_kmajor = true: A[k * lda + m]).

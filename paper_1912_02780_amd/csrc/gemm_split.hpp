@@ -86,12 +86,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     constexpr int BK = 32, NW = WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
     constexpr int AI = NP * BM / 16, BI = NP * BN / 16;   // 1 KiB direct-to-LDS loads per stage
-    static_assert(TM >= 1 && TN >= 1 && AI % NW == 0 && BI % NW == 0, "bad tile");
+    static_assert(TM >= 1 && TN >= 1, "bad tile");
     // two stages in distinct arrays, so that the compiler can tell the stage being filled from the
     // one being read and does not wait for the loads in flight before reading
     __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM][BK], As1[NP][BM][BK];
     __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN][BK], Bs1[NP][BN][BK];
-    static_assert(16 * (WN + 4) * 4 * ((NW + 1) / 2) <= (int)sizeof(As0), "epilogue slabs must fit");
+    // the 16-byte plane epilogue needs a slab of 16 x (WN + 4) floats per wave in As0 and As1
+    constexpr bool kVecEpilogue = 16 * (WN + 4) * 4 * ((NW + 1) / 2) <= (int)sizeof(As0);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
@@ -118,16 +119,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     const int lr = lane >> 2, lp = lane & 3;
     auto issue = [&](auto& As, auto& Bs, int k0) {
 #pragma unroll
-        for (int e = 0; e < AI / NW; ++e) {
+        for (int e = 0; e < (AI + NW - 1) / NW; ++e) {
             const int g = wave + NW * e, q = g / (BM / 16), rb = g % (BM / 16);
+            if (AI % NW != 0 && g >= AI) break;   // wave-uniform
             const int row = rb * 16 + lr;
             const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
             const __bf16* src = A + q * p.a_ps + (i64)min(m0 + row, p.M - 1) * p.lda + (gk < kend ? gk : kbeg);
             __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&As[q][rb * 16][0], 16, 0, 0);
         }
 #pragma unroll
-        for (int e = 0; e < BI / NW; ++e) {
+        for (int e = 0; e < (BI + NW - 1) / NW; ++e) {
             const int g = wave + NW * e, q = g / (BN / 16), rb = g % (BN / 16);
+            if (BI % NW != 0 && g >= BI) break;   // wave-uniform
             const int row = rb * 16 + lr;
             const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
             const __bf16* src = B + q * p.b_ps + (i64)min(n0 + row, p.N - 1) * p.ldb + (gk < kend ? gk : kbeg);
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     }
 
     // epilogue: D row of accumulator register r of lane l is 4 (l / 16) + r, column l % 16
-    if constexpr (OUT >= 2) {
+    if constexpr (OUT >= 2 && kVecEpilogue) {
         if (p.vec_out && p.splits == 1) {
             float* slab = (wave < (NW + 1) / 2 ? (float*)&As0[0][0][0] : (float*)&As1[0][0][0]) +
                           (wave % ((NW + 1) / 2)) * 16 * (WN + 4);
@@ -249,11 +252,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 }
 
 // Tile shapes: 1 = 64 x 64 (4 waves of 32 x 32), 2 = 128 x 128 (4 waves of 64 x 64),
-// 3 = 256 x 128 (8 waves of 64 x 64).  LDS: two stages of NP x (BM + BN) x 64 bytes (at most
-// 144 KiB).
+// 3 = 256 x 128 (8 waves of 64 x 64), 4 = 64 x 64 as 4 waves of 16 rows x 64 columns (outputs of at
+// most 64 columns: every wave covers all of them).  LDS: two stages of NP x (BM + BN) x 64 bytes (at
+// most 144 KiB).
 template <int NP, int OUT, int TAG>
 void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
-    if (tile == 3)
+    if (tile == 4)
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 4, 1, 0>), grid, dim3(256), 0, s, a);
+    else if (tile == 3)
         hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, TAG>), grid, dim3(512), 0, s, a);
     else if (tile == 2)
         hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, TAG>), grid, dim3(256), 0, s, a);

@@ -4,7 +4,8 @@
 // layouts) is met in an adaptive pass with tuning enabled, every admissible configuration is run
 // on a scratch output (beta = 0, so the real output is untouched), timed with HIP events on the
 // caller's stream, and the fastest is kept in a process-wide table.  The configurations are the
-// tiles {64 x 64, 128 x 128, and 256 x 128 for bf16 planes} times the split-K counts {s0, then the
+// tiles {64 x 64, 128 x 128, and for bf16 planes 256 x 128 and, for outputs of at most 64 columns,
+// 64 x 64 on full-width waves} times the split-K counts {s0, then the
 // powers of two above it up to 32}, s0 being the least count that keeps FP32 accumulation chains
 // short (1 for FP64 and for short K).  Later contractions of that shape (including fixed passes
 // that are being captured into a graph) take the table entry without timing anything.
@@ -70,10 +71,11 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
     const i64 nz = (i64)op.batch * op.batch2;
     const int minsp = gemm_chain_splits(prec, op);
     std::vector<GemmCfg> cands;
-    for (int tile = 1; tile <= (np > 1 ? 3 : 2); ++tile) {
+    for (int tile = 1; tile <= (np > 1 ? 4 : 2); ++tile) {
         if (tile == 2 && std::max(op.M, op.N) < 128) continue;
         if (tile == 3 && op.M < 256) continue;
-        const int BMt = tile == 3 ? 256 : (tile == 2 ? 128 : 64), BNt = tile == 1 ? 64 : 128;
+        if (tile == 4 && op.N > 64) continue;
+        const int BMt = tile_rows(tile), BNt = tile_cols(tile);
         const i64 tiles = (i64)((op.M + BMt - 1) / BMt) * ((op.N + BNt - 1) / BNt) * nz;
         // the chain floor is always a candidate (the untuned path would take it too); larger
         // split counts only within the trial limits

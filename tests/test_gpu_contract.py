@@ -1,7 +1,8 @@
 """The MFMA contraction kernel (diagnostic entry point of the C ABI) against float64 matmul.
 
 Covers every precision, the four operand layouts, ragged edges (K not a multiple of 8: the bf16
-planes' masked last chunk), every tile shape and split-K.  FP64 must agree to rounding; FP32 to
+planes' masked last chunk), every tile shape (with the tile for outputs of at most 64 columns and
+the short, wide case computed as its transpose) and split-K.  FP64 must agree to rounding; FP32 to
 single precision; split-bf16 with two planes (three products) to the ~2^-17 relative error of the
 two-plane representation and the dropped x1*y1 term; with three planes (six products) to single
 precision.
@@ -60,3 +61,13 @@ def test_contract(B, prec, akm, bkm, shape):
 @pytest.mark.parametrize("layout", [(False, False), (True, True)])
 def test_contract_large_tile(B, prec, layout):
     test_contract(B, prec, layout[0], layout[1], (8200, 4100, 70))
+
+
+# at most 64 output columns and many rows: the full-width-wave tile (ragged in M, N, K); and the
+# transposed case, at most 64 rows and many columns, which is computed as its transpose on that tile
+# (with split-K for the long K)
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("layout", [(False, False), (True, True)])
+@pytest.mark.parametrize("shape", [(3001, 45, 333), (50, 2100, 5003)])
+def test_contract_tall_and_wide(B, prec, layout, shape):
+    test_contract(B, prec, layout[0], layout[1], shape)
