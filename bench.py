@@ -65,7 +65,7 @@ TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_027
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 40 launches per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "00d5eb6c136f29be629b1ef5cb22e5e8164449182848e32e5a460bbbe843ace8", "fetch_kib": 4112175.1, "write_kib": 1493623.8},
+    ("chi48", "bf16x6"): {"sources_sha256": "7a68ab4df3c6c76fae2d1a4241445809b6e671a2bba5fc0a710affc847d69f72", "fetch_kib": 4126870.4, "write_kib": 1493609.0},
 }
 
 
