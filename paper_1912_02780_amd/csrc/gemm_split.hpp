@@ -61,7 +61,7 @@ __device__ inline void store_planes_vec(const KArgs& p, int zb, const v4f (&acc)
                             h[t] = (__bf16)v[t];
                             v[t] -= (float)h[t];
                         }
-                        *(v8bf*)(C + q * p.c_ps + off) = h;
+                        __builtin_nontemporal_store(h, (v8bf*)(C + q * p.c_ps + off));
                     }
                 } else {
                     for (int t = 0; t < 8 && gn + t < p.N; ++t) put_out<OUT>(p.C, off + t, p.c_ps, (double)v[t], 0.0);

@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in
             vec_t v;
 #pragma unroll
             for (int e = 0; e < V; ++e) v[e] = t[tw * V + e][cc];
-            *(vec_t*)(out + (i64)c * ld_out + r) = v;
+            __builtin_nontemporal_store(v, (vec_t*)(out + (i64)c * ld_out + r));
         } else {
 #pragma unroll
             for (int e = 0; e < V; ++e)
