@@ -84,7 +84,15 @@ struct IdxMap {
     static IdxMap split(i64 div, i64 s1, i64 s0) { IdxMap m; m.div = div; m.s1 = s1; m.s0 = s0; return m; }
 };
 
-__host__ __device__ inline i64 idx_off(const IdxMap& m, i64 i) { return (i / m.div) * m.s1 + (i % m.div) * m.s0; }
+__host__ __device__ inline i64 idx_off(const IdxMap& m, i64 i) {
+    if (i < m.div) return i * m.s0;   // every index of a linear map; the first block of a split one
+    if (m.div <= 0xffffffffLL && i <= 0xffffffffLL) {
+        // 32-bit division (a 64-bit one is a long instruction sequence on the GPU)
+        const unsigned q = (unsigned)i / (unsigned)m.div, r = (unsigned)i - q * (unsigned)m.div;
+        return (i64)q * m.s1 + (i64)r * m.s0;
+    }
+    return (i / m.div) * m.s1 + (i % m.div) * m.s0;
+}
 
 // Arithmetic of a contraction, which is also the storage format of its operands: FP64, FP32, or
 // FP32 values carried as 2 (BF16X3: three bf16 products) or 3 (BF16X6: six products) bf16 planes.

@@ -49,8 +49,13 @@ __device__ inline void store_planes_vec(const KArgs& p, int zb, const v4f (&acc)
             const int gm = r0 + i * 16 + row, gn = c0 + cg;
             if (gm < p.M && gn < p.N) {
                 float v[8];
+                if (p.alpha == 1.0) {   // exact: (float)(1.0 * (double)x) == x
 #pragma unroll
-                for (int t = 0; t < 8; ++t) v[t] = (float)(p.alpha * (double)slab[row * SLD + cg + t]);
+                    for (int t = 0; t < 8; ++t) v[t] = slab[row * SLD + cg + t];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) v[t] = (float)(p.alpha * (double)slab[row * SLD + cg + t]);
+                }
                 const i64 off = cbase + idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
                 if (gn + 8 <= p.N) {
 #pragma unroll
