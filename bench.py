@@ -64,8 +64,8 @@ TRAFFIC_FACTORS = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_02780_amd/csrc/gemm.hip",
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
-    # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 40 launches per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "7a68ab4df3c6c76fae2d1a4241445809b6e671a2bba5fc0a710affc847d69f72", "fetch_kib": 4126870.4, "write_kib": 1493609.0},
+    # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 20 launches of that size per pass
+    ("chi48", "bf16x6"): {"sources_sha256": "3b83be200a0e34bd3ec6c9910c944a5b5580ade8fa8b5220de3b3f95a7830f7e", "fetch_kib": 5313004.3, "write_kib": 1697940.6},
 }
 
 

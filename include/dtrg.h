@@ -243,8 +243,9 @@ const char* dtrg_last_error(void);
  * with A(r, k) = A_dev[r * lda + k] (a_kmajor = 0) or A_dev[k * lda + r] (a_kmajor = 1) and
  * B(c, k) = B_dev[c * ldb + k] (b_kmajor = 0) or B_dev[k * ldb + c] (b_kmajor = 1).
  * precision DTRG_FP64: A, B, C are double.  DTRG_FP32 / DTRG_BF16X3 / DTRG_BF16X6: A, B are float
- * and C is double if out_f64 else float (the split precisions first split A and B into K-contiguous
- * bf16 planes in a scratch buffer the library keeps per thread).  Device pointers; enqueued on `stream`, not synchronised.
+ * and C is double if out_f64 else float (the split precisions first split A and B into bf16 planes,
+ * each in its own layout, K-contiguous or K-major, in a scratch buffer the library keeps per thread).
+ * Device pointers; enqueued on `stream`, not synchronised.
  */
 dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
                           const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,

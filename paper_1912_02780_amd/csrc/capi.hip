@@ -516,16 +516,21 @@ dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev,
             g.A = A_dev; g.lda = lda; g.a_kmajor = a_kmajor != 0;
             g.B = B_dev; g.ldb = ldb; g.b_kmajor = b_kmajor != 0;
         } else {
-            // FP32 operands split into K-contiguous bf16 planes (rows padded to 8) in a scratch buffer
-            const i64 ld = ((i64)K + 7) / 8 * 8;
-            const i64 a_ps = (i64)M * ld, b_ps = (i64)N * ld;
+            // FP32 operands split into bf16 planes in their own layout (K-contiguous or K-major,
+            // rows padded to 8 elements) in a scratch buffer
+            auto r8 = [](i64 x) { return (x + 7) / 8 * 8; };
+            const i64 lda_p = r8(a_kmajor ? M : K), ldb_p = r8(b_kmajor ? N : K);
+            const i64 a_ps = (i64)(a_kmajor ? K : M) * lda_p, b_ps = (i64)(b_kmajor ? K : N) * ldb_p;
             planes.ensure((size_t)((np * (a_ps + b_ps) * 2 + 7) / 8) + 2);
             __bf16* pa = (__bf16*)planes.p;
             __bf16* pb = pa + np * a_ps;
-            split_matrix((const float*)A_dev, lda, a_kmajor != 0, M, K, pa, ld, a_ps, np, s);
-            split_matrix((const float*)B_dev, ldb, b_kmajor != 0, N, K, pb, ld, b_ps, np, s);
-            g.A = pa; g.lda = ld; g.a_ps = a_ps;
-            g.B = pb; g.ldb = ld; g.b_ps = b_ps;
+            // a K-major matrix is split as the row-major K x M matrix it is stored as
+            if (a_kmajor) split_matrix((const float*)A_dev, lda, false, K, M, pa, lda_p, a_ps, np, s);
+            else split_matrix((const float*)A_dev, lda, false, M, K, pa, lda_p, a_ps, np, s);
+            if (b_kmajor) split_matrix((const float*)B_dev, ldb, false, K, N, pb, ldb_p, b_ps, np, s);
+            else split_matrix((const float*)B_dev, ldb, false, N, K, pb, ldb_p, b_ps, np, s);
+            g.A = pa; g.lda = lda_p; g.a_ps = a_ps; g.a_kmajor = a_kmajor != 0;
+            g.B = pb; g.ldb = ldb_p; g.b_ps = b_ps; g.b_kmajor = b_kmajor != 0;
         }
         dtrg::gemm(pr, precision == DTRG_FP64 || out_f64 ? Out::F64 : Out::F32, g, s, ws);
         return DTRG_OK;

@@ -124,23 +124,29 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     DTRG_REQUIRE(out != Out::Split || (split && op.beta == 0.0), DTRG_EINVAL,
                  "gemm: split output needs a split contraction and beta = 0");
     if (split) {
-        // K-contiguous planes only: 16-byte aligned rows of at least round8(K) elements
-        DTRG_REQUIRE(!op.a_kmajor && !op.b_kmajor, DTRG_EINVAL, "gemm: split operands must be K-contiguous");
-        DTRG_REQUIRE(op.lda % 8 == 0 && op.ldb % 8 == 0 && op.lda >= round8(op.K) && op.ldb >= round8(op.K),
-                     DTRG_EINVAL, "gemm: split operand rows must be padded to a multiple of 8 elements");
+        // planes with 16-byte aligned rows padded to a multiple of 8 elements: K-contiguous rows of
+        // at least round8(K) elements, or K-major rows of at least round8(M) (round8(N)) elements,
+        // the latter only into FP64 or FP32 outputs
+        DTRG_REQUIRE(op.lda % 8 == 0 && op.ldb % 8 == 0, DTRG_EINVAL,
+                     "gemm: split operand rows must be padded to a multiple of 8 elements");
+        DTRG_REQUIRE(op.lda >= round8(op.a_kmajor ? op.M : op.K) && op.ldb >= round8(op.b_kmajor ? op.N : op.K),
+                     DTRG_EINVAL, "gemm: split operand rows shorter than their padded extent");
+        DTRG_REQUIRE(!(op.a_kmajor || op.b_kmajor) || out != Out::Split, DTRG_EINVAL,
+                     "gemm: K-major split operands need an FP64 or FP32 output");
         DTRG_REQUIRE((op.a_ps | op.b_ps | op.a_bs | op.b_bs | op.a_bs2 | op.b_bs2) % 8 == 0, DTRG_EINVAL,
                      "gemm: split operand strides must be multiples of 8 elements");
         DTRG_REQUIRE(((uintptr_t)op.A | (uintptr_t)op.B) % 16 == 0, DTRG_EINVAL,
                      "gemm: split operands must be 16-byte aligned");
     }
-    const i64 a_row = split ? round8(op.K) : op.K, b_row = a_row;
+    // the kernels read whole 16-byte chunks of split rows: the row extent is padded to 8 elements
+    auto ext = [&](i64 x) { return split ? round8(x) : x; };
     if (op.K > 0 && op.a_cap >= 0) {
-        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (op.M - 1) : (i64)(op.M - 1) * op.lda + (a_row - 1)) +
+        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (ext(op.M) - 1) : (i64)(op.M - 1) * op.lda + (ext(op.K) - 1)) +
                        (i64)(op.batch - 1) * op.a_bs + (i64)(op.batch2 - 1) * op.a_bs2 + (i64)(np - 1) * op.a_ps;
         DTRG_REQUIRE(mx < op.a_cap, DTRG_EINVAL, "gemm: operand A out of bounds");
     }
     if (op.K > 0 && op.b_cap >= 0) {
-        const i64 mx = (op.b_kmajor ? (i64)(op.K - 1) * op.ldb + (op.N - 1) : (i64)(op.N - 1) * op.ldb + (b_row - 1)) +
+        const i64 mx = (op.b_kmajor ? (i64)(op.K - 1) * op.ldb + (ext(op.N) - 1) : (i64)(op.N - 1) * op.ldb + (ext(op.K) - 1)) +
                        (i64)(op.batch - 1) * op.b_bs + (i64)(op.batch2 - 1) * op.b_bs2 + (i64)(np - 1) * op.b_ps;
         DTRG_REQUIRE(mx < op.b_cap, DTRG_EINVAL, "gemm: operand B out of bounds");
     }
@@ -205,7 +211,7 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
             break;
         case Prec::BF16X3:
         case Prec::BF16X6:
-            launch_gemm_split(a, grid, np, oc, cfg.tile, op.tag, s);
+            launch_gemm_split(a, grid, np, oc, cfg.tile, op.tag, op.a_kmajor, op.b_kmajor, s);
             break;
     }
     DTRG_HIP(hipGetLastError());

@@ -261,8 +261,9 @@ void launch_mfma4(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, hipStr
 // per-precision launchers (one translation unit each, compiled in parallel)
 void launch_gemm_f64(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, hipStream_t s);
 void launch_gemm_f32(const KArgs& a, dim3 grid, bool akm, bool bkm, int tag, bool big, bool out_f64, hipStream_t s);
-// split-bf16 planes (gemm_split.hip): np = 2 or 3 planes per operand, out = 0 double, 1 float,
-// 2 / 3 bf16 planes; tile 1 = 64 x 64, 2 = 128 x 128, 3 = 256 x 128
-void launch_gemm_split(const KArgs& a, dim3 grid, int np, int out, int tile, int tag, hipStream_t s);
+// split-bf16 planes (gemm_split*.hip): np = 2 or 3 planes per operand, out = 0 double, 1 float,
+// 2 / 3 bf16 planes; tile as in GemmCfg; akm / bkm: K-major operand (FP64 or FP32 output only)
+void launch_gemm_split(const KArgs& a, dim3 grid, int np, int out, int tile, int tag, bool akm, bool bkm,
+                       hipStream_t s);
 
 }  // namespace dtrg

@@ -86,16 +86,103 @@ typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
 // or 72 bytes, or the permutation by r mod 4, leaves two-way conflicts).
 __device__ inline int lds_pos(int r, int k) { return ((((k >> 3) ^ (r >> 1)) & 3) << 3) | (k & 7); }
 
-template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int TAG>
+// K-major operands (stored X[k][m], m contiguous) keep that layout in LDS: K-tile row k holds the R
+// values m of the tile, its 16-byte chunks permuted by kswz(k) so that the four rows (at one
+// column range) that a transposing fragment read touches, and the four lane groups of a wave, fall
+// on different banks.
+template <int R>
+__device__ inline int kswz_pos(int k, int m) {
+    const int sw = (2 * (k & 3) + 8 * ((k >> 3) & 3)) & (R / 8 - 1);
+    return k * R + ((((m >> 3) ^ sw) & (R / 8 - 1)) << 3) + (m & 7);
+}
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) v4s lds_v4s_t;
+
+// One operand of the contraction (R rows of the block tile, NP planes, KM: K-major storage) in LDS
+// as 32-wide K tiles: loads, tail zeroing and MFMA fragment reads.
+template <int NP, int R, bool KM>
+struct SplitOperand {
+    // Direct-to-LDS loads of K tile k0: instruction g of the block fills 1 KiB of one plane, lane l
+    // the 16 bytes at l * 16.  K-contiguous: 16 rows x 64 bytes; position l % 4 of row l / 4 holds
+    // the chunk of logical index (l % 4) ^ (row / 2 mod 4).  K-major: 1024 / (2 R) K rows of R
+    // values; the position holds the chunk kswz_pos puts there.  Rows beyond the operand are
+    // clamped to its last row (they only feed outputs that are never stored); chunks beyond kend,
+    // and K-major chunks past the row's padded end, load any valid chunk, and kend's tail is zeroed
+    // in LDS afterwards.
+    // (NW waves; a trip count known at compile time keeps the loads in one unrolled block, free to
+    // be scheduled among the MFMAs)
+    template <int NW>
+    __device__ static void issue(const __bf16* X, i64 ld, i64 ps, int rows, int base, __bf16 (&L)[NP][R * 32],
+                                 int k0, int kbeg, int kend, int wave, int lane) {
+        constexpr int NI = NP * R / 16;
+#pragma unroll
+        for (int e = 0; e < (NI + NW - 1) / NW; ++e) {
+            const int g = wave + NW * e;
+            if (NI % NW != 0 && g >= NI) break;   // wave-uniform
+            const int q = g / (R / 16), rb = g % (R / 16);
+            const __bf16* src;
+            if constexpr (!KM) {
+                const int row = rb * 16 + (lane >> 2);
+                const int gk = k0 + 8 * (((lane & 3) ^ (row >> 1)) & 3);
+                src = X + q * ps + (i64)min(base + row, rows - 1) * ld + (gk < kend ? gk : kbeg);
+            } else {
+                const int e = rb * 512 + lane * 8, k = e / R;
+                const int sw = (2 * (k & 3) + 8 * ((k >> 3) & 3)) & (R / 8 - 1);
+                const int m = ((((e % R) >> 3) ^ sw) & (R / 8 - 1)) << 3;
+                const int gk = k0 + k;
+                const int gm = base + m < ((rows + 7) & ~7) ? base + m : 0;
+                src = X + q * ps + (i64)(gk < kend ? gk : kbeg) * ld + gm;
+            }
+            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&L[q][rb * 512], 16, 0, 0);
+        }
+    }
+    // zero the K values at or beyond kv of a stage holding a partial K tile
+    __device__ static void zero_tail(__bf16 (&L)[NP][R * 32], int kv, int tid, int nthr) {
+        for (int idx = tid; idx < NP * R * 32; idx += nthr) {
+            const int q = idx / (R * 32), e = idx % (R * 32);
+            int k;
+            if constexpr (!KM) {
+                const int row = e / 32, pk = e % 32;
+                k = (((pk >> 3) ^ (row >> 1)) & 3) * 8 + (pk & 7);   // lds_pos is an involution per row
+            } else {
+                k = e / R;
+            }
+            if (k >= kv) L[q][e] = (__bf16)0.f;
+        }
+    }
+    // MFMA fragment of plane q for rows rbase .. rbase + 15: lane l holds row rbase + l % 16,
+    // K values 8 (l / 16) .. 8 (l / 16) + 7.  K-major: two ds_read_b64_tr_b16, each of which hands
+    // lane j of a 16-lane group element j of four consecutive K rows (measured on gfx950: of the
+    // 16 lanes' 8-byte chunks, lane j receives element j % 4 of chunks j / 4, j / 4 + 4, ...).
+    __device__ static v8bf frag(const __bf16 (&L)[NP][R * 32], int q, int rbase, int lane) {
+        const int li = lane & 15, lk = lane >> 4;
+        if constexpr (!KM) {
+            const int r = rbase + li;
+            return *(const v8bf*)&L[q][r * 32 + lds_pos(r, 8 * lk)];
+        } else {
+            const int m = rbase + 4 * (li & 3);
+            const int k0 = 8 * lk + (li >> 2);
+            const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s_t*)&L[q][kswz_pos<R>(k0, m)]);
+            const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s_t*)&L[q][kswz_pos<R>(k0 + 4, m)]);
+            const v8s w = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            return __builtin_bit_cast(v8bf, w);
+        }
+    }
+};
+
+template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int TAG, bool AKM = false, bool BKM = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     constexpr int BK = 32, NW = WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
-    constexpr int AI = NP * BM / 16, BI = NP * BN / 16;   // 1 KiB direct-to-LDS loads per stage
     static_assert(TM >= 1 && TN >= 1, "bad tile");
+    typedef SplitOperand<NP, BM, AKM> OpA;
+    typedef SplitOperand<NP, BN, BKM> OpB;
     // two stages in distinct arrays, so that the compiler can tell the stage being filled from the
     // one being read and does not wait for the loads in flight before reading
-    __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM][BK], As1[NP][BM][BK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN][BK], Bs1[NP][BN][BK];
+    __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM * BK], As1[NP][BM * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN * BK], Bs1[NP][BN * BK];
     // the 16-byte plane epilogue needs a slab of 16 x (WN + 4) floats per wave in As0 and As1
     constexpr bool kVecEpilogue = 16 * (WN + 4) * 4 * ((NW + 1) / 2) <= (int)sizeof(As0);
 
@@ -116,41 +203,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // Direct-to-LDS loads: one instruction of a wave fills 16 rows x 64 bytes of one plane, lane
-    // l writing the 16 bytes at l * 16, i.e. row l / 4, chunk position l % 4, which holds the
-    // chunk of logical index (l % 4) ^ (row / 2 mod 4).  Rows beyond M (N) are clamped to the last
-    // row (they only feed outputs that are never stored); chunks at or beyond kend load any valid
-    // chunk and are zeroed in LDS afterwards (zero_tail).
-    const int lr = lane >> 2, lp = lane & 3;
     auto issue = [&](auto& As, auto& Bs, int k0) {
-#pragma unroll
-        for (int e = 0; e < (AI + NW - 1) / NW; ++e) {
-            const int g = wave + NW * e, q = g / (BM / 16), rb = g % (BM / 16);
-            if (AI % NW != 0 && g >= AI) break;   // wave-uniform
-            const int row = rb * 16 + lr;
-            const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
-            const __bf16* src = A + q * p.a_ps + (i64)min(m0 + row, p.M - 1) * p.lda + (gk < kend ? gk : kbeg);
-            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&As[q][rb * 16][0], 16, 0, 0);
-        }
-#pragma unroll
-        for (int e = 0; e < (BI + NW - 1) / NW; ++e) {
-            const int g = wave + NW * e, q = g / (BN / 16), rb = g % (BN / 16);
-            if (BI % NW != 0 && g >= BI) break;   // wave-uniform
-            const int row = rb * 16 + lr;
-            const int gk = k0 + 8 * ((lp ^ (row >> 1)) & 3);
-            const __bf16* src = B + q * p.b_ps + (i64)min(n0 + row, p.N - 1) * p.ldb + (gk < kend ? gk : kbeg);
-            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&Bs[q][rb * 16][0], 16, 0, 0);
-        }
+        OpA::template issue<NW>(A, p.lda, p.a_ps, p.M, m0, As, k0, kbeg, kend, wave, lane);
+        OpB::template issue<NW>(B, p.ldb, p.b_ps, p.N, n0, Bs, k0, kbeg, kend, wave, lane);
     };
     // zero the elements k >= kend of a stage holding the last, partial K tile (after its loads landed)
     auto zero_tail = [&](auto& As, auto& Bs, int k0) {
-        const int kv = kend - k0;
-        for (int idx = tid; idx < NP * (BM + BN) * BK; idx += 64 * NW) {
-            const int k = idx % BK, rr = idx / BK, q = rr / (BM + BN), row = rr % (BM + BN);
-            if (k < kv) continue;
-            if (row < BM) As[q][row][lds_pos(row, k)] = (__bf16)0.f;
-            else Bs[q][row - BM][lds_pos(row - BM, k)] = (__bf16)0.f;
-        }
+        OpA::zero_tail(As, kend - k0, tid, 64 * NW);
+        OpB::zero_tail(Bs, kend - k0, tid, 64 * NW);
     };
     const int li = lane & 15, lk = lane >> 4;
     auto compute = [&](auto& As, auto& Bs) {
@@ -158,15 +218,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int r = wm0 + i * 16 + li;
-                a[q][i] = *(const v8bf*)&As[q][r][lds_pos(r, 8 * lk)];
-            }
+            for (int i = 0; i < TM; ++i) a[q][i] = OpA::frag(As, q, wm0 + i * 16, lane);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int r = wn0 + j * 16 + li;
-                b[q][j] = *(const v8bf*)&Bs[q][r][lds_pos(r, 8 * lk)];
-            }
+            for (int j = 0; j < TN; ++j) b[q][j] = OpB::frag(Bs, q, wn0 + j * 16, lane);
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -226,7 +280,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     // epilogue: D row of accumulator register r of lane l is 4 (l / 16) + r, column l % 16
     if constexpr (OUT >= 2 && kVecEpilogue) {
         if (p.vec_out && p.splits == 1) {
-            float* slab = (wave < (NW + 1) / 2 ? (float*)&As0[0][0][0] : (float*)&As1[0][0][0]) +
+            float* slab = (wave < (NW + 1) / 2 ? (float*)&As0[0][0] : (float*)&As1[0][0]) +
                           (wave % ((NW + 1) / 2)) * 16 * (WN + 4);
             store_planes_vec<OUT>(p, zb, acc, m0 + wm0, n0 + wn0, slab);
             return;
@@ -260,25 +314,48 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 // 3 = 256 x 128 (8 waves of 64 x 64), 4 = 64 x 64 as 4 waves of 16 rows x 64 columns (outputs of at
 // most 64 columns: every wave covers all of them).  LDS: two stages of NP x (BM + BN) x 64 bytes (at
 // most 144 KiB).
-template <int NP, int OUT, int TAG>
+template <int NP, int OUT, int TAG, bool AKM, bool BKM>
 void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
     if (tile == 4)
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 4, 1, 0>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 4, 1, 0, AKM, BKM>), grid, dim3(256), 0, s, a);
     else if (tile == 3)
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, TAG>), grid, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, TAG, AKM, BKM>), grid, dim3(512), 0, s, a);
     else if (tile == 2)
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, TAG>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, TAG, AKM, BKM>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 2, 2, 0>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 2, 2, 0, AKM, BKM>), grid, dim3(256), 0, s, a);
 }
 
 // tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
-template <int NP, int OUT>
+template <int NP, int OUT, bool AKM = false, bool BKM = false>
 void launch_split_tag(const KArgs& a, dim3 grid, int tile, int tag, hipStream_t s) {
-    if (tile >= 2 && tag == 7) { launch_split_tile<NP, OUT, 7>(a, grid, tile, s); return; }
-    if (tile >= 2 && tag == 8) { launch_split_tile<NP, OUT, 8>(a, grid, tile, s); return; }
-    if (tile >= 2 && tag == 9) { launch_split_tile<NP, OUT, 9>(a, grid, tile, s); return; }
-    launch_split_tile<NP, OUT, 0>(a, grid, tile, s);
+    if (tile >= 2 && tag == 7) { launch_split_tile<NP, OUT, 7, AKM, BKM>(a, grid, tile, s); return; }
+    if (tile >= 2 && tag == 8) { launch_split_tile<NP, OUT, 8, AKM, BKM>(a, grid, tile, s); return; }
+    if (tile >= 2 && tag == 9) { launch_split_tile<NP, OUT, 9, AKM, BKM>(a, grid, tile, s); return; }
+    launch_split_tile<NP, OUT, 0, AKM, BKM>(a, grid, tile, s);
+}
+
+// operand layouts: K-major operands only with FP64 or FP32 outputs (the contractions that read a
+// chi^5 intermediate in its producer's layout all write FP64)
+template <int NP>
+void launch_split_np(const KArgs& a, dim3 grid, int out, int tile, int tag, bool akm, bool bkm, hipStream_t s) {
+    if (!akm && !bkm) {
+        if (out == 0) launch_split_tag<NP, 0>(a, grid, tile, tag, s);
+        else if (out == 1) launch_split_tag<NP, 1>(a, grid, tile, tag, s);
+        else launch_split_tag<NP, NP>(a, grid, tile, tag, s);
+        return;
+    }
+    DTRG_REQUIRE(out == 0 || out == 1, DTRG_EINVAL, "split contraction: K-major operands need an FP64 or FP32 output");
+    if (akm && bkm) {
+        if (out == 0) launch_split_tag<NP, 0, true, true>(a, grid, tile, tag, s);
+        else launch_split_tag<NP, 1, true, true>(a, grid, tile, tag, s);
+    } else if (akm) {
+        if (out == 0) launch_split_tag<NP, 0, true, false>(a, grid, tile, tag, s);
+        else launch_split_tag<NP, 1, true, false>(a, grid, tile, tag, s);
+    } else {
+        if (out == 0) launch_split_tag<NP, 0, false, true>(a, grid, tile, tag, s);
+        else launch_split_tag<NP, 1, false, true>(a, grid, tile, tag, s);
+    }
 }
 
 }  // namespace dtrg

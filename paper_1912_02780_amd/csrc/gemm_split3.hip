@@ -3,22 +3,13 @@
 
 namespace dtrg {
 
-void launch_gemm_split3(const KArgs& a, dim3 grid, int out, int tile, int tag, hipStream_t s) {
-    if (out == 0) launch_split_tag<3, 0>(a, grid, tile, tag, s);
-    else if (out == 1) launch_split_tag<3, 1>(a, grid, tile, tag, s);
-    else launch_split_tag<3, 3>(a, grid, tile, tag, s);
-}
+void launch_gemm_split2(const KArgs& a, dim3 grid, int out, int tile, int tag, bool akm, bool bkm, hipStream_t s);
 
-}  // namespace dtrg
-
-namespace dtrg {
-
-void launch_gemm_split2(const KArgs& a, dim3 grid, int out, int tile, int tag, hipStream_t s);
-
-void launch_gemm_split(const KArgs& a, dim3 grid, int np, int out, int tile, int tag, hipStream_t s) {
+void launch_gemm_split(const KArgs& a, dim3 grid, int np, int out, int tile, int tag, bool akm, bool bkm,
+                       hipStream_t s) {
     DTRG_REQUIRE(np == 2 || np == 3, DTRG_EINVAL, "split contraction: 2 or 3 planes");
-    if (np == 2) launch_gemm_split2(a, grid, out, tile, tag, s);
-    else launch_gemm_split3(a, grid, out, tile, tag, s);
+    if (np == 2) launch_gemm_split2(a, grid, out, tile, tag, akm, bkm, s);
+    else launch_split_np<3>(a, grid, out, tile, tag, akm, bkm, s);
 }
 
 }  // namespace dtrg

@@ -37,14 +37,14 @@ void for_each_buf(const dtrg_plan& P, F f) {
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
-                            &o.X1, &o.X2, &o.X3};
+                            &o.X1, &o.X2};
         for (auto* b : v) f(b->mem.p, b->mem.bytes());
     }
     for (auto& st : P.steps) {
         const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam, &st.Ak, &st.Bk, &st.Gk};
         for (auto* b : v) f(b->p, b->bytes());
-        f(st.P1Tk.mem.p, st.P1Tk.mem.bytes());
-        f(st.Q2bk.mem.p, st.Q2bk.mem.bytes());
+        f(st.P1k.mem.p, st.P1k.mem.bytes());
+        f(st.Q2k.mem.p, st.Q2k.mem.bytes());
     }
 }
 
@@ -251,25 +251,23 @@ void gram_of_step(Ctx& c, const StepCk& st, int k) {
 // Row strides of the operand layouts of one step (every row padded to a multiple of 8).
 struct Lds {
     i64 Wt, Wt2, UT, Us, Tp, Tb, Tb2, TpT, Tpb, Tpb2;      // chi^4 / n x b class
-    i64 P1, P1T, Q2, Q2b, QbA, QbB, X5A, X5B;              // chi^5 class
+    i64 P1, Q2, QbA, X5A;                                  // chi^5 class
     explicit Lds(const StepShape& s) {
         const i64 X = s.X, Y = s.Y, K = s.K, b = s.b, n = s.n;
         Wt = pad8(X); Wt2 = pad8(b * X); UT = pad8(n); Us = pad8(b);
         Tp = pad8(X); Tb = pad8(X * Y); Tb2 = pad8(Y * X); TpT = pad8(Y * X * Y);
         Tpb = pad8(K * Y * Y); Tpb2 = pad8(K);
-        P1 = pad8(X * Y); P1T = pad8(K * Y * X); Q2 = pad8(X * X); Q2b = pad8(K * Y * Y);
-        QbA = pad8(Y * X); QbB = pad8(K * Y * X); X5A = pad8(K * X); X5B = pad8(Y * X * Y);
+        P1 = pad8(X * Y); Q2 = pad8(X * X); QbA = pad8(Y * X); X5A = pad8(K * X);
     }
     // per-instance element counts of the buffers (rows x row stride)
-    static void sizes(const StepShape& s, i64 out[13]) {
+    static void sizes(const StepShape& s, i64 out[12]) {
         const Lds l(s);
         const i64 X = s.X, Y = s.Y, K = s.K, b = s.b, n = s.n;
         out[0] = b * X * l.Wt; out[1] = X * l.Wt2; out[2] = b * l.UT; out[3] = n * l.Us;
         out[4] = Y * X * Y * l.Tp; out[5] = Y * X * l.Tb; out[6] = Y * X * l.Tb2; out[7] = X * l.TpT;
         out[8] = K * l.Tpb; out[9] = K * Y * Y * l.Tpb2;
-        out[10] = std::max({K * Y * X * l.P1, X * X * l.Q2b, Y * X * l.QbB, Y * X * Y * l.X5A});   // X1
-        out[11] = std::max(K * Y * Y * l.Q2, K * Y * X * l.QbA);                                  // X2
-        out[12] = std::max(X * Y * l.P1T, K * X * l.X5B);                                         // X3
+        out[10] = std::max(K * Y * X * l.P1, Y * X * Y * l.X5A);   // X1
+        out[11] = std::max(K * Y * Y * l.Q2, K * Y * X * l.QbA);   // X2
     }
 };
 
@@ -300,8 +298,9 @@ void prep_operands(Ctx& c, const StepCk& st, const OpSet& o, bool backward, bool
     }
 }
 
-// P1[(alpha,y,i)][(b,j)] = sum_a Wt[(alpha,b)][a] Tp[y][(i,j)][a]   (batched over y), into X1
-void proj1(Ctx& c, const StepCk& st, const OpSet& o) {
+// P1[(alpha,y,i)][(b,j)] = sum_a Wt[(alpha,b)][a] Tp[y][(i,j)][a]   (batched over y), into P1
+// (X1, or the step's kept buffer)
+void proj1(Ctx& c, const StepCk& st, const OpSet& o, const OpBuf& P1) {
     const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
     const Lds l(st.sh);
     GemmOp g;
@@ -309,44 +308,35 @@ void proj1(Ctx& c, const StepCk& st, const OpSet& o) {
     set_ops(g, op_of(o.Wt, l.Wt), op_of(o.Tp, l.Tp));
     g.a_bs = 0;
     g.b_bs = (i64)X * Y * l.Tp;
-    set_out(g, op_of(o.X1, l.P1));
+    set_out(g, op_of(P1, l.P1));
     g.c_bs = (i64)X * l.P1;
     g.rmap = IdxMap::split(X, (i64)Y * X * l.P1, Y);
     g.cmap = IdxMap::split(Y, l.P1, 1);
     c.run(g, o.pr, own_out(o.pr));
 }
 
-// out[c][r] = in[r][c] between two operand buffers of the same format (all planes and instances)
-void transpose_op(Ctx& c, const OpBuf& in, i64 ld_in, int rows, int cols, const OpBuf& out, i64 ld_out) {
-    DTRG_REQUIRE(in.per >= (i64)rows * ld_in && ld_in >= cols && out.per >= (i64)cols * ld_out && ld_out >= rows &&
-                     in.esz == out.esz && in.np == out.np && in.nb == c.P->nb && out.nb == c.P->nb,
-                 DTRG_EINVAL, "transpose: operand buffer too small");
-    transpose_planes(in.p(), out.p(), in.esz, rows, cols, ld_in, ld_out, c.P->nb, in.per, out.per, in.np, in.ps(),
-                     out.ps(), c.s);
-}
-
 // the join (the chi^7 term): Q2[(alpha,y,z)][(i,m)] = sum_{(b,j)} P1[(alpha,y,i)][(b,j)] Tb[(z,m)][(b,j)],
-// from X1 into X2
-void join(Ctx& c, const StepCk& st, const OpSet& o) {
+// from P1 into Q2 (X1 into X2, or the step's kept buffers)
+void join(Ctx& c, const StepCk& st, const OpSet& o, const OpBuf& P1, const OpBuf& Q2) {
     const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
     const Lds l(st.sh);
     GemmOp g;
     g.tag = 7;
     g.M = K * Y * X; g.N = Y * X; g.K = X * Y;
-    set_ops(g, op_of(o.X1, l.P1), op_of(o.Tb, l.Tb));
-    set_out(g, op_of(o.X2, l.Q2));
+    set_ops(g, op_of(P1, l.P1), op_of(o.Tb, l.Tb));
+    set_out(g, op_of(Q2, l.Q2));
     g.rmap = IdxMap::split(X, (i64)Y * l.Q2, X);
     g.cmap = IdxMap::split(X, l.Q2, 1);
     c.run(g, o.pr, own_out(o.pr));
 }
 
 // T'[alpha][beta][y][z] = sum_{(i,m)} Q2[(alpha,y,z)][(i,m)] UT[beta][(i,m)]   (FP64 out)
-void proj3(Ctx& c, const StepCk& st, const OpSet& o, DevBuf<double>& Tn) {
+void proj3(Ctx& c, const StepCk& st, const OpSet& o, const OpBuf& Q2, DevBuf<double>& Tn) {
     const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
     const Lds l(st.sh);
     GemmOp g;
     g.M = K * Y * Y; g.N = K; g.K = X * X;
-    set_ops(g, op_of(o.X2, l.Q2), op_of(o.UT, l.UT));
+    set_ops(g, op_of(Q2, l.Q2), op_of(o.UT, l.UT));
     g.C = Tn.p; g.c_bs2 = Tn.bs;
     g.rmap = IdxMap::split((i64)Y * Y, (i64)K * Y * Y, 1);
     g.cmap = IdxMap::linear((i64)Y * Y);
@@ -603,13 +593,13 @@ void alloc_kept(dtrg_plan* P) {
         StepCk& st = P->steps[k];
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
         const Lds l(st.sh);
-        const i64 X = st.sh.X, Y = st.sh.Y;
+        const i64 X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
         const int np = prec_planes(o.pr), esz = o.pr == Prec::F64 ? 8 : (o.pr == Prec::F32 ? 4 : 2);
-        const i64 e1 = X * Y * l.P1T, e2 = X * X * l.Q2b;
+        const i64 e1 = K * Y * X * l.P1, e2 = K * Y * Y * l.Q2;
         const i64 bytes = (i64)np * nb * (pad8(e1) + pad8(e2)) * esz;
         if (bytes > left) continue;
-        st.P1Tk.alloc(o.pr, nb, e1);
-        st.Q2bk.alloc(o.pr, nb, e2);
+        st.P1k.alloc(o.pr, nb, e1);
+        st.Q2k.alloc(o.pr, nb, e2);
         st.keep_join = true;
         left -= bytes;
     }
@@ -619,7 +609,7 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
     const i64 D4 = (i64)P->D * P->D * P->D * P->D;
     i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1;
-    i64 osz[2][13] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
+    i64 osz[2][12] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
     bool used[2] = {false, false};
     for (auto& s : sh) {
         const i64 a4 = std::max<i64>((i64)s.X * s.X * s.Y * s.Y, (i64)s.K * s.K * s.Y * s.Y);
@@ -633,9 +623,9 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         Kmax = std::max<i64>(Kmax, s.K);
         const int f = s.mixed ? 1 : 0;
         used[f] = true;
-        i64 z[13];
+        i64 z[12];
         Lds::sizes(s, z);
-        for (int i = 0; i < 13; ++i) osz[f][i] = std::max(osz[f][i], z[i]);
+        for (int i = 0; i < 12; ++i) osz[f][i] = std::max(osz[f][i], z[i]);
     }
     P->T0buf.alloc_inst(nb, D4); P->T0barbuf.alloc_inst(nb, D4); P->dT0buf.alloc_inst(nb, D4);
     for (DevBuf<double>* b : {&P->TA, &P->TB, &P->Tn, &P->Tbar, &P->Tbar2, &P->Wk, &P->A, &P->B})
@@ -644,8 +634,8 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         OpSet& o = P->ops[f];
         o.pr = f == 0 ? Prec::F64 : P->prec;
         if (!used[f]) continue;
-        OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2, &o.X1, &o.X2, &o.X3};
-        for (int i = 0; i < 13; ++i) v[i]->alloc(o.pr, nb, std::max<i64>(osz[f][i], 8));
+        OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2, &o.X1, &o.X2};
+        for (int i = 0; i < 12; ++i) v[i]->alloc(o.pr, nb, std::max<i64>(osz[f][i], 8));
     }
     P->Gw.alloc_inst(nb, n2); P->Gt.alloc_inst(nb, n2);
     for (DevBuf<double>* b : {&P->V1, &P->V2, &P->Y1, &P->Y2}) b->alloc_inst(nb, nbk);
@@ -942,11 +932,12 @@ void plan_forward(dtrg_plan* P, Mode mode) {
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
         const Lds l(st.sh);
         prep_operands(c, st, o, false);
-        proj1(c, st, o);
-        if (st.keep_join) transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, st.P1Tk, l.P1T);
-        join(c, st, o);
-        if (st.keep_join) transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, st.Q2bk, l.Q2b);
-        proj3(c, st, o, P->Tn);
+        // P and the join go straight into the step's kept buffers when the plan keeps them
+        const OpBuf& P1 = st.keep_join ? st.P1k : o.X1;
+        const OpBuf& Q2 = st.keep_join ? st.Q2k : o.X2;
+        proj1(c, st, o, P1);
+        join(c, st, o, P1, Q2);
+        proj3(c, st, o, Q2, P->Tn);
         // c_k = |T'|, L += 2^-k ln c_k, 1/c_k
         norm2(P->Tn.p, P->Tn.bs, (i64)K * K * Y * Y, nb, P->sc(k, 0), P->S, c.s, P->ws);
         accum_log(P->sc(k, 0), ldexp1(-k), P->sp(0), P->sc(k, 1), P->S, nb, P->flags.p, c.s);
@@ -986,28 +977,28 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         //   Tpb [beta][(alpha,y,z)] and Tpb2 [(alpha,y,z)][beta]  (from Tbar [y][z][alpha][beta])
         permute_op(P, pr, P->Tbar, o.Tpb, pd4(Y, Y, K, K, 3, 2, 0, 1), 3, l.Tpb, P->sc(k, 1), c.s);
         permute_op(P, pr, P->Tbar, o.Tpb2, pd4(Y, Y, K, K, 2, 0, 1, 3), 1, l.Tpb2, P->sc(k, 1), c.s);
-        // P1T [(b,j)][(alpha,y,i)] and Q2b [(i,m)][(alpha,y,z)]: kept by the forward pass, or
-        // recomputed: P1 (X1) and the join (X2), transposed into X3 and X1 (once P1 is consumed)
+        // P1 [(alpha,y,i)][(b,j)] and Q2 [(alpha,y,z)][(i,m)]: kept by the forward pass, or
+        // recomputed into X1 and X2.  The adjoint contractions read them, and Q_bar and P_bar below,
+        // in their producers' layouts as K-major operands (no transposed copies)
         prep_operands(c, st, o, true, !st.keep_join);
-        const OpBuf& P1T = st.keep_join ? st.P1Tk : o.X3;
-        const OpBuf& Q2b = st.keep_join ? st.Q2bk : o.X1;
+        const OpBuf& P1 = st.keep_join ? st.P1k : o.X1;
+        const OpBuf& Q2 = st.keep_join ? st.Q2k : o.X2;
         if (!st.keep_join) {
-            proj1(c, st, o);
-            transpose_op(c, o.X1, l.P1, K * Y * X, X * Y, o.X3, l.P1T);
-            join(c, st, o);
-            transpose_op(c, o.X2, l.Q2, K * Y * Y, X * X, o.X1, l.Q2b);
+            proj1(c, st, o, P1);
+            join(c, st, o, P1, Q2);
         }
-        // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2b[(i,m)][(alpha,y,z)] Tpb[beta][(alpha,y,z)]
+        // w_bar_R[(i,m)][beta] = sum_{(alpha,y,z)} Q2[(alpha,y,z)][(i,m)] Tpb[beta][(alpha,y,z)]
         {
             GemmOp g;
             g.M = n; g.N = K; g.K = K * Y * Y;
-            set_ops(g, op_of(Q2b, l.Q2b), op_of(o.Tpb, l.Tpb));
+            set_ops(g, op_of(Q2, l.Q2), op_of(o.Tpb, l.Tpb));
+            g.a_kmajor = true;
             g.C = P->Ub.p; g.c_bs2 = P->Ub.bs;
             g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
             c.run(g, pr, Out::F64);
         }
-        // QbA[(alpha,y,i)][(z,m)] = sum_beta Tpb2[(alpha,y,z)][beta] Us[(i,m)][beta]   (X2), and its
-        // transpose QbB [(z,m)][(alpha,y,i)] (X1)
+        // QbA[(alpha,y,i)][(z,m)] = sum_beta Tpb2[(alpha,y,z)][beta] Us[(i,m)][beta]   (X2; a
+        // recomputed Q2 there is consumed)
         {
             GemmOp g;
             g.M = K * Y * Y; g.N = n; g.K = K;
@@ -1017,13 +1008,13 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.cmap = IdxMap::split(X, l.QbA, 1);
             c.run(g, pr, own_out(pr));
         }
-        transpose_op(c, o.X2, l.QbA, K * Y * X, Y * X, o.X1, l.QbB);
         fill(P->Tbar2.p, P->Tbar2.bs, (i64)X * X * Y * Y, nb, 0.0, c.s);
-        // Tbar_lower[b][m][j][z] = sum_{(alpha,y,i)} QbB[(z,m)][(alpha,y,i)] P1T[(b,j)][(alpha,y,i)]   (chi^7)
+        // Tbar_lower[b][m][j][z] = sum_{(alpha,y,i)} QbA[(alpha,y,i)][(z,m)] P1[(alpha,y,i)][(b,j)]   (chi^7)
         {
             GemmOp g;
             g.M = Y * X; g.N = X * Y; g.K = K * Y * X;
-            set_ops(g, op_of(o.X1, l.QbB), op_of(P1T, l.P1T));
+            set_ops(g, op_of(o.X2, l.QbA), op_of(P1, l.P1));
+            g.a_kmajor = g.b_kmajor = true;
             g.C = P->Tbar2.p; g.c_bs2 = P->Tbar2.bs;
             g.rmap = IdxMap::split(X, 1, (i64)Y * Y);
             g.cmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
@@ -1031,8 +1022,8 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.tag = 9;
             c.run(g, pr, Out::F64);
         }
-        // X5A[(y,i,j)][(alpha,b)] = sum_{(z,m)} QbA[(alpha,y,i)][(z,m)] Tb2[(j,b)][(z,m)]   (chi^7, X1), and
-        // its transpose X5B [(alpha,b)][(y,i,j)] (X3)
+        // X5A[(y,i,j)][(alpha,b)] = sum_{(z,m)} QbA[(alpha,y,i)][(z,m)] Tb2[(j,b)][(z,m)]   (chi^7, X1;
+        // a recomputed P1 there is consumed)
         {
             GemmOp g;
             g.M = K * Y * X; g.N = Y * X; g.K = Y * X;
@@ -1043,7 +1034,6 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.tag = 8;
             c.run(g, pr, own_out(pr));
         }
-        transpose_op(c, o.X1, l.X5A, Y * X * Y, K * X, o.X3, l.X5B);
         // Tbar_upper[a][i][y][j] += sum_{(alpha,b)} X5A[y][(i,j)][(alpha,b)] Wt2[a][(alpha,b)]   (batched over y)
         {
             GemmOp g;
@@ -1056,11 +1046,12 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.beta = 1.0;
             c.run(g, pr, Out::F64);
         }
-        // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} TpT[a][(y,i,j)] X5B[(alpha,b)][(y,i,j)]
+        // w_bar_L[(a,b)][alpha] += sum_{(y,i,j)} TpT[a][(y,i,j)] X5A[(y,i,j)][(alpha,b)]
         {
             GemmOp g;
             g.M = X; g.N = K * X; g.K = Y * X * Y;
-            set_ops(g, op_of(o.TpT, l.TpT), op_of(o.X3, l.X5B));
+            set_ops(g, op_of(o.TpT, l.TpT), op_of(o.X1, l.X5A));
+            g.b_kmajor = true;
             g.C = P->Ub.p; g.c_bs2 = P->Ub.bs;
             g.rmap = IdxMap::linear((i64)X * K);
             g.cmap = IdxMap::split(X, 1, K);

@@ -68,7 +68,7 @@ struct OpBuf {
 struct OpSet {
     Prec pr = Prec::F64;
     OpBuf Wt, Wt2, UT, Us, Tp, Tb, Tb2, TpT, Tpb, Tpb2;   // chi^4 / n x b class
-    OpBuf X1, X2, X3;                                      // chi^5 class
+    OpBuf X1, X2;                                          // chi^5 class
 };
 
 struct StepCk {
@@ -78,9 +78,10 @@ struct StepCk {
     DevBuf<double> lam;    // b eigenvalues / Ritz values, descending
     // forward intermediates kept for the backward pass (within the plan's checkpoint budget)
     bool keep_gram = false;          // Ak, Bk, Gk: half-environments and normalised Gram
-    bool keep_join = false;          // P1Tk, Q2bk: first projection and join, transposed
+    bool keep_join = false;          // P1k, Q2k: first projection and join (written there by the
+                                     // forward pass, read by the backward)
     DevBuf<double> Ak, Bk, Gk;
-    OpBuf P1Tk, Q2bk;
+    OpBuf P1k, Q2k;
     // schedule (written by adaptive passes, replayed by fixed passes)
     int iters = 0;         // subspace iterations
     int cheb = 0;          // degree of the complement expansion (0: none)
