@@ -25,6 +25,9 @@ namespace {
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
 constexpr int JT = 512;    // Jacobi: 8 waves (one wave is slower: the row and column updates need the width)
+constexpr int JG = JT / 128;                 // Jacobi: groups of 128 threads
+constexpr int JS = (JM / 2 + JG - 1) / JG;   // pair slots per group
+static_assert(JM <= 128, "one row or column element per thread of a group");
 constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
@@ -94,30 +97,57 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
             __syncthreads();
             const int na = nact;
             if (na > 0) {
-                // rows: row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q.  Slot i of group g
-                // (128 threads each) covers the row pair, one column per thread
+                // Slot i = g + JG t of group g (128 threads) is one active pair; thread l of the group
+                // takes column l of its two rows, then row l of its two columns (and of V).  A
+                // round's pairs are disjoint, so a thread issues every LDS read of a pass before its
+                // first store: one round trip per pass instead of one per pair.
                 const int g = tid >> 7, l = tid & 127;
-                for (int i = g; i < na; i += JT / 128) {
-                    const int p = rp[i], q = rq[i];
-                    const double c = rc[i], sn = rs[i];
-                    for (int j = l; j < n; j += 128) {
-                        const double ap = A[p * JLD + j], aq = A[q * JLD + j];
-                        A[p * JLD + j] = c * ap - sn * aq;
-                        A[q * JLD + j] = sn * ap + c * aq;
+                const bool lv = l < n;
+                const int lc = lv ? l : n - 1;
+                const int ns = (na - g + JG - 1) / JG;   // active slots of this group (wave-uniform)
+                int sp[JS], sq[JS];
+                double sc[JS], ss[JS];
+#pragma unroll
+                for (int t = 0; t < JS; ++t) {
+                    if (t >= ns) continue;
+                    const int i = g + JG * t;
+                    sp[t] = rp[i]; sq[t] = rq[i]; sc[t] = rc[i]; ss[t] = rs[i];
+                }
+                // rows: row_p <- c row_p - s row_q ; row_q <- s row_p + c row_q
+                {
+                    double ap[JS], aq[JS];
+#pragma unroll
+                    for (int t = 0; t < JS; ++t) {
+                        if (t >= ns) continue;
+                        ap[t] = A[sp[t] * JLD + lc];
+                        aq[t] = A[sq[t] * JLD + lc];
+                    }
+#pragma unroll
+                    for (int t = 0; t < JS; ++t) {
+                        if (t >= ns || !lv) continue;
+                        A[sp[t] * JLD + l] = sc[t] * ap[t] - ss[t] * aq[t];
+                        A[sq[t] * JLD + l] = ss[t] * ap[t] + sc[t] * aq[t];
                     }
                 }
                 __syncthreads();
-                // columns of A and of V, one row per thread
-                for (int i = g; i < na; i += JT / 128) {
-                    const int p = rp[i], q = rq[i];
-                    const double c = rc[i], sn = rs[i];
-                    for (int r = l; r < n; r += 128) {
-                        const double ap = A[r * JLD + p], aq = A[r * JLD + q];
-                        A[r * JLD + p] = c * ap - sn * aq;
-                        A[r * JLD + q] = sn * ap + c * aq;
-                        const double vp = V[r * JLD + p], vq = V[r * JLD + q];
-                        V[r * JLD + p] = c * vp - sn * vq;
-                        V[r * JLD + q] = sn * vp + c * vq;
+                // columns of A and of V
+                {
+                    double ap[JS], aq[JS], vp[JS], vq[JS];
+#pragma unroll
+                    for (int t = 0; t < JS; ++t) {
+                        if (t >= ns) continue;
+                        ap[t] = A[lc * JLD + sp[t]];
+                        aq[t] = A[lc * JLD + sq[t]];
+                        vp[t] = V[lc * JLD + sp[t]];
+                        vq[t] = V[lc * JLD + sq[t]];
+                    }
+#pragma unroll
+                    for (int t = 0; t < JS; ++t) {
+                        if (t >= ns || !lv) continue;
+                        A[l * JLD + sp[t]] = sc[t] * ap[t] - ss[t] * aq[t];
+                        A[l * JLD + sq[t]] = ss[t] * ap[t] + sc[t] * aq[t];
+                        V[l * JLD + sp[t]] = sc[t] * vp[t] - ss[t] * vq[t];
+                        V[l * JLD + sq[t]] = ss[t] * vp[t] + sc[t] * vq[t];
                     }
                 }
             }
@@ -195,6 +225,7 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
         rprev = rdk;
         __syncthreads();
     }
+    __syncthreads();   // the scaled last column and pivot, written after the last phase's barrier
     // X = L^{-1}, one barrier per row: phase k removes row k, scaled by 1 / L[k][k], from the rows
     // below and writes back the scaled row k-1, which phase k no longer reads
     double inv_prev = 1.0;
@@ -210,6 +241,9 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
         inv_prev = inv;
         __syncthreads();
     }
+    // the last phase scaled row b-1 of X after its barrier: every thread's scaling must land before
+    // any thread reads X below
+    __syncthreads();
     // Rinv = (L^{-1})^T
     for (int idx = tid; idx < b * b; idx += CT) {
         const int i = idx / b, j = idx % b;
