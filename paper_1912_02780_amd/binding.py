@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3, "bf16
 EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "dtrg_plan_forward",
             "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_batch_create", "dtrg_batch_run",
             "dtrg_batch_step_info", "dtrg_batch_profile", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
-            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_version"]
+            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_contract_config", "dtrg_version"]
 
 
 class Options(ctypes.Structure):
@@ -94,6 +94,10 @@ def _load():
     lib.dtrg_contract.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_longlong, c_int, c_void_p, c_longlong,
                                   c_int, c_void_p, c_longlong, c_int, c_double, c_double, c_void_p]
     lib.dtrg_contract.restype = c_int
+    lib.dtrg_contract_config.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_longlong, c_int, c_void_p,
+                                         c_longlong, c_int, c_void_p, c_longlong, c_int, c_double, c_double, c_int,
+                                         c_int, c_void_p]
+    lib.dtrg_contract_config.restype = c_int
     return lib
 
 
@@ -298,8 +302,10 @@ def tuned_shapes() -> int:
 
 
 def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, a_kmajor=False, b_kmajor=False,
-                  alpha=1.0, beta=0.0, stream=None):
-    """C = alpha * A' B'^T + beta * C with A' = A or A.T (a_kmajor), B' = B or B.T (b_kmajor)."""
+                  alpha=1.0, beta=0.0, stream=None, tile=0, splits=0):
+    """C = alpha * A' B'^T + beta * C with A' = A or A.T (a_kmajor), B' = B or B.T (b_kmajor).
+
+    tile / splits: the kernel configuration (0 = the library's choice; dtrg_contract_config)."""
     prec = PRECISIONS[precision]
     if a_kmajor:
         K, M = A.shape
@@ -317,9 +323,15 @@ def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Ten
         raise TypeError("fp64 contraction writes float64")
     if tuple(C.shape) != (M, N):
         raise ValueError("C has the wrong shape")
-    _check(lib.dtrg_contract(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
-                             c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()), N,
-                             int(out_f64), float(alpha), float(beta), _stream(stream)))
+    if tile or splits:
+        _check(lib.dtrg_contract_config(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
+                                        c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()),
+                                        N, int(out_f64), float(alpha), float(beta), int(tile), int(splits),
+                                        _stream(stream)))
+    else:
+        _check(lib.dtrg_contract(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
+                                 c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()), N,
+                                 int(out_f64), float(alpha), float(beta), _stream(stream)))
     return C
 
 

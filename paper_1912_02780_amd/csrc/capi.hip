@@ -496,6 +496,13 @@ int dtrg_tuned_shapes(void) { return tuned_count(); }
 dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
                           const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc, int out_f64,
                           double alpha, double beta, void* stream) {
+    return dtrg_contract_config(precision, M, N, K, A_dev, lda, a_kmajor, B_dev, ldb, b_kmajor, C_dev, ldc, out_f64,
+                                alpha, beta, 0, 0, stream);
+}
+
+dtrg_status dtrg_contract_config(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
+                                 const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,
+                                 int out_f64, double alpha, double beta, int tile, int splits, void* stream) {
     g_last_error.clear();
     static thread_local Scratch ws;
     static thread_local DevBuf<double> planes;
@@ -506,11 +513,15 @@ dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev,
         DTRG_REQUIRE(lda >= (a_kmajor ? M : K) && ldb >= (b_kmajor ? N : K) && ldc >= N, DTRG_EINVAL,
                      "leading dimension too small");
         const Prec pr = prec_of(precision);
+        DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(pr) > 1 ? 5 : 2), DTRG_EINVAL, "bad tile code");
+        DTRG_REQUIRE(splits >= 0 && splits <= 64, DTRG_EINVAL, "split-K count out of range (0 to 64)");
         const hipStream_t s = (hipStream_t)stream;
         GemmOp g;
         g.M = M; g.N = N; g.K = K;
         g.C = C_dev; g.rmap = IdxMap::linear(ldc); g.cmap = IdxMap::linear(1);
         g.alpha = alpha; g.beta = beta;
+        g.cfg.tile = tile;
+        g.cfg.splits = splits;
         const int np = prec_planes(pr);
         if (np == 1) {
             g.A = A_dev; g.lda = lda; g.a_kmajor = a_kmajor != 0;

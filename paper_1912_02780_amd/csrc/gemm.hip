@@ -185,7 +185,7 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     }
 
     const GemmCfg cfg = gemm_resolve(prec, op);
-    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || ((cfg.tile == 3 || cfg.tile == 4) && split), DTRG_EINVAL,
+    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || ((cfg.tile >= 3 && cfg.tile <= 5) && split), DTRG_EINVAL,
                  "gemm: bad tile configuration");
     const int BM = tile_rows(cfg.tile), BN = tile_cols(cfg.tile);
     const int BK = bk_of(prec, cfg.tile);

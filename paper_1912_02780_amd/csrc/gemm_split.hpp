@@ -172,19 +172,23 @@ struct SplitOperand {
     }
 };
 
-template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int TAG, bool AKM = false, bool BKM = false>
+template <int NP, int OUT, int BM, int BN, int WGM, int WGN, int TAG, bool AKM = false, bool BKM = false, int ST = 2>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
     constexpr int BK = 32, NW = WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
     static_assert(TM >= 1 && TN >= 1, "bad tile");
     typedef SplitOperand<NP, BM, AKM> OpA;
     typedef SplitOperand<NP, BN, BKM> OpB;
-    // two stages in distinct arrays, so that the compiler can tell the stage being filled from the
-    // one being read and does not wait for the loads in flight before reading
-    __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM * BK], As1[NP][BM * BK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN * BK], Bs1[NP][BN * BK];
-    // the 16-byte plane epilogue needs a slab of 16 x (WN + 4) floats per wave in As0 and As1
-    constexpr bool kVecEpilogue = 16 * (WN + 4) * 4 * ((NW + 1) / 2) <= (int)sizeof(As0);
+    // ST = 2: two stages in distinct arrays, so that the compiler can tell the stage being filled
+    // from the one being read and does not wait for the loads in flight before reading.  ST = 1: one
+    // stage (half the LDS, so that two blocks share a compute unit and one block's output stores
+    // overlap the other's loads; for short K, where there is little to pipeline)
+    static_assert(ST == 1 || ST == 2, "one or two stages");
+    __shared__ __attribute__((aligned(16))) __bf16 As0[NP][BM * BK], As1[ST == 2 ? NP : 1][ST == 2 ? BM * BK : 8];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs0[NP][BN * BK], Bs1[ST == 2 ? NP : 1][ST == 2 ? BN * BK : 8];
+    // the 16-byte plane epilogue needs a slab of 16 x (WN + 4) floats per wave: in As0 and As1 with
+    // two stages, in As0 with one
+    constexpr bool kVecEpilogue = 16 * (WN + 4) * 4 * (ST == 2 ? (NW + 1) / 2 : NW) <= (int)sizeof(As0);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
@@ -247,41 +251,56 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
         __syncthreads();
     };
 
-    // K tiles t = 0 .. nt-1; tile t in stage t % 2; the loads of tile t + 1 are in flight while
-    // tile t is multiplied
+    // K tiles t = 0 .. nt-1; with two stages, tile t is in stage t % 2 and the loads of tile t + 1
+    // are in flight while tile t is multiplied
     const int nt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     const bool ragged = (kend - kbeg) % BK != 0;
-    if (nt > 0) {
-        issue(As0, Bs0, kbeg);
-        landed();
-        if (nt == 1 && ragged) {
-            zero_tail(As0, Bs0, kbeg);
+    if constexpr (ST == 1) {
+        // one stage: load, multiply, and a barrier before the next tile overwrites the stage
+        for (int t = 0; t < nt; ++t) {
+            issue(As0, Bs0, kbeg + t * BK);
+            landed();
+            if (t == nt - 1 && ragged) {
+                zero_tail(As0, Bs0, kbeg + t * BK);
+                __syncthreads();
+            }
+            compute(As0, Bs0);
             __syncthreads();
         }
-    }
-    for (int t = 0; t < nt; t += 2) {
-        if (t + 1 < nt) issue(As1, Bs1, kbeg + (t + 1) * BK);
-        compute(As0, Bs0);
-        landed();
-        if (t + 1 >= nt) break;
-        if (t + 2 == nt && ragged) {
-            zero_tail(As1, Bs1, kbeg + (t + 1) * BK);
-            __syncthreads();
+    } else {
+        if (nt > 0) {
+            issue(As0, Bs0, kbeg);
+            landed();
+            if (nt == 1 && ragged) {
+                zero_tail(As0, Bs0, kbeg);
+                __syncthreads();
+            }
         }
-        if (t + 2 < nt) issue(As0, Bs0, kbeg + (t + 2) * BK);
-        compute(As1, Bs1);
-        landed();
-        if (t + 3 == nt && ragged) {
-            zero_tail(As0, Bs0, kbeg + (t + 2) * BK);
-            __syncthreads();
+        for (int t = 0; t < nt; t += 2) {
+            if (t + 1 < nt) issue(As1, Bs1, kbeg + (t + 1) * BK);
+            compute(As0, Bs0);
+            landed();
+            if (t + 1 >= nt) break;
+            if (t + 2 == nt && ragged) {
+                zero_tail(As1, Bs1, kbeg + (t + 1) * BK);
+                __syncthreads();
+            }
+            if (t + 2 < nt) issue(As0, Bs0, kbeg + (t + 2) * BK);
+            compute(As1, Bs1);
+            landed();
+            if (t + 3 == nt && ragged) {
+                zero_tail(As0, Bs0, kbeg + (t + 2) * BK);
+                __syncthreads();
+            }
         }
     }
 
     // epilogue: D row of accumulator register r of lane l is 4 (l / 16) + r, column l % 16
     if constexpr (OUT >= 2 && kVecEpilogue) {
         if (p.vec_out && p.splits == 1) {
-            float* slab = (wave < (NW + 1) / 2 ? (float*)&As0[0][0] : (float*)&As1[0][0]) +
-                          (wave % ((NW + 1) / 2)) * 16 * (WN + 4);
+            float* slab = ST == 1 ? (float*)&As0[0][0] + wave * 16 * (WN + 4)
+                                  : (wave < (NW + 1) / 2 ? (float*)&As0[0][0] : (float*)&As1[0][0]) +
+                                        (wave % ((NW + 1) / 2)) * 16 * (WN + 4);
             store_planes_vec<OUT>(p, zb, acc, m0 + wm0, n0 + wn0, slab);
             return;
         }
@@ -312,11 +331,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
 
 // Tile shapes: 1 = 64 x 64 (4 waves of 32 x 32), 2 = 128 x 128 (4 waves of 64 x 64),
 // 3 = 256 x 128 (8 waves of 64 x 64), 4 = 64 x 64 as 4 waves of 16 rows x 64 columns (outputs of at
-// most 64 columns: every wave covers all of them).  LDS: two stages of NP x (BM + BN) x 64 bytes (at
-// most 144 KiB).
+// most 64 columns: every wave covers all of them), 5 = tile 2 with a single LDS stage (short K).
+// LDS: two stages of NP x (BM + BN) x 64 bytes (at most 144 KiB), one for tile 5.
 template <int NP, int OUT, int TAG, bool AKM, bool BKM>
 void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
-    if (tile == 4)
+    if (tile == 5)
+        hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, 0, AKM, BKM, 1>), grid, dim3(256), 0, s, a);
+    else if (tile == 4)
         hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 64, 64, 4, 1, 0, AKM, BKM>), grid, dim3(256), 0, s, a);
     else if (tile == 3)
         hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 256, 128, 4, 2, TAG, AKM, BKM>), grid, dim3(512), 0, s, a);
@@ -329,9 +350,9 @@ void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
 // tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
 template <int NP, int OUT, bool AKM = false, bool BKM = false>
 void launch_split_tag(const KArgs& a, dim3 grid, int tile, int tag, hipStream_t s) {
-    if (tile >= 2 && tag == 7) { launch_split_tile<NP, OUT, 7, AKM, BKM>(a, grid, tile, s); return; }
-    if (tile >= 2 && tag == 8) { launch_split_tile<NP, OUT, 8, AKM, BKM>(a, grid, tile, s); return; }
-    if (tile >= 2 && tag == 9) { launch_split_tile<NP, OUT, 9, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3) && tag == 7) { launch_split_tile<NP, OUT, 7, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3) && tag == 8) { launch_split_tile<NP, OUT, 8, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3) && tag == 9) { launch_split_tile<NP, OUT, 9, AKM, BKM>(a, grid, tile, s); return; }
     launch_split_tile<NP, OUT, 0, AKM, BKM>(a, grid, tile, s);
 }
 

@@ -4,8 +4,8 @@
 // layouts) is met in an adaptive pass with tuning enabled, every admissible configuration is run
 // on a scratch output (beta = 0, so the real output is untouched), timed with HIP events on the
 // caller's stream, and the fastest is kept in a process-wide table.  The configurations are the
-// tiles {64 x 64, 128 x 128, and for bf16 planes 256 x 128 and, for outputs of at most 64 columns,
-// 64 x 64 on full-width waves} times the split-K counts {s0, then the
+// tiles {64 x 64, 128 x 128, and for bf16 planes 256 x 128, for outputs of at most 64 columns
+// 64 x 64 on full-width waves, and for K of at most 128 the single-stage 128 x 128} times the split-K counts {s0, then the
 // powers of two above it up to 32}, s0 being the least count that keeps FP32 accumulation chains
 // short (1 for FP64 and for short K).  Later contractions of that shape (including fixed passes
 // that are being captured into a graph) take the table entry without timing anything.
@@ -71,8 +71,9 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
     const i64 nz = (i64)op.batch * op.batch2;
     const int minsp = gemm_chain_splits(prec, op);
     std::vector<GemmCfg> cands;
-    for (int tile = 1; tile <= (np > 1 ? 4 : 2); ++tile) {
-        if (tile == 2 && std::max(op.M, op.N) < 128) continue;
+    for (int tile = 1; tile <= (np > 1 ? 5 : 2); ++tile) {
+        if ((tile == 2 || tile == 5) && std::max(op.M, op.N) < 128) continue;
+        if (tile == 5 && op.K > 128) continue;
         if (tile == 3 && op.M < 256) continue;
         if (tile == 4 && op.N > 64) continue;
         const int BMt = tile_rows(tile), BNt = tile_cols(tile);

@@ -71,3 +71,45 @@ def test_contract_large_tile(B, prec, layout):
 @pytest.mark.parametrize("shape", [(3001, 45, 333), (50, 2100, 5003)])
 def test_contract_tall_and_wide(B, prec, layout, shape):
     test_contract(B, prec, layout[0], layout[1], shape)
+
+
+# every tile code of each precision forced through the configuration entry point, with one and with
+# three K-chunks (ragged in M, N and K; both operand layouts)
+CONFIG_SHAPES = [(300, 260, 129), (70, 45, 37), (129, 257, 1000)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("layout", [(False, False), (True, True), (True, False)])
+@pytest.mark.parametrize("shape", CONFIG_SHAPES)
+def test_contract_every_tile(B, prec, layout, shape):
+    akm, bkm = layout
+    M, N, K = shape
+    g = torch.Generator().manual_seed(M * 7919 + N * 31 + K)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    A_in = torch.randn((K, M) if akm else (M, K), generator=g, dtype=torch.float64).to(dt)
+    B_in = torch.randn((K, N) if bkm else (N, K), generator=g, dtype=torch.float64).to(dt)
+    C0 = torch.randn((M, N), generator=g, dtype=torch.float64)
+    Am = A_in.double().T if akm else A_in.double()
+    Bm = B_in.double() if bkm else B_in.double().T
+    ref = 1.25 * (Am @ Bm) + 0.5 * C0
+    dev = torch.device("cuda:0")
+    tiles = [1, 2] if prec in ("fp64", "fp32") else [1, 2, 3, 4, 5]
+    for tile in tiles:
+        for splits in (1, 3):
+            print(f"[gpu] contract config {prec} {layout} {shape} tile {tile} splits {splits}", flush=True)
+            C = C0.to(dev)
+            B.dtrg_contract(prec, A_in.to(dev), B_in.to(dev), C, a_kmajor=akm, b_kmajor=bkm, alpha=1.25, beta=0.5,
+                            tile=tile, splits=splits)
+            torch.cuda.synchronize()
+            err = float((C.cpu() - ref).norm() / ref.norm())
+            assert err < TOL[prec], (prec, layout, shape, tile, splits, err)
+
+
+def test_contract_config_rejects_bad_codes(B):
+    dev = torch.device("cuda:0")
+    A = torch.randn(8, 8, dtype=torch.float64, device=dev)
+    C = torch.zeros(8, 8, dtype=torch.float64, device=dev)
+    for tile, splits in ((3, 0), (6, 0), (-1, 0), (1, 65), (1, -2)):
+        with pytest.raises(B.DtrgError) as e:
+            B.dtrg_contract("fp64", A, A, C, tile=tile, splits=splits)
+        assert e.value.status == B.DTRG_EINVAL
