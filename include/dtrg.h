@@ -80,7 +80,9 @@ typedef struct {
     int block_size;           /* subspace block b (> chi', <= 96); 0 = automatic (min(96, max(chi' + 16,
                                  2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates */
     int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
-                                 (64 x 64, 128 x 128, and 256 x 128 for the bf16-plane precisions)
+                                 (64 x 64, 128 x 128, and for the bf16-plane precisions 256 x 128,
+                                 64 x 64 on full-width waves for outputs of at most 64 columns and
+                                 128 x 128 with one LDS stage for K of at most 128)
                                  and split-K factor (the least one that keeps every FP32
                                  accumulation chain at 4096 products or fewer, then the powers of two
                                  above it up to 32) of the MFMA kernels on a scratch output and keep
