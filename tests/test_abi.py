@@ -118,3 +118,25 @@ def test_batch_argument_validation_without_device_work():
     lib.dtrg_batch_destroy(None)
     lib.dtrg_batch_device_bytes.restype = ctypes.c_size_t
     assert lib.dtrg_batch_device_bytes(None) == 0
+
+
+def test_contract_config_validation_without_device_work():
+    """Bad tile codes and split counts are rejected before any device work (the pointers are never
+    dereferenced)."""
+    lib = _lib()
+    f = lib.dtrg_contract_config
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
+                  ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
+                  ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    p = ctypes.c_void_p(64)
+    # FP64 has tiles 1 and 2 only; the bf16-plane precisions 1 to 5; split counts 0 to 64
+    for prec, tile, splits in ((0, 3, 0), (0, 6, 0), (1, 5, 0), (3, 6, 0), (3, -1, 0), (3, 1, 65), (0, 1, -1)):
+        st = f(prec, 8, 8, 8, p, 8, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, tile, splits, None)
+        assert st == 1, (prec, tile, splits)
+        msg = lib.dtrg_last_error()
+        assert b"tile" in msg or b"split" in msg
+    # NULL operands and short leading dimensions are rejected first
+    assert f(3, 8, 8, 8, None, 8, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1
+    assert f(3, 8, 8, 8, p, 4, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1
