@@ -173,10 +173,6 @@ void permute(const double* in, double* out, const PermDesc& d, double alpha, dou
 // to FP32, plane q the bf16 rounding of what the planes before it leave), rows padded per d
 void permute_out(const double* in, void* out, int out_code, const PermDesc& d, double alpha, const double* scale_dev,
                  i64 scale_bs, hipStream_t s);
-// out[c][r] = in[r][c] (r < rows, c < cols, row strides ld_in / ld_out) for np planes (plane strides
-// ps_in / ps_out) of nb instances (strides bs_in / bs_out); esz = element size in bytes (2, 4, 8)
-void transpose_planes(const void* in, void* out, int esz, int rows, int cols, i64 ld_in, i64 ld_out, int nb,
-                      i64 bs_in, i64 bs_out, int np, i64 ps_in, i64 ps_out, hipStream_t s);
 // planes of an FP32 matrix, K-contiguous: out[q][r][k] from in(r, k) (in[r * ld_in + k], or
 // in[k * ld_in + r] if kmajor), rows r < rows, k < cols, row stride ld_out, plane stride ps
 void split_matrix(const float* in, i64 ld_in, bool kmajor, int rows, int cols, void* out, i64 ld_out, i64 ps, int np,

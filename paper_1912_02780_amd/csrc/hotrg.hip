@@ -7,11 +7,11 @@
 //   G   [(a,c)][(b,d)] = n x n             Gram of the (x1, x2) unfolding, then sym / trace
 //   U   [n][b]                             eigenvectors (first K columns are w[x1][x2][alpha])
 // The operands of the projection contractions and of their adjoints are stored in the step's
-// contraction format (FP64, FP32 or bf16 planes) and always K-contiguous for the contraction that
-// reads them, rows padded to a multiple of 8 elements: permutations of T, U and the incoming
-// gradient write them from FP64, each contraction's scatter epilogue writes its result in the layout
-// of its first consumer, and a tiled transpose makes the copy that a second consumer contracting it
-// over the other indices reads.  The layouts are written next to their producers.
+// contraction format (FP64, FP32 or bf16 planes), rows padded to a multiple of 8 elements:
+// permutations of T, U and the incoming gradient write them from FP64, and each contraction's
+// scatter epilogue writes its result in the layout of its first consumer, for which it is
+// K-contiguous; a second consumer that contracts it over the other indices reads the same buffer as
+// a K-major operand.  The layouts are written next to their producers.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -571,8 +571,8 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, bool mixed)
 }
 
 // Forward intermediates kept for the backward pass, within P->ck_budget bytes: first the FP64
-// half-environments and Gram of every step (from the last step back), then the transposed first
-// projection and join of each step (from the last step back).  Steps that do not fit recompute
+// half-environments and Gram of every step (from the last step back), then the first projection
+// and the join of each step (from the last step back; the forward pass writes them there).  Steps that do not fit recompute
 // them in the backward pass.
 void alloc_kept(dtrg_plan* P) {
     const int nb = P->nb;

@@ -321,53 +321,6 @@ int np_of(int nb) {
     return nb == 1 ? kRedBlocks : std::max(16, std::min(kRedBlocks, 4096 / nb));
 }
 
-// out[c][r] = in[r][c] for every plane and instance: 64 x 64 tiles through LDS, reads and writes
-// coalesced along the contiguous index of each side in 8-byte words (V elements of type E) where the
-// tile is inside the matrix and the rows are 8-byte aligned, element by element at the edges.
-template <class E, int V>
-__global__ __launch_bounds__(256) void transpose_kernel(const E* __restrict__ in, E* __restrict__ out, int rows,
-                                                        int cols, i64 ld_in, i64 ld_out, int nb, i64 bs_in,
-                                                        i64 bs_out, i64 ps_in, i64 ps_out, int vec_ok) {
-    constexpr int T = 64, W = T / V;        // words per tile row
-    __shared__ E t[T][T + 1];
-    const int z = blockIdx.z;               // plane * nb + instance
-    const int q = z / nb, i = z % nb;
-    in += q * ps_in + i * bs_in;
-    out += q * ps_out + i * bs_out;
-    const int r0 = blockIdx.y * T, c0 = blockIdx.x * T;
-    const int tw = threadIdx.x % W, tr = threadIdx.x / W;
-    constexpr int RSTEP = 256 / W;
-    const bool full = vec_ok && r0 + T <= rows && c0 + T <= cols;
-    for (int rr = tr; rr < T; rr += RSTEP) {
-        const int r = r0 + rr, c = c0 + tw * V;
-        if (full) {
-            typedef E vec_t __attribute__((ext_vector_type(V)));
-            const vec_t v = *(const vec_t*)(in + (i64)r * ld_in + c);
-#pragma unroll
-            for (int e = 0; e < V; ++e) t[rr][tw * V + e] = v[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (r < rows && c + e < cols) t[rr][tw * V + e] = in[(i64)r * ld_in + c + e];
-        }
-    }
-    __syncthreads();
-    for (int cc = tr; cc < T; cc += RSTEP) {
-        const int c = c0 + cc, r = r0 + tw * V;
-        if (full) {
-            typedef E vec_t __attribute__((ext_vector_type(V)));
-            vec_t v;
-#pragma unroll
-            for (int e = 0; e < V; ++e) v[e] = t[tw * V + e][cc];
-            __builtin_nontemporal_store(v, (vec_t*)(out + (i64)c * ld_out + r));
-        } else {
-#pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (c < cols && r + e < rows) out[(i64)c * ld_out + r + e] = t[tw * V + e][cc];
-        }
-    }
-}
-
 }  // namespace
 
 void permute(const double* in, double* out, const PermDesc& d, double alpha, double beta,
@@ -392,29 +345,6 @@ void permute_out(const double* in, void* out, int out_code, const PermDesc& d, d
                                    0.0, scale_dev, scale_bs); break;
         default: hipLaunchKernelGGL((permute_kernel<double, 3>), g, dim3(256), 0, s, in, out, k, d.in_bs, d.out_bs,
                                     alpha, 0.0, scale_dev, scale_bs); break;
-    }
-    DTRG_HIP(hipGetLastError());
-}
-
-void transpose_planes(const void* in, void* out, int esz, int rows, int cols, i64 ld_in, i64 ld_out, int nb,
-                      i64 bs_in, i64 bs_out, int np, i64 ps_in, i64 ps_out, hipStream_t s) {
-    if (rows <= 0 || cols <= 0) return;
-    DTRG_REQUIRE((i64)nb * np < 65536, DTRG_EINVAL, "transpose: too many planes x instances");
-    const dim3 g((cols + 63) / 64, (rows + 63) / 64, nb * np);
-    // 8-byte words need 8-byte aligned rows, instances and planes on both sides
-    const i64 al = 8 / esz;
-    const int vec_ok = (ld_in % al == 0 && ld_out % al == 0 && bs_in % al == 0 && bs_out % al == 0 && ps_in % al == 0 &&
-                        ps_out % al == 0 && ((uintptr_t)in | (uintptr_t)out) % 8 == 0) ? 1 : 0;
-    if (esz == 8)
-        hipLaunchKernelGGL((transpose_kernel<double, 1>), g, dim3(256), 0, s, (const double*)in, (double*)out, rows,
-                           cols, ld_in, ld_out, nb, bs_in, bs_out, ps_in, ps_out, vec_ok);
-    else if (esz == 4)
-        hipLaunchKernelGGL((transpose_kernel<float, 2>), g, dim3(256), 0, s, (const float*)in, (float*)out, rows, cols,
-                           ld_in, ld_out, nb, bs_in, bs_out, ps_in, ps_out, vec_ok);
-    else {
-        DTRG_REQUIRE(esz == 2, DTRG_EINVAL, "transpose: element size 2, 4 or 8");
-        hipLaunchKernelGGL((transpose_kernel<unsigned short, 4>), g, dim3(256), 0, s, (const unsigned short*)in,
-                           (unsigned short*)out, rows, cols, ld_in, ld_out, nb, bs_in, bs_out, ps_in, ps_out, vec_ok);
     }
     DTRG_HIP(hipGetLastError());
 }
