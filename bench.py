@@ -13,7 +13,8 @@ Workloads (--workload):
       bounded sample of the same workload.  The plan keeps the forward intermediates the backward
       pass would otherwise recompute (the library default, a 64 GiB budget); the same pass with one
       checkpoint per RG step and the recompute inside the backward step (checkpoint_gib = 0) is
-      timed beside it and reported under "recompute_in_step".
+      timed beside it and reported under "recompute_in_step".  The tile autotuner is on: one
+      untimed pass before the warm-up times every contraction shape's configurations once.
   batch256
       256 Ising temperatures beta_i = 0.30 + 0.30 i / 255 with chi_i = (32, 16, 24)[i mod 3], 30 steps
       each, forward + backward to d(lnZ/N)/dbeta for every instance, replayed from one captured HIP
@@ -28,7 +29,7 @@ Workloads (--workload):
       path (step 1e-5, and its Richardson extrapolation with step 5e-6) and the FP64 gradient.
       The backward stores one checkpoint per RG step and recomputes inside the step
       (checkpoint_gib = 0); the pass with the forward intermediates kept (64 GiB budget) is timed
-      beside it under "with_kept_intermediates".
+      beside it under "with_kept_intermediates".  The tile autotuner is on (an untimed pass first).
 
     python bench.py [--workload chi48|batch256|ising_chi64] [--steps K] [--warmup W]
                     [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--no-cpu-baseline]
@@ -166,7 +167,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     D, chi, n = 4, args.chi, args.n_steps
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
     ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
-    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
+    opts = B.default_options(contract=args.contract, autotune=1, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -174,6 +175,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         g, _ = B.dtrg_hotrg_backward(plan, 1.0)
         return L, g
 
+    one_step()   # the autotuner times each contraction shape the first time it is met: not timed
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -199,7 +201,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
                                 f"{n} RG steps, forward + backward to dlnZ/dT0"),
-                   "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64",
+                   "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": 1,
                    "checkpoint_gib": ck, "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
                              traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None),
@@ -209,7 +211,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
-        opts0 = B.default_options(contract=args.contract, checkpoint_gib=0.0)
+        opts0 = B.default_options(contract=args.contract, autotune=1, checkpoint_gib=0.0)
         plan0 = B.dtrg_plan_create(D, chi, n, opts0, dev)
         sec = _time_passes(B, torch, plan0, T0, None, 1, max(1, min(args.steps, 3)))
         out["recompute_in_step"] = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
@@ -316,7 +318,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
     dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
     ck = 0.0 if args.checkpoint_gib is None else args.checkpoint_gib
-    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
+    opts = B.default_options(contract=args.contract, autotune=1, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -325,6 +327,8 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         return L, db
 
     free_min = free0
+    one_step()   # the autotuner times each contraction shape the first time it is met: not timed
+    free_min = min(free_min, torch.cuda.mem_get_info(dev)[0])
     for _ in range(args.warmup):
         one_step()
         free_min = min(free_min, torch.cuda.mem_get_info(dev)[0])
@@ -345,7 +349,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     if ck == 0.0 and not args.no_policy_compare:
         # the same pass with the forward intermediates kept for the backward (64 GiB budget)
         _progress("timing the pass with the forward intermediates kept")
-        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0), dev)
+        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, autotune=1, checkpoint_gib=64.0), dev)
         sec = _time_passes(B, torch, plan_k, T0, dT0, 1, 1)
         kept = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
                 "plan_device_GB": plan_k.device_bytes() / 1e9, "checkpoint_gib": 64.0}
@@ -368,7 +372,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         "metric": "HOTRG fwd+bwd RG-steps/s, Ising at beta_c, chi=64 (split-bf16 contractions, FP64 eigensolver)",
         "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": f"2D Ising at beta={beta}, HOTRG chi={chi}, {n} RG steps, forward + backward to dlnZ/dbeta",
-                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12,
+                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12, "autotune": 1,
                    "checkpoint_gib": ck, "checkpoint": ("one checkpoint per RG step, recompute inside the step"
                                                         if ck == 0.0 else "forward intermediates kept within the budget")},
         "peak_hbm": {"plan_device_GB": plan_bytes / 1e9, "torch_max_allocated_GB": peak_torch / 1e9,

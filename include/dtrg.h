@@ -84,9 +84,9 @@ typedef struct {
                                  64 x 64 on full-width waves for outputs of at most 64 columns and
                                  128 x 128 with one LDS stage for K of at most 128)
                                  and split-K factor (the least one that keeps every FP32
-                                 accumulation chain at 4096 products or fewer, then the powers of two
-                                 above it up to 32) of the MFMA kernels on a scratch output and keep
-                                 the fastest for that shape (a table shared by all plans of the
+                                 accumulation chain at 4096 products or fewer, then 2, 3, 4, 5, 6, 8,
+                                 12, 16, 24 and 32 above it) of the MFMA kernels on a scratch output
+                                 (the least of three timed runs) and keep the fastest for that shape (a table shared by all plans of the
                                  process); 0: fixed heuristic.  Default 0 */
     int profile;              /* 1: time the chi^7 join contractions with HIP events on the plan's
                                  stream (read with dtrg_plan_profile); default 0 */
