@@ -29,7 +29,8 @@ Workloads (--workload):
       path (step 1e-5, and its Richardson extrapolation with step 5e-6) and the FP64 gradient.
       The backward stores one checkpoint per RG step and recomputes inside the step
       (checkpoint_gib = 0); the pass with the forward intermediates kept (64 GiB budget) is timed
-      beside it under "with_kept_intermediates".  The tile autotuner is on (an untimed pass first).
+      beside it under "with_kept_intermediates".  The fixed tile heuristic (no autotuner, whose
+      trial buffers would add to the reported peak device memory).
 
     python bench.py [--workload chi48|batch256|ising_chi64] [--steps K] [--warmup W]
                     [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--no-cpu-baseline]
@@ -66,7 +67,7 @@ TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_027
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 20 launches of that size per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "d417e468591649482684850ba215a65199b69d485bcce96c39898efee1db4d81", "fetch_kib": 5365031.8, "write_kib": 1699946.6},
+    ("chi48", "bf16x6"): {"sources_sha256": "d417e468591649482684850ba215a65199b69d485bcce96c39898efee1db4d81", "fetch_kib": 5219061.9, "write_kib": 1699828.2},
 }
 
 
@@ -318,7 +319,9 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
     dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
     ck = 0.0 if args.checkpoint_gib is None else args.checkpoint_gib
-    opts = B.default_options(contract=args.contract, autotune=1, profile=1, checkpoint_gib=ck)
+    # the fixed tile heuristic: the autotuner's trial output and split-K workspace would add to the
+    # peak device memory this workload reports
+    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -327,8 +330,6 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         return L, db
 
     free_min = free0
-    one_step()   # the autotuner times each contraction shape the first time it is met: not timed
-    free_min = min(free_min, torch.cuda.mem_get_info(dev)[0])
     for _ in range(args.warmup):
         one_step()
         free_min = min(free_min, torch.cuda.mem_get_info(dev)[0])
@@ -349,7 +350,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     if ck == 0.0 and not args.no_policy_compare:
         # the same pass with the forward intermediates kept for the backward (64 GiB budget)
         _progress("timing the pass with the forward intermediates kept")
-        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, autotune=1, checkpoint_gib=64.0), dev)
+        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0), dev)
         sec = _time_passes(B, torch, plan_k, T0, dT0, 1, 1)
         kept = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
                 "plan_device_GB": plan_k.device_bytes() / 1e9, "checkpoint_gib": 64.0}
@@ -372,7 +373,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
         "metric": "HOTRG fwd+bwd RG-steps/s, Ising at beta_c, chi=64 (split-bf16 contractions, FP64 eigensolver)",
         "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": f"2D Ising at beta={beta}, HOTRG chi={chi}, {n} RG steps, forward + backward to dlnZ/dbeta",
-                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12, "autotune": 1,
+                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12, "autotune": 0,
                    "checkpoint_gib": ck, "checkpoint": ("one checkpoint per RG step, recompute inside the step"
                                                         if ck == 0.0 else "forward intermediates kept within the budget")},
         "peak_hbm": {"plan_device_GB": plan_bytes / 1e9, "torch_max_allocated_GB": peak_torch / 1e9,
