@@ -267,13 +267,14 @@ def test_gpu_mixed_vs_oracle_small(B, prec, case):
         assert _rel(g, go) < GRAD_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
-def test_gpu_mixed_vs_golden_chi48(B, prec):
+# the benchmark's configuration (three-plane split-bf16 with the tile autotuner) among them
+@pytest.mark.parametrize("prec,autotune", [("fp32", 0), ("bf16x3", 0), ("bf16x6", 0), ("bf16x6", 1)])
+def test_gpu_mixed_vs_golden_chi48(B, prec, autotune):
     from paper_1912_02780_amd import inputs as I
     gd = _golden("random_d4_seed0_chi48_n24")
     T0 = I.random_d4_T0(0)
-    _say(f"[gpu] mixed {prec} golden chi48")
-    lnZ, g, _, _ = _gpu(B, T0, 48, 24, None, contract=prec)
+    _say(f"[gpu] mixed {prec} golden chi48 autotune={autotune}")
+    lnZ, g, _, _ = _gpu(B, T0, 48, 24, None, contract=prec, autotune=autotune)
     go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
     _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.2e}  T0bar rel {_rel(g, go):.2e}")
     assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-6
