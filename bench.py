@@ -13,8 +13,9 @@ Workloads (--workload):
       bounded sample of the same workload.  The plan keeps the forward intermediates the backward
       pass would otherwise recompute (the library default, a 64 GiB budget); the same pass with one
       checkpoint per RG step and the recompute inside the backward step (checkpoint_gib = 0) is
-      timed beside it and reported under "recompute_in_step".  The tile autotuner is on: one
-      untimed pass before the warm-up times every contraction shape's configurations once.
+      timed beside it and reported under "recompute_in_step", and the same pass run as a
+      one-instance batch replayed from a captured HIP graph under "graph_replay".  The tile autotuner
+      is on: one untimed pass before the warm-up times every contraction shape's configurations once.
   batch256
       256 Ising temperatures beta_i = 0.30 + 0.30 i / 255 with chi_i = (32, 16, 24)[i mod 3], 30 steps
       each, forward + backward to d(lnZ/N)/dbeta for every instance, replayed from one captured HIP
@@ -218,6 +219,26 @@ def bench_chi48(args, B, I, torch, np, dev):
         out["recompute_in_step"] = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
                                     "plan_device_GB": plan0.device_bytes() / 1e9, "checkpoint_gib": 0.0}
         plan0.close()
+    if not args.no_policy_compare:
+        # the same pass as a one-instance batch replayed from a captured HIP graph (the schedule
+        # recorded by an adaptive run: no host round trips, no launch gaps)
+        _progress("timing the pass as a graph replay")
+        bt = B.dtrg_batch_create(D, [chi], n, opts, dev)
+        T0s = T0.reshape((1,) + tuple(T0.shape)).contiguous()
+        Tb = torch.empty_like(T0s)
+        B.dtrg_batch_run(bt, T0s, None, 1.0, backward=True, replay=False, T0bar=Tb)
+        for _ in range(max(1, args.warmup)):   # the first replay captures the graph
+            B.dtrg_batch_run(bt, T0s, None, 1.0, backward=True, replay=True, T0bar=Tb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Lr, _, _ = B.dtrg_batch_run(bt, T0s, None, 1.0, backward=True, replay=True, T0bar=Tb)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        rep = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
+               "lnZ_per_site": float(Lr[0]), "T0bar_equal_to_plan_pass": bool(torch.equal(Tb[0], g))}
+        out["graph_replay"] = rep
+        bt.close()
     if not args.no_cpu_baseline:
         _progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(chi, n, D)
