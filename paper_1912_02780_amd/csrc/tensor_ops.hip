@@ -66,14 +66,35 @@ PermK make_perm(const PermDesc& d, int np = 1) {
     return k;
 }
 
+// input offset of output element idx; 32-bit division when the instance has fewer than 2^31
+// elements (a 64-bit division is a long instruction sequence on the GPU)
 __device__ inline i64 perm_src(const PermK& p, i64 idx) {
     i64 off = 0;
+    if (p.total < (1LL << 31)) {
+        unsigned u = (unsigned)idx;
+        for (int i = p.rank - 1; i >= 0; --i) {
+            const unsigned d = (unsigned)p.odims[i], q = u / d;
+            off += (i64)(u - q * d) * p.istr[i];
+            u = q;
+        }
+        return off;
+    }
     for (int i = p.rank - 1; i >= 0; --i) {
         const i64 q = idx / p.odims[i];
         off += (idx - q * p.odims[i]) * p.istr[i];
         idx = q;
     }
     return off;
+}
+
+// output offset of output element i (rows of rowlen elements at stride out_ld, or dense)
+__device__ inline i64 perm_dst(const PermK& p, i64 i) {
+    if (p.rowlen <= 0) return i;
+    if (p.total < (1LL << 31)) {
+        const unsigned u = (unsigned)i, r = (unsigned)p.rowlen, q = u / r;
+        return (i64)q * p.out_ld + (u - q * r);
+    }
+    return (i / p.rowlen) * p.out_ld + i % p.rowlen;
 }
 
 // x blocks per instance for n elements, keeping the whole grid near 8192 blocks
@@ -115,8 +136,7 @@ __global__ __launch_bounds__(256) void permute_kernel(const TI* __restrict__ in,
     const double a = scale ? alpha * scale[z * scale_bs] : alpha;
     const i64 ob = z * out_bs;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < p.total; i += (i64)gridDim.x * blockDim.x) {
-        const i64 o = p.rowlen > 0 ? (i / p.rowlen) * p.out_ld + i % p.rowlen : i;
-        put_elem<OUT>(out, ob + o, p.out_ps, a * (double)in[perm_src(p, i)], beta);
+        put_elem<OUT>(out, ob + perm_dst(p, i), p.out_ps, a * (double)in[perm_src(p, i)], beta);
     }
 }
 
