@@ -22,7 +22,8 @@
  * The caller owns T0_dev, T0bar_dev and the stream.  A plan owns its checkpoints and workspaces
  * (device memory allocated with hipMalloc when the plan is created, released by
  * dtrg_plan_destroy).  A step's checkpoint is its normalised input tensor, its isometry and its
- * spectrum; the backward recomputes the rest of the step from it.  The contraction kernel's
+ * spectrum; the backward recomputes the rest of the step from it, except the forward
+ * intermediates the plan keeps within dtrg_options.checkpoint_gib.  The contraction kernel's
  * split-K scratch (and the autotuner's trial output) grows on the first forward and backward of a
  * plan; later calls on the plan allocate no device memory.
  *
