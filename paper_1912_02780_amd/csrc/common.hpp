@@ -221,9 +221,11 @@ constexpr int kJacobiMax = 96;
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
                 int nb, int max_sweeps, int* sweeps_dev, hipStream_t s);
 // Upper-triangular R^{-1} of the Cholesky factor of (S + shift * I), S b x b (ld b); the
-// shift is shift_rel * trace(S).  flag_dev[i] |= 2 on a non-positive pivot.
+// shift is shift_rel * trace(S).  flag_dev[i] |= 2 on a non-positive pivot.  near_dev (nullable):
+// near_dev[i] = 1 if every entry of S_i is within near_tol of the identity's, else 0.  skip_dev
+// (nullable): instances with skip_dev[i] != 0 get R^{-1} = I without a factorisation.
 void chol_inverse(const double* S, i64 s_bs, int b, double shift_rel, double* Rinv, i64 r_bs, int nb, int* flag_dev,
-                  hipStream_t s);
+                  hipStream_t s, const int* skip_dev = nullptr, int* near_dev = nullptr, double near_tol = 0.0);
 // norms of the b columns of V (n x b, ld ldv) -> out[0..b)
 void col_norms(const double* V, int n, int b, int ldv, i64 v_bs, double* out_dev, i64 out_bs, int nb, hipStream_t s);
 // V[:, j] /= nrm[j] where nrm[j] > tiny * max(nrm); other columns replaced by hash noise

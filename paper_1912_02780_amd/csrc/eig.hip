@@ -9,7 +9,9 @@
 //   accuracy.  (One pass over the disjoint 2 x 2 blocks of pair rows and pair columns, with one
 //   barrier less per round, measured 40% slower: its LDS accesses scatter over the banks.)
 // * chol_inverse: Cholesky of a (shifted) b x b Gram in LDS and the inverse of its triangular
-//   factor, for CholeskyQR of the subspace block.
+//   factor, for CholeskyQR of the subspace block.  It can report whether the Gram is the identity
+//   to a tolerance (the block is nearly orthonormal), and a later call can skip its work on that
+//   report and return the identity.
 // * element-wise helpers for Ritz residuals, column normalisation, the broadened inverse gaps of
 //   the eigenvector adjoint and the Chebyshev expansion of the complement (interval, node values,
 //   three-term recurrence, coefficient tail and boundedness checks).
@@ -177,20 +179,40 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
 // updates run on a 16 x 16 thread grid, one barrier per column (or row).
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, i64 s_bs, int b,
                                                        double shift_rel, double* __restrict__ Rinv, i64 r_bs,
-                                                       int* flag) {
+                                                       int* flag, const int* __restrict__ skip, int* __restrict__ near,
+                                                       double near_tol) {
     __shared__ double L[JM * JLD];
     __shared__ double Xs[JM * JLD];
     __shared__ double tr;
+    __shared__ double wmax[CT / 64];
     const int tid = threadIdx.x;
     S += blockIdx.x * s_bs;
     Rinv += blockIdx.x * r_bs;
     flag += blockIdx.x;
+    if (skip && skip[blockIdx.x]) {
+        // the block is orthonormal to working accuracy already: R^{-1} = I
+        for (int idx = tid; idx < b * b; idx += CT) Rinv[(i64)(idx / b) * b + idx % b] = (idx / b == idx % b) ? 1.0 : 0.0;
+        return;
+    }
+    double dev = 0.0;
     for (int i = tid; i < b * b; i += CT) {
         const int r = i / b, c = i % b;
-        L[r * JLD + c] = 0.5 * (S[(i64)r * b + c] + S[(i64)c * b + r]);
+        const double v = 0.5 * (S[(i64)r * b + c] + S[(i64)c * b + r]);
+        L[r * JLD + c] = v;
         Xs[r * JLD + c] = (r == c) ? 1.0 : 0.0;
+        dev = fmax(dev, fabs(v - (r == c ? 1.0 : 0.0)));   // fmax drops a NaN: checked below
+        if (!isfinite(v)) dev = INFINITY;
+    }
+    if (near) {
+        for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
+        if ((tid & 63) == 0) wmax[tid >> 6] = dev;
     }
     __syncthreads();
+    if (near && tid == 0) {
+        double m = 0.0;
+        for (int w = 0; w < CT / 64; ++w) m = fmax(m, wmax[w]);
+        near[blockIdx.x] = m <= near_tol ? 1 : 0;
+    }
     if (tid == 0) {
         double s = 0.0;
         for (int i = 0; i < b; ++i) s += L[i * JLD + i];
@@ -454,10 +476,11 @@ void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 
 }
 
 void chol_inverse(const double* S, i64 s_bs, int b, double shift_rel, double* Rinv, i64 r_bs, int nb, int* flag_dev,
-                  hipStream_t s) {
+                  hipStream_t s, const int* skip_dev, int* near_dev, double near_tol) {
     DTRG_REQUIRE(b >= 1 && b <= kJacobiMax, DTRG_EINVAL, "chol_inverse: b out of range");
     DTRG_REQUIRE(flag_dev, DTRG_EINVAL, "chol_inverse: flag array required");
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(nb), dim3(CT), 0, s, S, s_bs, b, shift_rel, Rinv, r_bs, flag_dev);
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(nb), dim3(CT), 0, s, S, s_bs, b, shift_rel, Rinv, r_bs, flag_dev,
+                       skip_dev, near_dev, near_tol);
     DTRG_HIP(hipGetLastError());
 }
 

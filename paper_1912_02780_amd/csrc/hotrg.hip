@@ -63,7 +63,7 @@ i64 dtrg_plan::cap_bytes(const void* ptr) const {
 size_t dtrg_plan::bytes() const {
     size_t t = 0;
     for_each_buf(*this, [&](const void*, size_t nbytes) { t += nbytes; });
-    return t + flags.bytes() + misc.bytes();
+    return t + flags.bytes() + misc.bytes() + orth.bytes();
 }
 
 namespace dtrg {
@@ -401,7 +401,11 @@ constexpr int kFlagErrors = kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlag
 
 // Orthonormalise the n x b blocks V (instance stride vbs) in place: a shifted CholeskyQR pass
 // (stable for any condition number up to 1/u, which the normalised iterate can reach when the
-// Gram has a cluster of noise-level eigenvalues) followed by two plain passes.
+// Gram has a cluster of noise-level eigenvalues) followed by two plain passes.  The third pass is
+// skipped, on the device and per instance, when the second finds its input orthonormal to within
+// kOrthNear (an input that close has condition number below 1 + b kOrthNear, so that one pass
+// leaves it orthonormal to working accuracy); this is the usual case once the iteration converges.
+constexpr double kOrthNear = 1e-6;
 void orthonormalise(Ctx& c, double* V, double* Vtmp, i64 vbs, int n, int b) {
     dtrg_plan* P = c.P;
     double* cur = V;
@@ -416,7 +420,8 @@ void orthonormalise(Ctx& c, double* V, double* Vtmp, i64 vbs, int n, int b) {
         set_bs(g, vbs, vbs, P->Sg.bs);
         c.gemm(g);
         const double shift = pass == 0 ? 11.0 * ((double)n * b + (double)b * (b + 1)) * std::ldexp(1.0, -53) : 0.0;
-        chol_inverse(P->Sg.p, P->Sg.bs, b, shift, P->Rinv.p, P->Rinv.bs, P->nb, P->flags.p, c.s);
+        chol_inverse(P->Sg.p, P->Sg.bs, b, shift, P->Rinv.p, P->Rinv.bs, P->nb, P->flags.p, c.s,
+                     pass == 2 ? P->orth.p : nullptr, pass == 1 ? P->orth.p : nullptr, kOrthNear);
         GemmOp h;
         h.M = n; h.N = b; h.K = b;
         h.A = cur; h.lda = b;
@@ -655,6 +660,7 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     P->scal.alloc_inst(nb, P->S);
     P->flags.alloc_inst(nb, 1);
     P->misc.alloc(4);
+    P->orth.alloc_inst(nb, 1);
     P->steps.clear();
     P->steps.resize(sh.size());
     for (size_t k = 0; k < sh.size(); ++k) {
