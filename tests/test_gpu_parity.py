@@ -281,6 +281,29 @@ def test_gpu_mixed_vs_golden_chi48(B, prec, autotune):
     assert _rel(g, go) < GRAD_TOL[prec]
 
 
+# chi = 36: every contraction of a full-size step is ragged against the tiles (the join is
+# M = 36^3 = 46656 by N = 1296 by K = 1296: 182.25 row tiles of 256, 10.1 column tiles of 128, and a
+# partial last K tile of 32), and the subspace block (b = 72) is not a multiple of a tile either
+@pytest.fixture(scope="module")
+def oracle_chi36():
+    from oracle import hotrg as O
+    from paper_1912_02780_amd import inputs as I
+    T0 = I.random_d4_T0(1)
+    _say("[gpu] oracle for random_d4_seed1_chi36_n7 on the host")
+    Lo, go, _ = O.lnZ_and_grad(T0, 36, 7)
+    return T0, Lo, go
+
+
+@pytest.mark.parametrize("prec,autotune,ltol,gtol", [("fp64", 0, 1e-10, 1e-10), ("bf16x6", 1, 1e-6, 1e-5)])
+def test_gpu_ragged_mid_size_vs_oracle(B, oracle_chi36, prec, autotune, ltol, gtol):
+    T0, Lo, go = oracle_chi36
+    _say(f"[gpu] ragged chi36 n7 {prec} autotune={autotune}")
+    lnZ, g, _, _ = _gpu(B, T0, 36, 7, None, contract=prec, autotune=autotune)
+    _say(f"    lnZ rel {abs(lnZ / Lo - 1):.2e}  T0bar rel {_rel(g, go):.2e}")
+    assert abs(lnZ / Lo - 1) < ltol
+    assert _rel(g, go) < gtol
+
+
 # ---------------------------------------------------------------------------------------------
 # finite differences in beta at full size (FP64 path), and the chi = 64 critical run
 # ---------------------------------------------------------------------------------------------
