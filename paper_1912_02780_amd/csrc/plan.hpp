@@ -105,8 +105,9 @@ struct dtrg_plan {
     dtrg::DevBuf<double> scal;  // nb x S
     dtrg::DevBuf<int> flags;    // nb error flags
     dtrg::DevBuf<int> misc;     // 4 ints: Jacobi sweep counter
-    dtrg::DevBuf<int> orth;     // nb ints: the subspace block was orthonormal to working accuracy
-                                // before the second CholeskyQR pass (the third is skipped)
+    dtrg::DevBuf<int> orth;     // nb ints: the second CholeskyQR pass found its input orthonormal
+                                // to within 1e-6, so that its output is orthonormal to working
+                                // accuracy and the third pass is skipped
     std::vector<double> scal_h; // host copy of scal after a pass (adaptive passes, or on demand)
     std::vector<int> flags_h;
     dtrg::Scratch ws;
