@@ -15,7 +15,8 @@ Workloads (--workload):
       checkpoint per RG step and the recompute inside the backward step (checkpoint_gib = 0) is
       timed beside it and reported under "recompute_in_step", and the same pass run as a
       one-instance batch replayed from a captured HIP graph under "graph_replay".  The tile autotuner
-      is on: one untimed pass before the warm-up times every contraction shape's configurations once.
+      is on (--autotune 0: the fixed heuristic): one untimed pass before the warm-up times every
+      contraction shape's configurations once.
   batch256
       256 Ising temperatures beta_i = 0.30 + 0.30 i / 255 with chi_i = (32, 16, 24)[i mod 3], 30 steps
       each, forward + backward to d(lnZ/N)/dbeta for every instance, replayed from one captured HIP
@@ -34,7 +35,8 @@ Workloads (--workload):
       trial buffers would add to the reported peak device memory).
 
     python bench.py [--workload chi48|batch256|ising_chi64] [--steps K] [--warmup W]
-                    [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--no-cpu-baseline]
+                    [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--autotune 0|1]
+                    [--no-cpu-baseline]
 """
 
 from __future__ import annotations
@@ -169,7 +171,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     D, chi, n = 4, args.chi, args.n_steps
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
     ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
-    opts = B.default_options(contract=args.contract, autotune=1, profile=1, checkpoint_gib=ck)
+    opts = B.default_options(contract=args.contract, autotune=args.autotune, profile=1, checkpoint_gib=ck)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -203,7 +205,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         "ms_per_step": wall / args.steps * 1e3,
         "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
                                 f"{n} RG steps, forward + backward to dlnZ/dT0"),
-                   "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": 1,
+                   "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": args.autotune,
                    "checkpoint_gib": ck, "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
                              traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None),
@@ -213,7 +215,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
-        opts0 = B.default_options(contract=args.contract, autotune=1, checkpoint_gib=0.0)
+        opts0 = B.default_options(contract=args.contract, autotune=args.autotune, checkpoint_gib=0.0)
         plan0 = B.dtrg_plan_create(D, chi, n, opts0, dev)
         sec = _time_passes(B, torch, plan0, T0, None, 1, max(1, min(args.steps, 3)))
         out["recompute_in_step"] = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
@@ -421,6 +423,9 @@ def main():
     ap.add_argument("--chi", type=int, default=None, help="chi48: 48 by default; ising_chi64: 64")
     ap.add_argument("--n-steps", type=int, default=None, help="chi48: 24 by default; ising_chi64: 30")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="chi48: time every contraction shape's tile configurations once (1) or use the fixed "
+                         "heuristic (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-policy-compare", action="store_true",
                     help="skip the pass timed with the other checkpoint policy (for profiles of one policy)")
