@@ -27,14 +27,17 @@ namespace {
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
 constexpr int JT = 512;    // Jacobi: 8 waves (one wave is slower: the row and column updates need the width)
-constexpr int JG = JT / 128;                 // Jacobi: groups of 128 threads
-constexpr int JS = (JM / 2 + JG - 1) / JG;   // pair slots per group
 static_assert(JM <= 128, "one row or column element per thread of a group");
 constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
+// GW: threads per group (one row or column element each, so n <= GW): 128, or 64 for n <= 64, which
+// keeps every thread busy there and gives each group half as many pairs
+template <int GW>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
                                                      double* __restrict__ lam, i64 lam_bs, double* __restrict__ Vout,
                                                      int ldv, i64 v_bs, int max_sweeps, int* sweeps_out) {
+    constexpr int JG = JT / GW;                  // groups
+    constexpr int JS = (JM / 2 + JG - 1) / JG;   // pair slots per group
     __shared__ double A[JM * JLD];
     __shared__ double V[JM * JLD];
     __shared__ int rp[JM / 2], rq[JM / 2];
@@ -99,11 +102,11 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
             __syncthreads();
             const int na = nact;
             if (na > 0) {
-                // Slot i = g + JG t of group g (128 threads) is one active pair; thread l of the group
+                // Slot i = g + JG t of group g (GW threads) is one active pair; thread l of the group
                 // takes column l of its two rows, then row l of its two columns (and of V).  A
                 // round's pairs are disjoint, so a thread issues every LDS read of a pass before its
                 // first store: one round trip per pass instead of one per pair.
-                const int g = tid >> 7, l = tid & 127;
+                const int g = tid / GW, l = tid % GW;
                 const bool lv = l < n;
                 const int lc = lv ? l : n - 1;
                 const int ns = (na - g + JG - 1) / JG;   // active slots of this group (wave-uniform)
@@ -470,8 +473,12 @@ dim3 grid2(i64 n, int nb) {
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
                 int nb, int max_sweeps, int* sweeps_dev, hipStream_t s) {
     DTRG_REQUIRE(n >= 1 && n <= kJacobiMax, DTRG_EINVAL, "jacobi_eig: n out of range");
-    hipLaunchKernelGGL(jacobi_kernel, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv, v_bs,
-                       max_sweeps, sweeps_dev);
+    if (n <= 64)
+        hipLaunchKernelGGL(jacobi_kernel<64>, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv,
+                           v_bs, max_sweeps, sweeps_dev);
+    else
+        hipLaunchKernelGGL(jacobi_kernel<128>, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv,
+                           v_bs, max_sweeps, sweeps_dev);
     DTRG_HIP(hipGetLastError());
 }
 
