@@ -26,13 +26,14 @@ namespace {
 
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
-constexpr int JT = 512;    // Jacobi: 8 waves (one wave is slower: the row and column updates need the width)
 static_assert(JM <= 128, "one row or column element per thread of a group");
 constexpr int CT = 256;    // Cholesky / inverse: 4 waves
 
-// GW: threads per group (one row or column element each, so n <= GW): 128, or 64 for n <= 64, which
-// keeps every thread busy there and gives each group half as many pairs
-template <int GW>
+// GW: threads per group, one row (or column) element each, so n <= GW; JT threads in all (a single
+// wave is slower: the row and column updates need the width).  12 waves, in groups of GW = 64 for
+// n <= 64 and of GW = 96 for n <= 96 (a group may then straddle two waves): every thread of a group
+// has an element, and the 12 or 8 groups share the pairs of a round.
+template <int GW, int JT>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
                                                      double* __restrict__ lam, i64 lam_bs, double* __restrict__ Vout,
                                                      int ldv, i64 v_bs, int max_sweeps, int* sweeps_out) {
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
                 const int g = tid / GW, l = tid % GW;
                 const bool lv = l < n;
                 const int lc = lv ? l : n - 1;
-                const int ns = (na - g + JG - 1) / JG;   // active slots of this group (wave-uniform)
+                const int ns = (na - g + JG - 1) / JG;   // active slots of this group
                 int sp[JS], sq[JS];
                 double sc[JS], ss[JS];
 #pragma unroll
@@ -473,12 +474,13 @@ dim3 grid2(i64 n, int nb) {
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
                 int nb, int max_sweeps, int* sweeps_dev, hipStream_t s) {
     DTRG_REQUIRE(n >= 1 && n <= kJacobiMax, DTRG_EINVAL, "jacobi_eig: n out of range");
+    static_assert(kJacobiMax <= 96, "the widest Jacobi group has 96 threads");
     if (n <= 64)
-        hipLaunchKernelGGL(jacobi_kernel<64>, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv,
-                           v_bs, max_sweeps, sweeps_dev);
+        hipLaunchKernelGGL((jacobi_kernel<64, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
+                           ldv, v_bs, max_sweeps, sweeps_dev);
     else
-        hipLaunchKernelGGL(jacobi_kernel<128>, dim3(nb), dim3(JT), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V, ldv,
-                           v_bs, max_sweeps, sweeps_dev);
+        hipLaunchKernelGGL((jacobi_kernel<96, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
+                           ldv, v_bs, max_sweeps, sweeps_dev);
     DTRG_HIP(hipGetLastError());
 }
 
