@@ -27,7 +27,8 @@ namespace {
 constexpr int JM = kJacobiMax;
 constexpr int JLD = JM + 1;
 static_assert(JM <= 128, "one row or column element per thread of a group");
-constexpr int CT = 256;    // Cholesky / inverse: 4 waves
+constexpr int CG = 32;              // Cholesky / inverse: a CG x CG thread grid for the updates
+constexpr int CT = CG * CG;         // (16 waves)
 
 // GW: threads per group, one row (or column) element each, so n <= GW; JT threads in all (a single
 // wave is slower: the row and column updates need the width).  12 waves, in groups of GW = 64 for
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
 // Lower Cholesky factor L of (S + shift I) in LDS (right-looking, rank-1 trailing updates in
 // parallel), then X = L^{-1} by the same elimination applied to the identity (row k of X is
 // final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.  The
-// updates run on a 16 x 16 thread grid, one barrier per column (or row).
+// updates run on a CG x CG thread grid, one barrier per column (or row).
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, i64 s_bs, int b,
                                                        double shift_rel, double* __restrict__ Rinv, i64 r_bs,
                                                        int* flag, const int* __restrict__ skip, int* __restrict__ near,
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
     // Cholesky, right-looking, one barrier per column: phase k takes the pivot and column k as phase
     // k-1 left them, applies the rank-1 update with the scaled column to the trailing lower
     // triangle, and writes back the scaled column k-1, which phase k no longer reads
-    const int tx = tid & 15, ty = tid >> 4;
+    const int tx = tid % CG, ty = tid / CG;
     double dprev = 1.0, rprev = 1.0;
     for (int k = 0; k <= b; ++k) {
         if (k > 0) {
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
             d = 1e-300;
         }
         const double dk = sqrt(d), rdk = 1.0 / dk;
-        for (int i = k + 1 + ty; i < b; i += 16) {
+        for (int i = k + 1 + ty; i < b; i += CG) {
             const double lik = L[i * JLD + k] * rdk;
-            for (int j = k + 1 + tx; j <= i; j += 16) L[i * JLD + j] -= lik * (L[j * JLD + k] * rdk);
+            for (int j = k + 1 + tx; j <= i; j += CG) L[i * JLD + j] -= lik * (L[j * JLD + k] * rdk);
         }
         dprev = dk;
         rprev = rdk;
@@ -260,9 +261,9 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
             for (int j = tid; j < k; j += CT) Xs[(k - 1) * JLD + j] *= inv_prev;
         if (k == b) break;
         const double inv = 1.0 / L[k * JLD + k];
-        for (int i = k + 1 + ty; i < b; i += 16) {
+        for (int i = k + 1 + ty; i < b; i += CG) {
             const double lik = L[i * JLD + k];
-            for (int j = tx; j <= k; j += 16) Xs[i * JLD + j] -= lik * (Xs[k * JLD + j] * inv);
+            for (int j = tx; j <= k; j += CG) Xs[i * JLD + j] -= lik * (Xs[k * JLD + j] * inv);
         }
         inv_prev = inv;
         __syncthreads();
