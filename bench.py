@@ -58,6 +58,10 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (2 bf16 planes, 3 products, fp32 accumulate)",
          "bf16x6": "bf16x6 (3 bf16 planes, 6 products, fp32 accumulate)"}
 DEFAULT_CONTRACT = {"chi48": "bf16x6", "batch256": "bf16x6", "ising_chi64": "bf16x6"}
+# chi = 64 at beta_c: FP32 accumulation chains of at most 512 products in the contractions with outputs
+# of at most chi^4 (the long-K adjoints; FP64 sums of the chunks), which brings d(lnZ/N)/dbeta from
+# 1.1e-5 to 5.5e-6 of the FP64 result for 2% of the pass
+CHI64_CHAIN = 512
 
 
 # L2-miss byte counters of the timed join kernel per launch, from two rocprofv3 --pmc passes over
@@ -103,10 +107,21 @@ def _threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(chi: int, n_steps: int, D: int = 4, seed: int = 0):
-    """Time the FP64 oracle on a bounded sample of the workload: the first 4 steps (forward +
-    backward, small bonds) and one full-size step (forward step and its adjoint, from the tensor
-    those 4 steps produce); extrapolate t(n) = t(first 4) + (n - 4) t(full step)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(chi, n_steps, D, seed, forward_only=False):
+    """Seconds of the FP64 oracle on a bounded sample of the workload: the first 4 steps (forward +
+    backward, small bonds) and one full-size step (forward step and its adjoint, from the tensor those
+    4 steps produce).  Returns (t_first4, t_full_forward, t_full_adjoint or None)."""
     import numpy as np
     from oracle import hotrg as O
     from paper_1912_02780_amd import inputs as I
@@ -123,16 +138,48 @@ def cpu_baseline(chi: int, n_steps: int, D: int = 4, seed: int = 0):
     X = T.shape[0]
     w = U[:, :kept].reshape(X, X, kept)
     _, _, Tn = O.project(T, w)
+    t_fwd = time.perf_counter() - t1
+    if forward_only:
+        return t_small, t_fwd, None
     rec = O.StepRecord(T=T, c=float(np.linalg.norm(Tn)), U=U, lam=lam, trace_G=t, G_hat=G_hat, A=A, B=Bm,
                        chi_kept=kept)
+    t2 = time.perf_counter()
     O.step_adjoint(rec, np.ones_like(Tn) / Tn.size, O.DEFAULT_BROADENING)
-    t_full = time.perf_counter() - t1
-    t_run = t_small + (n_steps - 4) * t_full
+    return t_small, t_fwd, time.perf_counter() - t2
+
+
+def cpu_baseline(chi: int, n_steps: int, D: int = 4, seed: int = 0, reps: int = 3):
+    """The FP64 oracle on this host, on a bounded sample of the workload (see _oracle_sample),
+    extrapolated to the whole pass: t(n) = t(first 4) + (n - 4) t(full-size step).  With every BLAS
+    thread: the median of `reps` samples.  With one thread: the first 4 steps and the full-size
+    forward step are timed and the full-size adjoint is scaled from it by the adjoint / forward ratio of
+    the multi-thread samples (the single-thread adjoint alone would take minutes)."""
+    import statistics
+    runs = [_oracle_sample(chi, n_steps, D, seed) for _ in range(reps)]
+    totals = [a + (n_steps - 4) * (b + c) for a, b, c in runs]
+    mid = sorted(range(reps), key=lambda i: totals[i])[reps // 2]
+    t_run = totals[mid]
+    t_small, t_fwd, t_adj = runs[mid]
+    ratio = statistics.median(c / b for _, b, c in runs)
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            s1, f1, _ = _oracle_sample(chi, n_steps, D, seed, forward_only=True)
+        t1_run = s1 + (n_steps - 4) * f1 * (1.0 + ratio)
+        one = {"value": n_steps / t1_run, "unit": "RG-steps/s", "cores": 1,
+               "sample": (f"one BLAS thread: first 4 steps {s1:.2f} s, full-size forward step {f1:.2f} s, its adjoint "
+                          f"taken as {ratio:.2f} x that (the multi-thread ratio); extrapolated to {n_steps} steps = "
+                          f"{t1_run:.1f} s")}
+    except Exception as e:  # pragma: no cover
+        one = {"error": str(e)}
     return {
         "value": n_steps / t_run, "unit": "RG-steps/s", "cores": int(_threads()), "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle on this host: forward+backward of the first 4 steps ({t_small:.2f} s) and one "
-                   f"full-size chi={chi} step (Gram, full eigh, projection, step adjoint: {t_full:.2f} s); "
-                   f"extrapolated to {n_steps} steps = {t_run:.1f} s"),
+        "cpu_model": _cpu_model(), "reps": reps,
+        "sample": (f"FP64 NumPy oracle on this host, median of {reps}: forward+backward of the first 4 steps "
+                   f"({t_small:.2f} s) and one full-size chi={chi} step (Gram, full eigh, projection {t_fwd:.2f} s; "
+                   f"step adjoint {t_adj:.2f} s); extrapolated to {n_steps} steps = {t_run:.1f} s"),
+        "one_thread": one,
     }
 
 
@@ -171,7 +218,9 @@ def bench_chi48(args, B, I, torch, np, dev):
     D, chi, n = 4, args.chi, args.n_steps
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
     ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
-    opts = B.default_options(contract=args.contract, autotune=args.autotune, profile=1, checkpoint_gib=ck)
+    chain = 4096 if args.max_fp32_chain is None else args.max_fp32_chain
+    opts = B.default_options(contract=args.contract, autotune=args.autotune, profile=1, checkpoint_gib=ck,
+                             max_fp32_chain=chain)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -206,7 +255,8 @@ def bench_chi48(args, B, I, torch, np, dev):
         "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
                                 f"{n} RG steps, forward + backward to dlnZ/dT0"),
                    "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": args.autotune,
-                   "checkpoint_gib": ck, "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
+                   "checkpoint_gib": ck, "max_fp32_chain": chain, "lnZ_per_site": L,
+                   "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
                              traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None),
         **err,
@@ -215,7 +265,8 @@ def bench_chi48(args, B, I, torch, np, dev):
     if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
-        opts0 = B.default_options(contract=args.contract, autotune=args.autotune, checkpoint_gib=0.0)
+        opts0 = B.default_options(contract=args.contract, autotune=args.autotune, checkpoint_gib=0.0,
+                                  max_fp32_chain=chain)
         plan0 = B.dtrg_plan_create(D, chi, n, opts0, dev)
         sec = _time_passes(B, torch, plan0, T0, None, 1, max(1, min(args.steps, 3)))
         out["recompute_in_step"] = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
@@ -241,9 +292,36 @@ def bench_chi48(args, B, I, torch, np, dev):
                "lnZ_per_site": float(Lr[0]), "T0bar_equal_to_plan_pass": bool(torch.equal(Tb[0], g))}
         out["graph_replay"] = rep
         bt.close()
+    if not args.no_policy_compare and args.contract != "fp64":
+        # the plain FP64 GPU path on the same workload (same checkpoint policy and tuner): the
+        # mixed-precision speedup at the accuracy reported above
+        _progress("timing the FP64 path")
+        o64 = B.default_options(contract="fp64", autotune=args.autotune, checkpoint_gib=ck)
+        p64 = B.dtrg_plan_create(D, chi, n, o64, dev)
+        L64 = B.dtrg_plan_forward(p64, T0)     # (tuning pass)
+        g64, _ = B.dtrg_hotrg_backward(p64, 1.0)
+        sec = _time_passes(B, torch, p64, T0, None, 0, max(1, min(args.steps, 2)))
+        f64 = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3, "contract": "fp64"}
+        if err:
+            f64["lnZ_rel_err_vs_oracle"] = abs(L64 / gd["lnZ_per_site"] - 1.0)
+            f64["T0bar_rel_err_vs_oracle"] = float(np.linalg.norm(g64.cpu().numpy() - go) / np.linalg.norm(go))
+        out["fp64_path"] = f64
+        out["speedup_vs_fp64_path"] = out["value"] / f64["value"]
+        p64.close()
     if not args.no_cpu_baseline:
         _progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(chi, n, D)
+    if not args.no_extra_workloads and (chi, n) == (48, 24):
+        # the batched and chi = 64 workloads, compact (a few timed repetitions each), so that one
+        # default run reports all three
+        sub_args = argparse.Namespace(**vars(args))
+        sub_args.steps, sub_args.warmup, sub_args.compact = 2, 1, True
+        sub_args.checkpoint_gib = None
+        for name, fn, chi_s, n_s in (("batch256", bench_batch256, 48, 24), ("ising_chi64", bench_ising_chi64, 64, 30)):
+            _progress(f"compact {name}")
+            sub_args.chi, sub_args.n_steps = chi_s, n_s
+            out[name] = fn(sub_args, B, I, torch, np, dev)
+            torch.cuda.empty_cache()
     return out
 
 
@@ -265,13 +343,15 @@ def bench_batch256(args, B, I, torch, np, dev):
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     _progress(f"first adaptive run (with tuning) {t_first:.1f} s")
-    batch.profile(reset=True)
-    t0 = time.perf_counter()
-    L, _, d = B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=False, T0bar=T0bar)
-    torch.cuda.synchronize()
-    t_adaptive = time.perf_counter() - t0
-    launches, ms, flops = batch.profile(reset=True)
-    _progress(f"second adaptive run {t_adaptive:.1f} s")
+    t_adaptive, launches, ms, flops = None, 0, 0.0, 0.0
+    if not getattr(args, "compact", False):
+        batch.profile(reset=True)
+        t0 = time.perf_counter()
+        L, _, d = B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=False, T0bar=T0bar)
+        torch.cuda.synchronize()
+        t_adaptive = time.perf_counter() - t0
+        launches, ms, flops = batch.profile(reset=True)
+        _progress(f"second adaptive run {t_adaptive:.1f} s")
     for _ in range(max(1, args.warmup)):   # the first replay captures the graph
         B.dtrg_batch_run(batch, T0s, dT0s, 1.0, backward=True, replay=True, T0bar=T0bar)
     torch.cuda.synchronize()
@@ -297,7 +377,7 @@ def bench_batch256(args, B, I, torch, np, dev):
     seq_s = 0.0
     sample = {}
     for c in sorted(set(int(x) for x in chis)):
-        idx = [i for i in range(n_inst) if chis[i] == c][:args.seq_sample + 1]
+        idx = [i for i in range(n_inst) if chis[i] == c][:(1 if getattr(args, "compact", False) else args.seq_sample) + 1]
         plan = B.dtrg_plan_create(2, c, n, None, dev)
         ts = []
         for j, i in enumerate(idx):
@@ -314,6 +394,7 @@ def bench_batch256(args, B, I, torch, np, dev):
         sample[f"chi{c}"] = per
         seq_s += per * int((chis == c).sum())
     seq_value = n_inst * n / seq_s
+    batch.close()
     return {
         "metric": "HOTRG fwd+bwd aggregate RG-steps/s, 256 Ising temperatures with mixed chi (batched, graph replay)",
         "value": value, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
@@ -342,9 +423,10 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
     dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
     ck = 0.0 if args.checkpoint_gib is None else args.checkpoint_gib
+    chain = CHI64_CHAIN if args.max_fp32_chain is None else args.max_fp32_chain
     # the fixed tile heuristic: the autotuner's trial output and split-K workspace would add to the
     # peak device memory this workload reports
-    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck)
+    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck, max_fp32_chain=chain)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -369,11 +451,35 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     plan_bytes = plan.device_bytes()
     peak_torch = torch.cuda.max_memory_allocated(dev)
     plan.close()
+    golden = {}
+    gpath = os.path.join(ROOT, "tests", "golden", f"ising_b{beta}_chi{chi}_n{n}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gd = json.load(f)
+        golden = {"lnZ_rel_err_vs_oracle": abs(L / gd["lnZ_per_site"] - 1.0),
+                  "dlnZ_dbeta_rel_err_vs_oracle": abs(db / gd["dlnZ_dbeta"] - 1.0)}
+    common = {
+        "config": {"workload": f"2D Ising at beta={beta}, HOTRG chi={chi}, {n} RG steps, forward + backward to dlnZ/dbeta",
+                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12, "autotune": 0,
+                   "max_fp32_chain": chain, "max_fp32_chain_wide": 4096,
+                   "checkpoint_gib": ck, "checkpoint": ("one checkpoint per RG step, recompute inside the step"
+                                                        if ck == 0.0 else "forward intermediates kept within the budget")},
+        "peak_hbm": {"plan_device_GB": plan_bytes / 1e9, "torch_max_allocated_GB": peak_torch / 1e9,
+                     "hipMemGetInfo_used_increase_GB": (free0 - free_min) / 1e9, "total_GB": total / 1e9},
+        "lnZ_per_site": L, "dlnZ_dbeta": db, **golden,
+        "energy_rel_err_vs_onsager": abs(db / float(E.onsager_dlnZ_dbeta(beta)) - 1),
+        "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)"),
+    }
+    if getattr(args, "compact", False):
+        return {"metric": "HOTRG fwd+bwd RG-steps/s, Ising at beta_c, chi=64 (split-bf16 contractions, FP64 eigensolver)",
+                "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
+                "steps": args.steps, "warmup": args.warmup, **common}
     kept = None
     if ck == 0.0 and not args.no_policy_compare:
         # the same pass with the forward intermediates kept for the backward (64 GiB budget)
         _progress("timing the pass with the forward intermediates kept")
-        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0), dev)
+        plan_k = B.dtrg_plan_create(D, chi, n, B.default_options(contract=args.contract, checkpoint_gib=64.0,
+                                                                 max_fp32_chain=chain), dev)
         sec = _time_passes(B, torch, plan_k, T0, dT0, 1, 1)
         kept = {"value": n / sec, "unit": "RG-steps/s", "ms_per_step": sec * 1e3,
                 "plan_device_GB": plan_k.device_bytes() / 1e9, "checkpoint_gib": 64.0}
@@ -391,22 +497,14 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     fd2 = (lnZ64(beta + h / 2) - lnZ64(beta - h / 2)) / h
     rich = (4 * fd2 - fd) / 3
     p64.close()
-    u_ex = float(E.onsager_dlnZ_dbeta(beta))
     return {
         "metric": "HOTRG fwd+bwd RG-steps/s, Ising at beta_c, chi=64 (split-bf16 contractions, FP64 eigensolver)",
         "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
-        "config": {"workload": f"2D Ising at beta={beta}, HOTRG chi={chi}, {n} RG steps, forward + backward to dlnZ/dbeta",
-                   "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "eig_broadening": 1e-12, "autotune": 0,
-                   "checkpoint_gib": ck, "checkpoint": ("one checkpoint per RG step, recompute inside the step"
-                                                        if ck == 0.0 else "forward intermediates kept within the budget")},
-        "peak_hbm": {"plan_device_GB": plan_bytes / 1e9, "torch_max_allocated_GB": peak_torch / 1e9,
-                     "hipMemGetInfo_used_increase_GB": (free0 - free_min) / 1e9, "total_GB": total / 1e9},
-        "lnZ_per_site": L, "lnZ_fp64": L64, "lnZ_rel_err_vs_fp64": abs(L / L64 - 1),
-        "dlnZ_dbeta": db, "dlnZ_dbeta_fp64_ad": db64, "fd_central_h1e-5_fp64": fd, "fd_richardson_fp64": rich,
+        **common,
+        "lnZ_fp64": L64, "lnZ_rel_err_vs_fp64": abs(L / L64 - 1),
+        "dlnZ_dbeta_fp64_ad": db64, "fd_central_h1e-5_fp64": fd, "fd_richardson_fp64": rich,
         "rel_err_vs_fd_central": abs(db / fd - 1), "rel_err_vs_fd_richardson": abs(db / rich - 1),
         "fp64_ad_rel_err_vs_fd_richardson": abs(db64 / rich - 1), "rel_err_vs_fp64_ad": abs(db / db64 - 1),
-        "energy_rel_err_vs_onsager": abs(db / u_ex - 1),
-        "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)"),
         **({"with_kept_intermediates": kept} if kept else {}),
     }
 
@@ -432,6 +530,11 @@ def main():
     ap.add_argument("--checkpoint-gib", type=float, default=None,
                     help="device memory for kept forward intermediates (chi48 and batch256: 64 by default; "
                          "ising_chi64: 0, one checkpoint per RG step)")
+    ap.add_argument("--max-fp32-chain", type=int, default=None,
+                    help="longest FP32 accumulation chain of the small-output contractions (ising_chi64: 512 by "
+                         "default; others: the library default 4096)")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="chi48: skip the compact batch256 and ising_chi64 legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()

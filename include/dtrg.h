@@ -20,7 +20,8 @@
  * Memory.  Every pointer whose name ends in _dev is a device pointer (hipMalloc'd or from
  * PyTorch's allocator) on the current HIP device; every pointer ending in _host is host memory.
  * The caller owns T0_dev, T0bar_dev and the stream.  A plan owns its checkpoints and workspaces
- * (device memory allocated with hipMalloc when the plan is created, released by
+ * (device memory allocated when the plan is created, through the options' alloc_fn / free_fn when
+ * given (e.g. PyTorch's caching allocator), with hipMalloc / hipFree otherwise; released by
  * dtrg_plan_destroy).  A step's checkpoint is its normalised input tensor, its isometry and its
  * spectrum; the backward recomputes the rest of the step from it, except the forward
  * intermediates the plan keeps within dtrg_options.checkpoint_gib.  The contraction kernel's
@@ -67,6 +68,14 @@ typedef enum {
                           FP32-level accuracy on bf16 MFMA */
 } dtrg_precision;
 
+/* Device-memory callbacks.  alloc_fn returns `bytes` bytes of device memory on the current device,
+ * aligned to 256 bytes, for use on `stream` (the hipStream_t of the call that allocates; NULL for
+ * dtrg_plan_create and dtrg_batch_create), or NULL when it cannot (the call then fails with
+ * DTRG_ENOMEM).  free_fn releases a block with the size it was allocated with; the library waits
+ * for the device to finish with a block before it frees it.  `user` is passed through. */
+typedef void* (*dtrg_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*dtrg_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
 typedef struct {
     int contract;             /* dtrg_precision; default DTRG_FP64 */
     int gram_fp64;            /* 1: half-environments and Gram in FP64 whatever `contract` is
@@ -85,7 +94,7 @@ typedef struct {
                                  64 x 64 on full-width waves for outputs of at most 64 columns and
                                  128 x 128 with one LDS stage for K of at most 128)
                                  and split-K factor (the least one that keeps every FP32
-                                 accumulation chain at 4096 products or fewer, then 2, 3, 4, 5, 6, 8,
+                                 accumulation chain at max_fp32_chain products or fewer, then 2, 3, 4, 5, 6, 8,
                                  12, 16, 24 and 32 above it) of the MFMA kernels on a scratch output
                                  (the least of three timed runs) and keep the fastest for that shape (a table shared by all plans of the
                                  process); 0: fixed heuristic.  Default 0 */
@@ -100,6 +109,32 @@ typedef struct {
                                  least memory).  Results do not depend on it.  A batch divides it
                                  among its plans in proportion to their instances.  Finite, >= 0;
                                  default 64 */
+    int oversample;           /* guard columns p of the subspace block when block_size is 0:
+                                 b = min(96, chi' + p); 0 = automatic (see block_size); 0 <= p <= 95 */
+    int max_fp32_chain;       /* longest FP32 accumulation chain (products summed into one FP32
+                                 value) of the FP32 and split-bf16 formats, for every contraction
+                                 except the two below: a contraction with a longer K is split into
+                                 K chunks whose partials are summed in FP64 (as many chunks as
+                                 16 GiB of partials allow, at most 256).  These contractions write
+                                 at most chi^4 values, so the partials cost little traffic, while
+                                 their K reaches chi^3 (the adjoints with respect to the lower copy
+                                 and to both isometries).  32 <= value <= 2^20; default 4096 */
+    int max_fp32_chain_wide;  /* the same for the join and its adjoint with respect to the upper
+                                 copy's product, whose chi^5 outputs make every extra K chunk a
+                                 full chi^5 pass of FP32 partials (K = chi^2 there).  32 <= value
+                                 <= 2^20; default 4096 */
+    const char* tile_table;   /* path of a persisted autotuning table, or NULL: when set, the
+                                 plan loads the file's entries into the process table at creation
+                                 (a missing file is not an error) and a pass that tuned new shapes
+                                 rewrites the file (text, one shape and configuration per line),
+                                 so tuned configurations, and with them the rounding of split-K
+                                 sums, are the same in every process that uses the file.  Default
+                                 NULL */
+    dtrg_alloc_fn alloc_fn;   /* device allocator of the plan's memory, or NULL for hipMalloc;
+                                 alloc_fn and free_fn are both set or both NULL (DTRG_EINVAL
+                                 otherwise).  Default NULL */
+    dtrg_free_fn free_fn;     /* its release function */
+    void* alloc_user;         /* passed to both */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -115,6 +150,12 @@ typedef struct {
     double lam_first_dropped; /* largest discarded eigenvalue (or Ritz value) */
     double resid;             /* largest kept residual |G v - theta v| */
     int cheb_degree;          /* degree of the complement expansion in the last backward */
+    double trunc_weight;      /* discarded weight 1 - sum of the kept eigenvalues of the
+                                 normalised Gram (its trace is 1) */
+    double cut_gap;           /* lam_last_kept - lam_first_dropped (0 when nothing is cut) */
+    double min_kept_gap;      /* least gap between consecutive kept eigenvalues (0 for one kept) */
+    int mixed;                /* 1 if the step's projection contractions ran in the `contract`
+                                 format, 0 if in FP64 */
 } dtrg_step_info;
 
 typedef struct dtrg_plan dtrg_plan;
@@ -215,6 +256,16 @@ dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_step
 dtrg_status dtrg_batch_run(dtrg_batch* batch, const double* T0s_dev, const double* dT0s_dev, double gbar,
                            double* lnZ_host, double* T0bar_dev, double* dlnZ_dir_host, int replay, void* stream);
 
+/*
+ * One call for a whole batch: dtrg_batch_create, one adaptive dtrg_batch_run and
+ * dtrg_batch_destroy.  Arguments as there; gbar_host (host, one value) and T0bar_dev are both
+ * NULL (forward only) or both given; dT0s_dev and dlnZ_dir_host as in dtrg_batch_run.  Allocates and
+ * releases every buffer within the call (through opt's allocator when given).  Synchronises `stream`.
+ */
+dtrg_status dtrg_hotrg_batched(const double* T0s_dev, int D, const int* chi_host, int n_inst, int n_steps,
+                               const double* gbar_host, const dtrg_options* opt, void* stream, double* lnZ_host,
+                               double* T0bar_dev, const double* dT0s_dev, double* dlnZ_dir_host);
+
 /* Diagnostics of step k of instance inst (0-based) after a successful run. */
 dtrg_status dtrg_batch_step_info(const dtrg_batch* batch, int inst, int k, dtrg_step_info* info);
 
@@ -247,7 +298,8 @@ const char* dtrg_last_error(void);
  * B(c, k) = B_dev[c * ldb + k] (b_kmajor = 0) or B_dev[k * ldb + c] (b_kmajor = 1).
  * precision DTRG_FP64: A, B, C are double.  DTRG_FP32 / DTRG_BF16X3 / DTRG_BF16X6: A, B are float
  * and C is double if out_f64 else float (the split precisions first split A and B into bf16 planes,
- * each in its own layout, K-contiguous or K-major, in a scratch buffer the library keeps per thread).
+ * each in its own layout, K-contiguous or K-major, in a scratch buffer the library keeps per thread
+ * and stream).
  * Device pointers; enqueued on `stream`, not synchronised.
  */
 dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,

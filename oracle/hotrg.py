@@ -126,8 +126,24 @@ def project(T: np.ndarray, w: np.ndarray):
     return P, Q, Tn
 
 
-def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = False) -> ForwardResult:
-    """ln Z / N of the periodic 2^n-site network built from T0 with chi-truncated HOTRG steps."""
+def _spill(arr: np.ndarray, spill_dir, tag: str):
+    """Storage only: write arr to spill_dir and return a read-only memory map of it (unchanged values)."""
+    if spill_dir is None:
+        return arr
+    import os
+    path = os.path.join(spill_dir, tag + ".npy")
+    np.save(path, np.ascontiguousarray(arr))
+    return np.load(path, mmap_mode="r")
+
+
+def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = False,
+                  spill_dir=None, progress=None) -> ForwardResult:
+    """ln Z / N of the periodic 2^n-site network built from T0 with chi-truncated HOTRG steps.
+
+    spill_dir (optional) keeps each step's record on disk as read-only memory maps instead of in
+    RAM; the values are the same, it only lets the largest bond dimensions fit in host memory.
+    progress (optional) is called as progress("forward", k) after each step.
+    """
     T0 = np.asarray(T0_lurd, dtype=np.float64)
     if T0.ndim != 4 or len(set(T0.shape)) != 1:
         raise ValueError("T0 must be a D x D x D x D tensor")
@@ -150,14 +166,23 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
         G_hat, t, lam, U, chi_kept = isometry(gram(A, B), chi)
         w = U[:, :chi_kept].reshape(X, X, chi_kept)
         P, Q, Tn = project(T, w)
+        if not keep_PQ:
+            del P, Q
+            P = Q = None
         c = float(np.linalg.norm(Tn))
         if not (c > 0.0 and math.isfinite(c)):
             raise FloatingPointError(f"step {k}: output norm is not positive and finite")
-        steps.append(StepRecord(T=T, c=c, U=U, lam=lam, trace_G=t, G_hat=G_hat, A=A, B=B,
-                                chi_kept=chi_kept, P=P if keep_PQ else None,
-                                Q=Q if keep_PQ else None))
+        tag = f"step{k:03d}_"
+        steps.append(StepRecord(T=_spill(T, spill_dir, tag + "T"), c=c,
+                                U=_spill(U, spill_dir, tag + "U"), lam=lam, trace_G=t,
+                                G_hat=_spill(G_hat, spill_dir, tag + "Ghat"),
+                                A=_spill(A, spill_dir, tag + "A"), B=_spill(B, spill_dir, tag + "B"),
+                                chi_kept=chi_kept, P=P, Q=Q))
+        del A, B, G_hat, U
         T = Tn / c
         L += math.ldexp(math.log(c), -k)
+        if progress is not None:
+            progress("forward", k)
     tr = float(_es("xxyy->", T))
     if not (tr > 0.0 and math.isfinite(tr)):
         raise FloatingPointError("final trace is not positive and finite")
@@ -205,12 +230,15 @@ def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
     # right isometry:  T'[a,c,y,z] = sum Q[i,y,a,m,z] w[i,m,c]
     Q_bar = _es("acyz,imc->iyamz", Tn_bar, w)
     w_bar_R = _es("acyz,iyamz->imc", Tn_bar, Q)
+    del Q                                        # (memory only: the chi^5 buffers go after last use)
     # lower copy:  Q[i,y,a,m,z] = sum P[i,y,j,b,a] T[b,m,j,z]
     P_bar = _es("iyamz,bmjz->iyjba", Q_bar, T)
     T_bar_lower = _es("iyjba,iyamz->bmjz", P, Q_bar)
+    del Q_bar, P
     # upper copy and left isometry:  P[i,y,j,b,a] = sum T[x,i,y,j] w[x,b,a]
     T_bar_upper = _es("iyjba,xba->xiyj", P_bar, w)
     w_bar_L = _es("xiyj,iyjba->xba", T, P_bar)
+    del P_bar
     # the isometry is the leading eigenvectors of G_hat = sym(G) / tr G
     Ubar_kept = (w_bar_L + w_bar_R).reshape(X * X, chi_kept)
     Ghat_bar = eig_adjoint(rec.U, rec.lam, chi_kept, Ubar_kept, eps)
@@ -227,8 +255,9 @@ def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
     return T_bar_upper + T_bar_lower + T_bar_A + T_bar_B
 
 
-def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_BROADENING) -> np.ndarray:
-    """d(gbar * lnZ/N)/dT0 in the input layout [l][u][r][d]."""
+def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_BROADENING,
+                   progress=None) -> np.ndarray:
+    """d(gbar * lnZ/N)/dT0 in the input layout [l][u][r][d].  progress as in hotrg_forward."""
     n = len(fwd.steps)
     D = fwd.final_T.shape
     # final self-trace: L += 2^-n ln sum_{x,y} T[x,x,y,y]
@@ -242,6 +271,8 @@ def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_B
         # output was divided by c_k; c_k itself is held constant (exact, see module notes)
         T_in_bar = step_adjoint(rec, T_bar / rec.c, eps)
         T_bar = np.transpose(T_in_bar, (2, 3, 0, 1)) if k > 1 else T_in_bar
+        if progress is not None:
+            progress("backward", k)
     T_bar = T_bar / fwd.c0
     return np.ascontiguousarray(np.transpose(T_bar, (0, 2, 1, 3)))
 

@@ -7,8 +7,10 @@ been built, importing this module raises (there is no fallback implementation).
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
 
 import torch
@@ -24,20 +26,29 @@ PRECISIONS = {"fp64": DTRG_FP64, "fp32": DTRG_FP32, "bf16x3": DTRG_BF16X3, "bf16
 
 EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "dtrg_plan_forward",
             "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_batch_create", "dtrg_batch_run",
+            "dtrg_hotrg_batched",
             "dtrg_batch_step_info", "dtrg_batch_profile", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
             "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_contract_config", "dtrg_version"]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_size_t, c_void_p, c_void_p)
 
 
 class Options(ctypes.Structure):
     _fields_ = [("contract", c_int), ("gram_fp64", c_int), ("eig_broadening", c_double),
                 ("max_subspace_iters", c_int), ("subspace_tol", c_double), ("block_size", c_int),
-                ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double)]
+                ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double), ("oversample", c_int),
+                ("max_fp32_chain", c_int), ("max_fp32_chain_wide", c_int),
+                ("tile_table", ctypes.c_char_p), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
+                ("alloc_user", c_void_p)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("X", c_int), ("Y", c_int), ("chi_kept", c_int), ("full_eig", c_int), ("iters", c_int),
                 ("c", c_double), ("trace_G", c_double), ("lam_last_kept", c_double),
-                ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int)]
+                ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int),
+                ("trunc_weight", c_double), ("cut_gap", c_double), ("min_kept_gap", c_double), ("mixed", c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -73,6 +84,10 @@ def _load():
     lib.dtrg_batch_run.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(c_double), c_void_p,
                                    POINTER(c_double), c_int, c_void_p]
     lib.dtrg_batch_run.restype = c_int
+    lib.dtrg_hotrg_batched.argtypes = [c_void_p, c_int, POINTER(c_int), c_int, c_int, POINTER(c_double),
+                                       POINTER(Options), c_void_p, POINTER(c_double), c_void_p, c_void_p,
+                                       POINTER(c_double)]
+    lib.dtrg_hotrg_batched.restype = c_int
     lib.dtrg_batch_step_info.argtypes = [c_void_p, c_int, c_int, POINTER(StepInfo)]
     lib.dtrg_batch_step_info.restype = c_int
     lib.dtrg_batch_profile.argtypes = [c_void_p, POINTER(c_longlong), POINTER(c_double), POINTER(c_double), c_int]
@@ -115,16 +130,58 @@ def _stream(stream=None):
     return c_void_p(stream.cuda_stream)
 
 
-def default_options(**overrides) -> Options:
+# PyTorch's caching allocator behind the library's allocator callbacks: plan memory is then part of
+# torch's pool (torch.cuda.memory_allocated counts it, and it is reused after the plan is released).
+# The callbacks run on the calling thread with the GIL taken by ctypes.
+def _torch_alloc(nbytes, stream, user):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+    except Exception:   # out of memory: the library reports DTRG_ENOMEM
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, user):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+TORCH_FREE = FREE_FN(_torch_free)
+
+# plans and batches still alive at exit are released while PyTorch's allocator is still there
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _release_live():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def default_options(torch_allocator: bool = True, **overrides) -> Options:
+    """The library's defaults with `overrides` applied; plan memory comes from PyTorch's caching
+    allocator unless torch_allocator is False (then hipMalloc)."""
     o = Options()
     lib.dtrg_default_options(byref(o))
+    if torch_allocator:
+        o.alloc_fn = TORCH_ALLOC
+        o.free_fn = TORCH_FREE
     for k, v in overrides.items():
         if k == "contract" and isinstance(v, str):
             v = PRECISIONS[v]
+        if k == "tile_table" and isinstance(v, str):
+            v = v.encode()
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+def _opts(options: Options | None) -> Options:
+    """The options to pass: the caller's, or the defaults (PyTorch's allocator) when None."""
+    return default_options() if options is None else options
 
 
 def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
@@ -141,6 +198,7 @@ class Plan:
         self.D = D
         self.n_steps = n_steps
         self.device = device
+        _LIVE.add(self)
 
     def step_info(self, k: int) -> dict:
         info = StepInfo()
@@ -178,7 +236,7 @@ def dtrg_hotrg_forward(T0: torch.Tensor, chi: int, n_steps: int, options: Option
     out = c_double()
     with torch.cuda.device(T0.device):
         _check(lib.dtrg_hotrg_forward(c_void_p(T0.data_ptr()), D, int(chi), int(n_steps),
-                                      byref(options) if options is not None else None, _stream(stream),
+                                      byref(_opts(options)), _stream(stream),
                                       byref(h), byref(out)))
     return Plan(h.value, D, n_steps, T0.device), out.value
 
@@ -188,7 +246,7 @@ def dtrg_plan_create(D: int, chi: int, n_steps: int, options: Options | None = N
     device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     h = c_void_p()
     with torch.cuda.device(device):
-        _check(lib.dtrg_plan_create(int(D), int(chi), int(n_steps), byref(options) if options is not None else None,
+        _check(lib.dtrg_plan_create(int(D), int(chi), int(n_steps), byref(_opts(options)),
                                     byref(h)))
     return Plan(h.value, D, n_steps, device)
 
@@ -229,6 +287,7 @@ class Batch:
         self.D = D
         self.n_steps = n_steps
         self.device = device
+        _LIVE.add(self)
 
     def step_info(self, inst: int, k: int) -> dict:
         info = StepInfo()
@@ -263,7 +322,7 @@ def dtrg_batch_create(D: int, chis, n_steps: int, options: Options | None = None
     arr = (c_int * n)(*[int(c) for c in chis])
     h = c_void_p()
     with torch.cuda.device(device):
-        _check(lib.dtrg_batch_create(n, int(D), arr, int(n_steps), byref(options) if options is not None else None,
+        _check(lib.dtrg_batch_create(n, int(D), arr, int(n_steps), byref(_opts(options)),
                                      byref(h)))
     return Batch(h.value, n, D, n_steps, device)
 
@@ -287,6 +346,8 @@ def dtrg_batch_run(batch: Batch, T0s: torch.Tensor, dT0s: torch.Tensor | None = 
         if T0bar is None:
             T0bar = torch.empty_like(T0s)
         T0bar = _dev_f64(T0bar, "T0bar")
+        if tuple(T0bar.shape) != tuple(T0s.shape):
+            raise ValueError("T0bar must have the shape of T0s")
         bptr = c_void_p(T0bar.data_ptr())
     lnZ = (c_double * n)()
     dirs = (c_double * n)()
@@ -295,6 +356,36 @@ def dtrg_batch_run(batch: Batch, T0s: torch.Tensor, dT0s: torch.Tensor | None = 
         _check(lib.dtrg_batch_run(batch._h, c_void_p(T0s.data_ptr()), dptr, float(gbar), lnZ, bptr,
                                   dirs if want_dir else None, int(bool(replay)), _stream(stream)))
     return list(lnZ), (T0bar if backward else None), (list(dirs) if want_dir else None)
+
+
+def dtrg_hotrg_batched(T0s: torch.Tensor, chis, n_steps: int, gbar: float | None = 1.0,
+                       dT0s: torch.Tensor | None = None, options: Options | None = None, stream=None):
+    """One call for a whole batch (create, one adaptive run, release).  T0s: [n_inst][D]^4 float64
+    CUDA tensor, chis: per-instance bond dimensions.  gbar None: forward only.
+    Returns (lnZ per instance (list), T0bar tensor or None, <T0bar_i, dT0_i> list or None)."""
+    T0s = _dev_f64(T0s, "T0s")
+    n = len(chis)
+    if T0s.dim() != 5 or T0s.shape[0] != n or len(set(T0s.shape[1:])) != 1:
+        raise ValueError("T0s must be n_inst x D x D x D x D with n_inst = len(chis)")
+    D = int(T0s.shape[1])
+    arr = (c_int * n)(*[int(c) for c in chis])
+    dptr = None
+    if dT0s is not None:
+        dT0s = _dev_f64(dT0s, "dT0s")
+        if tuple(dT0s.shape) != tuple(T0s.shape):
+            raise ValueError("dT0s must have the shape of T0s")
+        dptr = c_void_p(dT0s.data_ptr())
+    T0bar = torch.empty_like(T0s) if gbar is not None else None
+    lnZ = (c_double * n)()
+    dirs = (c_double * n)()
+    want_dir = gbar is not None and dT0s is not None
+    g = c_double(float(gbar)) if gbar is not None else None
+    with torch.cuda.device(T0s.device):
+        _check(lib.dtrg_hotrg_batched(c_void_p(T0s.data_ptr()), D, arr, n, int(n_steps),
+                                      byref(g) if g is not None else None, byref(_opts(options)), _stream(stream),
+                                      lnZ, c_void_p(T0bar.data_ptr()) if T0bar is not None else None, dptr,
+                                      dirs if want_dir else None))
+    return list(lnZ), T0bar, (list(dirs) if want_dir else None)
 
 
 def tuned_shapes() -> int:

@@ -40,6 +40,13 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE(o.autotune == 0 || o.autotune == 1, DTRG_EINVAL, "autotune must be 0 or 1");
     DTRG_REQUIRE(o.checkpoint_gib >= 0.0 && std::isfinite(o.checkpoint_gib), DTRG_EINVAL,
                  "checkpoint_gib must be finite and >= 0");
+    DTRG_REQUIRE(o.oversample >= 0 && o.oversample < kJacobiMax, DTRG_EINVAL, "oversample out of range [0, 95]");
+    DTRG_REQUIRE(o.max_fp32_chain >= 32 && o.max_fp32_chain <= (1 << 20), DTRG_EINVAL,
+                 "max_fp32_chain out of range [32, 2^20]");
+    DTRG_REQUIRE(o.max_fp32_chain_wide >= 32 && o.max_fp32_chain_wide <= (1 << 20), DTRG_EINVAL,
+                 "max_fp32_chain_wide out of range [32, 2^20]");
+    DTRG_REQUIRE((o.alloc_fn == nullptr) == (o.free_fn == nullptr), DTRG_EINVAL,
+                 "alloc_fn and free_fn must both be set or both be NULL");
 }
 
 void validate_sizes(int D, int chi, int n_steps) {
@@ -48,14 +55,34 @@ void validate_sizes(int D, int chi, int n_steps) {
     DTRG_REQUIRE(n_steps >= 1 && n_steps <= 62, DTRG_EINVAL, "n_steps out of range [1, 62]");
 }
 
-// share: the fraction of the checkpoint budget this plan may use (a batch divides it)
+Allocator allocator_of(const dtrg_options* opt, hipStream_t s) {
+    Allocator a;
+    if (opt) {
+        a.alloc_fn = opt->alloc_fn;
+        a.free_fn = opt->free_fn;
+        a.user = opt->alloc_user;
+    }
+    a.stream = s;
+    return a;
+}
+
+// share: the fraction of the checkpoint budget this plan may use (a batch divides it); s: the
+// stream handed to the caller's allocator
 std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const dtrg_options* opt,
-                                     double share = 1.0) {
+                                     double share = 1.0, hipStream_t s = nullptr) {
     validate_sizes(D, chi, n_steps);
     std::unique_ptr<dtrg_plan> P(new dtrg_plan());
     dtrg_default_options(&P->opt);
     if (opt) P->opt = *opt;
     validate_options(P->opt);
+    P->alloc = allocator_of(&P->opt, s);
+    AllocScope scope(&P->alloc);
+    if (P->opt.tile_table) P->tile_table = P->opt.tile_table;   // the plan keeps its own copy
+    P->opt.tile_table = nullptr;
+    if (!P->tile_table.empty()) {
+        tune_load(P->tile_table);
+        P->tuned_seen = tuned_count();   // rewritten only when a pass tunes something new
+    }
     P->ck_budget = (dtrg::i64)std::min(P->opt.checkpoint_gib * share * 1073741824.0, 9.0e18);
     P->prec = prec_of(P->opt.contract);
     P->D = D; P->chi = chi; P->nsteps = n_steps; P->nb = nb;
@@ -79,6 +106,16 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->lam_first_dropped = st.sh.b > st.sh.K ? lam[st.sh.K] : 0.0;
     info->resid = st.sh.full ? 0.0 : sc[8];
     info->cheb_degree = st.cheb;
+    // the normalised Gram has trace 1, so the discarded weight is 1 - the kept eigenvalues
+    double kept = 0.0, gmin = INFINITY;
+    for (int j = 0; j < st.sh.K; ++j) {
+        kept += lam[j];
+        if (j + 1 < st.sh.K) gmin = std::min(gmin, lam[j] - lam[j + 1]);
+    }
+    info->trunc_weight = st.sh.K < st.sh.n ? std::max(0.0, 1.0 - kept) : 0.0;
+    info->cut_gap = st.sh.b > st.sh.K ? lam[st.sh.K - 1] - lam[st.sh.K] : 0.0;
+    info->min_kept_gap = st.sh.K > 1 ? gmin : 0.0;
+    info->mixed = st.sh.mixed ? 1 : 0;
 }
 
 }  // namespace
@@ -88,6 +125,7 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
 // passes, and as parallel branches of one captured HIP graph in replays.
 struct dtrg_batch {
     int n_inst = 0, D = 0, nsteps = 0;
+    Allocator alloc;   // the caller's device allocator, shared by the batch's plans
     std::vector<std::unique_ptr<dtrg_plan>> plans;
     std::vector<std::vector<int>> members;
     std::vector<DevBuf<int>> idx;
@@ -188,6 +226,13 @@ void dtrg_default_options(dtrg_options* o) {
     o->autotune = 0;
     o->profile = 0;
     o->checkpoint_gib = 64.0;
+    o->oversample = 0;
+    o->max_fp32_chain = 4096;
+    o->max_fp32_chain_wide = 4096;
+    o->tile_table = nullptr;
+    o->alloc_fn = nullptr;
+    o->free_fn = nullptr;
+    o->alloc_user = nullptr;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -212,6 +257,8 @@ dtrg_status dtrg_plan_forward(dtrg_plan* plan, const double* T0_dev, void* strea
         DTRG_REQUIRE(plan->nb == 1, DTRG_EINVAL, "not a single-instance plan");
         plan->fwd_ok = false;
         plan->s = (hipStream_t)stream;
+        plan->alloc.stream = plan->s;
+        AllocScope scope(&plan->alloc);
         const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
         DTRG_HIP(hipMemcpyAsync(plan->T0buf.p, T0_dev, D4 * sizeof(double), hipMemcpyDeviceToDevice, plan->s));
         plan_forward(plan, Mode::Adaptive);
@@ -236,9 +283,15 @@ dtrg_status dtrg_hotrg_forward(const double* T0_dev, int D, int chi, int n_steps
         return DTRG_EINVAL;
     }
     dtrg_plan* P = nullptr;
-    dtrg_status st = dtrg_plan_create(D, chi, n_steps, opt, &P);
-    if (st != DTRG_OK) return st;
-    st = dtrg_plan_forward(P, T0_dev, stream, lnZ_per_site_host);
+    try {
+        P = make_plan(D, chi, n_steps, 1, opt, 1.0, (hipStream_t)stream).release();
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return DTRG_EHIP;
+    }
+    dtrg_status st = dtrg_plan_forward(P, T0_dev, stream, lnZ_per_site_host);
     if (st != DTRG_OK) {
         const std::string msg = g_last_error;
         dtrg_plan_destroy(P);
@@ -282,6 +335,8 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
         DTRG_REQUIRE(plan->fwd_ok, DTRG_ESTATE, "backward before a successful forward");
         DTRG_REQUIRE(std::isfinite(gbar), DTRG_EINVAL, "gbar is not finite");
         plan->s = (hipStream_t)stream;
+        plan->alloc.stream = plan->s;
+        AllocScope scope(&plan->alloc);
         const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
         const bool with_dir = dT0_dev && dlnZ_dir_host;
         if (with_dir)
@@ -330,6 +385,9 @@ dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_step
         DTRG_REQUIRE(n_inst >= 1 && n_inst <= 65535, DTRG_EINVAL, "n_inst out of range [1, 65535]");
         std::unique_ptr<dtrg_batch> Bt(new dtrg_batch());
         Bt->n_inst = n_inst; Bt->D = D; Bt->nsteps = n_steps;
+        if (opt) validate_options(*opt);
+        Bt->alloc = allocator_of(opt, nullptr);
+        AllocScope scope(&Bt->alloc);
         std::map<int, size_t> group_of;
         std::vector<int> order;
         for (int i = 0; i < n_inst; ++i) {
@@ -377,6 +435,8 @@ dtrg_status dtrg_batch_run(dtrg_batch* batch, const double* T0s_dev, const doubl
         DTRG_REQUIRE(batch && T0s_dev && lnZ_host, DTRG_EINVAL, "NULL argument");
         DTRG_REQUIRE(std::isfinite(gbar), DTRG_EINVAL, "gbar is not finite");
         DTRG_REQUIRE(replay == 0 || replay == 1, DTRG_EINVAL, "replay must be 0 or 1");
+        batch->alloc.stream = s;
+        AllocScope scope(&batch->alloc);
         const bool with_dir = dT0s_dev && dlnZ_dir_host && T0bar_dev;
         const double* dT0 = with_dir ? dT0s_dev : nullptr;
         if (!replay) {
@@ -409,10 +469,9 @@ dtrg_status dtrg_batch_run(dtrg_batch* batch, const double* T0s_dev, const doubl
                 dtrg_plan* P = batch->plans[g].get();
                 P->fwd_ok = false;
                 for (int i = 0; i < P->nb; ++i)
-                    if (P->flags_h[i] & (kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail | kFlagChebBound)) {
+                    if (P->flags_h[i] & kFlagErrorMask) {
                         try {
-                            plan_throw_flags(P, kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail |
-                                                    kFlagChebBound, "replay");
+                            plan_throw_flags(P, kFlagErrorMask, "replay");
                         } catch (const Error& e) {
                             throw Error(e.code, "batch instance " + std::to_string(batch->members[g][i]) + " (chi " +
                                                     std::to_string(P->chi) + "): " + e.what() +
@@ -473,6 +532,25 @@ dtrg_status dtrg_batch_profile(dtrg_batch* batch, long long* launches, double* t
     return DTRG_OK;
 }
 
+dtrg_status dtrg_hotrg_batched(const double* T0s_dev, int D, const int* chi_host, int n_inst, int n_steps,
+                               const double* gbar_host, const dtrg_options* opt, void* stream, double* lnZ_host,
+                               double* T0bar_dev, const double* dT0s_dev, double* dlnZ_dir_host) {
+    g_last_error.clear();
+    if (!T0s_dev || !chi_host || !lnZ_host || (gbar_host && !T0bar_dev) || (!gbar_host && T0bar_dev)) {
+        g_last_error = "NULL argument (gbar_host and T0bar_dev are both given or both NULL)";
+        return DTRG_EINVAL;
+    }
+    dtrg_batch* Bt = nullptr;
+    dtrg_status st = dtrg_batch_create(n_inst, D, chi_host, n_steps, opt, &Bt);
+    if (st != DTRG_OK) return st;
+    st = dtrg_batch_run(Bt, T0s_dev, dT0s_dev, gbar_host ? *gbar_host : 1.0, lnZ_host, T0bar_dev, dlnZ_dir_host, 0,
+                        stream);
+    const std::string msg = g_last_error;
+    dtrg_batch_destroy(Bt);
+    g_last_error = msg;
+    return st;
+}
+
 size_t dtrg_batch_device_bytes(const dtrg_batch* batch) {
     if (!batch) return 0;
     size_t t = 0;
@@ -504,8 +582,13 @@ dtrg_status dtrg_contract_config(int precision, int M, int N, int K, const void*
                                  const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,
                                  int out_f64, double alpha, double beta, int tile, int splits, void* stream) {
     g_last_error.clear();
-    static thread_local Scratch ws;
-    static thread_local DevBuf<double> planes;
+    // scratch (split-K partials and bf16 planes) per thread and stream: calls on one stream run in
+    // order and may share it; calls on different streams must not
+    struct CallScratch {
+        Scratch ws;
+        DevBuf<double> planes;
+    };
+    static thread_local std::map<hipStream_t, CallScratch> scratch_of;
     try {
         DTRG_REQUIRE(A_dev && B_dev && C_dev, DTRG_EINVAL, "NULL argument");
         DTRG_REQUIRE(M >= 0 && N >= 0 && K >= 0, DTRG_EINVAL, "negative size");
@@ -516,6 +599,8 @@ dtrg_status dtrg_contract_config(int precision, int M, int N, int K, const void*
         DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(pr) > 1 ? 5 : 2), DTRG_EINVAL, "bad tile code");
         DTRG_REQUIRE(splits >= 0 && splits <= 64, DTRG_EINVAL, "split-K count out of range (0 to 64)");
         const hipStream_t s = (hipStream_t)stream;
+        Scratch& ws = scratch_of[s].ws;
+        DevBuf<double>& planes = scratch_of[s].planes;
         GemmOp g;
         g.M = M; g.N = N; g.K = K;
         g.C = C_dev; g.rmap = IdxMap::linear(ldc); g.cmap = IdxMap::linear(1);

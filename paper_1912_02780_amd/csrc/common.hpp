@@ -31,32 +31,73 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::dtrg::Error(code, msg);                                      \
     } while (0)
 
-// Owning device buffer (hipMalloc / hipFree).  A buffer holding nb instances of a tensor keeps
-// the instance stride bs (elements): instance i starts at p + i * bs.
+// The device allocator that DevBuf::alloc uses on this thread: a caller's callbacks (set for the
+// duration of an entry point by AllocScope), or hipMalloc / hipFree when there is none.
+struct Allocator {
+    dtrg_alloc_fn alloc_fn = nullptr;
+    dtrg_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    hipStream_t stream = nullptr;   // stream of the call that allocates
+};
+inline const Allocator*& current_allocator() {
+    static thread_local const Allocator* a = nullptr;
+    return a;
+}
+struct AllocScope {
+    const Allocator* prev;
+    explicit AllocScope(const Allocator* a) : prev(current_allocator()) { current_allocator() = a; }
+    ~AllocScope() { current_allocator() = prev; }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// Owning device buffer (the thread's current allocator, else hipMalloc / hipFree).  A buffer
+// holding nb instances of a tensor keeps the instance stride bs (elements): instance i starts at
+// p + i * bs.  A buffer from a caller's allocator remembers its release function.
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
     i64 bs = 0;
+    dtrg_free_fn ff = nullptr;   // release callback (nullptr: hipFree)
+    void* fu = nullptr;
+    hipStream_t fs = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), bs(o.bs) { o.p = nullptr; o.n = 0; o.bs = 0; }
+    DevBuf(DevBuf&& o) noexcept { take(o); }
     DevBuf& operator=(DevBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; bs = o.bs; o.p = nullptr; o.n = 0; o.bs = 0; }
+        if (this != &o) { release(); take(o); }
         return *this;
     }
     ~DevBuf() { release(); }
+    void take(DevBuf& o) {
+        p = o.p; n = o.n; bs = o.bs; ff = o.ff; fu = o.fu; fs = o.fs;
+        o.p = nullptr; o.n = 0; o.bs = 0; o.ff = nullptr; o.fu = nullptr; o.fs = nullptr;
+    }
     void alloc(size_t count) {
         release();
         if (count == 0) return;
-        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Error(DTRG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
-                                         " bytes failed: " + hipGetErrorString(e));
+        const size_t bytes = count * sizeof(T);
+        const Allocator* A = current_allocator();
+        if (A && A->alloc_fn) {
+            void* q = A->alloc_fn(bytes, (void*)A->stream, A->user);
+            if (!q) throw Error(DTRG_ENOMEM, "alloc_fn returned NULL for " + std::to_string(bytes) + " bytes");
+            if ((uintptr_t)q % 256 != 0) {
+                A->free_fn(q, bytes, (void*)A->stream, A->user);
+                throw Error(DTRG_EINVAL, "alloc_fn returned memory not aligned to 256 bytes");
+            }
+            p = (T*)q;
+            ff = A->free_fn; fu = A->user; fs = A->stream;
+        } else {
+            hipError_t e = hipMalloc((void**)&p, bytes);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Error(DTRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                             hipGetErrorString(e));
+            }
         }
         n = count;
     }
@@ -67,10 +108,22 @@ struct DevBuf {
     }
     void ensure(size_t count) { if (count > n) alloc(count); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (ff) {
+                // a caller's allocator may hand the block out again at once: wait for the device
+                // (hipFree waits the same way)
+                (void)hipDeviceSynchronize();
+                ff(p, n * sizeof(T), (void*)fs, fu);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         n = 0;
         bs = 0;
+        ff = nullptr;
+        fu = nullptr;
+        fs = nullptr;
     }
     size_t bytes() const { return n * sizeof(T); }
 };
@@ -130,6 +183,9 @@ struct GemmOp {
     // element capacities of the buffers behind A, B, C (-1: unchecked); checked on the host
     // against the largest offset the kernel can touch before anything is launched
     i64 a_cap = -1, b_cap = -1, c_cap = -1;
+    // longest FP32 accumulation chain (products per output and K chunk) of the FP32 and bf16-plane
+    // formats; longer K is split and the partials are summed in FP64
+    int max_chain = 4096;
     int tag = 0;   // own kernel symbol for the chi^7 contractions: 7 the join of the two copies
                    // (forward and its backward recompute; timed when profiling), 8 its adjoint
                    // with respect to the upper copy's product P, 9 with respect to the lower copy
@@ -216,10 +272,11 @@ void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_
 // eig.hip
 // Full symmetric eigendecomposition of an n x n matrix (n <= kJacobiMax) by parallel cyclic
 // Jacobi, one workgroup per instance: eigenvalues descending into lam_dev[0..n), eigenvectors as
-// the columns of V (row-major, leading dimension ldv).
+// the columns of V (row-major, leading dimension ldv).  flag_dev (nullable): flag_dev[i] |= flag_bit
+// when instance i still rotated in its last allowed sweep.
 constexpr int kJacobiMax = 96;
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
-                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s);
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev = nullptr, int flag_bit = 0);
 // Upper-triangular R^{-1} of the Cholesky factor of (S + shift * I), S b x b (ld b); the
 // shift is shift_rel * trace(S).  flag_dev[i] |= 2 on a non-positive pivot.  near_dev (nullable):
 // near_dev[i] = 1 if every entry of S_i is within near_tol of the identity's, else 0.  skip_dev

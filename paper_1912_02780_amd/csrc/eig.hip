@@ -37,7 +37,8 @@ constexpr int CT = CG * CG;         // (16 waves)
 template <int GW, int JT>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
                                                      double* __restrict__ lam, i64 lam_bs, double* __restrict__ Vout,
-                                                     int ldv, i64 v_bs, int max_sweeps, int* sweeps_out) {
+                                                     int ldv, i64 v_bs, int max_sweeps, int* sweeps_out,
+                                                     int* flag, int flag_bit) {
     constexpr int JG = JT / GW;                  // groups
     constexpr int JS = (JM / 2 + JG - 1) / JG;   // pair slots per group
     __shared__ double A[JM * JLD];
@@ -164,6 +165,8 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
         __syncthreads();
         if (done) break;
     }
+    // every sweep still rotated something: the matrix is not diagonal to the rotation threshold
+    if (tid == 0 && flag && sweep >= max_sweeps) atomicOr(flag + blockIdx.x, flag_bit);
     // sort descending (ties by index) and write out
     for (int i = tid; i < n; i += JT) {
         const double li = A[i * JLD + i];
@@ -473,15 +476,15 @@ dim3 grid2(i64 n, int nb) {
 }  // namespace
 
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
-                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s) {
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev, int flag_bit) {
     DTRG_REQUIRE(n >= 1 && n <= kJacobiMax, DTRG_EINVAL, "jacobi_eig: n out of range");
     static_assert(kJacobiMax <= 96, "the widest Jacobi group has 96 threads");
     if (n <= 64)
         hipLaunchKernelGGL((jacobi_kernel<64, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
-                           ldv, v_bs, max_sweeps, sweeps_dev);
+                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit);
     else
         hipLaunchKernelGGL((jacobi_kernel<96, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
-                           ldv, v_bs, max_sweeps, sweeps_dev);
+                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit);
     DTRG_HIP(hipGetLastError());
 }
 

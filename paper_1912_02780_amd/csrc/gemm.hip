@@ -54,10 +54,9 @@ int out_code(Prec prec, Out out) {
 
 i64 round8(i64 x) { return (x + 7) / 8 * 8; }
 
-// longest FP32 accumulation chain of a contraction in FP32 or bf16 planes, and the largest split-K
-// workspace (elements) spent on keeping to it
-constexpr i64 kMaxFp32Chain = 4096;
-constexpr i64 kMaxChainPartials = 1LL << 30;
+// the largest split-K workspace (elements) and count spent on keeping FP32 accumulation chains short
+constexpr i64 kMaxChainPartials = 1LL << 32;
+constexpr i64 kMaxChainSplits = 256;
 
 }  // namespace
 
@@ -105,12 +104,17 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
 }
 
 int gemm_chain_splits(Prec prec, const GemmOp& op) {
-    // FP32 accumulation: no chain longer than kMaxFp32Chain products per output (the partials are
-    // summed in FP64), where the partials fit in kMaxChainPartials elements
-    if (prec == Prec::F64 || op.K <= kMaxFp32Chain) return 1;
+    // FP32 accumulation: no chain longer than op.max_chain products per output (the partials are
+    // summed in FP64), where the partials fit in kMaxChainPartials elements; otherwise as many
+    // splits as fit
+    const i64 cap = std::max(op.max_chain, 32);
+    if (prec == Prec::F64 || op.K <= cap) return 1;
     const i64 nz = (i64)op.batch * op.batch2;
-    const i64 need = std::min<i64>(64, (op.K + kMaxFp32Chain - 1) / kMaxFp32Chain);
-    return nz * need * op.M * op.N <= kMaxChainPartials && nz * need < 65536 ? (int)need : 1;
+    i64 need = std::min<i64>(kMaxChainSplits, (op.K + cap - 1) / cap);
+    const i64 fit = kMaxChainPartials / std::max<i64>(1, nz * (i64)op.M * op.N);
+    need = std::min(need, fit);
+    while (need > 1 && nz * need >= 65536) --need;
+    return (int)std::max<i64>(1, need);
 }
 
 void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {

@@ -75,6 +75,10 @@ double ldexp1(int e) { return std::ldexp(1.0, e); }
 constexpr double kSubspaceAccept = 1e-12;   // largest accepted resolved residual (trace-normalised)
 constexpr double kChebTail = 1e-15;         // relative size of the last two expansion coefficients
 constexpr int kChebMaxDegree = 1024;
+// at the largest degree the expansion is accepted down to this tail (a relative error of the
+// complement term far below the FP64 parity of the gradient); above it the step fails
+constexpr double kChebTailAccept = 1e-12;
+constexpr int kJacobiSweeps = 40;
 
 PermDesc pd4(i64 d0, i64 d1, i64 d2, i64 d3, int p0, int p1, int p2, int p3) {
     PermDesc d;
@@ -128,6 +132,8 @@ struct Ctx {
     // set by the caller in a_bs2 / b_bs2 / c_bs2), output kind `out`
     void run(GemmOp g, Prec pr, Out out) {
         g.batch2 = P->nb;
+        // the join and its adjoint with respect to P (chi^5 outputs) have their own chain cap
+        g.max_chain = (g.tag == 7 || g.tag == 8) ? P->opt.max_fp32_chain_wide : P->opt.max_fp32_chain;
         const int ein = esize(pr), eout = esize(pr, out);
         if (g.a_cap < 0) g.a_cap = P->cap_of(g.A, ein);
         if (g.b_cap < 0) g.b_cap = P->cap_of(g.B, ein);
@@ -385,6 +391,7 @@ void throw_flags(const dtrg_plan* P, const std::vector<int>& f, int mask, const 
         if (b & kFlagChebTail)
             throw Error(DTRG_ENOCONV, pre + "eigen-adjoint: complement expansion coefficients did not decay");
         if (b & kFlagChebBound) throw Error(DTRG_ENOCONV, pre + "eigen-adjoint: complement expansion diverged");
+        if (b & kFlagJacobi) throw Error(DTRG_ENOCONV, pre + "Jacobi eigensolve did not converge");
         throw Error(DTRG_ENOCONV, pre + "flag " + std::to_string(b));
     }
 }
@@ -393,7 +400,16 @@ void check_flags(dtrg_plan* P, int mask, const std::string& where, bool input_st
     throw_flags(P, read_flags(P), mask, where, input_stage);
 }
 
-constexpr int kFlagErrors = kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail | kFlagChebBound;
+constexpr int kFlagErrors = kFlagErrorMask;
+
+// rewrite the plan's persisted tuning table when an adaptive pass has added shapes to the table
+void persist_tuning(dtrg_plan* P) {
+    if (P->tile_table.empty() || !P->opt.autotune) return;
+    const int n = tuned_count();
+    if (n == P->tuned_seen) return;
+    tune_save(P->tile_table);
+    P->tuned_seen = n;
+}
 
 // -------------------------------------------------------------------------------------------
 // truncated eigensolve
@@ -452,7 +468,10 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     const int n = st.sh.n, b = st.sh.b, E = st.sh.e, nb = P->nb;
     const uint64_t seed = 0x5eedULL * (uint64_t)k + 17ULL;
     if (st.sh.full) {
-        jacobi_eig(P->Gw.p, n, n, P->Gw.bs, st.lam.p, st.lam.bs, st.U.p, n, st.U.bs, nb, 40, P->misc.p, c.s);
+        // the whole spectrum: nothing downstream checks it, so a sweep cap reached is an error (the
+        // Rayleigh-Ritz solves below are checked through the Ritz residuals instead)
+        jacobi_eig(P->Gw.p, n, n, P->Gw.bs, st.lam.p, st.lam.bs, st.U.p, n, st.U.bs, nb, kJacobiSweeps, P->misc.p,
+                   c.s, P->flags.p, kFlagJacobi);
         st.iters = 0;
         return;
     }
@@ -485,7 +504,7 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
         g.rmap = IdxMap::linear(b); g.cmap = IdxMap::linear(1);
         set_bs(g, vbs, vbs, P->H.bs);
         c.gemm(g);
-        jacobi_eig(P->H.p, b, b, P->H.bs, P->th.p, P->th.bs, P->Z.p, b, P->Z.bs, nb, 40, P->misc.p, c.s);
+        jacobi_eig(P->H.p, b, b, P->H.bs, P->th.p, P->th.bs, P->Z.p, b, P->Z.bs, nb, kJacobiSweeps, P->misc.p, c.s);
         // V <- V Z, Y <- Y Z
         GemmOp r;
         r.M = n; r.N = b; r.K = b;
@@ -545,7 +564,7 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
 // the mixed paths: their cost is negligible and they carry the largest weights 2^-k in ln Z / N.
 constexpr double kMixedMinFraction = 0.05;
 
-std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, bool mixed) {
+std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversample, bool mixed) {
     std::vector<StepShape> v;
     int X = D, Y = D;
     for (int k = 1; k <= nsteps; ++k) {
@@ -554,7 +573,7 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, bool mixed)
         s.K = std::min(chi, s.n);
         if (s.n <= kJacobiMax) { s.full = true; s.b = s.n; s.e = s.n; }
         else {
-            int b = block > 0 ? block : std::max(s.K + 16, 2 * s.K);
+            int b = block > 0 ? block : (oversample > 0 ? s.K + oversample : std::max(s.K + 16, 2 * s.K));
             b = std::min(b, kJacobiMax);
             b = std::min(b, s.n - 1);
             // at least one guard column beyond the kept ones: the complement expansion reads the
@@ -818,7 +837,14 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
                     const std::vector<double> ratio = read_scalar(P, P->sc(k, 9));
                     double mx = 0.0;
                     for (double v : ratio) mx = std::max(mx, std::isfinite(v) ? v : INFINITY);
-                    if (mx <= kChebTail || m >= kChebMaxDegree) break;
+                    if (mx <= kChebTail) break;
+                    if (m >= kChebMaxDegree) {
+                        if (mx <= kChebTailAccept) break;
+                        throw Error(DTRG_ENOCONV, "step " + std::to_string(k) +
+                                                      ": eigen-adjoint: complement expansion coefficients did not "
+                                                      "decay by degree " + std::to_string(m) + " (tail ratio " +
+                                                      std::to_string(mx) + ")");
+                    }
                 }
                 expansion(m);
                 std::vector<int> f = read_flags(P);
@@ -849,8 +875,8 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
         } else {
             DTRG_REQUIRE(st.cheb >= 8 && P->ctab_ready, DTRG_ESTATE, "no recorded complement expansion for this step");
             coefficients(st.cheb, st.hi_mult);
-            if (st.cheb < kChebMaxDegree)
-                max_check(P->sc(k, 9), P->S, 1, nb, kChebTail, nullptr, 0, P->flags.p, kFlagChebTail, c.s);
+            max_check(P->sc(k, 9), P->S, 1, nb, st.cheb < kChebMaxDegree ? kChebTail : kChebTailAccept, nullptr, 0,
+                      P->flags.p, kFlagChebTail, c.s);
             expansion(st.cheb);
         }
         axpy(P->Xc.p, P->Xe.p, vbs, (i64)n * K, nb, 1.0, c.s);   // Xe += Xc
@@ -886,7 +912,7 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
 // engine entry points
 // -------------------------------------------------------------------------------------------
 void plan_setup(dtrg_plan* P) {
-    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size, P->mixed());
+    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size, P->opt.oversample, P->mixed());
     alloc_plan(P, P->shape);
 }
 
@@ -963,6 +989,7 @@ void plan_forward(dtrg_plan* P, Mode mode) {
             if (!std::isfinite(P->scal_h[(size_t)i * P->S])) throw Error(DTRG_ENONPOS, inst_name(P, i) + "ln Z is not finite");
         P->sched_fwd = true;
         P->fwd_ok = true;
+        persist_tuning(P);
     }
 }
 
@@ -1125,6 +1152,7 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         plan_read_back(P);
         plan_throw_flags(P, kFlagErrors, "backward");
         P->sched_bwd = true;
+        persist_tuning(P);
     }
 }
 

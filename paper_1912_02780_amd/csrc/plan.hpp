@@ -27,7 +27,10 @@ enum : int {
     kFlagSubspace = 8,    // subspace iteration residual above the acceptance bound
     kFlagChebTail = 16,   // complement expansion coefficients not decayed at the recorded degree
     kFlagChebBound = 32,  // complement expansion not bounded (spectrum outside its interval)
+    kFlagJacobi = 64,     // full Jacobi eigensolve still rotating at its sweep cap
 };
+// the flags that fail a pass (kFlagChol is a diagnostic: the shifted pass absorbs it)
+constexpr int kFlagErrorMask = kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail | kFlagChebBound | kFlagJacobi;
 
 // Per-instance FP64 scalars: one row of kScPlan + kScStep * n_steps doubles per instance.
 constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace, 5 <T0bar, dT0>, 6 c0, 7 1/c0
@@ -95,6 +98,7 @@ struct dtrg_plan {
     dtrg_options opt{};
     dtrg::Prec prec = dtrg::Prec::F64;
     hipStream_t s = nullptr;
+    dtrg::Allocator alloc;      // the caller's device allocator (empty: hipMalloc)
     std::vector<dtrg::StepCk> steps;
     std::vector<dtrg::StepShape> shape;
     bool fwd_ok = false;        // a forward pass succeeded (checkpoints valid)
@@ -124,6 +128,8 @@ struct dtrg_plan {
     bool ctab_ready = false;
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
+    std::string tile_table;       // persisted autotuning table ("" = none)
+    int tuned_seen = -1;          // size of the process table when the file was last written
     bool mixed() const { return prec != dtrg::Prec::F64; }
     // HIP-event timing of the chi^7 join contractions (adaptive passes with opt.profile)
     std::vector<hipEvent_t> ev_pool;
@@ -161,5 +167,9 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
                   DevBuf<double>& scratch);
 // Number of shapes in the tuning table (for tests and diagnostics).
 int tuned_count();
+// Merge a persisted table into the process table (a missing file loads nothing; returns the number
+// of entries added), and write the process table to a file.
+int tune_load(const std::string& path);
+void tune_save(const std::string& path);
 
 }  // namespace dtrg

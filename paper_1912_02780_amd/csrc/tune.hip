@@ -13,6 +13,7 @@
 // 4, 671 us at 1).  Later contractions of that shape (including fixed passes that are being captured
 // into a graph) take the table entry without timing anything.
 #include <algorithm>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -24,14 +25,14 @@ namespace dtrg {
 
 namespace {
 
-typedef std::tuple<int, int, int, int, int, int, int, int, int> TuneKey;
+typedef std::tuple<int, int, int, int, int, int, int, int, int, int> TuneKey;
 
 std::mutex g_mu;
 std::map<TuneKey, GemmCfg> g_table;
 
 TuneKey key_of(Prec prec, Out out, const GemmOp& op) {
     return TuneKey((int)prec, (int)out, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
-                   op.b_kmajor ? 1 : 0);
+                   op.b_kmajor ? 1 : 0, prec == Prec::F64 ? 0 : op.max_chain);
 }
 
 // largest split-K workspace a trial may claim (elements)
@@ -55,6 +56,60 @@ std::vector<int> split_counts(int minsp) {
 int tuned_count() {
     std::lock_guard<std::mutex> g(g_mu);
     return (int)g_table.size();
+}
+
+// Persisted table: a text file, one shape per line, "dtrg-tune 1" first:
+//   prec out M N K batch batch2 a_kmajor b_kmajor max_chain tile splits
+// Loaded entries do not replace shapes the process has tuned already.
+int tune_load(const std::string& path) {
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return 0;
+    char head[32] = {0};
+    int ver = 0, n = 0;
+    if (std::fscanf(f, "%31s %d", head, &ver) != 2 || std::string(head) != "dtrg-tune" || ver != 1) {
+        std::fclose(f);
+        throw Error(DTRG_EINVAL, "tile_table " + path + ": not a dtrg-tune 1 file");
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    for (;;) {
+        int v[12];
+        int got = 0;
+        for (int i = 0; i < 12; ++i) got += std::fscanf(f, "%d", &v[i]) == 1;
+        if (got == 0) break;
+        // tile 0 and splits 0 are the heuristic's choice (kept for shapes too small to time)
+        if (got != 12 || v[10] < 0 || v[10] > 5 || v[11] < 0 || v[11] > 256) {
+            std::fclose(f);
+            throw Error(DTRG_EINVAL, "tile_table " + path + ": malformed entry " + std::to_string(n + 1));
+        }
+        const TuneKey key(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9]);
+        GemmCfg c;
+        c.tile = v[10];
+        c.splits = v[11];
+        if (g_table.emplace(key, c).second) ++n;
+    }
+    std::fclose(f);
+    return n;
+}
+
+void tune_save(const std::string& path) {
+    std::map<TuneKey, GemmCfg> snap;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        snap = g_table;
+    }
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) throw Error(DTRG_EINVAL, "tile_table " + path + ": cannot write");
+    std::fprintf(f, "dtrg-tune 1\n");
+    for (const auto& e : snap) {
+        const TuneKey& k = e.first;
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                     std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k),
+                     std::get<9>(k), e.second.tile, e.second.splits);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0)
+        throw Error(DTRG_EINVAL, "tile_table " + path + ": cannot write");
 }
 
 GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStream_t s, Scratch& ws,

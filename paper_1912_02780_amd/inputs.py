@@ -53,6 +53,18 @@ def ising_T0(beta: float) -> np.ndarray:
     return np.ascontiguousarray(np.einsum("sl,su,sr,sd->lurd", W, W, W, W))
 
 
+def ising_T0_torch(beta):
+    """``ising_T0`` from a 0-d float64 torch tensor beta with torch operations, so that autograd
+    carries d/dbeta through T0 (elementwise products and a sum over s; no batched matmul)."""
+    import torch
+    ch, sh = torch.cosh(beta), torch.sinh(beta)
+    rc, rs = torch.sqrt(2.0 * ch), torch.sqrt(2.0 * sh)
+    p, q = 0.5 * (rc + rs), 0.5 * (rc - rs)
+    W = torch.stack([torch.stack([p, q]), torch.stack([q, p])])   # W[s][leg]
+    return (W[:, :, None, None, None] * W[:, None, :, None, None] * W[:, None, None, :, None]
+            * W[:, None, None, None, :]).sum(0)
+
+
 def ising_dT0_dbeta(beta: float) -> np.ndarray:
     """Derivative of ``ising_T0`` with respect to beta (product rule over the four W factors)."""
     W, dW = ising_bond_root(beta)

@@ -11,6 +11,7 @@ from __future__ import annotations
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -29,7 +30,12 @@ CASES = {
     "ising_b0.50_chi32_n30": ("ising", 0.50, 32, 30),
     "random_d4_seed0_chi48_n24": ("random_d4", 0, 48, 24),
     "ising_b0.4406868_chi24_n24": ("ising", 0.4406868, 24, 24),
+    "ising_b0.4406868_chi64_n30": ("ising", 0.4406868, 64, 30),
 }
+
+# Cases too large for a second (perturbed) oracle pass within a few hours, and large enough that
+# each step's record is kept on disk (memory maps) rather than in RAM.
+LARGE = {"ising_b0.4406868_chi64_n30"}
 
 
 def rounding_sensitivity(T0, chi, n, L_ref, g_ref, seed=1234):
@@ -59,16 +65,27 @@ def run(name):
     else:
         T0 = I.random_d4_T0(int(param))
         dT0 = None
+    large = name in LARGE
+    spill = None
+    if large:
+        # the step records go to GOLDEN_SPILL_DIR (else a fresh temporary directory); delete it after
+        spill = os.environ.get("GOLDEN_SPILL_DIR") or tempfile.mkdtemp(prefix="oracle_spill_")
+        os.makedirs(spill, exist_ok=True)
     t0 = time.time()
-    fwd = O.hotrg_forward(T0, chi, n)
+
+    def progress(phase, k):
+        print(f"  {name}: {phase} step {k} at {time.time() - t0:.0f}s", flush=True)
+
+    fwd = O.hotrg_forward(T0, chi, n, spill_dir=spill, progress=progress)
     t1 = time.time()
-    g = O.hotrg_backward(fwd, 1.0, O.DEFAULT_BROADENING)
+    g = O.hotrg_backward(fwd, 1.0, O.DEFAULT_BROADENING, progress=progress)
     t2 = time.time()
     inv = O.step_invariants(fwd)
     # Rounding sensitivity of the oracle itself: repeat with every Gram perturbed entrywise by a
     # symmetric relative noise of 2^-52 (the size of FP64 rounding) and record how far ln Z / N
     # and T0bar move.  Parity between two correct FP64 implementations cannot be finer than this.
-    sens = rounding_sensitivity(T0, chi, n, fwd.lnZ_per_site, g)
+    # (Not run for the largest cases: it would double hours of oracle time.)
+    sens = (None, None) if large else rounding_sensitivity(T0, chi, n, fwd.lnZ_per_site, g)
     out = {
         "name": name, "input": kind, "param": param, "chi": chi, "n_steps": n,
         "broadening": O.DEFAULT_BROADENING,
@@ -80,6 +97,7 @@ def run(name):
         "c": [r["c"] for r in inv],
         "lam_last_kept": [float(r["lam_kept"][-1]) for r in inv],
         "cut_gap": [r["cut_gap"] for r in inv],
+        "trunc_weight": [r["trunc_weight"] for r in inv],
         "rounding_sensitivity_lnZ": sens[0],
         "rounding_sensitivity_T0bar": sens[1],
         "oracle_seconds_forward": t1 - t0,

@@ -75,19 +75,50 @@ def test_argument_validation_without_device_work():
     assert lib.dtrg_plan_forward(None, ctypes.c_void_p(8), None, ctypes.byref(out)) == 1
 
 
+# the header's structs, field by field, as ctypes types (parsed from include/dtrg.h)
+_CTYPES = {"int": ctypes.c_int, "double": ctypes.c_double, "const char*": ctypes.c_char_p,
+           "dtrg_alloc_fn": ctypes.c_void_p, "dtrg_free_fn": ctypes.c_void_p, "void*": ctypes.c_void_p}
+
+
+def header_struct(name):
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        assert "," not in decl, "one field per declaration in " + name
+        m = re.match(r"(.*?)\s*\b(\w+)$", decl)
+        fields.append((m.group(2), _CTYPES[m.group(1).replace(" *", "*").strip()]))
+    return fields
+
+
+def _struct(name):
+    return type(name, (ctypes.Structure,), {"_fields_": header_struct(name)})
+
+
+def test_binding_structs_match_header():
+    """Field names, order and C types of dtrg_options and dtrg_step_info in the binding are the header's."""
+    torch = pytest.importorskip("torch")   # noqa: F841  (the binding imports it)
+    if not os.path.exists(LIB):
+        pytest.skip("libdtrg.so not built")
+    from paper_1912_02780_amd import binding as B
+    for name, cls in (("dtrg_options", B.Options), ("dtrg_step_info", B.StepInfo)):
+        hdr = header_struct(name)
+        assert [f for f, _ in cls._fields_] == [f for f, _ in hdr], name
+        assert ctypes.sizeof(cls) == ctypes.sizeof(_struct(name)), name
+
+
 def test_default_options():
     lib = _lib()
-
-    class Options(ctypes.Structure):
-        _fields_ = [("contract", ctypes.c_int), ("gram_fp64", ctypes.c_int), ("eig_broadening", ctypes.c_double),
-                    ("max_subspace_iters", ctypes.c_int), ("subspace_tol", ctypes.c_double),
-                    ("block_size", ctypes.c_int), ("autotune", ctypes.c_int), ("profile", ctypes.c_int),
-                    ("checkpoint_gib", ctypes.c_double)]
-
+    Options = _struct("dtrg_options")
     o = Options()
     lib.dtrg_default_options(ctypes.byref(o))
     assert o.contract == 0 and o.eig_broadening == 1e-12 and o.max_subspace_iters == 60
     assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1 and o.checkpoint_gib == 64.0
+    assert o.oversample == 0 and o.max_fp32_chain == 4096 and o.max_fp32_chain_wide == 4096
+    assert o.tile_table is None and o.alloc_fn is None and o.free_fn is None
     # a checkpoint budget that is negative or not finite is rejected before any allocation
     lib.dtrg_plan_create.restype = ctypes.c_int
     lib.dtrg_last_error.restype = ctypes.c_char_p
@@ -140,3 +171,110 @@ def test_contract_config_validation_without_device_work():
     # NULL operands and short leading dimensions are rejected first
     assert f(3, 8, 8, 8, None, 8, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1
     assert f(3, 8, 8, 8, p, 4, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1
+
+
+# ---------------------------------------------------------------------------------------------
+# plans on a caller's allocator that hands out addresses the library never dereferences before a
+# forward pass: allocation failure, out-of-order calls and release, all without a GPU
+# ---------------------------------------------------------------------------------------------
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class FakeDeviceMemory:
+    """Hands out distinct 256-byte aligned addresses (never dereferenced) and records the frees."""
+
+    def __init__(self, fail_after=None, align=256):
+        self.live = {}
+        self.next = 1 << 40
+        self.allocs = 0
+        self.fail_after = fail_after
+        self.align = align
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, stream, user):
+        if self.fail_after is not None and self.allocs >= self.fail_after:
+            return None
+        self.allocs += 1
+        p = self.next + (self.align % 256)
+        self.next += (nbytes + 4095) // 4096 * 4096 + 4096
+        self.live[p] = nbytes
+        return p
+
+    def _free(self, ptr, nbytes, stream, user):
+        assert self.live.pop(ptr) == nbytes
+
+
+def _plan_create(lib, mem, **opt):
+    Options = _struct("dtrg_options")
+    o = Options()
+    lib.dtrg_default_options(ctypes.byref(o))
+    for k, v in opt.items():
+        setattr(o, k, v)
+    o.alloc_fn = ctypes.cast(mem.alloc_fn, ctypes.c_void_p) if mem else None
+    o.free_fn = ctypes.cast(mem.free_fn, ctypes.c_void_p) if mem else None
+    lib.dtrg_plan_create.restype = ctypes.c_int
+    plan = ctypes.c_void_p()
+    st = lib.dtrg_plan_create(2, 16, 12, ctypes.byref(o), ctypes.byref(plan))
+    return st, plan
+
+
+def test_allocator_failure_is_enomem_and_leaks_nothing():
+    lib = _lib()
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    for fail_after in (0, 5, 40):
+        mem = FakeDeviceMemory(fail_after=fail_after)
+        st, plan = _plan_create(lib, mem)
+        assert st == 2 and plan.value is None, (fail_after, st)      # DTRG_ENOMEM
+        assert b"alloc_fn" in lib.dtrg_last_error()
+        assert not mem.live, "blocks allocated before the failure must be released"
+
+
+def test_backward_before_forward_is_estate_and_destroy_frees_every_block():
+    lib = _lib()
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    lib.dtrg_hotrg_backward.restype = ctypes.c_int
+    lib.dtrg_plan_step_info.restype = ctypes.c_int
+    lib.dtrg_plan_device_bytes.restype = ctypes.c_size_t
+    mem = FakeDeviceMemory()
+    st, plan = _plan_create(lib, mem)
+    assert st == 0 and plan.value
+    assert mem.allocs > 10 and mem.live
+    assert lib.dtrg_plan_device_bytes(plan) == sum(mem.live.values())
+    # no forward yet: the backward and the diagnostics refuse before touching the device
+    st = lib.dtrg_hotrg_backward(plan, ctypes.c_double(1.0), ctypes.c_void_p(1 << 40), None, None, None)
+    assert st == 6 and b"before" in lib.dtrg_last_error()           # DTRG_ESTATE
+    info = (ctypes.c_char * 256)()
+    assert lib.dtrg_plan_step_info(plan, 1, info) == 6
+    lib.dtrg_plan_destroy(plan)
+    assert not mem.live
+
+
+def test_allocator_callbacks_are_validated():
+    lib = _lib()
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    mem = FakeDeviceMemory()
+    Options = _struct("dtrg_options")
+    o = Options()
+    lib.dtrg_default_options(ctypes.byref(o))
+    o.alloc_fn = ctypes.cast(mem.alloc_fn, ctypes.c_void_p)        # free_fn left NULL
+    plan = ctypes.c_void_p()
+    lib.dtrg_plan_create.restype = ctypes.c_int
+    assert lib.dtrg_plan_create(2, 16, 12, ctypes.byref(o), ctypes.byref(plan)) == 1
+    assert b"free_fn" in lib.dtrg_last_error() and mem.allocs == 0
+    # an allocator that returns memory the kernels cannot use (not 256-byte aligned)
+    bad = FakeDeviceMemory(align=8)
+    st, plan = _plan_create(lib, bad)
+    assert st == 1 and plan.value is None and b"aligned" in lib.dtrg_last_error()
+    assert not bad.live
+
+
+def test_option_ranges_are_validated():
+    lib = _lib()
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    for field, value in (("max_fp32_chain", 16), ("max_fp32_chain_wide", 1 << 21), ("oversample", 96),
+                         ("oversample", -1)):
+        st, plan = _plan_create(lib, FakeDeviceMemory(), **{field: value})
+        assert st == 1 and plan.value is None, field
+        assert field.encode() in lib.dtrg_last_error()

@@ -11,6 +11,9 @@ Tolerances (FP64 path):
     FP64 implementation, the oracle included, so parity cannot be finer than s;
   * per-step scales c_k within 1e-11 + lam_K (lam_K the smallest kept eigenvalue of the normalised
     Gram: swapping nearly degenerate vectors across the cut moves c_k by at most that weight).
+Every T0bar bound is asserted twice: normwise, and entry by entry as
+max_i |g_i - ref_i| / (|ref_i| + 1e-6 max_j |ref_j|) (the floor only matters for entries a million
+times below the largest; the Ising and random-tensor gradients have none that small).
 Exact references (enumeration, brute force) within a few ulps of the value.
 """
 
@@ -57,6 +60,16 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
+ELEM_FLOOR = 1e-6
+
+
+def _elem(a, b):
+    """Largest entry-wise relative difference, with a floor of ELEM_FLOOR times the largest entry."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    den = np.abs(b) + ELEM_FLOOR * max(float(np.abs(b).max()), 1e-300)
+    return float(np.max(np.abs(a - b) / den))
+
+
 # ---------------------------------------------------------------------------------------------
 # exact references
 # ---------------------------------------------------------------------------------------------
@@ -81,6 +94,7 @@ def test_gpu_bruteforce_2x2(B, seed):
     lnZ, g, _, _ = _gpu(B, T0, 16, 2)
     assert abs(lnZ - math.log(Z) / 4) < 1e-14
     assert _rel(g, dZ / Z / 4) < 1e-13
+    assert _elem(g, dZ / Z / 4) < 1e-12
 
 
 # ---------------------------------------------------------------------------------------------
@@ -121,6 +135,7 @@ def test_gpu_vs_oracle_small(B, case):
     Lo, go, fwd = O.lnZ_and_grad(T0, chi, n)
     assert abs(lnZ / Lo - 1) < 1e-12, (lnZ, Lo)
     assert _rel(g, go) < 1e-10, _rel(g, go)
+    assert _elem(g, go) < 1e-10, _elem(g, go)
     if dT0 is not None:
         do = float(np.sum(go * dT0))
         assert abs(d / do - 1) < 1e-10, (d, do)
@@ -178,12 +193,13 @@ def test_gpu_vs_golden_fp64(B, name):
     lnZ, g, d, plan = _gpu(B, T0, gd["chi"], gd["n_steps"], dT0)
     go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
     tol_g = max(1e-10, 10.0 * gd.get("rounding_sensitivity_T0bar", 0.0))
-    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.3e}  T0bar rel {_rel(g, go):.3e} (tol {tol_g:.1e})"
-         + (f"  dbeta rel {abs(d / gd['dlnZ_dbeta'] - 1):.3e}" if dT0 is not None else ""))
+    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.3e}  T0bar rel {_rel(g, go):.3e} elem {_elem(g, go):.3e} "
+         f"(tol {tol_g:.1e})" + (f"  dbeta rel {abs(d / gd['dlnZ_dbeta'] - 1):.3e}" if dT0 is not None else ""))
     assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-10
     if dT0 is not None:
         assert abs(d / gd["dlnZ_dbeta"] - 1) < 1e-10
     assert _rel(g, go) < tol_g
+    assert _elem(g, go) < tol_g
     for k in range(1, gd["n_steps"] + 1):
         assert abs(plan.step_info(k)["c"] / gd["c"][k - 1] - 1) < 1e-11 + gd["lam_last_kept"][k - 1]
 
@@ -244,27 +260,52 @@ MIXED = [
 GRAD_TOL = {"fp32": 1e-5, "bf16x3": 3e-4, "bf16x6": 1e-5}
 
 
+def _ising_symmetric(T):
+    """Projection of a [l][u][r][d] gradient onto the tensors invariant under the Ising model's
+    symmetries: the square's point group and the global spin flip (index 0 <-> 1 on every leg, under
+    which the bond factor W = [[p, q], [q, p]] is invariant).  The average of the 16 images."""
+    from paper_1912_02780_amd import inputs as I
+    imgs = I.square_group_images(np.asarray(T))
+    imgs = imgs + [np.flip(x, axis=(0, 1, 2, 3)) for x in imgs]
+    return sum(imgs) / len(imgs)
+
+
+# Ising T0bar entry by entry.  In the ordered phase (beta = 0.50) the spectrum of the Gram comes in
+# pairs that the spin flip makes (nearly) degenerate, and the cut splits such pairs: which member is
+# kept is decided by rounding, and the part of T0bar odd under the flip follows it (the FP64
+# oracle's own T0bar moves by 1e-5 under relative Gram noise of 2^-52 at chi = 32).  That part is
+# bounded loosely (ISING_T0BAR_TOL: measured 7.5e-4 FP32, 3.5e-2 two-plane, 1.5e-4 three-plane at
+# beta = 0.50, chi = 12); the symmetric part, the only one a symmetric perturbation of T0 such as
+# dT0/dbeta sees, is held to the format's gradient bound (measured 5.5e-7, 1.3e-5, 4.3e-7).
+ISING_T0BAR_TOL = {"fp32": 3e-3, "bf16x3": 1e-1, "bf16x6": 1e-3}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("case", MIXED, ids=[c[0] for c in MIXED])
 def test_gpu_mixed_vs_oracle_small(B, prec, case):
-    """Ising inputs: the gradient that matters is d(lnZ/N)/dbeta; their full T0bar is ill-conditioned
-    (cuts through near-degenerate pairs amplify contraction rounding by 1/gap, FP64 included) and is
-    only reported.  Random tensors: the full T0bar is checked."""
+    """Ising inputs: d(lnZ/N)/dbeta at the format's gradient bound and the full T0bar entry by entry at
+    ISING_T0BAR_TOL.  Random tensors: the full T0bar, normwise and entry by entry, at the gradient
+    bound."""
     from oracle import hotrg as O
     name, spec, chi, n = case
     T0, dT0 = _input(spec)
     _say(f"[gpu] mixed {prec} {name}")
     lnZ, g, d, _ = _gpu(B, T0, chi, n, dT0, contract=prec)
     Lo, go, _ = O.lnZ_and_grad(T0, chi, n)
-    msg = f"    lnZ rel {abs(lnZ / Lo - 1):.2e}  T0bar rel {_rel(g, go):.2e}"
+    msg = f"    lnZ rel {abs(lnZ / Lo - 1):.2e}  T0bar rel {_rel(g, go):.2e} elem {_elem(g, go):.2e}"
     if dT0 is not None:
         msg += f"  dbeta rel {abs(d / float(np.sum(go * dT0)) - 1):.2e}"
     _say(msg)
     assert abs(lnZ / Lo - 1) < 1e-6
     if dT0 is not None:
+        es = _elem(_ising_symmetric(g), _ising_symmetric(go))
+        _say(f"    symmetric part of T0bar: elem {es:.2e}")
         assert abs(d / float(np.sum(go * dT0)) - 1) < GRAD_TOL[prec]
+        assert es < GRAD_TOL[prec]
+        assert _elem(g, go) < ISING_T0BAR_TOL[prec]
     else:
         assert _rel(g, go) < GRAD_TOL[prec]
+        assert _elem(g, go) < GRAD_TOL[prec]
 
 
 # the benchmark's configuration (three-plane split-bf16 with the tile autotuner) among them
@@ -276,9 +317,10 @@ def test_gpu_mixed_vs_golden_chi48(B, prec, autotune):
     _say(f"[gpu] mixed {prec} golden chi48 autotune={autotune}")
     lnZ, g, _, _ = _gpu(B, T0, 48, 24, None, contract=prec, autotune=autotune)
     go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
-    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.2e}  T0bar rel {_rel(g, go):.2e}")
+    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.2e}  T0bar rel {_rel(g, go):.2e} elem {_elem(g, go):.2e}")
     assert abs(lnZ / gd["lnZ_per_site"] - 1) < 1e-6
     assert _rel(g, go) < GRAD_TOL[prec]
+    assert _elem(g, go) < GRAD_TOL[prec]
 
 
 # chi = 36: every contraction of a full-size step is ragged against the tiles (the join is
@@ -313,7 +355,7 @@ def test_gpu_ragged_mid_size_vs_oracle(B, oracle_ragged, name, prec, autotune, l
     _, chi, n = RAGGED[name]
     _say(f"[gpu] ragged {name} {prec} autotune={autotune}")
     lnZ, g, d, _ = _gpu(B, T0, chi, n, dT0, contract=prec, autotune=autotune)
-    msg = f"    lnZ rel {abs(lnZ / Lo - 1):.2e}  T0bar rel {_rel(g, go):.2e}"
+    msg = f"    lnZ rel {abs(lnZ / Lo - 1):.2e}  T0bar rel {_rel(g, go):.2e} elem {_elem(g, go):.2e}"
     if dT0 is not None:
         do = float(np.sum(go * dT0))
         msg += f"  dbeta rel {abs(d / do - 1):.2e}"
@@ -321,8 +363,11 @@ def test_gpu_ragged_mid_size_vs_oracle(B, oracle_ragged, name, prec, autotune, l
     assert abs(lnZ / Lo - 1) < ltol
     if dT0 is not None:
         assert abs(d / do - 1) < gtol
+        if prec == "fp64":
+            assert _elem(g, go) < 1e-8
     else:
         assert _rel(g, go) < gtol
+        assert _elem(g, go) < gtol
 
 
 # ---------------------------------------------------------------------------------------------
@@ -361,31 +406,66 @@ def test_gpu_dbeta_vs_finite_differences_chi32(B, beta, tol_fd):
     assert abs(d / rich - 1) < max(tol_fd / 10, 2e-7)
 
 
-def test_gpu_chi64_critical_dbeta(B):
-    """Ising at beta_c, chi = 64, 30 steps: the FP64 gradient against Richardson-extrapolated central
-    differences of the FP64 forward, and the three-plane split-bf16 gradient against the FP64 one.
-    The second bound needs the 4096-product cap on FP32 accumulation chains (without it: 1.4e-4)."""
+# Ising at beta_c, chi = 64, 30 steps: one checkpoint per RG step with the recompute inside the step
+# (checkpoint_gib = 0).  Split-bf16 with FP32 accumulation chains of at most 512 products in the
+# contractions whose outputs are at most chi^4 (FP64 sums of the K chunks; the chi^5-output join and
+# its adjoint keep 4096): with 4096 everywhere d(lnZ/N)/dbeta is 1.1e-5 from FP64, with 512 on the
+# small-output contractions 5.5e-6.
+CHI64 = "ising_b0.4406868_chi64_n30"
+CHI64_MIXED = dict(contract="bf16x6", max_fp32_chain=512, checkpoint_gib=0.0)
+
+
+@pytest.fixture(scope="module")
+def chi64_fp64(B):
     from paper_1912_02780_amd import inputs as I
-    beta, chi, n, h = 0.4406868, 64, 30, 1e-5
-    _say(f"[gpu] chi={chi} critical: FP64 gradient and finite differences")
+    gd = _golden(CHI64)
     dev = torch.device("cuda:0")
-    T0 = torch.from_numpy(I.ising_T0(beta)).to(dev)
-    dT0 = torch.from_numpy(I.ising_dT0_dbeta(beta)).to(dev)
-    plan, L64 = B.dtrg_hotrg_forward(T0, chi, n)
-    _, d64 = B.dtrg_hotrg_backward(plan, 1.0, dT0)
+    T0 = torch.from_numpy(I.ising_T0(gd["param"])).to(dev)
+    dT0 = torch.from_numpy(I.ising_dT0_dbeta(gd["param"])).to(dev)
+    _say(f"[gpu] {CHI64}: FP64 path, one checkpoint per step")
+    plan, L = B.dtrg_hotrg_forward(T0, 64, 30, B.default_options(checkpoint_gib=0.0))
+    g, d = B.dtrg_hotrg_backward(plan, 1.0, dT0)
+    return gd, T0, dT0, plan, L, g.cpu().numpy(), d
+
+
+def test_gpu_chi64_critical_fp64_vs_golden(B, chi64_fp64):
+    gd, _, _, plan, L, g, d = chi64_fp64
+    go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
+    _say(f"    lnZ rel {abs(L / gd['lnZ_per_site'] - 1):.2e}  dbeta rel {abs(d / gd['dlnZ_dbeta'] - 1):.2e}  "
+         f"T0bar rel {_rel(g, go):.2e} elem {_elem(g, go):.2e}")
+    assert abs(L / gd["lnZ_per_site"] - 1) < 1e-10
+    assert abs(d / gd["dlnZ_dbeta"] - 1) < 1e-10
+    assert _elem(g, go) < 1e-6
+    for k in range(1, 31):
+        info = plan.step_info(k)
+        assert abs(info["c"] / gd["c"][k - 1] - 1) < 1e-11 + gd["lam_last_kept"][k - 1]
+        assert info["cheb_degree"] < 1024
+
+
+def test_gpu_chi64_critical_fp64_vs_finite_differences(B, chi64_fp64):
+    """The FP64 gradient against Richardson-extrapolated central differences of the FP64 forward."""
+    gd, _, _, plan, _, _, d = chi64_fp64
+    beta, h = gd["param"], 1e-5
     f = {}
     for s in (-1.0, -0.5, 0.5, 1.0):
-        f[s], _ = _lnZ_gpu(B, beta + s * h, chi, n, plan)
+        f[s], _ = _lnZ_gpu(B, beta + s * h, 64, 30, plan)
     rich = (4 * (f[0.5] - f[-0.5]) / h - (f[1.0] - f[-1.0]) / (2 * h)) / 3
-    plan.close()
-    _say(f"    FP64 AD {d64:.12f}  Richardson FD {rich:.12f}  rel {abs(d64 / rich - 1):.1e}")
-    assert abs(d64 / rich - 1) < 2e-6
-    _say("[gpu] chi=64 critical: bf16x6")
-    p6, L6 = B.dtrg_hotrg_forward(T0, chi, n, B.default_options(contract="bf16x6"))
+    _say(f"    FP64 AD {d:.12f}  Richardson FD {rich:.12f}  rel {abs(d / rich - 1):.1e}")
+    assert abs(d / rich - 1) < 2e-6
+
+
+def test_gpu_chi64_critical_bf16x6_vs_golden(B, chi64_fp64):
+    gd, T0, dT0, _, _, _, _ = chi64_fp64
+    _say(f"[gpu] {CHI64}: split-bf16 (six products), chains <= 512 / 4096, one checkpoint per step")
+    torch.cuda.reset_peak_memory_stats()
+    p6, L6 = B.dtrg_hotrg_forward(T0, 64, 30, B.default_options(**CHI64_MIXED))
     _, d6 = B.dtrg_hotrg_backward(p6, 1.0, dT0)
-    _say(f"    bf16x6 lnZ rel {abs(L6 / L64 - 1):.1e}  dbeta rel {abs(d6 / d64 - 1):.1e}")
-    assert abs(L6 / L64 - 1) < 1e-7
-    assert abs(d6 / d64 - 1) < 3e-5
+    peak = torch.cuda.max_memory_allocated() / 2**30
+    dl, dd = abs(L6 / gd["lnZ_per_site"] - 1), abs(d6 / gd["dlnZ_dbeta"] - 1)
+    _say(f"    lnZ rel {dl:.2e}  dbeta rel {dd:.2e}  peak {peak:.1f} GiB (plan {p6.device_bytes() / 2**30:.1f} GiB)")
+    assert dl < 1e-6
+    assert dd < 1e-5
+    assert all(p6.step_info(k)["cheb_degree"] < 1024 for k in range(1, 31))
 
 
 def test_gpu_autotuned_plan(B):
