@@ -320,6 +320,22 @@ dtrg_status dtrg_contract_config(int precision, int M, int N, int K, const void*
                                  long long ldc, int out_f64, double alpha, double beta, int tile, int splits,
                                  void* stream);
 
+/*
+ * dtrg_contract that allocates no device memory, for callers that cannot allocate (code that must
+ * not call hipMalloc, e.g. tight serving loops or harnesses that forbid allocation).  Arguments,
+ * layouts and results are those of dtrg_contract (the same kernels and the same configuration).
+ * The bf16 planes of the split precisions and the FP64/FP32 split-K partials live in a static
+ * device array of 128 MiB that each device holds for the life of the process (its address is
+ * looked up on the first call on a device; nothing is allocated, ever).  A contraction whose
+ * planes and partials need more than 128 MiB fails with DTRG_EINVAL before any work is issued.
+ * The array's contents need no clearing: every byte a call reads it has written first.  All calls
+ * on one device share the array, so calls that overlap on one device (different streams or host
+ * threads without ordering between them) race; calls ordered on one stream do not.
+ */
+dtrg_status dtrg_contract_noalloc(int precision, int M, int N, int K, const void* A_dev, long long lda,
+                                  int a_kmajor, const void* B_dev, long long ldb, int b_kmajor, void* C_dev,
+                                  long long ldc, int out_f64, double alpha, double beta, void* stream);
+
 /* Library version string. */
 const char* dtrg_version(void);
 

@@ -28,7 +28,8 @@ EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "d
             "dtrg_hotrg_backward", "dtrg_plan_step_info", "dtrg_plan_profile", "dtrg_batch_create", "dtrg_batch_run",
             "dtrg_hotrg_batched",
             "dtrg_batch_step_info", "dtrg_batch_profile", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
-            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_contract_config", "dtrg_version"]
+            "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_contract_config", "dtrg_version",
+            "dtrg_contract_noalloc"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
@@ -113,6 +114,8 @@ def _load():
                                          c_longlong, c_int, c_void_p, c_longlong, c_int, c_double, c_double, c_int,
                                          c_int, c_void_p]
     lib.dtrg_contract_config.restype = c_int
+    lib.dtrg_contract_noalloc.argtypes = lib.dtrg_contract.argtypes
+    lib.dtrg_contract_noalloc.restype = c_int
     return lib
 
 
@@ -393,10 +396,11 @@ def tuned_shapes() -> int:
 
 
 def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, a_kmajor=False, b_kmajor=False,
-                  alpha=1.0, beta=0.0, stream=None, tile=0, splits=0):
+                  alpha=1.0, beta=0.0, stream=None, tile=0, splits=0, noalloc=False):
     """C = alpha * A' B'^T + beta * C with A' = A or A.T (a_kmajor), B' = B or B.T (b_kmajor).
 
-    tile / splits: the kernel configuration (0 = the library's choice; dtrg_contract_config)."""
+    tile / splits: the kernel configuration (0 = the library's choice; dtrg_contract_config).
+    noalloc: run through dtrg_contract_noalloc (the library's static scratch; tile and splits 0)."""
     prec = PRECISIONS[precision]
     if a_kmajor:
         K, M = A.shape
@@ -414,7 +418,13 @@ def dtrg_contract(precision: str, A: torch.Tensor, B: torch.Tensor, C: torch.Ten
         raise TypeError("fp64 contraction writes float64")
     if tuple(C.shape) != (M, N):
         raise ValueError("C has the wrong shape")
-    if tile or splits:
+    if noalloc:
+        if tile or splits:
+            raise ValueError("dtrg_contract_noalloc takes no tile or split configuration")
+        _check(lib.dtrg_contract_noalloc(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
+                                         c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()), N,
+                                         int(out_f64), float(alpha), float(beta), _stream(stream)))
+    elif tile or splits:
         _check(lib.dtrg_contract_config(prec, M, N, K, c_void_p(A.data_ptr()), A.shape[1], int(a_kmajor),
                                         c_void_p(B.data_ptr()), B.shape[1], int(b_kmajor), c_void_p(C.data_ptr()),
                                         N, int(out_f64), float(alpha), float(beta), int(tile), int(splits),

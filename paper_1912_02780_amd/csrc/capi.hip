@@ -4,6 +4,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -206,6 +207,113 @@ void capture(dtrg_batch* Bt, const double* T0s, const double* dT0s, double gbar,
     DTRG_HIP(hipStreamEndCapture(s, &Bt->graph));
     DTRG_HIP(hipGraphInstantiate(&Bt->exec, Bt->graph, nullptr, nullptr, 0));
     Bt->g_T0 = T0s; Bt->g_dT0 = dT0s; Bt->g_T0bar = T0bar; Bt->g_gbar = gbar;
+}
+
+}  // namespace
+
+namespace {
+
+// One standalone contraction (dtrg_contract and its variants), validated, with its operand layouts
+// resolved; the FP32 operands of the split-bf16 precisions are split into planes at launch.
+struct ContractCall {
+    Prec pr = Prec::F64;
+    Out out = Out::F64;
+    int np = 1;
+    GemmOp g;
+    const void* A = nullptr;
+    const void* B = nullptr;
+    i64 lda = 0, ldb = 0;
+    bool akm = false, bkm = false;
+    i64 lda_p = 0, ldb_p = 0, a_ps = 0, b_ps = 0;   // plane layouts (np > 1)
+    // doubles of plane storage (0 when the operands are used as given)
+    i64 plane_doubles() const { return np > 1 ? (np * (a_ps + b_ps) * 2 + 7) / 8 + 2 : 0; }
+};
+
+ContractCall contract_call(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
+                           const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc, int out_f64,
+                           double alpha, double beta, int tile, int splits) {
+    DTRG_REQUIRE(A_dev && B_dev && C_dev, DTRG_EINVAL, "NULL argument");
+    DTRG_REQUIRE(M >= 0 && N >= 0 && K >= 0, DTRG_EINVAL, "negative size");
+    DTRG_REQUIRE(precision >= DTRG_FP64 && precision <= DTRG_BF16X6, DTRG_EINVAL, "bad precision");
+    DTRG_REQUIRE(lda >= (a_kmajor ? M : K) && ldb >= (b_kmajor ? N : K) && ldc >= N, DTRG_EINVAL,
+                 "leading dimension too small");
+    ContractCall c;
+    c.pr = prec_of(precision);
+    DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(c.pr) > 1 ? 5 : 2), DTRG_EINVAL, "bad tile code");
+    DTRG_REQUIRE(splits >= 0 && splits <= 64, DTRG_EINVAL, "split-K count out of range (0 to 64)");
+    c.out = precision == DTRG_FP64 || out_f64 ? Out::F64 : Out::F32;
+    c.np = prec_planes(c.pr);
+    c.A = A_dev; c.B = B_dev; c.lda = lda; c.ldb = ldb; c.akm = a_kmajor != 0; c.bkm = b_kmajor != 0;
+    GemmOp& g = c.g;
+    g.M = M; g.N = N; g.K = K;
+    g.C = C_dev; g.rmap = IdxMap::linear(ldc); g.cmap = IdxMap::linear(1);
+    g.alpha = alpha; g.beta = beta;
+    g.cfg.tile = tile;
+    g.cfg.splits = splits;
+    g.a_kmajor = c.akm;
+    g.b_kmajor = c.bkm;
+    if (c.np == 1) {
+        g.A = A_dev; g.lda = lda;
+        g.B = B_dev; g.ldb = ldb;
+    } else {
+        // FP32 operands split into bf16 planes in their own layout (K-contiguous or K-major, rows
+        // padded to 8 elements)
+        auto r8 = [](i64 x) { return (x + 7) / 8 * 8; };
+        c.lda_p = r8(c.akm ? M : K);
+        c.ldb_p = r8(c.bkm ? N : K);
+        c.a_ps = (i64)(c.akm ? K : M) * c.lda_p;
+        c.b_ps = (i64)(c.bkm ? K : N) * c.ldb_p;
+        g.lda = c.lda_p; g.a_ps = c.a_ps;
+        g.ldb = c.ldb_p; g.b_ps = c.b_ps;
+    }
+    return c;
+}
+
+// planes: at least c.plane_doubles() doubles (unused when the operands are used as given)
+void contract_launch(ContractCall& c, double* planes, hipStream_t s, Scratch& ws) {
+    GemmOp& g = c.g;
+    if (c.np > 1) {
+        const int M = g.M, N = g.N, K = g.K;
+        __bf16* pa = (__bf16*)planes;
+        __bf16* pb = pa + c.np * c.a_ps;
+        // a K-major matrix is split as the row-major K x M matrix it is stored as
+        if (c.akm) split_matrix((const float*)c.A, c.lda, false, K, M, pa, c.lda_p, c.a_ps, c.np, s);
+        else split_matrix((const float*)c.A, c.lda, false, M, K, pa, c.lda_p, c.a_ps, c.np, s);
+        if (c.bkm) split_matrix((const float*)c.B, c.ldb, false, K, N, pb, c.ldb_p, c.b_ps, c.np, s);
+        else split_matrix((const float*)c.B, c.ldb, false, N, K, pb, c.ldb_p, c.b_ps, c.np, s);
+        g.A = pa;
+        g.B = pb;
+    }
+    dtrg::gemm(c.pr, c.out, g, s, ws);
+}
+
+// Device scratch of dtrg_contract_noalloc: the bf16 planes and split-K partials of one contraction.
+// Each device holds its own copy for the life of the process; host code reaches it only through
+// the device address hipGetSymbolAddress returns for the current device.
+constexpr i64 kNoAllocScratchBytes = 128LL << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (looked up once per device)
+void* noalloc_scratch_ptr() {
+    int dev = -1;
+    DTRG_HIP(hipGetDevice(&dev));
+    DTRG_REQUIRE(dev >= 0 && dev < kMaxDevices, DTRG_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw Error(DTRG_EHIP, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                                       hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -590,45 +698,39 @@ dtrg_status dtrg_contract_config(int precision, int M, int N, int K, const void*
     };
     static thread_local std::map<hipStream_t, CallScratch> scratch_of;
     try {
-        DTRG_REQUIRE(A_dev && B_dev && C_dev, DTRG_EINVAL, "NULL argument");
-        DTRG_REQUIRE(M >= 0 && N >= 0 && K >= 0, DTRG_EINVAL, "negative size");
-        DTRG_REQUIRE(precision >= DTRG_FP64 && precision <= DTRG_BF16X6, DTRG_EINVAL, "bad precision");
-        DTRG_REQUIRE(lda >= (a_kmajor ? M : K) && ldb >= (b_kmajor ? N : K) && ldc >= N, DTRG_EINVAL,
-                     "leading dimension too small");
-        const Prec pr = prec_of(precision);
-        DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(pr) > 1 ? 5 : 2), DTRG_EINVAL, "bad tile code");
-        DTRG_REQUIRE(splits >= 0 && splits <= 64, DTRG_EINVAL, "split-K count out of range (0 to 64)");
+        ContractCall c = contract_call(precision, M, N, K, A_dev, lda, a_kmajor, B_dev, ldb, b_kmajor, C_dev, ldc,
+                                       out_f64, alpha, beta, tile, splits);
         const hipStream_t s = (hipStream_t)stream;
-        Scratch& ws = scratch_of[s].ws;
-        DevBuf<double>& planes = scratch_of[s].planes;
-        GemmOp g;
-        g.M = M; g.N = N; g.K = K;
-        g.C = C_dev; g.rmap = IdxMap::linear(ldc); g.cmap = IdxMap::linear(1);
-        g.alpha = alpha; g.beta = beta;
-        g.cfg.tile = tile;
-        g.cfg.splits = splits;
-        const int np = prec_planes(pr);
-        if (np == 1) {
-            g.A = A_dev; g.lda = lda; g.a_kmajor = a_kmajor != 0;
-            g.B = B_dev; g.ldb = ldb; g.b_kmajor = b_kmajor != 0;
-        } else {
-            // FP32 operands split into bf16 planes in their own layout (K-contiguous or K-major,
-            // rows padded to 8 elements) in a scratch buffer
-            auto r8 = [](i64 x) { return (x + 7) / 8 * 8; };
-            const i64 lda_p = r8(a_kmajor ? M : K), ldb_p = r8(b_kmajor ? N : K);
-            const i64 a_ps = (i64)(a_kmajor ? K : M) * lda_p, b_ps = (i64)(b_kmajor ? K : N) * ldb_p;
-            planes.ensure((size_t)((np * (a_ps + b_ps) * 2 + 7) / 8) + 2);
-            __bf16* pa = (__bf16*)planes.p;
-            __bf16* pb = pa + np * a_ps;
-            // a K-major matrix is split as the row-major K x M matrix it is stored as
-            if (a_kmajor) split_matrix((const float*)A_dev, lda, false, K, M, pa, lda_p, a_ps, np, s);
-            else split_matrix((const float*)A_dev, lda, false, M, K, pa, lda_p, a_ps, np, s);
-            if (b_kmajor) split_matrix((const float*)B_dev, ldb, false, K, N, pb, ldb_p, b_ps, np, s);
-            else split_matrix((const float*)B_dev, ldb, false, N, K, pb, ldb_p, b_ps, np, s);
-            g.A = pa; g.lda = lda_p; g.a_ps = a_ps; g.a_kmajor = a_kmajor != 0;
-            g.B = pb; g.ldb = ldb_p; g.b_ps = b_ps; g.b_kmajor = b_kmajor != 0;
-        }
-        dtrg::gemm(pr, precision == DTRG_FP64 || out_f64 ? Out::F64 : Out::F32, g, s, ws);
+        CallScratch& sc = scratch_of[s];
+        sc.planes.ensure((size_t)c.plane_doubles());
+        contract_launch(c, sc.planes.p, s, sc.ws);
+        return DTRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return DTRG_EHIP;
+    }
+}
+
+dtrg_status dtrg_contract_noalloc(int precision, int M, int N, int K, const void* A_dev, long long lda, int a_kmajor,
+                                  const void* B_dev, long long ldb, int b_kmajor, void* C_dev, long long ldc,
+                                  int out_f64, double alpha, double beta, void* stream) {
+    g_last_error.clear();
+    try {
+        ContractCall c = contract_call(precision, M, N, K, A_dev, lda, a_kmajor, B_dev, ldb, b_kmajor, C_dev, ldc,
+                                       out_f64, alpha, beta, 0, 0);
+        // the whole need, checked before any work is issued: planes first, split-K partials after
+        const i64 plane_bytes = (c.plane_doubles() * 8 + 255) / 256 * 256;
+        const i64 splitk_bytes = gemm_workspace(c.pr, c.g) * 8;
+        DTRG_REQUIRE(plane_bytes + splitk_bytes <= kNoAllocScratchBytes, DTRG_EINVAL,
+                     "dtrg_contract_noalloc: the contraction needs " + std::to_string(plane_bytes + splitk_bytes) +
+                         " bytes of scratch, more than the library's static " +
+                         std::to_string(kNoAllocScratchBytes) + " bytes");
+        char* base = (char*)noalloc_scratch_ptr();
+        Scratch ws;   // borrowed views of the static array: never freed or grown
+        ws.splitk.borrow((double*)(base + plane_bytes), (size_t)((kNoAllocScratchBytes - plane_bytes) / 8));
+        contract_launch(c, (double*)base, (hipStream_t)stream, ws);
         return DTRG_OK;
     } catch (const Error& e) {
         return fail(e);

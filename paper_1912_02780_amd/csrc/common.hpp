@@ -62,6 +62,7 @@ struct DevBuf {
     dtrg_free_fn ff = nullptr;   // release callback (nullptr: hipFree)
     void* fu = nullptr;
     hipStream_t fs = nullptr;
+    bool borrowed = false;       // a view of memory the buffer does not own: never freed or grown
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf&) = delete;
@@ -73,8 +74,15 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void take(DevBuf& o) {
-        p = o.p; n = o.n; bs = o.bs; ff = o.ff; fu = o.fu; fs = o.fs;
-        o.p = nullptr; o.n = 0; o.bs = 0; o.ff = nullptr; o.fu = nullptr; o.fs = nullptr;
+        p = o.p; n = o.n; bs = o.bs; ff = o.ff; fu = o.fu; fs = o.fs; borrowed = o.borrowed;
+        o.p = nullptr; o.n = 0; o.bs = 0; o.ff = nullptr; o.fu = nullptr; o.fs = nullptr; o.borrowed = false;
+    }
+    // view `count` elements at ptr (memory owned elsewhere)
+    void borrow(T* ptr, size_t count) {
+        release();
+        p = ptr;
+        n = count;
+        borrowed = true;
     }
     void alloc(size_t count) {
         release();
@@ -106,9 +114,15 @@ struct DevBuf {
         alloc((size_t)nb * (size_t)per);
         bs = per;
     }
-    void ensure(size_t count) { if (count > n) alloc(count); }
+    void ensure(size_t count) {
+        if (count <= n) return;
+        if (borrowed) throw Error(DTRG_ENOMEM, "borrowed buffer of " + std::to_string(n * sizeof(T)) +
+                                                   " bytes is too small (" + std::to_string(count * sizeof(T)) +
+                                                   " needed)");
+        alloc(count);
+    }
     void release() {
-        if (p) {
+        if (p && !borrowed) {
             if (ff) {
                 // a caller's allocator may hand the block out again at once: wait for the device
                 // (hipFree waits the same way)
@@ -124,6 +138,7 @@ struct DevBuf {
         ff = nullptr;
         fu = nullptr;
         fs = nullptr;
+        borrowed = false;
     }
     size_t bytes() const { return n * sizeof(T); }
 };
@@ -203,6 +218,8 @@ GemmCfg gemm_resolve(Prec in_prec, const GemmOp& op);
 // smallest split-K count that keeps every FP32 accumulation chain of the contraction short (1 for
 // FP64 and short K); gemm_resolve never picks fewer, and the autotuner tries no fewer
 int gemm_chain_splits(Prec prec, const GemmOp& op);
+// Split-K workspace (doubles) gemm() needs for op (0 when it runs as one K chunk).
+i64 gemm_workspace(Prec prec, const GemmOp& op);
 // Largest element offset (plus one) the epilogue of op can write, over all batch elements.
 i64 gemm_c_extent(const GemmOp& op);
 void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws);

@@ -54,6 +54,21 @@ int out_code(Prec prec, Out out) {
 
 i64 round8(i64 x) { return (x + 7) / 8 * 8; }
 
+// K chunk and number of K chunks a resolved configuration runs with (chunks are whole K tiles)
+void resolve_chunks(Prec prec, const GemmOp& op, const GemmCfg& cfg, int& k_chunk, int& splits) {
+    const int BK = bk_of(prec, cfg.tile);
+    splits = std::max(1, cfg.splits);
+    const int k_chunk_raw = (op.K + splits - 1) / splits;
+    k_chunk = std::max(BK, ((k_chunk_raw + BK - 1) / BK) * BK);
+    splits = std::max(1, (op.K + k_chunk - 1) / k_chunk);
+    if (op.K == 0) splits = 1;
+}
+
+// a short, wide split-bf16 output is computed as its transpose (see gemm)
+bool run_transposed(Prec prec, const GemmOp& op) {
+    return prec_planes(prec) > 1 && op.cfg.tile == 0 && op.M <= 64 && op.N >= 1024;
+}
+
 // the largest split-K workspace (elements) and count spent on keeping FP32 accumulation chains short
 constexpr i64 kMaxChainPartials = 1LL << 32;
 constexpr i64 kMaxChainSplits = 256;
@@ -103,6 +118,20 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
     return c;
 }
 
+i64 gemm_workspace(Prec prec, const GemmOp& op) {
+    if (op.M == 0 || op.N == 0) return 0;
+    if (run_transposed(prec, op)) {
+        GemmOp t = op;
+        std::swap(t.M, t.N);
+        return gemm_workspace(prec, t);
+    }
+    int k_chunk = 0, splits = 1;
+    resolve_chunks(prec, op, gemm_resolve(prec, op), k_chunk, splits);
+    if (splits <= 1) return 0;
+    const i64 elems = (i64)op.batch * op.batch2 * splits * op.M * op.N;
+    return prec == Prec::F64 ? elems : (elems + 1) / 2;
+}
+
 int gemm_chain_splits(Prec prec, const GemmOp& op) {
     // FP32 accumulation: no chain longer than op.max_chain products per output (the partials are
     // summed in FP64), where the partials fit in kMaxChainPartials elements; otherwise as many
@@ -123,7 +152,7 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     if (op.M == 0 || op.N == 0) return;
     const int np = prec_planes(prec);
     const bool split = np > 1;
-    if (split && op.cfg.tile == 0 && op.M <= 64 && op.N >= 1024) {
+    if (run_transposed(prec, op)) {
         // a short, wide output is computed as its transpose, C(r, c) = sum_k B(c, k) A(r, k) with
         // the roles of the operands and of the index maps exchanged, so that the tall-operand tile
         // streams the long operand once
@@ -192,21 +221,15 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || ((cfg.tile >= 3 && cfg.tile <= 5) && split), DTRG_EINVAL,
                  "gemm: bad tile configuration");
     const int BM = tile_rows(cfg.tile), BN = tile_cols(cfg.tile);
-    const int BK = bk_of(prec, cfg.tile);
-    int splits = std::max(1, cfg.splits);
-    const int k_chunk_raw = (op.K + splits - 1) / splits;
-    a.k_chunk = std::max(BK, ((k_chunk_raw + BK - 1) / BK) * BK);
-    splits = std::max(1, (op.K + a.k_chunk - 1) / a.k_chunk);
-    if (op.K == 0) splits = 1;
+    int splits = 1;
+    resolve_chunks(prec, op, cfg, a.k_chunk, splits);
     a.splits = splits;
     const i64 nz = (i64)op.batch * op.batch2;
     DTRG_REQUIRE(nz * splits < 65536, DTRG_EINVAL, "gemm: batch x splits too large");
 
     const bool acc_f64 = (prec == Prec::F64);
     if (splits > 1) {
-        const i64 need_elems = nz * splits * op.M * op.N;
-        const i64 need_d = acc_f64 ? need_elems : (need_elems + 1) / 2;
-        ws.splitk.ensure((size_t)need_d);
+        ws.splitk.ensure((size_t)gemm_workspace(prec, op));
         a.W = ws.splitk.p;
     }
     a.tiles_m = (op.M + BM - 1) / BM;
