@@ -65,6 +65,7 @@ class StepRecord:
     chi_kept: int        # chi' = min(chi, X^2)
     P: np.ndarray | None = None
     Q: np.ndarray | None = None
+    w_fixed: np.ndarray | None = None   # the step's given isometry (then U, lam, A, B, G_hat are None)
 
 
 @dataclass
@@ -137,12 +138,14 @@ def _spill(arr: np.ndarray, spill_dir, tag: str):
 
 
 def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = False,
-                  spill_dir=None, progress=None) -> ForwardResult:
+                  spill_dir=None, progress=None, w_fixed=None) -> ForwardResult:
     """ln Z / N of the periodic 2^n-site network built from T0 with chi-truncated HOTRG steps.
 
     spill_dir (optional) keeps each step's record on disk as read-only memory maps instead of in
     RAM; the values are the same, it only lets the largest bond dimensions fit in host memory.
     progress (optional) is called as progress("forward", k) after each step.
+    w_fixed (optional) maps step numbers k to given isometries w[x1][x2][a] (chi' = min(chi, X^2)
+    columns): those steps project with them instead of the leading eigenvectors of their Gram.
     """
     T0 = np.asarray(T0_lurd, dtype=np.float64)
     if T0.ndim != 4 or len(set(T0.shape)) != 1:
@@ -162,9 +165,17 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
         if k > 1:
             T = np.ascontiguousarray(np.transpose(T, (2, 3, 0, 1)))
         X = T.shape[0]
-        A, B = half_environments(T)
-        G_hat, t, lam, U, chi_kept = isometry(gram(A, B), chi)
-        w = U[:, :chi_kept].reshape(X, X, chi_kept)
+        if w_fixed is not None and k in w_fixed:
+            w = np.asarray(w_fixed[k], dtype=np.float64)
+            chi_kept = min(chi, X * X)
+            if w.shape != (X, X, chi_kept):
+                raise ValueError(f"step {k}: isometry must have shape {(X, X, chi_kept)}")
+            A = B = G_hat = U = lam = None
+            t = math.nan
+        else:
+            A, B = half_environments(T)
+            G_hat, t, lam, U, chi_kept = isometry(gram(A, B), chi)
+            w = U[:, :chi_kept].reshape(X, X, chi_kept)
         P, Q, Tn = project(T, w)
         if not keep_PQ:
             del P, Q
@@ -173,11 +184,13 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
         if not (c > 0.0 and math.isfinite(c)):
             raise FloatingPointError(f"step {k}: output norm is not positive and finite")
         tag = f"step{k:03d}_"
+        fixed = w if U is None else None
         steps.append(StepRecord(T=_spill(T, spill_dir, tag + "T"), c=c,
-                                U=_spill(U, spill_dir, tag + "U"), lam=lam, trace_G=t,
-                                G_hat=_spill(G_hat, spill_dir, tag + "Ghat"),
-                                A=_spill(A, spill_dir, tag + "A"), B=_spill(B, spill_dir, tag + "B"),
-                                chi_kept=chi_kept, P=P, Q=Q))
+                                U=None if U is None else _spill(U, spill_dir, tag + "U"), lam=lam, trace_G=t,
+                                G_hat=None if G_hat is None else _spill(G_hat, spill_dir, tag + "Ghat"),
+                                A=None if A is None else _spill(A, spill_dir, tag + "A"),
+                                B=None if B is None else _spill(B, spill_dir, tag + "B"),
+                                chi_kept=chi_kept, P=P, Q=Q, w_fixed=fixed))
         del A, B, G_hat, U
         T = Tn / c
         L += math.ldexp(math.log(c), -k)
@@ -217,12 +230,15 @@ def eig_adjoint(U: np.ndarray, lam: np.ndarray, chi_kept: int, Ubar_kept: np.nda
     return U @ S @ U.T
 
 
-def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
-    """Gradient with respect to the step's input T, given the gradient w.r.t. its unnormalised output."""
+def projection_adjoint(rec: StepRecord, Tn_bar: np.ndarray):
+    """Adjoint of the step's projection (the HOTRG step with its isometry held fixed): the gradient
+    with respect to the input T through both copies, and the gradient w_bar with respect to the
+    isometry w[x1][x2][a] (through both of its occurrences), given the gradient w.r.t. the
+    unnormalised output."""
     T = rec.T
     X = T.shape[0]
     chi_kept = rec.chi_kept
-    w = rec.U[:, :chi_kept].reshape(X, X, chi_kept)
+    w = rec.w_fixed if rec.w_fixed is not None else rec.U[:, :chi_kept].reshape(X, X, chi_kept)
     if rec.P is not None:
         P, Q = rec.P, rec.Q
     else:
@@ -239,8 +255,17 @@ def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
     T_bar_upper = _es("iyjba,xba->xiyj", P_bar, w)
     w_bar_L = _es("xiyj,iyjba->xba", T, P_bar)
     del P_bar
+    return T_bar_upper + T_bar_lower, w_bar_L + w_bar_R
+
+
+def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
+    """Gradient with respect to the step's input T, given the gradient w.r.t. its unnormalised output."""
+    T = rec.T
+    X = T.shape[0]
+    chi_kept = rec.chi_kept
+    T_bar_proj, w_bar = projection_adjoint(rec, Tn_bar)
     # the isometry is the leading eigenvectors of G_hat = sym(G) / tr G
-    Ubar_kept = (w_bar_L + w_bar_R).reshape(X * X, chi_kept)
+    Ubar_kept = w_bar.reshape(X * X, chi_kept)
     Ghat_bar = eig_adjoint(rec.U, rec.lam, chi_kept, Ubar_kept, eps)
     t = rec.trace_G
     Gs_bar = Ghat_bar / t - (np.sum(Ghat_bar * rec.G_hat) / t) * np.eye(X * X)
@@ -252,12 +277,14 @@ def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
     T_bar_A = _es("abjk,bxyk->axyj", A_bar, T) + _es("abjk,axyj->bxyk", A_bar, T)
     # B[a,b,j,k] = sum T[a,x,j,y] T[b,x,k,y]
     T_bar_B = _es("abjk,bxky->axjy", B_bar, T) + _es("abjk,axjy->bxky", B_bar, T)
-    return T_bar_upper + T_bar_lower + T_bar_A + T_bar_B
+    return T_bar_proj + T_bar_A + T_bar_B
 
 
 def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_BROADENING,
-                   progress=None) -> np.ndarray:
-    """d(gbar * lnZ/N)/dT0 in the input layout [l][u][r][d].  progress as in hotrg_forward."""
+                   progress=None, w_bar_out=None) -> np.ndarray:
+    """d(gbar * lnZ/N)/dT0 in the input layout [l][u][r][d].  progress as in hotrg_forward.
+    Steps with a given isometry (w_fixed) contribute only their projection adjoint; their isometry
+    gradients d(gbar * lnZ/N)/dw go to the dict w_bar_out[k] when it is given."""
     n = len(fwd.steps)
     D = fwd.final_T.shape
     # final self-trace: L += 2^-n ln sum_{x,y} T[x,x,y,y]
@@ -269,7 +296,12 @@ def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_B
     for k in range(n, 0, -1):
         rec = fwd.steps[k - 1]
         # output was divided by c_k; c_k itself is held constant (exact, see module notes)
-        T_in_bar = step_adjoint(rec, T_bar / rec.c, eps)
+        if rec.w_fixed is not None:
+            T_in_bar, w_bar = projection_adjoint(rec, T_bar / rec.c)
+            if w_bar_out is not None:
+                w_bar_out[k] = w_bar
+        else:
+            T_in_bar = step_adjoint(rec, T_bar / rec.c, eps)
         T_bar = np.transpose(T_in_bar, (2, 3, 0, 1)) if k > 1 else T_in_bar
         if progress is not None:
             progress("backward", k)
@@ -288,6 +320,9 @@ def step_invariants(fwd: ForwardResult):
     for rec in fwd.steps:
         lam = rec.lam
         kept = rec.chi_kept
+        if lam is None:      # a step with a given isometry has no spectrum
+            out.append({"c": rec.c, "chi_kept": kept, "trunc_weight": None, "cut_gap": None, "lam_kept": None})
+            continue
         tw = float(np.sum(lam[kept:])) if kept < lam.size else 0.0
         gap = float(lam[kept - 1] - lam[kept]) if kept < lam.size else float("inf")
         out.append({"c": rec.c, "chi_kept": kept, "trunc_weight": tw, "cut_gap": gap,
