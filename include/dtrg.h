@@ -203,7 +203,41 @@ dtrg_status dtrg_plan_forward(dtrg_plan* plan, const double* T0_dev, void* strea
 dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
                                 const double* dT0_dev, double* dlnZ_dir_host, void* stream);
 
-/* Diagnostics of step k (1 <= k <= n_steps) of a plan whose forward succeeded. */
+/*
+ * Differentiable TRG (paper, main text: the isometries w of the RG steps as parameters of the
+ * network, their environments E_w = w_bar / N_i from the backward pass (Eq. EGrad), and the MERA
+ * update w <- U V^T from the SVD E_w = U S V^T).  Single-instance plans only.
+ *
+ * dtrg_plan_isometry: copy step k's isometry w[x1][x2][a] (n = X^2 rows of chi' values, row-major;
+ *   w_dev device, n chi' doubles) after a successful forward pass.
+ * dtrg_plan_fix_isometry: later forward passes project step k with the given isometry (w_dev
+ *   device, same layout; copied into the plan) instead of the leading eigenvectors of the step's
+ *   Gram, and the backward pass treats it as a parameter: it stops at the step's projection adjoint
+ *   (nothing flows through that step's Gram) and keeps d(gbar lnZ/N)/dw.  w_dev NULL releases it.
+ *   The plan needs a new forward pass afterwards (DTRG_ESTATE otherwise).
+ * dtrg_plan_isometry_grad: after a backward pass, d(gbar lnZ/N)/dw of a step with a fixed isometry
+ *   (wbar_dev device, n chi' doubles, layout of w): the environment E_w up to the positive factor
+ *   Z N / N_i (DTRG_EINVAL for a step without a fixed isometry).
+ * dtrg_isometry_optimize: forward pass of plain HOTRG on T0_dev (its ln Z / N to *lnZ_hotrg_host,
+ *   nullable), then n_sweeps sweeps over the first `layers` steps whose isometry truncates
+ *   (chi' < X^2), from the finest scale up; per sweep and step, n_inner MERA updates, each a
+ *   backward pass for the isometry gradient, the polar factor w <- U V^T (computed on the device
+ *   without squaring the gradient's condition number), and a forward pass with the new isometry;
+ *   the isometries above the optimised steps remain HOTRG's local ones, recomputed every pass.
+ *   ln Z / N after every update goes to history_host (host, n_sweeps * layers * n_inner doubles,
+ *   nullable), the last to *lnZ_host.  The optimised isometries stay fixed in the plan, whose last
+ *   forward pass is valid (a backward pass may follow).  chi' <= 48 on the optimised steps
+ *   (DTRG_EINVAL otherwise); DTRG_EINVAL if fewer steps truncate than `layers`.
+ * All four synchronise `stream`.
+ */
+dtrg_status dtrg_plan_isometry(dtrg_plan* plan, int k, double* w_dev, void* stream);
+dtrg_status dtrg_plan_fix_isometry(dtrg_plan* plan, int k, const double* w_dev, void* stream);
+dtrg_status dtrg_plan_isometry_grad(dtrg_plan* plan, int k, double* wbar_dev, void* stream);
+dtrg_status dtrg_isometry_optimize(dtrg_plan* plan, const double* T0_dev, int layers, int n_inner, int n_sweeps,
+                                   void* stream, double* lnZ_hotrg_host, double* lnZ_host, double* history_host);
+
+/* Diagnostics of step k (1 <= k <= n_steps) of a plan whose forward succeeded.  A step with a fixed
+ * isometry reports iters = -1 and zero spectrum fields. */
 dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* info);
 
 /*

@@ -29,7 +29,8 @@ EXPORTED = ["dtrg_default_options", "dtrg_hotrg_forward", "dtrg_plan_create", "d
             "dtrg_hotrg_batched",
             "dtrg_batch_step_info", "dtrg_batch_profile", "dtrg_batch_device_bytes", "dtrg_batch_destroy", "dtrg_tuned_shapes",
             "dtrg_plan_device_bytes", "dtrg_plan_destroy", "dtrg_last_error", "dtrg_contract", "dtrg_contract_config", "dtrg_version",
-            "dtrg_contract_noalloc"]
+            "dtrg_contract_noalloc", "dtrg_plan_isometry", "dtrg_plan_fix_isometry", "dtrg_plan_isometry_grad",
+            "dtrg_isometry_optimize"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
@@ -116,6 +117,12 @@ def _load():
     lib.dtrg_contract_config.restype = c_int
     lib.dtrg_contract_noalloc.argtypes = lib.dtrg_contract.argtypes
     lib.dtrg_contract_noalloc.restype = c_int
+    for name in ("dtrg_plan_isometry", "dtrg_plan_fix_isometry", "dtrg_plan_isometry_grad"):
+        getattr(lib, name).argtypes = [c_void_p, c_int, c_void_p, c_void_p]
+        getattr(lib, name).restype = c_int
+    lib.dtrg_isometry_optimize.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, POINTER(c_double),
+                                           POINTER(c_double), POINTER(c_double)]
+    lib.dtrg_isometry_optimize.restype = c_int
     return lib
 
 
@@ -279,6 +286,60 @@ def dtrg_hotrg_backward(plan: Plan, gbar: float = 1.0, dT0: torch.Tensor | None 
         _check(lib.dtrg_hotrg_backward(plan._h, float(gbar), c_void_p(T0bar.data_ptr()), dptr,
                                        byref(val) if dT0 is not None else None, _stream(stream)))
     return T0bar, (val.value if dT0 is not None else None)
+
+
+def dtrg_plan_isometry(plan: Plan, k: int, stream=None) -> torch.Tensor:
+    """Step k's isometry w[x1][x2][a] (float64, X x X x chi') after a forward pass."""
+    info = plan.step_info(k)
+    X, K = info["X"], info["chi_kept"]
+    w = torch.empty((X, X, K), dtype=torch.float64, device=plan.device)
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_plan_isometry(plan._h, int(k), c_void_p(w.data_ptr()), _stream(stream)))
+    return w
+
+
+def dtrg_plan_fix_isometry(plan: Plan, k: int, w: torch.Tensor | None, stream=None):
+    """Project step k with the given isometry w[x1][x2][a] in later passes (None: HOTRG's own again)."""
+    ptr = None
+    if w is not None:
+        w = _dev_f64(w, "w")
+        if w.dim() != 3 or w.shape[0] != w.shape[1]:
+            raise ValueError("w must be X x X x chi'")
+        ptr = c_void_p(w.data_ptr())
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_plan_fix_isometry(plan._h, int(k), ptr, _stream(stream)))
+        plan.fixed_shapes = getattr(plan, "fixed_shapes", {})
+        if w is None:
+            plan.fixed_shapes.pop(int(k), None)
+        else:
+            plan.fixed_shapes[int(k)] = tuple(w.shape)
+
+
+def dtrg_plan_isometry_grad(plan: Plan, k: int, stream=None) -> torch.Tensor:
+    """d(gbar lnZ/N)/dw of step k's fixed isometry after a backward pass (shape of w)."""
+    shape = getattr(plan, "fixed_shapes", {}).get(int(k))
+    if shape is None:
+        info = plan.step_info(k)
+        shape = (info["X"], info["X"], info["chi_kept"])
+    g = torch.empty(shape, dtype=torch.float64, device=plan.device)
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_plan_isometry_grad(plan._h, int(k), c_void_p(g.data_ptr()), _stream(stream)))
+    return g
+
+
+def dtrg_isometry_optimize(plan: Plan, T0: torch.Tensor, layers: int = 1, n_inner: int = 5, n_sweeps: int = 4,
+                           stream=None):
+    """Differentiable-TRG isometry optimisation (see include/dtrg.h).
+    Returns (ln Z / N of plain HOTRG, ln Z / N after the optimisation, history list)."""
+    T0 = _dev_f64(T0, "T0")
+    if tuple(T0.shape) != (plan.D,) * 4:
+        raise ValueError("T0 does not match the plan's D")
+    hist = (c_double * max(1, n_sweeps * layers * n_inner))()
+    l0, l1 = c_double(), c_double()
+    with torch.cuda.device(plan.device):
+        _check(lib.dtrg_isometry_optimize(plan._h, c_void_p(T0.data_ptr()), int(layers), int(n_inner), int(n_sweeps),
+                                          _stream(stream), byref(l0), byref(l1), hist))
+    return l0.value, l1.value, list(hist)[:n_sweeps * layers * n_inner]
 
 
 class Batch:

@@ -117,6 +117,21 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->cut_gap = st.sh.b > st.sh.K ? lam[st.sh.K - 1] - lam[st.sh.K] : 0.0;
     info->min_kept_gap = st.sh.K > 1 ? gmin : 0.0;
     info->mixed = st.sh.mixed ? 1 : 0;
+    if (st.fixed) {   // a given isometry: no Gram, no spectrum
+        info->full_eig = 0;
+        info->iters = -1;
+        info->trace_G = info->lam_last_kept = info->lam_first_dropped = info->resid = 0.0;
+        info->trunc_weight = info->cut_gap = info->min_kept_gap = 0.0;
+        info->cheb_degree = 0;
+    }
+}
+
+// step k of a single-instance plan, checked
+StepCk& plan_step(dtrg_plan* P, int k) {
+    DTRG_REQUIRE(P, DTRG_EINVAL, "NULL argument");
+    DTRG_REQUIRE(P->nb == 1, DTRG_EINVAL, "not a single-instance plan");
+    DTRG_REQUIRE(k >= 1 && k <= P->nsteps, DTRG_EINVAL, "step index out of range");
+    return P->steps[k - 1];
 }
 
 }  // namespace
@@ -458,6 +473,90 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
         if (plan) (void)hipStreamSynchronize(plan->s);
         return fail(e);
     } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return DTRG_EHIP;
+    }
+}
+
+dtrg_status dtrg_plan_isometry(dtrg_plan* plan, int k, double* w_dev, void* stream) {
+    g_last_error.clear();
+    try {
+        StepCk& st = plan_step(plan, k);
+        DTRG_REQUIRE(w_dev, DTRG_EINVAL, "NULL argument");
+        DTRG_REQUIRE(plan->fwd_ok, DTRG_ESTATE, "plan has no successful forward");
+        plan->s = (hipStream_t)stream;
+        copy2d(st.U.p, st.sh.b, st.U.bs, w_dev, st.sh.K, 0, st.sh.n, st.sh.K, 1, plan->s);
+        DTRG_HIP(hipStreamSynchronize(plan->s));
+        return DTRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+dtrg_status dtrg_plan_fix_isometry(dtrg_plan* plan, int k, const double* w_dev, void* stream) {
+    g_last_error.clear();
+    try {
+        StepCk& st = plan_step(plan, k);
+        plan->s = (hipStream_t)stream;
+        plan->alloc.stream = plan->s;
+        AllocScope scope(&plan->alloc);
+        plan->fwd_ok = false;
+        plan->sched_fwd = plan->sched_bwd = false;
+        if (!w_dev) {
+            st.fixed = false;
+            return DTRG_OK;
+        }
+        if (st.wbar.n == 0) st.wbar.alloc_inst(1, (i64)st.sh.n * st.sh.K);
+        copy2d(w_dev, st.sh.K, 0, st.U.p, st.sh.b, st.U.bs, st.sh.n, st.sh.K, 1, plan->s);
+        DTRG_HIP(hipStreamSynchronize(plan->s));
+        st.fixed = true;
+        return DTRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return DTRG_EHIP;
+    }
+}
+
+dtrg_status dtrg_plan_isometry_grad(dtrg_plan* plan, int k, double* wbar_dev, void* stream) {
+    g_last_error.clear();
+    try {
+        StepCk& st = plan_step(plan, k);
+        DTRG_REQUIRE(wbar_dev, DTRG_EINVAL, "NULL argument");
+        DTRG_REQUIRE(st.fixed, DTRG_EINVAL, "step has no fixed isometry");
+        DTRG_REQUIRE(plan->fwd_ok && plan->sched_bwd, DTRG_ESTATE, "no backward pass since the forward");
+        plan->s = (hipStream_t)stream;
+        copy2d(st.wbar.p, st.sh.K, 0, wbar_dev, st.sh.K, 0, st.sh.n, st.sh.K, 1, plan->s);
+        DTRG_HIP(hipStreamSynchronize(plan->s));
+        return DTRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+dtrg_status dtrg_isometry_optimize(dtrg_plan* plan, const double* T0_dev, int layers, int n_inner, int n_sweeps,
+                                   void* stream, double* lnZ_hotrg_host, double* lnZ_host, double* history_host) {
+    g_last_error.clear();
+    try {
+        DTRG_REQUIRE(plan && T0_dev && lnZ_host, DTRG_EINVAL, "NULL argument");
+        DTRG_REQUIRE(plan->nb == 1, DTRG_EINVAL, "not a single-instance plan");
+        plan->fwd_ok = false;
+        plan->s = (hipStream_t)stream;
+        plan->alloc.stream = plan->s;
+        AllocScope scope(&plan->alloc);
+        const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
+        DTRG_HIP(hipMemcpyAsync(plan->T0buf.p, T0_dev, D4 * sizeof(double), hipMemcpyDeviceToDevice, plan->s));
+        std::vector<double> hist;
+        plan_isometry_optimize(plan, layers, n_inner, n_sweeps, lnZ_hotrg_host, &hist);
+        *lnZ_host = plan->scal_h[0];
+        if (history_host) std::copy(hist.begin(), hist.end(), history_host);
+        return DTRG_OK;
+    } catch (const Error& e) {
+        if (plan) (void)hipStreamSynchronize(plan->s);
+        return fail(e);
+    } catch (const std::exception& e) {
+        if (plan) (void)hipStreamSynchronize(plan->s);
         g_last_error = e.what();
         return DTRG_EHIP;
     }

@@ -308,6 +308,9 @@ void col_normalise(double* V, int n, int b, int ldv, i64 v_bs, const double* nrm
 // res[j] = |Y[:, j] - theta[j] V[:, j]| for j < k
 void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, i64 v_bs, const double* theta_dev,
                     i64 th_bs, double* res_dev, i64 res_bs, int nb, hipStream_t s);
+// S = [[0, R], [R^T, 0]] (2K x 2K, row-major) from R (K x K): its eigenpairs are +-sigma_j with vectors
+// (u_j, +-v_j) / sqrt 2 for the singular triplets of R
+void sym_augment(const double* R, i64 r_bs, int K, double* S, i64 s_bs, int nb, hipStream_t s);
 // S[i][j] = F(lam_j - lam_i) * (Om[i][j] - Om[j][i]) / 2 on the k x k kept block (F_ii = 0),
 // F(d) = d / (d^2 + eps)
 void kept_block_adjoint(const double* Om, i64 om_bs, const double* lam_dev, i64 lam_bs, int k, double eps, double* S,

@@ -351,6 +351,20 @@ __global__ __launch_bounds__(256) void ritz_res_kernel(const double* V, const do
 
 __device__ inline double bgap(double d, double eps) { return d / (d * d + eps); }
 
+// S = [[0, R], [R^T, 0]] (2K x 2K, ld 2K) from R (K x K, ld K)
+__global__ __launch_bounds__(256) void sym_augment_kernel(const double* R, i64 r_bs, int K, double* S, i64 s_bs) {
+    R += blockIdx.y * r_bs;
+    S += blockIdx.y * s_bs;
+    const int m = 2 * K;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < m * m; idx += gridDim.x * blockDim.x) {
+        const int i = idx / m, j = idx % m;
+        double v = 0.0;
+        if (i < K && j >= K) v = R[i * K + (j - K)];
+        else if (i >= K && j < K) v = R[j * K + (i - K)];
+        S[idx] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void kept_block_kernel(const double* Om, i64 om_bs, const double* lam,
                                                           i64 lam_bs, int k, double eps, double* S, i64 s_bs) {
     Om += blockIdx.y * om_bs;
@@ -513,6 +527,11 @@ void ritz_residuals(const double* V, const double* Y, int n, int k, int ld, i64 
                     i64 th_bs, double* res_dev, i64 res_bs, int nb, hipStream_t s) {
     hipLaunchKernelGGL(ritz_res_kernel, dim3(k, nb), dim3(256), 0, s, V, Y, n, ld, v_bs, theta_dev, th_bs, res_dev,
                        res_bs);
+    DTRG_HIP(hipGetLastError());
+}
+
+void sym_augment(const double* R, i64 r_bs, int K, double* S, i64 s_bs, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(sym_augment_kernel, grid2((i64)4 * K * K, nb), dim3(256), 0, s, R, r_bs, K, S, s_bs);
     DTRG_HIP(hipGetLastError());
 }
 

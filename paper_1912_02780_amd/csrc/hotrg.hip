@@ -33,7 +33,8 @@ void for_each_buf(const dtrg_plan& P, F f) {
     const DevBuf<double>* w[] = {&P.TA, &P.TB, &P.Tn, &P.Tbar, &P.Tbar2, &P.Wk, &P.A, &P.B, &P.Gw, &P.Gt, &P.Ub,
                                  &P.Xe, &P.Xc, &P.Re, &P.Om, &P.Sm, &P.Vc, &P.Vp, &P.Vn, &P.Ye, &P.We, &P.V1, &P.V2,
                                  &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
-                                 &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red};
+                                 &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red,
+                                 &P.polS, &P.polV, &P.pollam};
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
@@ -41,7 +42,7 @@ void for_each_buf(const dtrg_plan& P, F f) {
         for (auto* b : v) f(b->mem.p, b->mem.bytes());
     }
     for (auto& st : P.steps) {
-        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam, &st.Ak, &st.Bk, &st.Gk};
+        const DevBuf<double>* v[] = {&st.T, &st.U, &st.lam, &st.Ak, &st.Bk, &st.Gk, &st.wbar};
         for (auto* b : v) f(b->p, b->bytes());
         f(st.P1k.mem.p, st.P1k.mem.bytes());
         f(st.Q2k.mem.p, st.Q2k.mem.bytes());
@@ -955,11 +956,14 @@ void plan_forward(dtrg_plan* P, Mode mode) {
             permute_checked(P, P->Tn, st.T.p, st.T.bs, pd4(ps.K, ps.K, ps.Y, ps.Y, 2, 3, 0, 1), 1.0,
                             P->sc(k - 1, 1), c.s);
         }
-        gram_of_step(c, st, k);
-        if (st.keep_gram) keep_gram(c, st, true);
-        if (c.adaptive()) check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
-        const StepCk* warm = (k >= 3) ? &P->steps[k - 3] : nullptr;
-        eigensolve(c, st, k, warm);
+        if (!st.fixed) {
+            gram_of_step(c, st, k);
+            if (st.keep_gram) keep_gram(c, st, true);
+            if (c.adaptive())
+                check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
+            const StepCk* warm = (k >= 3 && !P->steps[k - 3].fixed) ? &P->steps[k - 3] : nullptr;
+            eigensolve(c, st, k, warm);
+        }
         // projection (in the step's contraction format; the output T' is FP64)
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
         const Lds l(st.sh);
@@ -1091,6 +1095,14 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.beta = 1.0;
             c.run(g, pr, Out::F64);
         }
+        if (st.fixed) {
+            // the isometry is a parameter of its own: its gradient is kept, and nothing flows
+            // through the Gram of the step
+            copy2d(P->Ub.p, K, P->Ub.bs, st.wbar.p, K, st.wbar.bs, n, K, nb, c.s);
+            std::swap(P->Tbar, P->Tbar2);
+            if (c.adaptive()) check_flags(P, kFlagErrors, "backward step " + std::to_string(k));
+            continue;
+        }
         // the step's half-environments and normalised Gram: kept, or recomputed from its checkpoint
         if (st.keep_gram) {
             step_operands_TA_TB(c, st);
@@ -1154,6 +1166,92 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         P->sched_bwd = true;
         persist_tuning(P);
     }
+}
+
+// MERA update of step k's fixed isometry (paper, main text: the SVD E = U S V^T of the environment
+// and w <- U V^T, which maximises Tr(E^T w)) from the gradient in st.wbar, which is E up to a
+// positive factor.  The polar factor is formed without squaring E's condition number (the
+// environments reach condition numbers of 1e8): E = Q R with the shifted CholeskyQR3 of the
+// eigensolver (orthonormal to working accuracy for condition numbers up to ~1/u), R = Q^T E, and
+// polar(R) = sum_j u_j v_j^T from the positive eigenpairs of [[0, R], [R^T, 0]] (Jacobi), whose
+// eigenvectors are (u_j, v_j) / sqrt 2; then w = Q polar(R).  K <= 48 (2K within the Jacobi kernel).
+void polar_update(dtrg_plan* P, int k) {
+    StepCk& st = P->steps[k - 1];
+    const int n = st.sh.n, K = st.sh.K, b = st.sh.b, nb = P->nb, m = 2 * K;
+    DTRG_REQUIRE(st.fixed, DTRG_ESTATE, "polar update of a step without a fixed isometry");
+    DTRG_REQUIRE(m <= kJacobiMax, DTRG_EINVAL, "isometry optimisation needs chi' <= 48 on the optimised steps");
+    Ctx c{P, P->s, Mode::Adaptive};
+    if (P->polS.n < (size_t)m * m * nb) {
+        P->polS.alloc_inst(nb, (i64)m * m);
+        P->polV.alloc_inst(nb, (i64)m * m);
+        P->pollam.alloc_inst(nb, m);
+    }
+    const i64 vbs = P->V1.bs;
+    // Q: E orthonormalised (in V1, ld K)
+    copy2d(st.wbar.p, K, st.wbar.bs, P->V1.p, K, vbs, n, K, nb, c.s);
+    orthonormalise(c, P->V1.p, P->V2.p, vbs, n, K);
+    // R = Q^T E (K x K, in H)
+    {
+        GemmOp g;
+        g.M = K; g.N = K; g.K = n;
+        g.A = P->V1.p; g.lda = K; g.a_kmajor = true;
+        g.B = st.wbar.p; g.ldb = K; g.b_kmajor = true;
+        g.C = P->H.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+        set_bs(g, vbs, st.wbar.bs, P->H.bs);
+        c.gemm(g);
+    }
+    sym_augment(P->H.p, P->H.bs, K, P->polS.p, P->polS.bs, nb, c.s);
+    jacobi_eig(P->polS.p, m, m, P->polS.bs, P->pollam.p, P->pollam.bs, P->polV.p, m, P->polV.bs, nb, kJacobiSweeps,
+               P->misc.p, c.s, P->flags.p, kFlagJacobi);
+    // polar(R)[r][c] = 2 sum_{j < K} V[r][j] V[K + c][j]   (into Rinv, K x K)
+    {
+        GemmOp g;
+        g.M = K; g.N = K; g.K = K;
+        g.A = P->polV.p; g.lda = m;
+        g.B = P->polV.p + (i64)K * m; g.ldb = m;
+        g.C = P->Rinv.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+        g.alpha = 2.0;
+        set_bs(g, P->polV.bs, P->polV.bs, P->Rinv.bs);
+        c.gemm(g);
+    }
+    // w = Q polar(R), into the first K columns of U (ld b)
+    {
+        GemmOp g;
+        g.M = n; g.N = K; g.K = K;
+        g.A = P->V1.p; g.lda = K;
+        g.B = P->Rinv.p; g.ldb = K; g.b_kmajor = true;
+        g.C = st.U.p; g.rmap = IdxMap::linear(b); g.cmap = IdxMap::linear(1);
+        set_bs(g, vbs, P->Rinv.bs, st.U.bs);
+        c.gemm(g);
+    }
+    check_flags(P, kFlagJacobi, "step " + std::to_string(k) + ": polar factor of the isometry gradient");
+}
+
+void plan_isometry_optimize(dtrg_plan* P, int layers, int n_inner, int n_sweeps, double* lnZ_hotrg,
+                            std::vector<double>* history) {
+    DTRG_REQUIRE(P->nb == 1, DTRG_EINVAL, "isometry optimisation needs a single-instance plan");
+    DTRG_REQUIRE(layers >= 1 && n_inner >= 1 && n_sweeps >= 0, DTRG_EINVAL, "layers, n_inner >= 1 and n_sweeps >= 0");
+    for (auto& st : P->steps) st.fixed = false;
+    plan_forward(P, Mode::Adaptive);   // plain HOTRG: its isometries start the optimisation
+    if (lnZ_hotrg) *lnZ_hotrg = P->scal_h[0];
+    std::vector<int> opt;
+    for (int k = 1; k <= P->nsteps && (int)opt.size() < layers; ++k)
+        if (P->steps[k - 1].sh.K < P->steps[k - 1].sh.n) opt.push_back(k);
+    DTRG_REQUIRE((int)opt.size() == layers, DTRG_EINVAL, "fewer truncating steps than layers to optimise");
+    for (int k : opt) {
+        StepCk& st = P->steps[k - 1];
+        DTRG_REQUIRE(2 * st.sh.K <= kJacobiMax, DTRG_EINVAL, "isometry optimisation needs chi' <= 48 on the optimised steps");
+        if (st.wbar.n == 0) st.wbar.alloc_inst(1, (i64)st.sh.n * st.sh.K);
+        st.fixed = true;   // U already holds HOTRG's isometry of the step
+    }
+    for (int s = 0; s < n_sweeps; ++s)
+        for (int k : opt)
+            for (int it = 0; it < n_inner; ++it) {
+                plan_backward(P, 1.0, false, Mode::Adaptive);
+                polar_update(P, k);
+                plan_forward(P, Mode::Adaptive);
+                if (history) history->push_back(P->scal_h[0]);
+            }
 }
 
 }  // namespace dtrg

@@ -89,6 +89,11 @@ struct StepCk {
     int iters = 0;         // subspace iterations
     int cheb = 0;          // degree of the complement expansion (0: none)
     double hi_mult = 1.0;  // widening factor of the complement interval
+    // a given isometry (the first K columns of U, set by the caller or by the isometry optimiser):
+    // the forward projects with it instead of the leading eigenvectors of the step's Gram, and the
+    // backward stops at the projection adjoint and leaves d(gbar lnZ/N)/dw in wbar [n][K]
+    bool fixed = false;
+    DevBuf<double> wbar;
 };
 
 }  // namespace dtrg
@@ -127,6 +132,7 @@ struct dtrg_plan {
     dtrg::DevBuf<double> ctab;  // Chebyshev DCT tables of degree 8, 16, ..., 1024
     bool ctab_ready = false;
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
+    dtrg::DevBuf<double> polS, polV, pollam;   // polar factor of an isometry gradient (2K x 2K, 2K)
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)
     int tuned_seen = -1;          // size of the process table when the file was last written
@@ -158,6 +164,15 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode);
 // Read scalars and flags back (synchronises the plan's stream); throw the error of the first
 // flagged instance (bits in mask).
 void plan_read_back(dtrg_plan* P);
+// Differentiable-TRG isometry optimisation of the first `layers` truncating steps of a
+// single-instance plan (T0 already in P->T0buf): n_sweeps sweeps over the layers from the finest
+// scale up, n_inner MERA updates per layer and sweep (a backward pass for the isometry gradient E,
+// w <- U V^T from E = U S V^T, a forward pass).  history (nullable): ln Z / N after every update.
+// Leaves the optimised isometries fixed in the plan and its last forward pass valid.
+void plan_isometry_optimize(dtrg_plan* P, int layers, int n_inner, int n_sweeps, double* lnZ_hotrg,
+                            std::vector<double>* history);
+// The MERA update of step k's fixed isometry from the gradient in its wbar: w <- polar factor.
+void polar_update(dtrg_plan* P, int k);
 void plan_throw_flags(const dtrg_plan* P, int mask, const std::string& where);
 
 // tune.hip: the tile configuration for op, measured once per shape when tuning is allowed

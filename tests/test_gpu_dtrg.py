@@ -1,0 +1,126 @@
+"""GPU tests of the differentiable-TRG isometry optimisation (through the C ABI) against the oracle
+(oracle/dtrg.py) and Onsager's solution.
+
+* With the oracle's HOTRG isometries fixed on both sides (the same gauge), ln Z / N within 1e-12 and
+  the isometry gradients entry by entry within 1e-9 (the gradients of the fixed steps do not depend
+  on the gauges the two eigensolvers pick for the higher steps).
+* The whole optimisation: ln Z / N after every MERA update within 1e-10 of the oracle's trajectory
+  (the update is gauge covariant, w O -> polar(E O) = polar(E) O, so the trajectories agree although
+  the two sides start from differently signed eigenvectors).
+* The paper's Fig. 2 property at a size the oracle is too slow for (chi = 16, three layers): the
+  optimised free energy is closer to Onsager's than plain HOTRG's near T_c.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_02780_amd import binding
+    return binding
+
+
+def _inputs(case):
+    from paper_1912_02780_amd import inputs as I
+    if case == "ising_bc":
+        return I.ising_T0(0.4406868), 8, 12
+    return np.random.default_rng(11).random((3, 3, 3, 3)) + 0.2, 7, 8
+
+
+@pytest.mark.parametrize("case", ["ising_bc", "random_d3"])
+def test_gpu_isometry_gradient_vs_oracle(B, case):
+    from oracle import dtrg as DT
+    from oracle import hotrg as O
+    T0, chi, n = _inputs(case)
+    fwd = O.hotrg_forward(T0, chi, n)
+    steps = DT.truncating_steps(fwd)[:2]
+    w = {k: DT.isometry_of(fwd.steps[k - 1]) for k in steps}
+    Lo, wbar_o, _ = DT.lnZ_and_wbar(T0, chi, n, w)
+    _say(f"[gpu] isometry gradient {case} steps {steps}")
+    dev = torch.device("cuda:0")
+    t0 = torch.from_numpy(T0).to(dev)
+    plan = B.dtrg_plan_create(T0.shape[0], chi, n, None, dev)
+    for k in steps:
+        B.dtrg_plan_fix_isometry(plan, k, torch.from_numpy(np.ascontiguousarray(w[k])).to(dev))
+    L = B.dtrg_plan_forward(plan, t0)
+    B.dtrg_hotrg_backward(plan, 1.0)
+    assert abs(L / Lo - 1) < 1e-12, (L, Lo)
+    for k in steps:
+        g = B.dtrg_plan_isometry_grad(plan, k).cpu().numpy()
+        ref = wbar_o[k]
+        err = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
+        _say(f"    step {k}: max |dw - dw_oracle| / max |dw_oracle| = {err:.1e}")
+        assert err < 1e-9
+        assert plan.step_info(k)["iters"] == -1
+
+
+@pytest.mark.parametrize("case", ["ising_bc", "random_d3"])
+def test_gpu_isometry_optimisation_trajectory_vs_oracle(B, case):
+    from oracle import dtrg as DT
+    T0, chi, n = _inputs(case)
+    layers, n_inner, n_sweeps = 2, 4, 2
+    L0o, Lo, hist_o, _ = DT.optimize(T0, chi, n, layers=layers, n_inner=n_inner, n_sweeps=n_sweeps)
+    _say(f"[gpu] isometry optimisation {case}: layers {layers}, n_inner {n_inner}, sweeps {n_sweeps}")
+    dev = torch.device("cuda:0")
+    plan = B.dtrg_plan_create(T0.shape[0], chi, n, None, dev)
+    L0, L, hist = B.dtrg_isometry_optimize(plan, torch.from_numpy(T0).to(dev), layers, n_inner, n_sweeps)
+    rel = np.abs(np.array(hist) / np.array(hist_o) - 1)
+    _say(f"    HOTRG {L0:.15f} (oracle {L0o:.15f}); optimised {L:.15f} (oracle {Lo:.15f}); "
+         f"trajectory max rel {rel.max():.1e}")
+    assert abs(L0 / L0o - 1) < 1e-12
+    assert len(hist) == len(hist_o) == layers * n_inner * n_sweeps
+    assert rel.max() < 1e-10
+    # the plan's last forward is the optimised network's: a backward pass may follow
+    g, _ = B.dtrg_hotrg_backward(plan, 1.0)
+    assert abs(float((g.cpu().numpy() * T0).sum()) - 1.0) < 1e-10      # Euler identity
+
+
+@pytest.mark.parametrize("beta", [0.43, 0.4406868, 0.45])
+def test_gpu_isometry_optimisation_beats_hotrg_near_Tc(B, beta):
+    import exact_ising as E
+    from paper_1912_02780_amd import inputs as I
+    chi, n = 16, 24
+    dev = torch.device("cuda:0")
+    plan = B.dtrg_plan_create(2, chi, n, None, dev)
+    L0, L, hist = B.dtrg_isometry_optimize(plan, torch.from_numpy(I.ising_T0(beta)).to(dev), 3, 5, 2)
+    Lx = float(E.onsager_lnZ_per_site(beta))
+    e0, e1 = abs(L0 / Lx - 1), abs(L / Lx - 1)
+    _say(f"[gpu] dTRG beta={beta} chi={chi}: |df/f| HOTRG {e0:.2e} -> optimised {e1:.2e}")
+    assert L > L0 and e1 < e0
+
+
+def test_gpu_isometry_errors(B):
+    from paper_1912_02780_amd import inputs as I
+    dev = torch.device("cuda:0")
+    plan = B.dtrg_plan_create(2, 8, 6, None, dev)
+    t0 = torch.from_numpy(I.ising_T0(0.44)).to(dev)
+    B.dtrg_plan_forward(plan, t0)
+    with pytest.raises(B.DtrgError) as e:          # no fixed isometry on step 3
+        B.dtrg_plan_isometry_grad(plan, 3)
+    assert e.value.status == B.DTRG_EINVAL
+    w = B.dtrg_plan_isometry(plan, 3)
+    B.dtrg_plan_fix_isometry(plan, 3, w)
+    with pytest.raises(B.DtrgError) as e:          # the plan needs a forward pass first
+        B.dtrg_hotrg_backward(plan, 1.0)
+    assert e.value.status == B.DTRG_ESTATE
+    L = B.dtrg_plan_forward(plan, t0)
+    B.dtrg_plan_fix_isometry(plan, 3, None)
+    # HOTRG's own isometry again: the same network (to rounding: the eigensolver two steps up starts
+    # from step 3's Ritz vectors only when step 3 ran its own eigensolve)
+    assert abs(B.dtrg_plan_forward(plan, t0) / L - 1) < 1e-13
+    with pytest.raises(B.DtrgError) as e:          # more layers than truncating steps
+        B.dtrg_isometry_optimize(plan, t0, 9, 1, 1)
+    assert e.value.status == B.DTRG_EINVAL
