@@ -64,17 +64,21 @@ DEFAULT_CONTRACT = {"chi48": "bf16x6", "batch256": "bf16x6", "ising_chi64": "bf1
 CHI64_CHAIN = 512
 
 
-# L2-miss byte counters of the timed join kernel per launch, from two rocprofv3 --pmc passes over
-# one bench pass (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch averaged over the pass's launches),
-# scaled by what the same counters read for a plain 1 GiB device copy run first in the same
-# process (FETCH_SIZE reads 524308 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE reads 1048576 KiB
-# for 1048576 KiB written: factor 1.0).  Valid only for the kernel sources they were taken on.
+# HBM / Infinity-Cache byte counters (L2 misses) of the timed join kernel per launch, from two
+# rocprofv3 --pmc passes over one bench pass (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch averaged
+# over the pass's full-size launches), scaled by what the same counters read for kernels of known
+# traffic run first in the same process (--copy-calibration-mib 1024): a 1 GiB sum reads 524349 KiB
+# of FETCH_SIZE (factor 2.0), a 1 GiB fill writes 1048576 KiB of WRITE_SIZE (factor 1.0).  Valid only
+# for the kernel sources they were taken on.
 TRAFFIC_FACTORS = {"fetch": 2.0, "write": 1.0}
 TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_02780_amd/csrc/gemm.hip",
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 20 launches of that size per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "d417e468591649482684850ba215a65199b69d485bcce96c39898efee1db4d81", "fetch_kib": 5219061.9, "write_kib": 1699828.2},
+    ("chi48", "bf16x6"): {"sources_sha256": "8c13d784de82c1fdae4f97fb74c77b230f129e2c5ac976ed7b0e70168ae5fa77",
+                          "fetch_kib": 5007730.0, "write_kib": 1700350.0,
+                          # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), same runs
+                          "mfma_busy_counter": 0.579},
 }
 
 
@@ -87,9 +91,14 @@ def _sources_hash():
     return h.hexdigest()
 
 
-def traffic_bytes(workload, contract):
+def _measured(workload, contract):
     m = MEASURED_TRAFFIC.get((workload, contract))
-    if m is None or m["sources_sha256"] != _sources_hash():
+    return m if m is not None and m["sources_sha256"] == _sources_hash() else None
+
+
+def traffic_bytes(workload, contract):
+    m = _measured(workload, contract)
+    if m is None:
         return None
     return (m["fetch_kib"] * TRAFFIC_FACTORS["fetch"] + m["write_kib"] * TRAFFIC_FACTORS["write"]) * 1024.0
 
@@ -183,7 +192,7 @@ def cpu_baseline(chi: int, n_steps: int, D: int = 4, seed: int = 0, reps: int = 
     }
 
 
-def roofline(launches, ms, flops, contract, kernel, traffic=None):
+def roofline(launches, ms, flops, contract, kernel, traffic=None, busy_counter=None):
     if not (launches > 0 and ms > 0):
         return None
     achieved = flops / (ms * 1e-3) / 1e12
@@ -197,6 +206,8 @@ def roofline(launches, ms, flops, contract, kernel, traffic=None):
         out["mfma_busy_frac"] = achieved * PRODUCTS[contract] / peak
     if traffic is not None:
         out["traffic_unit"] = "bytes per launch (L2 misses: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
+    if busy_counter is not None:
+        out["mfma_busy_counter"] = busy_counter   # measured (rocprofv3 --pmc), not derived
     return out
 
 
@@ -258,7 +269,9 @@ def bench_chi48(args, B, I, torch, np, dev):
                    "checkpoint_gib": ck, "max_fp32_chain": chain, "lnZ_per_site": L,
                    "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
-                             traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None),
+                             traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None,
+                             (_measured("chi48", args.contract) or {}).get("mfma_busy_counter")
+                             if (chi, n) == (48, 24) else None),
         **err,
     }
     plan.close()
@@ -394,6 +407,7 @@ def bench_batch256(args, B, I, torch, np, dev):
         sample[f"chi{c}"] = per
         seq_s += per * int((chis == c).sum())
     seq_value = n_inst * n / seq_s
+    device_gb = batch.device_bytes() / 1e9
     batch.close()
     return {
         "metric": "HOTRG fwd+bwd aggregate RG-steps/s, 256 Ising temperatures with mixed chi (batched, graph replay)",
@@ -402,7 +416,7 @@ def bench_batch256(args, B, I, torch, np, dev):
                                 "(86/85/85), 30 RG steps each, forward + backward to dlnZ/dbeta, replayed from one "
                                 "HIP graph"),
                    "n_inst": n_inst, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": 1, "checkpoint_gib": ck,
-                   "device_GB": batch.device_bytes() / 1e9},
+                   "device_GB": device_gb},
         "adaptive_run_s": t_adaptive, "first_adaptive_run_s (incl. tuning)": t_first,
         "sequential_fp64_single_instance": {"value": seq_value, "unit": "RG-steps/s",
                                             "per_instance_s": sample, "sample_per_chi": args.seq_sample},
@@ -556,13 +570,15 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib > 0:
-        # a plain copy of known size (reads and writes exactly this many bytes) for counter scaling
-        src = torch.ones(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
+        # kernels of known traffic for scaling the HBM byte counters: a fill (writes exactly this
+        # many bytes), a sum (reads them; its output is one value) and a copy (reads and writes them)
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
+        s = src.sum()
+        dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, s
     fn = {"chi48": bench_chi48, "batch256": bench_batch256, "ising_chi64": bench_ising_chi64}[args.workload]
     res = fn(args, B, I, torch, np, dev)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,

@@ -100,6 +100,20 @@ def onsager_dlnZ_dbeta(beta: float) -> float:
     return float(-u)
 
 
+def _onsager_energy_mp(b):
+    s2, c2 = mpmath.sinh(2 * b), mpmath.cosh(2 * b)
+    kp = abs(1 - s2 * s2) / (c2 * c2)
+    K = mpmath.pi / (2 * mpmath.agm(1, kp))
+    return -(c2 / s2) * (1 + (2 / mpmath.pi) * (2 * mpmath.tanh(2 * b) ** 2 - 1) * K)
+
+
+def onsager_specific_heat(beta: float) -> float:
+    """Specific heat per site c = beta^2 d^2(lnZ/N)/dbeta^2 = -beta^2 du/dbeta, the derivative of the
+    closed-form energy above taken by mpmath at 30 digits (off the critical point, where c is finite)."""
+    b = mpmath.mpf(beta)
+    return float(-b * b * mpmath.diff(_onsager_energy_mp, b))
+
+
 def onsager_critical_lnZ_per_site() -> float:
     """ln Z / N at the exact critical coupling: ln(2)/2 + 2 G / pi."""
     return float(mpmath.log(2) / 2 + 2 * mpmath.catalan / mpmath.pi)

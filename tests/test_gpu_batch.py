@@ -239,3 +239,31 @@ def test_batch_full_shapes_vs_golden_and_onsager(B):
     # the replay of the recorded schedule gives the same numbers
     L1, g1, d1 = _run(B, batch, T0s, dT0s, replay=True)
     assert np.array_equal(L1, L) and np.array_equal(d1, d) and np.array_equal(g1, g)
+
+
+def test_batch_256_temperatures_replay_vs_onsager(B):
+    """The whole 256-temperature workload (beta_i = 0.30 + 0.30 i / 255, chi_i = (32, 16, 24)[i mod 3],
+    30 steps) in the benchmark's configuration (three-plane split-bf16, tile autotuner): the adaptive
+    run, then two replays of its HIP graph, every instance's free energy and energy against Onsager at
+    the bounds above, and the replays bit for bit equal to the adaptive run."""
+    import exact_ising as E
+    from paper_1912_02780_amd import inputs as I
+    betas = I.batch_betas(256)
+    chis = [int(c) for c in I.batch_chis(256)]
+    T0s, dT0s = _ising_inputs(betas)
+    _say("[gpu] 256-temperature batch: adaptive run")
+    batch = B.dtrg_batch_create(2, chis, 30, B.default_options(contract="bf16x6", autotune=1))
+    L, g, d = _run(B, batch, T0s, dT0s)
+    for rep in range(2):
+        _say(f"[gpu] 256-temperature batch: replay {rep}")
+        L1, g1, d1 = _run(B, batch, T0s, dT0s, replay=True)
+        assert np.array_equal(L1, L) and np.array_equal(d1, d) and np.array_equal(g1, g)
+    worst = {}
+    for i, (beta, chi) in enumerate(zip(betas, chis)):
+        ef = abs(L[i] / float(E.onsager_lnZ_per_site(beta)) - 1)
+        eu = abs(d[i] / float(E.onsager_dlnZ_dbeta(beta)) - 1)
+        worst[chi] = max(worst.get(chi, (0, 0)), (eu, ef))
+        assert ef < ONSAGER_F_TOL, (beta, chi, ef)
+        assert eu < ONSAGER_U_TOL[chi], (beta, chi, eu)
+    _say("    worst (energy, free energy) vs Onsager per chi: "
+         + ", ".join(f"chi={c}: {u:.1e}, {f:.1e}" for c, (u, f) in sorted(worst.items())))

@@ -166,3 +166,29 @@ def test_gpu_step_info_diagnostics_vs_oracle(B):
         assert abs(info["cut_gap"] - gap) < 1e-12, k
         mkg = float(np.min(lam[:K - 1] - lam[1:K])) if K > 1 else 0.0
         assert abs(info["min_kept_gap"] - mkg) < 1e-12, k
+
+
+@pytest.mark.parametrize("beta,tol_onsager", [(0.30, 1e-5), (0.50, 1e-4)])
+def test_gpu_specific_heat(B, beta, tol_onsager):
+    """The specific heat from the autograd energy (Richardson central difference of the reverse-mode
+    energy, h = 1e-4): against the same difference of the oracle's energy at chi = 12 (the same
+    function of beta, so to rounding / h), and against Onsager at chi = 24."""
+    import exact_ising as E
+    from oracle import hotrg as O
+    from paper_1912_02780_amd import inputs as I
+    from paper_1912_02780_amd.autograd import ising_specific_heat
+
+    def u(b):
+        _, g, _ = O.lnZ_and_grad(I.ising_T0(b), 12, 16)
+        return -float(np.sum(g * I.ising_dT0_dbeta(b)))
+    h = 1e-4
+    d1 = (u(beta + h) - u(beta - h)) / (2 * h)
+    d2 = (u(beta + h / 2) - u(beta - h / 2)) / h
+    c_oracle = -beta * beta * (4 * d2 - d1) / 3
+    c12 = ising_specific_heat(beta, 12, 16, h)
+    c24 = ising_specific_heat(beta, 24, 24, h)
+    c_ex = E.onsager_specific_heat(beta)
+    _say(f"[gpu] specific heat beta={beta}: chi=12 {c12:.12f} (oracle {c_oracle:.12f}); chi=24 {c24:.10f} "
+         f"(Onsager {c_ex:.10f}, rel {abs(c24 / c_ex - 1):.1e})")
+    assert abs(c12 / c_oracle - 1) < 1e-8
+    assert abs(c24 / c_ex - 1) < tol_onsager

@@ -291,3 +291,16 @@ def test_mutation_dropped_lower_copy_adjoint():
         assert not _pins_pass()
     finally:
         O.step_adjoint = orig
+
+
+def test_specific_heat_closed_form_vs_oracle_differences():
+    """c = -beta^2 du/dbeta: Onsager's (mpmath derivative of the closed-form energy) against the
+    Richardson central difference (h = 1e-4, 5e-5) of the oracle's reverse-mode energy at chi = 12."""
+    def u(beta):
+        _, g, _ = O.lnZ_and_grad(I.ising_T0(beta), 12, 16)
+        return -float(np.sum(g * I.ising_dT0_dbeta(beta)))
+    beta, h = 0.30, 1e-4
+    d1 = (u(beta + h) - u(beta - h)) / (2 * h)
+    d2 = (u(beta + h / 2) - u(beta - h / 2)) / h
+    c = -beta * beta * (4 * d2 - d1) / 3
+    assert abs(c / E.onsager_specific_heat(beta) - 1) < 3e-6
