@@ -343,8 +343,10 @@ dtrg_status dtrg_contract(int precision, int M, int N, int K, const void* A_dev,
 /*
  * Diagnostic: dtrg_contract with the kernel configuration given instead of chosen.  tile: 0 = the
  * library's choice; 1 = 64 x 64 and 2 = 128 x 128 blocks (every precision); for DTRG_BF16X3 and
- * DTRG_BF16X6 also 3 = 256 x 128, 4 = 64 x 64 on four waves that each cover all 64 columns, and
- * 5 = 128 x 128 with a single LDS stage.  splits: 0 = the library's choice (at least the count that
+ * DTRG_BF16X6 also 3 = 256 x 128, 4 = 64 x 64 on four waves that each cover all 64 columns,
+ * 5 = 128 x 128 with a single LDS stage, and 6 = 256 x 256 on 32 x 32 MFMA tiles with K tiles of 16
+ * and three LDS stages (K-contiguous operands and K a multiple of 16 only: DTRG_EINVAL when either
+ * operand is K-major or 16 does not divide K).  splits: 0 = the library's choice (at least the count that
  * keeps every FP32 accumulation chain at 4096 products or fewer), else 1 to 64 K-chunks whose
  * partials are summed in FP64 in a fixed order (a count below that floor is taken as given).
  * DTRG_EINVAL for a tile code the precision does not have or a count outside 0 to 64.

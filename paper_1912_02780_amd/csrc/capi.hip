@@ -254,7 +254,9 @@ ContractCall contract_call(int precision, int M, int N, int K, const void* A_dev
                  "leading dimension too small");
     ContractCall c;
     c.pr = prec_of(precision);
-    DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(c.pr) > 1 ? 5 : 2), DTRG_EINVAL, "bad tile code");
+    DTRG_REQUIRE(tile >= 0 && tile <= (prec_planes(c.pr) > 1 ? 6 : 2), DTRG_EINVAL, "bad tile code");
+    DTRG_REQUIRE(tile != 6 || (!a_kmajor && !b_kmajor && K % 16 == 0), DTRG_EINVAL,
+                 "tile code 6 takes K-contiguous operands and K a multiple of 16 only");
     DTRG_REQUIRE(splits >= 0 && splits <= 64, DTRG_EINVAL, "split-K count out of range (0 to 64)");
     c.out = precision == DTRG_FP64 || out_f64 ? Out::F64 : Out::F32;
     c.np = prec_planes(c.pr);

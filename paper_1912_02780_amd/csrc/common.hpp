@@ -176,8 +176,8 @@ struct GemmCfg {
     int tile = 0;
     int splits = 0;
 };
-inline int tile_rows(int tile) { return tile == 3 ? 256 : ((tile == 2 || tile == 5) ? 128 : 64); }
-inline int tile_cols(int tile) { return (tile == 2 || tile == 3 || tile == 5) ? 128 : 64; }
+inline int tile_rows(int tile) { return (tile == 3 || tile == 6) ? 256 : ((tile == 2 || tile == 5) ? 128 : 64); }
+inline int tile_cols(int tile) { return tile == 6 ? 256 : ((tile == 2 || tile == 3 || tile == 5) ? 128 : 64); }
 
 // One (batched) contraction C[z](r, c) = alpha * sum_k A[z](r, k) B[z](c, k) + beta * C[z](r, c).
 //   A stored as [M][K] (a_kmajor = false: A[m * lda + k]) or [K][M] (a_kmajor = true: A[k * lda + m]).

@@ -44,7 +44,7 @@ i64 map_max(const IdxMap& m, i64 count) {
 }
 
 // K tile of the kernel that runs a configuration (split-K chunks are multiples of it)
-int bk_of(Prec prec, int) { return prec_planes(prec) == 1 ? 16 : 32; }
+int bk_of(Prec prec, int tile) { return prec_planes(prec) == 1 || tile == 6 ? 16 : 32; }
 
 int out_code(Prec prec, Out out) {
     if (out == Out::F64) return 0;
@@ -218,8 +218,10 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     }
 
     const GemmCfg cfg = gemm_resolve(prec, op);
-    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || ((cfg.tile >= 3 && cfg.tile <= 5) && split), DTRG_EINVAL,
+    DTRG_REQUIRE(cfg.tile == 1 || cfg.tile == 2 || ((cfg.tile >= 3 && cfg.tile <= 6) && split), DTRG_EINVAL,
                  "gemm: bad tile configuration");
+    DTRG_REQUIRE(cfg.tile != 6 || (!op.a_kmajor && !op.b_kmajor && op.K % 16 == 0), DTRG_EINVAL,
+                 "gemm: tile 6 takes K-contiguous operands and K a multiple of 16 only");
     const int BM = tile_rows(cfg.tile), BN = tile_cols(cfg.tile);
     int splits = 1;
     resolve_chunks(prec, op, cfg, a.k_chunk, splits);

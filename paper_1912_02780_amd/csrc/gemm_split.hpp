@@ -329,12 +329,275 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_split_kernel(KArgs p) {
             }
 }
 
+// ------------------------------------------------------------------------------------------
+// 256 x 256 tiles on v_mfma_f32_32x32x16_bf16 with K tiles of 16 and three LDS stages (tile code 6;
+// K-contiguous operands, K a multiple of 16).  Three bf16 planes of a 256 x 256 block tile at BK = 16
+// take 48 KiB per stage, so that three stages fit in 144 KiB and a K tile's loads are issued two tiles
+// before it is multiplied (the 256 x 128 tile at BK = 32 on the 16 x 16 MFMA has room for two stages
+// only), and each operand row loaded feeds twice the outputs of the 256 x 128 tile's B rows.
+// Operand layout in LDS: row r of plane q holds the tile's 16 K values (32 bytes) as two 16-byte
+// chunks, chunk c at position c ^ ((r >> 3) & 1), so that the 16 rows read by a 16-lane group of a
+// fragment load cover all 256 bytes of the banks once.  Fragment of a 32-row block for lane l: row
+// l % 32, the 8 K values of chunk l / 32 (A and B use the same K assignment, so the dot products are
+// those of the contraction).  Accumulator register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.
+// ------------------------------------------------------------------------------------------
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ inline int s32_pos(int r, int c) { return r * 16 + ((c ^ ((r >> 3) & 1)) << 3); }
+
+// s_waitcnt immediate: at most n vector-memory operations of this wave still in flight, no wait on
+// the other counters
+template <int N>
+__device__ inline void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int NP, int R>
+struct Split32Operand {
+    static constexpr int NI = NP * R / 32;   // 1 KiB direct-to-LDS loads per K tile
+    static_assert(NI >= 8, "at least one load per wave");
+    // loads of K tile k0: instruction g of the block fills 1 KiB of one plane (32 rows x 32 bytes),
+    // lane l the chunk at LDS position l; rows beyond the operand are clamped to its last row (they
+    // only feed outputs that are never stored) and chunks at or beyond kend load the chunk at kbeg
+    // (every wave issues the same number, PW: where NW does not divide NI, the waves past the end
+    // repeat their previous load, the same 16 bytes to the same place, so that the count of loads in
+    // flight is the same in every wave)
+    template <int NW>
+    static constexpr int PW = (NI + NW - 1) / NW;
+    template <int NW>
+    __device__ static void issue(const __bf16* X, i64 ld, i64 ps, int rows, int base, __bf16 (&L)[NP][R * 16],
+                                 int k0, int kbeg, int kend, int wave, int lane) {
+#pragma unroll
+        for (int e = 0; e < PW<NW>; ++e) {
+            const int g = wave + NW * e < NI ? wave + NW * e : wave + NW * (e - 1);
+            const int q = g / (R / 32), rb = g % (R / 32);
+            const int row = rb * 32 + (lane >> 1);
+            const int c = (lane & 1) ^ ((row >> 3) & 1);
+            const int gk = k0 + 8 * c;
+            const __bf16* src = X + q * ps + (i64)min(base + row, rows - 1) * ld + (gk < kend ? gk : kbeg);
+            __builtin_amdgcn_global_load_lds((gbl_cvoid_t*)src, (lds_void_t*)&L[q][rb * 512], 16, 0, 0);
+        }
+    }
+    __device__ static v8bf frag(const __bf16 (&L)[NP][R * 16], int q, int rbase, int lane) {
+        const int r = rbase + (lane & 31);
+        return *(const v8bf*)&L[q][s32_pos(r, lane >> 5)];
+    }
+};
+
+template <int NP, int OUT, int TAG>
+__global__ __launch_bounds__(512) void gemm_split32_kernel(KArgs p) {
+    constexpr int BM = 256, BN = 256, BK = 16, ST = 3, NW = 8, WGM = 2, WGN = 4;
+    constexpr int WM = BM / WGM, WN = BN / WGN, TM = WM / 32, TN = WN / 32;
+    typedef Split32Operand<NP, BM> OpA;
+    typedef Split32Operand<NP, BN> OpB;
+    // one LDS variable per stage (both operands), so that the compiler's alias analysis tells the
+    // stage being filled from the one being read and inserts no wait for the loads in flight before
+    // the fragment reads (it tracks the direct-to-LDS writes of a few distinct variables only)
+    struct Stage {
+        __bf16 a[NP][BM * BK];
+        __bf16 b[NP][BN * BK];
+    };
+    __shared__ __attribute__((aligned(16))) Stage S0, S1, S2;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+    int tmi, tni;
+    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
+    const int m0 = tmi * BM, n0 = tni * BN;
+    const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
+    const int kbeg = zs * p.k_chunk;
+    const int kend = min(p.K, kbeg + p.k_chunk);
+    const __bf16* A = (const __bf16*)p.A + batch_off(p, zb, p.a_bs, p.a_bs2);
+    const __bf16* B = (const __bf16*)p.B + batch_off(p, zb, p.b_bs, p.b_bs2);
+
+    // an (empty) use of an accumulation register makes the compiler keep the MFMA accumulators in
+    // the AGPR half of the register file, apart from the fragments and addresses
+    asm volatile("" ::: "a0");
+    v16f acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto stage = [&](auto I) -> Stage& {
+        constexpr int s = decltype(I)::value;
+        if constexpr (s == 0) return S0;
+        else if constexpr (s == 1) return S1;
+        else return S2;
+    };
+    auto stA = [&](auto I) -> auto& { return stage(I).a; };
+    auto stB = [&](auto I) -> auto& { return stage(I).b; };
+    auto issue = [&](auto& As, auto& Bs, int k0) {
+        OpA::template issue<NW>(A, p.lda, p.a_ps, p.M, m0, As, k0, kbeg, kend, wave, lane);
+        OpB::template issue<NW>(B, p.ldb, p.b_ps, p.N, n0, Bs, k0, kbeg, kend, wave, lane);
+    };
+    // fragments of a stage, and the MFMAs on them
+    struct Frags {
+        v8bf a[NP][TM], b[NP][TN];
+    };
+    auto read = [&](auto& As, auto& Bs, Frags& f) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) f.b[q][j] = OpB::frag(Bs, q, wn0 + j * 32, lane);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) f.a[q][i] = OpA::frag(As, q, wm0 + i * 32, lane);
+        }
+    };
+    auto multiply = [&](const Frags& f) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (NP == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[1][i], f.b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][i], f.b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][i], f.b[0][j], acc[i][j], 0, 0, 0);
+                } else {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[2][i], f.b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[1][i], f.b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][i], f.b[2][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[1][i], f.b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][i], f.b[1][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][i], f.b[0][j], acc[i][j], 0, 0, 0);
+                }
+            }
+    };
+    // Tile t is in stage t % 3.  Step t waits until only the loads of tile t + 1 are in flight (and for
+    // its LDS reads); the barrier then makes every wave's loads of tile t visible, and every wave has
+    // finished tile t - 1, whose stage takes the loads of tile t + 2; then the fragments of tile t are
+    // read and multiplied.  s_barrier goes through inline assembly with a memory clobber:
+    // __syncthreads would also wait for the loads of tile t + 1.
+    // The loop runs whole groups of three steps, and every step issues its loads and reads its stage;
+    // steps past the last tile skip only the multiply, and their loads (K at or beyond the chunk end:
+    // the chunk's first K values, by issue's rule) go to stages that are not multiplied.  Every path
+    // through the loop then issues the same loads in the same order, which is what the compiler's own
+    // wait analysis needs to agree that the wait suffices (it cannot follow conditions on the tile
+    // count, and would otherwise wait for every load in flight before each fragment read); and the
+    // loop has a single exit, which keeps the accumulators in place (with several exits the compiler
+    // copies them between register halves on every trip).  Every wave issues LPW loads per tile.
+    // Chunks are whole K tiles: the host admits this tile for K a multiple of 16 only.
+    constexpr int LPW = OpA::template PW<NW> + OpB::template PW<NW>;
+    static_assert(LPW < 16, "vmcnt range");
+    const int nt = kend > kbeg ? (kend - kbeg) / BK : 0;
+    auto step = [&](auto I, int t) {
+        constexpr int s = decltype(I)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vm<LPW>();
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        // the next loads go out first (a scheduling barrier keeps them ahead of the MFMAs)
+        constexpr int sn = (s + 2) % 3;
+        issue(stA(std::integral_constant<int, sn>()), stB(std::integral_constant<int, sn>()), kbeg + (t + 2) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+        Frags f;
+        read(stA(I), stB(I), f);
+        if (t < nt) multiply(f);   // block-uniform
+    };
+    if (nt > 0) {   // block-uniform; an empty K chunk leaves the accumulators at zero
+        issue(S0.a, S0.b, kbeg);
+        issue(S1.a, S1.b, kbeg + BK);
+        for (int t = 0; t < nt; t += 3) {
+            step(std::integral_constant<int, 0>(), t);
+            step(std::integral_constant<int, 1>(), t + 1);
+            step(std::integral_constant<int, 2>(), t + 2);
+        }
+    }
+    __syncthreads();   // all loads have landed and every wave is done with the stages before they hold epilogue slabs
+
+    const int lc = lane & 31, lg = lane >> 5;
+    if constexpr (OUT >= 2) {
+        if (p.vec_out && p.splits == 1) {
+            // per wave an LDS slab of 16 rows x (WN + 4) floats (four waves per stage); the 32 rows of
+            // an MFMA tile go through it in two halves, registers 8 h .. 8 h + 7 holding rows 16 h .. 16 h + 15
+            constexpr int SLD = WN + 4, GPR = WN / 8;
+            static_assert(4 * 16 * SLD * 4 <= (int)sizeof(Stage), "four slabs per stage");
+            float* const slab = (wave < 4 ? (float*)&S0 : (float*)&S1) + (wave & 3) * 16 * SLD;
+            const i64 cbase = batch_off(p, zb, p.c_bs, p.c_bs2);
+            __bf16* C = (__bf16*)p.C;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int r = 8 * h; r < 8 * h + 8; ++r)
+                            slab[(8 * ((r >> 2) - 2 * h) + 4 * lg + (r & 3)) * SLD + j * 32 + lc] = acc[i][j][r];
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int gi = lane; gi < 16 * GPR; gi += 64) {
+                        const int row = gi / GPR, cg = (gi % GPR) * 8;
+                        const int gm = m0 + wm0 + i * 32 + 16 * h + row, gn = n0 + wn0 + cg;
+                        if (gm < p.M && gn < p.N) {
+                            float v[8];
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const float x = slab[row * SLD + cg + t];
+                                v[t] = p.alpha == 1.0 ? x : (float)(p.alpha * (double)x);
+                            }
+                            const i64 off = cbase + idx_off(p.rmap, gm) + idx_off(p.cmap, gn);
+                            if (gn + 8 <= p.N) {
+#pragma unroll
+                                for (int q = 0; q < OUT; ++q) {
+                                    v8bf hv;
+#pragma unroll
+                                    for (int t = 0; t < 8; ++t) {
+                                        hv[t] = (__bf16)v[t];
+                                        v[t] -= (float)hv[t];
+                                    }
+                                    __builtin_nontemporal_store(hv, (v8bf*)(C + q * p.c_ps + off));
+                                }
+                            } else {
+                                for (int t = 0; t < 8 && gn + t < p.N; ++t) put_out<OUT>(p.C, off + t, p.c_ps, (double)v[t], 0.0);
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            return;
+        }
+    }
+    if (p.splits > 1) {
+        float* W = (float*)p.W + (i64)blockIdx.z * p.M * p.N;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int gm = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lg + (r & 3), gn = n0 + wn0 + j * 32 + lc;
+                    if (gm < p.M && gn < p.N) W[(i64)gm * p.N + gn] = acc[i][j][r];
+                }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int gm = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lg + (r & 3), gn = n0 + wn0 + j * 32 + lc;
+                if (gm < p.M && gn < p.N) write_elem<OUT>(p, zb, gm, gn, p.alpha * (double)acc[i][j][r]);
+            }
+}
+
 // Tile shapes: 1 = 64 x 64 (4 waves of 32 x 32), 2 = 128 x 128 (4 waves of 64 x 64),
 // 3 = 256 x 128 (8 waves of 64 x 64), 4 = 64 x 64 as 4 waves of 16 rows x 64 columns (outputs of at
 // most 64 columns: every wave covers all of them), 5 = tile 2 with a single LDS stage (short K).
 // LDS: two stages of NP x (BM + BN) x 64 bytes (at most 144 KiB), one for tile 5.
 template <int NP, int OUT, int TAG, bool AKM, bool BKM>
 void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
+    if (tile == 6) {
+        DTRG_REQUIRE(!AKM && !BKM, DTRG_EINVAL, "split contraction: tile 6 takes K-contiguous operands only");
+        if constexpr (!AKM && !BKM) hipLaunchKernelGGL((gemm_split32_kernel<NP, OUT, TAG>), grid, dim3(512), 0, s, a);
+        return;
+    }
     if (tile == 5)
         hipLaunchKernelGGL((gemm_split_kernel<NP, OUT, 128, 128, 2, 2, 0, AKM, BKM, 1>), grid, dim3(256), 0, s, a);
     else if (tile == 4)
@@ -350,9 +613,9 @@ void launch_split_tile(const KArgs& a, dim3 grid, int tile, hipStream_t s) {
 // tags 7, 8, 9 (the three chi^7 contractions) get their own symbols on the large tiles only
 template <int NP, int OUT, bool AKM = false, bool BKM = false>
 void launch_split_tag(const KArgs& a, dim3 grid, int tile, int tag, hipStream_t s) {
-    if ((tile == 2 || tile == 3) && tag == 7) { launch_split_tile<NP, OUT, 7, AKM, BKM>(a, grid, tile, s); return; }
-    if ((tile == 2 || tile == 3) && tag == 8) { launch_split_tile<NP, OUT, 8, AKM, BKM>(a, grid, tile, s); return; }
-    if ((tile == 2 || tile == 3) && tag == 9) { launch_split_tile<NP, OUT, 9, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3 || tile == 6) && tag == 7) { launch_split_tile<NP, OUT, 7, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3 || tile == 6) && tag == 8) { launch_split_tile<NP, OUT, 8, AKM, BKM>(a, grid, tile, s); return; }
+    if ((tile == 2 || tile == 3 || tile == 6) && tag == 9) { launch_split_tile<NP, OUT, 9, AKM, BKM>(a, grid, tile, s); return; }
     launch_split_tile<NP, OUT, 0, AKM, BKM>(a, grid, tile, s);
 }
 

@@ -5,8 +5,9 @@
 // a scratch output (beta = 0, so the real output is untouched), timed with HIP events on the
 // caller's stream (the least of three runs after a warm-up), and the fastest is kept in a
 // process-wide table.  The configurations are the tiles {64 x 64, 128 x 128, and for bf16 planes
-// 256 x 128, for outputs of at most 64 columns 64 x 64 on full-width waves, and for K of at most 128
-// the single-stage 128 x 128} times the split-K counts {s0, then 2, 3, 4, 5, 6, 8, 12, 16, 24, 32
+// 256 x 128, for outputs of at most 64 columns 64 x 64 on full-width waves, for K of at most 128
+// the single-stage 128 x 128, and for K-contiguous operands of at least 256 rows and columns and K a
+// multiple of 16 the three-stage 256 x 256 on 32 x 32 MFMA tiles} times the split-K counts {s0, then 2, 3, 4, 5, 6, 8, 12, 16, 24, 32
 // above it}, s0 being the least count that keeps FP32 accumulation chains short (1 for FP64 and for
 // short K).  Counts that are not powers of two bring a grid of a few hundred tiles closer to a whole
 // number of rounds over the compute units (a 2304^3 FP64 contraction: 476 us at 3 splits, 525 us at
@@ -77,7 +78,7 @@ int tune_load(const std::string& path) {
         for (int i = 0; i < 12; ++i) got += std::fscanf(f, "%d", &v[i]) == 1;
         if (got == 0) break;
         // tile 0 and splits 0 are the heuristic's choice (kept for shapes too small to time)
-        if (got != 12 || v[10] < 0 || v[10] > 5 || v[11] < 0 || v[11] > 256) {
+        if (got != 12 || v[10] < 0 || v[10] > 6 || v[11] < 0 || v[11] > 256) {
             std::fclose(f);
             throw Error(DTRG_EINVAL, "tile_table " + path + ": malformed entry " + std::to_string(n + 1));
         }
@@ -132,8 +133,9 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
     const i64 nz = (i64)op.batch * op.batch2;
     const int minsp = gemm_chain_splits(prec, op);
     std::vector<GemmCfg> cands;
-    for (int tile = 1; tile <= (np > 1 ? 5 : 2); ++tile) {
+    for (int tile = 1; tile <= (np > 1 ? 6 : 2); ++tile) {
         if ((tile == 2 || tile == 5) && std::max(op.M, op.N) < 128) continue;
+        if (tile == 6 && (op.a_kmajor || op.b_kmajor || op.M < 256 || op.N < 256 || op.K % 16 != 0)) continue;
         if (tile == 5 && op.K > 128) continue;
         if (tile == 3 && op.M < 256) continue;
         if (tile == 4 && op.N > 64) continue;

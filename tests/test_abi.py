@@ -162,12 +162,17 @@ def test_contract_config_validation_without_device_work():
                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     lib.dtrg_last_error.restype = ctypes.c_char_p
     p = ctypes.c_void_p(64)
-    # FP64 has tiles 1 and 2 only; the bf16-plane precisions 1 to 5; split counts 0 to 64
-    for prec, tile, splits in ((0, 3, 0), (0, 6, 0), (1, 5, 0), (3, 6, 0), (3, -1, 0), (3, 1, 65), (0, 1, -1)):
+    # FP64 and FP32 have tiles 1 and 2 only; the bf16-plane precisions 1 to 6; split counts 0 to 64
+    for prec, tile, splits in ((0, 3, 0), (0, 6, 0), (1, 5, 0), (3, 7, 0), (3, -1, 0), (3, 1, 65), (0, 1, -1)):
         st = f(prec, 8, 8, 8, p, 8, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, tile, splits, None)
         assert st == 1, (prec, tile, splits)
         msg = lib.dtrg_last_error()
         assert b"tile" in msg or b"split" in msg
+    # tile 6: K-contiguous operands and K a multiple of 16 only
+    for tile, K, akm, bkm in ((6, 20, 0, 0), (6, 8, 0, 0), (6, 32, 1, 0), (6, 32, 0, 1)):
+        st = f(3, 8, 8, K, p, 64, akm, p, 64, bkm, p, 8, 1, 1.0, 0.0, tile, 1, None)
+        assert st == 1, (tile, K, akm, bkm)
+        assert b"tile" in lib.dtrg_last_error()
     # NULL operands and short leading dimensions are rejected first
     assert f(3, 8, 8, 8, None, 8, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1
     assert f(3, 8, 8, 8, p, 4, 0, p, 8, 0, p, 8, 1, 1.0, 0.0, 1, 1, None) == 1

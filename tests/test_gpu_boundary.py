@@ -146,6 +146,58 @@ def test_gpu_tile_table_persists_across_processes(B, tmp_path):
     assert np.array_equal(a, b)
 
 
+_CHILD48 = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, {root!r})
+from paper_1912_02780_amd import binding as B, inputs as I
+T0 = torch.from_numpy(I.random_d4_T0(0)).to("cuda:0")
+o = B.default_options(contract="bf16x6", autotune=1, tile_table={path!r})
+plan, L = B.dtrg_hotrg_forward(T0, 48, 24, o)
+g, _ = B.dtrg_hotrg_backward(plan)
+np.save({out!r}, np.concatenate([[L], g.cpu().numpy().ravel()]))
+"""
+
+
+def test_gpu_forced_deep_tile_chi48_vs_golden(B, tmp_path):
+    """Every contraction the three-stage 256 x 256 tile can take (K-contiguous operands, K a multiple
+    of 16, at least 256 rows and columns) forced onto it through a tile_table: the full chi = 48 pass,
+    with its bf16-plane outputs written by the tile's 16-byte epilogue, against the FP64 golden at the
+    three-plane tolerance."""
+    tile = 6
+    import json
+    path = str(tmp_path / "tune.txt")
+    outs = [str(tmp_path / f"r{i}.npy") for i in range(2)]
+    src = _CHILD48.format(root=ROOT, path=path, out=outs[0])
+    _say(f"[gpu] forced tile {tile}: tuning child")
+    r = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    lines = open(path).read().splitlines()
+    forced = 0
+    out_lines = [lines[0]]
+    for ln in lines[1:]:
+        v = [int(x) for x in ln.split()]
+        prec, M, N, K, akm, bkm = v[0], v[2], v[3], v[4], v[7], v[8]
+        if prec >= 2 and not akm and not bkm and M >= 256 and N >= 256 and K % 16 == 0:
+            v[10] = tile
+            forced += 1
+        out_lines.append(" ".join(str(x) for x in v))
+    assert forced >= 3, forced
+    open(path, "w").write("\n".join(out_lines) + "\n")
+    _say(f"    {forced} of {len(lines) - 1} shapes forced onto tile {tile}")
+    src = _CHILD48.format(root=ROOT, path=path, out=outs[1])
+    r = subprocess.run([sys.executable, "-c", src], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    res = np.load(outs[1])
+    gd = json.load(open(os.path.join(ROOT, "tests", "golden", "random_d4_seed0_chi48_n24.json")))
+    go = np.array(gd["T0bar"]).ravel()
+    lnZ, g = float(res[0]), res[1:]
+    rel_l = abs(lnZ / gd["lnZ_per_site"] - 1)
+    rel_g = float(np.linalg.norm(g - go) / np.linalg.norm(go))
+    _say(f"    lnZ rel {rel_l:.2e}  T0bar rel {rel_g:.2e}")
+    assert rel_l < 1e-6
+    assert rel_g < 1e-5
+
+
 def test_gpu_step_info_diagnostics_vs_oracle(B):
     """trunc_weight, cut_gap and min_kept_gap of every step against the oracle's full spectrum
     (absolute 1e-12 on the trace-normalised spectrum)."""

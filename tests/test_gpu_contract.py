@@ -105,6 +105,45 @@ def test_contract_every_tile(B, prec, layout, shape):
             assert err < TOL[prec], (prec, layout, shape, tile, splits, err)
 
 
+# the three-stage 256 x 256 tile on 32 x 32 MFMA tiles: K-contiguous operands and K a multiple of 16;
+# ragged M and N, tile counts per chunk that are and are not multiples of the stage count (steps past
+# the last tile), a single K tile, fewer rows than a tile, and split-K with chunk counts that leave a
+# short last chunk
+DEEP_SHAPES = [(300, 260, 144), (1000, 530, 1008), (257, 300, 16), (100, 700, 4096), (520, 270, 2320)]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("shape", DEEP_SHAPES)
+def test_contract_deep_tiles(B, prec, shape):
+    M, N, K = shape
+    g = torch.Generator().manual_seed(M * 7919 + N * 31 + K + 5)
+    A_in = torch.randn((M, K), generator=g, dtype=torch.float64).float()
+    B_in = torch.randn((N, K), generator=g, dtype=torch.float64).float()
+    C0 = torch.randn((M, N), generator=g, dtype=torch.float64)
+    ref = 1.25 * (A_in.double() @ B_in.double().T) + 0.5 * C0
+    dev = torch.device("cuda:0")
+    for tile in (6,):
+        for splits in (1, 3, 5):
+            print(f"[gpu] contract deep {prec} {shape} tile {tile} splits {splits}", flush=True)
+            C = C0.to(dev)
+            B.dtrg_contract(prec, A_in.to(dev), B_in.to(dev), C, alpha=1.25, beta=0.5, tile=tile, splits=splits)
+            torch.cuda.synchronize()
+            err = float((C.cpu() - ref).norm() / ref.norm())
+            assert err < TOL[prec], (prec, shape, tile, splits, err)
+    # K-major operands and K not a multiple of 16 are refused for these tiles
+    A = A_in.to(dev)
+    for kw in (dict(a_kmajor=True), dict(b_kmajor=True)):
+        Ak = A.T.contiguous() if kw.get("a_kmajor") else A
+        Bk = B_in.to(dev).T.contiguous() if kw.get("b_kmajor") else B_in.to(dev)
+        with pytest.raises(B.DtrgError) as e:
+            B.dtrg_contract(prec, Ak, Bk, C0.to(dev), tile=6, splits=1, **kw)
+        assert e.value.status == B.DTRG_EINVAL
+    with pytest.raises(B.DtrgError) as e:
+        B.dtrg_contract(prec, A[:, :K - 8].contiguous(), B_in.to(dev)[:, :K - 8].contiguous(), C0.to(dev), tile=6,
+                        splits=1)
+    assert e.value.status == B.DTRG_EINVAL
+
+
 def test_contract_config_rejects_bad_codes(B):
     dev = torch.device("cuda:0")
     A = torch.randn(8, 8, dtype=torch.float64, device=dev)
