@@ -75,10 +75,10 @@ TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_027
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 20 launches of that size per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "8c13d784de82c1fdae4f97fb74c77b230f129e2c5ac976ed7b0e70168ae5fa77",
-                          "fetch_kib": 5007730.0, "write_kib": 1700350.0,
+    ("chi48", "bf16x6"): {"sources_sha256": "fa540df6beae5dcb0d0558b82951510950e835e64502cb2c10b7b2f43dba6cd3",
+                          "fetch_kib": 5168610.0, "write_kib": 1699270.0,
                           # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), same runs
-                          "mfma_busy_counter": 0.579},
+                          "mfma_busy_counter": 0.576},
 }
 
 
@@ -211,6 +211,34 @@ def roofline(launches, ms, flops, contract, kernel, traffic=None, busy_counter=N
     return out
 
 
+def library_reference(torch, M, N, K, contract, reps=5):
+    """The vendor library (hipBLASLt through torch.matmul) on the same MFMA work as one launch of the
+    join: for the P-product split-bf16 formats one bf16 GEMM with the products laid side by side along
+    K (M x P K times P K x N, FP32 accumulation), for FP32 and FP64 the plain GEMM.  Context for the
+    roofline, not part of the path: the same peak, the same algorithmic flops (2 M N K)."""
+    P = PRODUCTS[contract]
+    dt = {"fp64": torch.float64, "fp32": torch.float32}.get(contract, torch.bfloat16)
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(0)
+    A = torch.randn((M, P * K), device=dev, dtype=torch.float32, generator=g).to(dt)
+    Bm = torch.randn((P * K, N), device=dev, dtype=torch.float32, generator=g).to(dt)
+    for _ in range(2):
+        C = A @ Bm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        C = A @ Bm
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del A, Bm, C
+    torch.cuda.empty_cache()
+    return {"what": f"torch.matmul {str(dt).replace('torch.', '')} M={M} N={N} K={P * K} (hipBLASLt): the "
+                    f"join's MFMA work ({P} product{'s' if P > 1 else ''} per multiply-add)",
+            "avg_ms": ms, "achieved": 2.0 * M * N * K / (ms * 1e-3) / 1e12}
+
+
 def _time_passes(B, torch, plan, T0, dT0, warmup, steps):
     """Wall time per forward + backward pass of an existing plan (after `warmup` passes)."""
     for _ in range(warmup):
@@ -275,6 +303,9 @@ def bench_chi48(args, B, I, torch, np, dev):
         **err,
     }
     plan.close()
+    if out["roofline"] is not None and not args.no_library_reference:
+        _progress("timing the vendor library on the join's MFMA work")
+        out["roofline"]["library_same_work"] = library_reference(torch, chi ** 3, chi ** 2, chi ** 2, args.contract)
     if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
@@ -547,6 +578,8 @@ def main():
     ap.add_argument("--max-fp32-chain", type=int, default=None,
                     help="longest FP32 accumulation chain of the small-output contractions (ising_chi64: 512 by "
                          "default; others: the library default 4096)")
+    ap.add_argument("--no-library-reference", action="store_true",
+                    help="skip timing the vendor library (torch.matmul) on the join's MFMA work")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="chi48: skip the compact batch256 and ising_chi64 legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
