@@ -16,6 +16,14 @@ C-contiguous.
   averaged over the eight leg permutations of the square's point group (four rotations, each
   with and without the left/right mirror), so that it is invariant under the lattice
   symmetries.
+* Quantum XY chain H = sum_i S^x_i S^x_{i+1} + S^y_i S^y_{i+1} (spin 1/2, J = 1; paper, main text
+  "Infinite quantum XY chain" and Supplemental Material F): the matrix-product operator of the
+  second-order Trotter-Suzuki density operator rho(tau) = exp(-tau/2 H_o) exp(-tau H_e)
+  exp(-tau/2 H_o), H_o (H_e) the bonds inside (between) two-spin cells.  One MPO tensor per cell
+  M[l][u][r][d]: l, r the bonds to the neighbouring cells, u the cell's two-spin output index,
+  d its input index (4 values each: 2 s1 + s2, spin up = 0).
+* Random matrix-product operator tensor M[l][u][r][d]: i.i.d. uniform [0, 1) entries plus 0.1 from
+  ``numpy.random.default_rng(seed)``, no symmetry (its transfer matrix is not symmetric).
 """
 
 from __future__ import annotations
@@ -112,3 +120,43 @@ def batch_betas(n: int = 256, lo: float = 0.30, hi: float = 0.60) -> np.ndarray:
 def batch_chis(n: int = 256, mix: tuple[int, ...] = (32, 16, 24)) -> np.ndarray:
     """Bond dimensions of the mixed batch: chi_i = mix[i mod len(mix)]."""
     return np.array([mix[i % len(mix)] for i in range(n)], dtype=np.int64)
+
+
+def xy_bond_gate(t: float) -> np.ndarray:
+    """exp(-t h) for one XY bond h = S^x S^x + S^y S^y on two spins, as G[a_out][b_out][a_in][b_in].
+
+    h couples only |01> and |10> (matrix element 1/2 each way), so exp(-t h) is the identity on |00>,
+    |11> and cosh(t/2) 1 - sinh(t/2) sigma_x on the {|01>, |10>} pair."""
+    g = np.eye(4)
+    ch, sh = math.cosh(0.5 * t), math.sinh(0.5 * t)
+    g[1, 1] = g[2, 2] = ch
+    g[1, 2] = g[2, 1] = -sh
+    return g.reshape(2, 2, 2, 2)
+
+
+def xy_trotter_mpo(tau: float) -> np.ndarray:
+    """MPO tensor M[l][u][r][d] of rho(tau) for the infinite XY chain in two-spin cells.
+
+    The gate exp(-tau h) on the bond between cells (spin 2 of one cell, spin 1 of the next) is split
+    by an SVD of its (a_out a_in) x (b_out b_in) unfolding into sum_k L[a_out, a_in, k] R[b_out, b_in, k]
+    (singular values shared as square roots, all four kept); the cell's tensor applies
+    exp(-tau/2 h) on its inner bond, then R on spin 1 (bond l) and L on spin 2 (bond r), then
+    exp(-tau/2 h) again."""
+    if not tau > 0.0:
+        raise ValueError("tau must be positive")
+    G = xy_bond_gate(tau)
+    Gm = np.transpose(G, (0, 2, 1, 3)).reshape(4, 4)     # [(a_out a_in), (b_out b_in)]
+    U, sv, Vt = np.linalg.svd(Gm)
+    Lg = (U * np.sqrt(sv)).reshape(2, 2, 4)              # [a_out][a_in][k]
+    Rg = (np.sqrt(sv)[:, None] * Vt).T.reshape(2, 2, 4)  # [b_out][b_in][k]
+    gh = xy_bond_gate(0.5 * tau).reshape(4, 4)           # inner bond, [(s1 s2)_out][(s1 s2)_in]
+    # E[(s1 s2)_out, (s1 s2)_in, l, r] = R[s1_out, s1_in, l] L[s2_out, s2_in, r]
+    E = np.einsum("acl,bdr->abcdlr", Rg, Lg).reshape(4, 4, 4, 4)
+    M = np.einsum("uA,ABlr,Bd->lurd", gh, E, gh)
+    return np.ascontiguousarray(M)
+
+
+def random_mpo(seed: int = 0, D: int = 3, d: int = 2) -> np.ndarray:
+    """Random positive MPO tensor [l][u][r][d] (bond D, physical d) without symmetries."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.random((D, d, D, d)) + 0.1)
