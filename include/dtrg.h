@@ -135,6 +135,19 @@ typedef struct {
                                  otherwise).  Default NULL */
     dtrg_free_fn free_fn;     /* its release function */
     void* alloc_user;         /* passed to both */
+    int chain_phys;           /* 0: the paper's scheme (a), a square-lattice network of one D^4 tensor
+                                 coarse-grained along alternating directions and closed by its
+                                 self-trace.  d > 0: scheme (b) (paper, Fig. 1(b) and the infinite
+                                 XY chain): T0 is one cell's matrix-product operator M[l][u][r][d]
+                                 of bond D and physical dimension d (D x d x D x d doubles); every
+                                 step squares the operator (the upper copy's input leg joined to
+                                 the lower copy's output leg, the doubled bonds compressed by the
+                                 step's isometry, the physical legs keeping dimension d), and the
+                                 infinite chain is closed by the dominant eigenvalue of the final
+                                 transfer matrix E[l][r] = sum_u M_n[l][r][u][u].  ln Z / N is then
+                                 ln Z per cell per Trotter slice, and dtrg_step_info.lnZ_at_step
+                                 gives it after every step.  0 <= d <= 16; batches take 0 only.
+                                 Default 0 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -156,6 +169,8 @@ typedef struct {
     double min_kept_gap;      /* least gap between consecutive kept eigenvalues (0 for one kept) */
     int mixed;                /* 1 if the step's projection contractions ran in the `contract`
                                  format, 0 if in FP64 */
+    double lnZ_at_step;       /* scheme (b) (chain_phys > 0): ln Z per cell per Trotter slice of the
+                                 chain closed after this step (rho(2^k tau)); NaN for scheme (a) */
 } dtrg_step_info;
 
 typedef struct dtrg_plan dtrg_plan;
@@ -165,7 +180,8 @@ void dtrg_default_options(dtrg_options* opt);
 
 /*
  * Forward pass: ln Z / N for the 2^n_steps-site periodic network of T0.
- *   T0_dev        device, D^4 doubles, [l][u][r][d]; read only; all entries finite, not all 0.
+ *   T0_dev        device, D^4 doubles, [l][u][r][d] (with opt->chain_phys = d > 0: one MPO cell,
+ *                 D x d x D x d doubles); read only; all entries finite, not all 0.
  *   D             bond dimension of T0, 1 <= D <= 64.
  *   chi           truncation bond dimension, 1 <= chi <= 80.
  *   n_steps       number of single-direction HOTRG steps, 1 <= n_steps <= 62.
@@ -219,7 +235,8 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
  *   (wbar_dev device, n chi' doubles, layout of w): the environment E_w up to the positive factor
  *   Z N / N_i (DTRG_EINVAL for a step without a fixed isometry).
  * dtrg_isometry_optimize: forward pass of plain HOTRG on T0_dev (its ln Z / N to *lnZ_hotrg_host,
- *   nullable), then n_sweeps sweeps over the first `layers` steps whose isometry truncates
+ *   nullable), then n_sweeps sweeps over the first `layers` steps whose isometry truncates (a
+ *   scheme-(b) plan: the last `layers`, the optimisation depth below the final temperature)
  *   (chi' < X^2), from the finest scale up; per sweep and step, n_inner MERA updates, each a
  *   backward pass for the isometry gradient, the polar factor w <- U V^T (computed on the device
  *   without squaring the gradient's condition number), and a forward pass with the new isometry;

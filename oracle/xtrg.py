@@ -35,7 +35,11 @@ Readings where the paper is not explicit (each also listed in the design notes):
   translation invariant with a one-tensor unit cell);
 * the dominant eigenvalue of E is simple, real and positive (checked; the run stops otherwise);
 * the optimisation window is the last `depth` truncating steps of the run to the target
-  temperature; the isometries below it keep their local HOSVD values.
+  temperature; the isometries below it keep their local HOSVD values;
+* the environment of the last step's isometry has rank <= 2 (the derivative of the closing
+  eigenvalue is l r^T), so Tr(E^T w) does not determine the rest of w: the update is
+  w <- polar(E + mu |E|_F w) with mu = 1e-6, which keeps the current isometry where the environment
+  is silent (and changes the well-determined directions by O(mu)).
 """
 
 from __future__ import annotations
@@ -47,6 +51,8 @@ import numpy as np
 
 from . import hotrg as H
 from .dtrg import polar
+
+POLAR_TIE_BREAK = 1e-6
 
 
 @dataclass
@@ -196,7 +202,9 @@ def optimize(M0, chi, n_steps, depth=1, n_inner=5, n_sweeps=3, eps=H.DEFAULT_BRO
             for _ in range(n_inner):
                 _, wbar, _ = lnZ_and_wbar(M0, chi, n_steps, w, eps)
                 X, K = w[k].shape[0], w[k].shape[2]
-                w[k] = polar(wbar[k].reshape(X * X, K)).reshape(X, X, K)
+                E = wbar[k].reshape(X * X, K)
+                E = E + POLAR_TIE_BREAK * np.linalg.norm(E) * w[k].reshape(X * X, K)
+                w[k] = polar(E).reshape(X, X, K)
                 history.append(chain_forward(M0, chi, n_steps, w_fixed=w).lnZ_per_tensor)
     L = history[-1] if history else fwd0.lnZ_per_tensor
     return fwd0.lnZ_per_tensor, L, history, w

@@ -43,14 +43,15 @@ class Options(ctypes.Structure):
                 ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double), ("oversample", c_int),
                 ("max_fp32_chain", c_int), ("max_fp32_chain_wide", c_int),
                 ("tile_table", ctypes.c_char_p), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
-                ("alloc_user", c_void_p)]
+                ("alloc_user", c_void_p), ("chain_phys", c_int)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("X", c_int), ("Y", c_int), ("chi_kept", c_int), ("full_eig", c_int), ("iters", c_int),
                 ("c", c_double), ("trace_G", c_double), ("lam_last_kept", c_double),
                 ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int),
-                ("trunc_weight", c_double), ("cut_gap", c_double), ("min_kept_gap", c_double), ("mixed", c_int)]
+                ("trunc_weight", c_double), ("cut_gap", c_double), ("min_kept_gap", c_double), ("mixed", c_int),
+                ("lnZ_at_step", c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -203,9 +204,12 @@ def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
 class Plan:
     """Owns a dtrg_plan (the forward checkpoints); released with the object."""
 
-    def __init__(self, handle: int, D: int, n_steps: int, device):
+    def __init__(self, handle: int, D: int, n_steps: int, device, phys: int = 0):
         self._h = c_void_p(handle)
         self.D = D
+        self.phys = phys
+        # input layout [l][u][r][d]: D^4, or an MPO cell D x d x D x d (scheme (b))
+        self.in_shape = (D, phys, D, phys) if phys else (D, D, D, D)
         self.n_steps = n_steps
         self.device = device
         _LIVE.add(self)
@@ -261,10 +265,44 @@ def dtrg_plan_create(D: int, chi: int, n_steps: int, options: Options | None = N
     return Plan(h.value, D, n_steps, device)
 
 
+def _chain_options(options: Options | None, d: int) -> Options:
+    """A copy of the options (or the defaults) with chain_phys = d."""
+    src = _opts(options)
+    o = Options()
+    ctypes.pointer(o)[0] = src
+    o.chain_phys = int(d)
+    return o
+
+
+def dtrg_chain_forward(M0: torch.Tensor, chi: int, n_steps: int, options: Options | None = None, stream=None):
+    """Scheme (b): returns (plan, ln Z per cell per Trotter slice) of the infinite chain of the MPO cell
+    M0 [l][u][r][d] (D x d x D x d float64 CUDA tensor) squared n_steps times."""
+    M0 = _dev_f64(M0, "M0")
+    if M0.dim() != 4 or M0.shape[0] != M0.shape[2] or M0.shape[1] != M0.shape[3]:
+        raise ValueError("M0 must be D x d x D x d")
+    D, d = int(M0.shape[0]), int(M0.shape[1])
+    h = c_void_p()
+    out = c_double()
+    with torch.cuda.device(M0.device):
+        _check(lib.dtrg_hotrg_forward(c_void_p(M0.data_ptr()), D, int(chi), int(n_steps),
+                                      byref(_chain_options(options, d)), _stream(stream), byref(h), byref(out)))
+    return Plan(h.value, D, n_steps, M0.device, d), out.value
+
+
+def dtrg_chain_plan_create(D: int, d: int, chi: int, n_steps: int, options: Options | None = None,
+                           device=None) -> Plan:
+    """Allocate a scheme-(b) plan for MPO cells of bond D and physical dimension d."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = c_void_p()
+    with torch.cuda.device(device):
+        _check(lib.dtrg_plan_create(int(D), int(chi), int(n_steps), byref(_chain_options(options, d)), byref(h)))
+    return Plan(h.value, D, n_steps, device, d)
+
+
 def dtrg_plan_forward(plan: Plan, T0: torch.Tensor, stream=None) -> float:
     T0 = _dev_f64(T0, "T0")
-    if tuple(T0.shape) != (plan.D,) * 4:
-        raise ValueError("T0 does not match the plan's D")
+    if tuple(T0.shape) != plan.in_shape:
+        raise ValueError("T0 does not match the plan's input shape")
     out = c_double()
     with torch.cuda.device(plan.device):
         _check(lib.dtrg_plan_forward(plan._h, c_void_p(T0.data_ptr()), _stream(stream), byref(out)))
@@ -273,12 +311,11 @@ def dtrg_plan_forward(plan: Plan, T0: torch.Tensor, stream=None) -> float:
 
 def dtrg_hotrg_backward(plan: Plan, gbar: float = 1.0, dT0: torch.Tensor | None = None, stream=None):
     """Returns (T0bar, <T0bar, dT0> or None)."""
-    D = plan.D
-    T0bar = torch.empty((D, D, D, D), dtype=torch.float64, device=plan.device)
+    T0bar = torch.empty(plan.in_shape, dtype=torch.float64, device=plan.device)
     dptr = None
     if dT0 is not None:
         dT0 = _dev_f64(dT0, "dT0")
-        if tuple(dT0.shape) != (D, D, D, D):
+        if tuple(dT0.shape) != plan.in_shape:
             raise ValueError("dT0 must have the shape of T0")
         dptr = c_void_p(dT0.data_ptr())
     val = c_double()
@@ -332,8 +369,8 @@ def dtrg_isometry_optimize(plan: Plan, T0: torch.Tensor, layers: int = 1, n_inne
     """Differentiable-TRG isometry optimisation (see include/dtrg.h).
     Returns (ln Z / N of plain HOTRG, ln Z / N after the optimisation, history list)."""
     T0 = _dev_f64(T0, "T0")
-    if tuple(T0.shape) != (plan.D,) * 4:
-        raise ValueError("T0 does not match the plan's D")
+    if tuple(T0.shape) != plan.in_shape:
+        raise ValueError("T0 does not match the plan's input shape")
     hist = (c_double * max(1, n_sweeps * layers * n_inner))()
     l0, l1 = c_double(), c_double()
     with torch.cuda.device(plan.device):

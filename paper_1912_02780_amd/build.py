@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdtrg.so")
-SOURCES = ["gemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_split2.hip", "gemm_split3.hip", "tensor_ops.hip", "eig.hip", "tune.hip",
+SOURCES = ["gemm.hip", "gemm_f64.hip", "gemm_f32.hip", "gemm_split2.hip", "gemm_split3.hip", "tensor_ops.hip", "chain.hip", "eig.hip", "tune.hip",
            "hotrg.hip", "capi.hip"]
 ARCH = "gfx950"
 

@@ -48,6 +48,7 @@ void validate_options(const dtrg_options& o) {
                  "max_fp32_chain_wide out of range [32, 2^20]");
     DTRG_REQUIRE((o.alloc_fn == nullptr) == (o.free_fn == nullptr), DTRG_EINVAL,
                  "alloc_fn and free_fn must both be set or both be NULL");
+    DTRG_REQUIRE(o.chain_phys >= 0 && o.chain_phys <= 16, DTRG_EINVAL, "chain_phys out of range [0, 16]");
 }
 
 void validate_sizes(int D, int chi, int n_steps) {
@@ -87,6 +88,7 @@ std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const 
     P->ck_budget = (dtrg::i64)std::min(P->opt.checkpoint_gib * share * 1073741824.0, 9.0e18);
     P->prec = prec_of(P->opt.contract);
     P->D = D; P->chi = chi; P->nsteps = n_steps; P->nb = nb;
+    P->phys = P->opt.chain_phys;
     plan_setup(P.get());
     return P;
 }
@@ -117,6 +119,7 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->cut_gap = st.sh.b > st.sh.K ? lam[st.sh.K - 1] - lam[st.sh.K] : 0.0;
     info->min_kept_gap = st.sh.K > 1 ? gmin : 0.0;
     info->mixed = st.sh.mixed ? 1 : 0;
+    info->lnZ_at_step = P->chain() ? sc[10] : NAN;
     if (st.fixed) {   // a given isometry: no Gram, no spectrum
         info->full_eig = 0;
         info->iters = -1;
@@ -358,6 +361,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->alloc_fn = nullptr;
     o->free_fn = nullptr;
     o->alloc_user = nullptr;
+    o->chain_phys = 0;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -384,7 +388,7 @@ dtrg_status dtrg_plan_forward(dtrg_plan* plan, const double* T0_dev, void* strea
         plan->s = (hipStream_t)stream;
         plan->alloc.stream = plan->s;
         AllocScope scope(&plan->alloc);
-        const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
+        const i64 D4 = plan->t0_elems();
         DTRG_HIP(hipMemcpyAsync(plan->T0buf.p, T0_dev, D4 * sizeof(double), hipMemcpyDeviceToDevice, plan->s));
         plan_forward(plan, Mode::Adaptive);
         *lnZ_per_site_host = plan->scal_h[0];
@@ -462,7 +466,7 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
         plan->s = (hipStream_t)stream;
         plan->alloc.stream = plan->s;
         AllocScope scope(&plan->alloc);
-        const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
+        const i64 D4 = plan->t0_elems();
         const bool with_dir = dT0_dev && dlnZ_dir_host;
         if (with_dir)
             DTRG_HIP(hipMemcpyAsync(plan->dT0buf.p, dT0_dev, D4 * sizeof(double), hipMemcpyDeviceToDevice, plan->s));
@@ -547,7 +551,7 @@ dtrg_status dtrg_isometry_optimize(dtrg_plan* plan, const double* T0_dev, int la
         plan->s = (hipStream_t)stream;
         plan->alloc.stream = plan->s;
         AllocScope scope(&plan->alloc);
-        const i64 D4 = (i64)plan->D * plan->D * plan->D * plan->D;
+        const i64 D4 = plan->t0_elems();
         DTRG_HIP(hipMemcpyAsync(plan->T0buf.p, T0_dev, D4 * sizeof(double), hipMemcpyDeviceToDevice, plan->s));
         std::vector<double> hist;
         plan_isometry_optimize(plan, layers, n_inner, n_sweeps, lnZ_hotrg_host, &hist);
@@ -595,6 +599,7 @@ dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_step
         std::unique_ptr<dtrg_batch> Bt(new dtrg_batch());
         Bt->n_inst = n_inst; Bt->D = D; Bt->nsteps = n_steps;
         if (opt) validate_options(*opt);
+        DTRG_REQUIRE(!opt || opt->chain_phys == 0, DTRG_EINVAL, "batches run scheme (a) only (chain_phys must be 0)");
         Bt->alloc = allocator_of(opt, nullptr);
         AllocScope scope(&Bt->alloc);
         std::map<int, size_t> group_of;

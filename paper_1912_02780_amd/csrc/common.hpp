@@ -286,14 +286,38 @@ void gather_rows(const double* src, i64 src_bs, const int* idx_dev, double* dst,
 void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_dev, i64 mx_bs, int* flag_dev,
                int bit, hipStream_t s);
 
+// chain.hip (scheme (b): closing the infinite chain of cells)
+// largest transfer matrix the closing kernel takes, its residual bound, and the squarings of E
+constexpr int kChainMaxK = 2048;
+constexpr double kChainResidual = 1e-8;
+constexpr int kChainSquarings = 24;
+// E[l][r] = scale * sum_u T[l][r][u][u] for T [K][K][Y][Y] (scale from scale_dev[i * sc_bs], or 1)
+void chain_transfer(const double* T, i64 tbs, int K, int Y, const double* scale_dev, i64 sc_bs, double* E, i64 ebs,
+                    int nb, hipStream_t s);
+// P /= max |P|; flag_dev[i] |= bit if that maximum is zero or not finite
+void chain_normalise(double* P, i64 bs, i64 n, int nb, int* flag_dev, int bit, hipStream_t s);
+// lambda (to lam_dev), r (unit norm) and l (l^T r = 1) into lr [r | l] from E and its converged
+// normalised power P (both K x K, instance strides ebs, pbs); flag_dev[i] |= bit if lambda is not
+// positive or either eigenvector residual exceeds kChainResidual relative
+void chain_dominant_finish(const double* E, i64 ebs, const double* P, i64 pbs, int K, int nb, double* lr, i64 lrbs,
+                           double* lam_dev, i64 sc_bs, int* flag_dev, int bit, hipStream_t s);
+// backward seed: T[y][z][a][b] = delta(y, z) gw l[a] r[b] / lambda
+void chain_seed(double* T, i64 bs, int K, int Y, const double* lr, i64 lrbs, double gw, const double* lam_dev,
+                i64 sc_bs, int nb, hipStream_t s);
+// out = L + w ln lambda (per instance)
+void chain_lnZ_at(const double* L_dev, const double* lam_dev, double w, double* out_dev, i64 sc_bs, int nb,
+                  hipStream_t s);
+
 // eig.hip
 // Full symmetric eigendecomposition of an n x n matrix (n <= kJacobiMax) by parallel cyclic
 // Jacobi, one workgroup per instance: eigenvalues descending into lam_dev[0..n), eigenvectors as
 // the columns of V (row-major, leading dimension ldv).  flag_dev (nullable): flag_dev[i] |= flag_bit
-// when instance i still rotated in its last allowed sweep.
+// when instance i still rotated in its last allowed sweep.  Off-diagonal entries below
+// floor_rel |A|_F are left in place.
 constexpr int kJacobiMax = 96;
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
-                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev = nullptr, int flag_bit = 0);
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev = nullptr, int flag_bit = 0,
+                double floor_rel = 0x1p-60);
 // Upper-triangular R^{-1} of the Cholesky factor of (S + shift * I), S b x b (ld b); the
 // shift is shift_rel * trace(S).  flag_dev[i] |= 2 on a non-positive pivot.  near_dev (nullable):
 // near_dev[i] = 1 if every entry of S_i is within near_tol of the identity's, else 0.  skip_dev

@@ -5,8 +5,10 @@
 //   round-robin (Berger table) order: in every round n/2 disjoint index pairs are rotated at once,
 //   rows first, then columns, each pass with one thread per row (or column) element of a pair, so
 //   that a wave touches consecutive LDS words.  A pair is rotated while |a_pq| > 1e-16
-//   sqrt(|a_pp a_qq|) (or above an absolute floor), which keeps small eigenvalues to high relative
-//   accuracy.  (One pass over the disjoint 2 x 2 blocks of pair rows and pair columns, with one
+//   sqrt(|a_pp a_qq|) and above an absolute floor (floor_rel |A|_F: 2^-60 for the spectra of the
+//   eigensolver, which reach the FP64 floor; the callers may raise it to the rounding level of the
+//   matrix, where rotations among large entries keep leaving residues of about u |A| next to small
+//   eigenvalues), which keeps small eigenvalues to high relative accuracy.  (One pass over the disjoint 2 x 2 blocks of pair rows and pair columns, with one
 //   barrier less per round, measured 40% slower: its LDS accesses scatter over the banks.)
 // * chol_inverse: Cholesky of a (shifted) b x b Gram in LDS and the inverse of its triangular
 //   factor, for CholeskyQR of the subspace block.  It can report whether the Gram is the identity
@@ -38,7 +40,7 @@ template <int GW, int JT>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ Ain, int n, int lda, i64 a_bs,
                                                      double* __restrict__ lam, i64 lam_bs, double* __restrict__ Vout,
                                                      int ldv, i64 v_bs, int max_sweeps, int* sweeps_out,
-                                                     int* flag, int flag_bit) {
+                                                     int* flag, int flag_bit, double floor_rel) {
     constexpr int JG = JT / GW;                  // groups
     constexpr int JS = (JM / 2 + JG - 1) / JG;   // pair slots per group
     __shared__ double A[JM * JLD];
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     __syncthreads();
     // entries below the rounding level of the matrix are not rotated away (they are noise; rotating
     // them only costs sweeps on spectra that reach the FP64 floor)
-    const double abs_floor = 0x1p-60 * fro + 1e-300;
+    const double abs_floor = floor_rel * fro + 1e-300;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (tid == 0) nrot = 0;
@@ -490,15 +492,15 @@ dim3 grid2(i64 n, int nb) {
 }  // namespace
 
 void jacobi_eig(const double* A, int n, int lda, i64 a_bs, double* lam_dev, i64 lam_bs, double* V, int ldv, i64 v_bs,
-                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev, int flag_bit) {
+                int nb, int max_sweeps, int* sweeps_dev, hipStream_t s, int* flag_dev, int flag_bit, double floor_rel) {
     DTRG_REQUIRE(n >= 1 && n <= kJacobiMax, DTRG_EINVAL, "jacobi_eig: n out of range");
     static_assert(kJacobiMax <= 96, "the widest Jacobi group has 96 threads");
     if (n <= 64)
         hipLaunchKernelGGL((jacobi_kernel<64, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
-                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit);
+                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit, floor_rel);
     else
         hipLaunchKernelGGL((jacobi_kernel<96, 768>), dim3(nb), dim3(768), 0, s, A, n, lda, a_bs, lam_dev, lam_bs, V,
-                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit);
+                           ldv, v_bs, max_sweeps, sweeps_dev, flag_dev, flag_bit, floor_rel);
     DTRG_HIP(hipGetLastError());
 }
 

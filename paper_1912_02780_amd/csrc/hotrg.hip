@@ -34,7 +34,7 @@ void for_each_buf(const dtrg_plan& P, F f) {
                                  &P.Xe, &P.Xc, &P.Re, &P.Om, &P.Sm, &P.Vc, &P.Vp, &P.Vn, &P.Ye, &P.We, &P.V1, &P.V2,
                                  &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
                                  &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red,
-                                 &P.polS, &P.polV, &P.pollam};
+                                 &P.polS, &P.polV, &P.pollam, &P.chain_lr};
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
@@ -393,6 +393,9 @@ void throw_flags(const dtrg_plan* P, const std::vector<int>& f, int mask, const 
             throw Error(DTRG_ENOCONV, pre + "eigen-adjoint: complement expansion coefficients did not decay");
         if (b & kFlagChebBound) throw Error(DTRG_ENOCONV, pre + "eigen-adjoint: complement expansion diverged");
         if (b & kFlagJacobi) throw Error(DTRG_ENOCONV, pre + "Jacobi eigensolve did not converge");
+        if (b & kFlagTransfer)
+            throw Error(DTRG_ENOCONV, pre + "dominant eigenvalue of the chain's transfer matrix not resolved (not "
+                                            "positive, or not separated from the next)");
         throw Error(DTRG_ENOCONV, pre + "flag " + std::to_string(b));
     }
 }
@@ -558,6 +561,36 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     copy2d(P->th.p, b, P->th.bs, st.lam.p, b, st.lam.bs, 1, b, nb, c.s);
 }
 
+// Scheme (b): close the chain after step k.  E = transfer matrix of T'_k / c_k (Tn, [K][K][Y][Y]) in
+// Gw; its powers E^(2^j), each rescaled by its largest entry, alternate between Gt and Sm (FP64 MFMA
+// products); the dominant eigenvalue goes to sc(k, 11) and [r | l] to chain_lr, and ln Z per cell per
+// slice of the chain closed here, L_k + 2^-k ln lambda_k, to sc(k, 10).
+void chain_close(Ctx& c, int k) {
+    dtrg_plan* P = c.P;
+    const StepShape& s = P->shape[k - 1];
+    const int K = s.K, Y = s.Y, nb = P->nb;
+    chain_transfer(P->Tn.p, P->Tn.bs, K, Y, P->sc(k, 1), P->S, P->Gw.p, P->Gw.bs, nb, c.s);
+    copy2d(P->Gw.p, K, P->Gw.bs, P->Gt.p, K, P->Gt.bs, K, K, nb, c.s);
+    chain_normalise(P->Gt.p, P->Gt.bs, (i64)K * K, nb, P->flags.p, kFlagTransfer, c.s);
+    DevBuf<double>* a = &P->Gt;
+    DevBuf<double>* b = &P->Sm;
+    for (int j = 0; j < kChainSquarings; ++j) {
+        // b = a a:  C(r, c) = sum_q A(r, q) B(c, q) with B(c, q) = a(q, c), a K-major operand
+        GemmOp g;
+        g.M = K; g.N = K; g.K = K;
+        g.A = a->p; g.lda = K;
+        g.B = a->p; g.ldb = K; g.b_kmajor = true;
+        g.C = b->p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+        set_bs(g, a->bs, a->bs, b->bs);
+        c.gemm(g);
+        chain_normalise(b->p, b->bs, (i64)K * K, nb, P->flags.p, kFlagTransfer, c.s);
+        std::swap(a, b);
+    }
+    chain_dominant_finish(P->Gw.p, P->Gw.bs, a->p, a->bs, K, nb, P->chain_lr.p, P->chain_lr.bs, P->sc(k, 11), P->S,
+                          P->flags.p, kFlagTransfer, c.s);
+    chain_lnZ_at(P->sp(0), P->sc(k, 11), ldexp1(-k), P->sc(k, 10), P->S, nb, c.s);
+}
+
 // -------------------------------------------------------------------------------------------
 // plan set-up
 // -------------------------------------------------------------------------------------------
@@ -565,9 +598,10 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
 // the mixed paths: their cost is negligible and they carry the largest weights 2^-k in ln Z / N.
 constexpr double kMixedMinFraction = 0.05;
 
-std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversample, bool mixed) {
+// phys > 0: scheme (b), the vertical legs keep dimension phys and every step merges vertically
+std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversample, bool mixed, int phys) {
     std::vector<StepShape> v;
-    int X = D, Y = D;
+    int X = D, Y = phys > 0 ? phys : D;
     for (int k = 1; k <= nsteps; ++k) {
         StepShape s;
         s.X = X; s.Y = Y; s.n = X * X;
@@ -584,8 +618,12 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversam
             s.e = s.K + (b - s.K) / 2;
         }
         v.push_back(s);
-        X = Y;
-        Y = s.K;
+        if (phys > 0) {
+            X = s.K;
+        } else {
+            X = Y;
+            Y = s.K;
+        }
     }
     if (mixed) {
         double mx = 0.0;
@@ -632,7 +670,7 @@ void alloc_kept(dtrg_plan* P) {
 
 void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
-    const i64 D4 = (i64)P->D * P->D * P->D * P->D;
+    const i64 D4 = P->t0_elems();
     i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1;
     i64 osz[2][12] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
     bool used[2] = {false, false};
@@ -653,6 +691,11 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         for (int i = 0; i < 12; ++i) osz[f][i] = std::max(osz[f][i], z[i]);
     }
     P->T0buf.alloc_inst(nb, D4); P->T0barbuf.alloc_inst(nb, D4); P->dT0buf.alloc_inst(nb, D4);
+    if (P->chain()) {
+        // the closing squarings use Gw (E), Gt and Sm (the powers): K x K fits in each
+        DTRG_REQUIRE(Kmax <= kChainMaxK, DTRG_EINVAL, "chain: chi' above the closing kernel's limit");
+        P->chain_lr.alloc_inst(nb, 2 * Kmax);
+    }
     for (DevBuf<double>* b : {&P->TA, &P->TB, &P->Tn, &P->Tbar, &P->Tbar2, &P->Wk, &P->A, &P->B})
         b->alloc_inst(nb, t4);
     for (int f = 0; f < 2; ++f) {
@@ -913,7 +956,7 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
 // engine entry points
 // -------------------------------------------------------------------------------------------
 void plan_setup(dtrg_plan* P) {
-    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size, P->opt.oversample, P->mixed());
+    P->shape = shapes(P->D, P->chi, P->nsteps, P->opt.block_size, P->opt.oversample, P->mixed(), P->phys);
     alloc_plan(P, P->shape);
 }
 
@@ -932,8 +975,8 @@ void plan_throw_flags(const dtrg_plan* P, int mask, const std::string& where) {
 
 void plan_forward(dtrg_plan* P, Mode mode) {
     Ctx c{P, P->s, mode};
-    const int D = P->D, nb = P->nb;
-    const i64 D4 = (i64)D * D * D * D;
+    const int D = P->D, nb = P->nb, d = P->phys;
+    const i64 D4 = P->t0_elems();
     const auto& sh = P->shape;
     DTRG_REQUIRE(mode == Mode::Adaptive || P->sched_fwd, DTRG_ESTATE, "fixed forward pass without a recorded schedule");
     P->fwd_ok = false;
@@ -949,7 +992,14 @@ void plan_forward(dtrg_plan* P, Mode mode) {
         StepCk& st = P->steps[k - 1];
         const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K;
         if (k == 1) {
-            permute_checked(P, P->T0buf, st.T.p, st.T.bs, pd4(D, D, D, D, 0, 2, 1, 3), 1.0, P->sp(7), c.s);
+            // [l][u][r][d] -> [l][r][u][d] (an MPO: D x d x D x d)
+            permute_checked(P, P->T0buf, st.T.p, st.T.bs,
+                            P->chain() ? pd4(D, d, D, d, 0, 2, 1, 3) : pd4(D, D, D, D, 0, 2, 1, 3), 1.0, P->sp(7), c.s);
+        } else if (P->chain()) {
+            // scheme (b): T_k = T'_{k-1} / c_{k-1} (every step merges vertically)
+            const StepShape& ps = sh[k - 2];
+            permute_checked(P, P->Tn, st.T.p, st.T.bs, pd4(ps.K, ps.K, ps.Y, ps.Y, 0, 1, 2, 3), 1.0,
+                            P->sc(k - 1, 1), c.s);
         } else {
             // T_k = permute(T'_{k-1} / c_{k-1}, (2,3,0,1))
             const StepShape& ps = sh[k - 2];
@@ -961,7 +1011,9 @@ void plan_forward(dtrg_plan* P, Mode mode) {
             if (st.keep_gram) keep_gram(c, st, true);
             if (c.adaptive())
                 check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
-            const StepCk* warm = (k >= 3 && !P->steps[k - 3].fixed) ? &P->steps[k - 3] : nullptr;
+            // warm start from the previous step in the same direction
+            const int kw = P->chain() ? k - 1 : k - 2;
+            const StepCk* warm = (kw >= 1 && !P->steps[kw - 1].fixed) ? &P->steps[kw - 1] : nullptr;
             eigensolve(c, st, k, warm);
         }
         // projection (in the step's contraction format; the output T' is FP64)
@@ -977,15 +1029,22 @@ void plan_forward(dtrg_plan* P, Mode mode) {
         // c_k = |T'|, L += 2^-k ln c_k, 1/c_k
         norm2(P->Tn.p, P->Tn.bs, (i64)K * K * Y * Y, nb, P->sc(k, 0), P->S, c.s, P->ws);
         accum_log(P->sc(k, 0), ldexp1(-k), P->sp(0), P->sc(k, 1), P->S, nb, P->flags.p, c.s);
+        if (P->chain()) chain_close(c, k);
         if (c.adaptive()) check_flags(P, kFlagErrors, "step " + std::to_string(k));
     }
-    // final self-trace of T_{n+1} = permute(T'_n / c_n)
     const StepShape& ls = sh.back();
-    P->Xf = ls.Y; P->Yf = ls.K;
-    permute_checked(P, P->Tn, P->Tbar2.p, P->Tbar2.bs, pd4(ls.K, ls.K, ls.Y, ls.Y, 2, 3, 0, 1), 1.0,
-                    P->sc(P->nsteps, 1), c.s);
-    trace_xxyy(P->Tbar2.p, P->Tbar2.bs, P->Xf, P->Yf, nb, P->sp(4), P->S, c.s);
-    accum_log(P->sp(4), ldexp1(-P->nsteps), P->sp(0), nullptr, P->S, nb, P->flags.p, c.s);
+    if (P->chain()) {
+        // scheme (b): the infinite chain of the last step's cells, L += 2^-n ln lambda_n
+        P->Xf = ls.K; P->Yf = ls.Y;
+        accum_log(P->sc(P->nsteps, 11), ldexp1(-P->nsteps), P->sp(0), nullptr, P->S, nb, P->flags.p, c.s);
+    } else {
+        // final self-trace of T_{n+1} = permute(T'_n / c_n)
+        P->Xf = ls.Y; P->Yf = ls.K;
+        permute_checked(P, P->Tn, P->Tbar2.p, P->Tbar2.bs, pd4(ls.K, ls.K, ls.Y, ls.Y, 2, 3, 0, 1), 1.0,
+                        P->sc(P->nsteps, 1), c.s);
+        trace_xxyy(P->Tbar2.p, P->Tbar2.bs, P->Xf, P->Yf, nb, P->sp(4), P->S, c.s);
+        accum_log(P->sp(4), ldexp1(-P->nsteps), P->sp(0), nullptr, P->S, nb, P->flags.p, c.s);
+    }
     if (c.adaptive()) {
         plan_read_back(P);
         plan_throw_flags(P, kFlagErrors, "final trace");
@@ -1002,14 +1061,26 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
     const int ns = P->nsteps, nb = P->nb;
     DTRG_REQUIRE(P->sched_fwd, DTRG_ESTATE, "backward before a successful forward");
     DTRG_REQUIRE(mode == Mode::Adaptive || P->sched_bwd, DTRG_ESTATE, "fixed backward pass without a recorded schedule");
-    // seed: gradient w.r.t. T_{n+1} (dims [Xf][Xf][Yf][Yf])
-    seed_trace_grad(P->Tbar.p, P->Tbar.bs, P->Xf, P->Yf, nb, gbar * ldexp1(-ns), P->sp(4), P->S, c.s);
+    // seed: gradient w.r.t. the last step's normalised output, in the layout [y][z][alpha][beta] the
+    // step adjoint reads (scheme (a): T_{n+1} = permute(T'_n / c_n), dims [Xf][Xf][Yf][Yf], through its
+    // self-trace; scheme (b): T'_n / c_n through ln lambda of its transfer matrix)
+    if (P->chain())
+        chain_seed(P->Tbar.p, P->Tbar.bs, P->Xf, P->Yf, P->chain_lr.p, P->chain_lr.bs, gbar * ldexp1(-ns),
+                   P->sc(ns, 11), P->S, nb, c.s);
+    else
+        seed_trace_grad(P->Tbar.p, P->Tbar.bs, P->Xf, P->Yf, nb, gbar * ldexp1(-ns), P->sp(4), P->S, c.s);
     for (int k = ns; k >= 1; --k) {
         StepCk& st = P->steps[k - 1];
         const int X = st.sh.X, Y = st.sh.Y, K = st.sh.K, n = st.sh.n, b = st.sh.b;
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
         const Prec pr = o.pr;
         const Lds l(st.sh);
+        if (P->chain() && k < ns) {
+            // scheme (b): the gradient w.r.t. T_{k+1} = T'_k / c_k is in [l][r][u][d]; the step
+            // adjoint reads it as [y][z][alpha][beta]
+            permute_checked(P, P->Tbar, P->Tbar2.p, P->Tbar2.bs, pd4(K, K, Y, Y, 2, 3, 0, 1), 1.0, nullptr, c.s);
+            std::swap(P->Tbar, P->Tbar2);
+        }
         // incoming gradient / c_k in the two layouts it is contracted in:
         //   Tpb [beta][(alpha,y,z)] and Tpb2 [(alpha,y,z)][beta]  (from Tbar [y][z][alpha][beta])
         permute_op(P, pr, P->Tbar, o.Tpb, pd4(Y, Y, K, K, 3, 2, 0, 1), 3, l.Tpb, P->sc(k, 1), c.s);
@@ -1156,9 +1227,9 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         if (c.adaptive()) check_flags(P, kFlagErrors, "backward step " + std::to_string(k));
     }
     // T0bar[l][u][r][d] = permute(Tbar [l][r][u][d]) / c0
-    const int D = P->D;
-    const i64 D4 = (i64)D * D * D * D;
-    permute_checked(P, P->Tbar, P->T0barbuf.p, P->T0barbuf.bs, pd4(D, D, D, D, 0, 2, 1, 3), 1.0, P->sp(7), c.s);
+    const int D = P->D, Yd = P->chain() ? P->phys : P->D;
+    const i64 D4 = P->t0_elems();
+    permute_checked(P, P->Tbar, P->T0barbuf.p, P->T0barbuf.bs, pd4(D, D, Yd, Yd, 0, 2, 1, 3), 1.0, P->sp(7), c.s);
     if (with_dir) dot(P->T0barbuf.p, P->dT0buf.p, D4, D4, nb, P->sp(5), P->S, c.s, P->ws);
     if (c.adaptive()) {
         plan_read_back(P);
@@ -1187,22 +1258,39 @@ void polar_update(dtrg_plan* P, int k) {
         P->pollam.alloc_inst(nb, m);
     }
     const i64 vbs = P->V1.bs;
+    // the environment E = w_bar; scheme (b): E + mu |E|_F w with the step's current isometry w (the
+    // last layer's environment has rank <= 2, the derivative of the transfer matrix's eigenvalue
+    // being l r^T, so the maximisers of Tr(E^T w) leave the rest of w free: the term keeps it)
+    const double* E = st.wbar.p;
+    i64 ebs = st.wbar.bs;
+    if (P->chain()) {
+        norm2(st.wbar.p, st.wbar.bs, (i64)n * K, nb, P->sp(8), P->S, c.s, P->ws);
+        copy2d(st.U.p, b, st.U.bs, P->We.p, K, P->We.bs, n, K, nb, c.s);
+        scale_inplace(P->We.p, P->We.bs, (i64)n * K, nb, kPolarTieBreak, P->sp(8), P->S, false, c.s);
+        DTRG_REQUIRE(nb == 1, DTRG_EINVAL, "isometry optimisation needs a single-instance plan");
+        axpy(st.wbar.p, P->We.p, 0, (i64)n * K, 1, 1.0, c.s);
+        E = P->We.p;
+        ebs = P->We.bs;
+    }
     // Q: E orthonormalised (in V1, ld K)
-    copy2d(st.wbar.p, K, st.wbar.bs, P->V1.p, K, vbs, n, K, nb, c.s);
+    copy2d(E, K, ebs, P->V1.p, K, vbs, n, K, nb, c.s);
     orthonormalise(c, P->V1.p, P->V2.p, vbs, n, K);
     // R = Q^T E (K x K, in H)
     {
         GemmOp g;
         g.M = K; g.N = K; g.K = n;
         g.A = P->V1.p; g.lda = K; g.a_kmajor = true;
-        g.B = st.wbar.p; g.ldb = K; g.b_kmajor = true;
+        g.B = E; g.ldb = K; g.b_kmajor = true;
         g.C = P->H.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
-        set_bs(g, vbs, st.wbar.bs, P->H.bs);
+        set_bs(g, vbs, ebs, P->H.bs);
         c.gemm(g);
     }
     sym_augment(P->H.p, P->H.bs, K, P->polS.p, P->polS.bs, nb, c.s);
+    // floor at the rounding level of [[0, R], [R^T, 0]]: the polar factor needs the singular vectors
+    // to working accuracy only, and rotations among its large entries leave residues of about u |R|
+    // next to the small singular values, which a lower floor keeps rotating
     jacobi_eig(P->polS.p, m, m, P->polS.bs, P->pollam.p, P->pollam.bs, P->polV.p, m, P->polV.bs, nb, kJacobiSweeps,
-               P->misc.p, c.s, P->flags.p, kFlagJacobi);
+               P->misc.p, c.s, P->flags.p, kFlagJacobi, 0x1p-50);
     // polar(R)[r][c] = 2 sum_{j < K} V[r][j] V[K + c][j]   (into Rinv, K x K)
     {
         GemmOp g;
@@ -1234,9 +1322,16 @@ void plan_isometry_optimize(dtrg_plan* P, int layers, int n_inner, int n_sweeps,
     for (auto& st : P->steps) st.fixed = false;
     plan_forward(P, Mode::Adaptive);   // plain HOTRG: its isometries start the optimisation
     if (lnZ_hotrg) *lnZ_hotrg = P->scal_h[0];
+    // scheme (a): the first `layers` truncating steps; scheme (b): the last `layers` (the optimisation
+    // depth n_d below the target temperature), visited from the lowest up
     std::vector<int> opt;
-    for (int k = 1; k <= P->nsteps && (int)opt.size() < layers; ++k)
-        if (P->steps[k - 1].sh.K < P->steps[k - 1].sh.n) opt.push_back(k);
+    if (P->chain()) {
+        for (int k = P->nsteps; k >= 1 && (int)opt.size() < layers; --k)
+            if (P->steps[k - 1].sh.K < P->steps[k - 1].sh.n) opt.insert(opt.begin(), k);
+    } else {
+        for (int k = 1; k <= P->nsteps && (int)opt.size() < layers; ++k)
+            if (P->steps[k - 1].sh.K < P->steps[k - 1].sh.n) opt.push_back(k);
+    }
     DTRG_REQUIRE((int)opt.size() == layers, DTRG_EINVAL, "fewer truncating steps than layers to optimise");
     for (int k : opt) {
         StepCk& st = P->steps[k - 1];

@@ -28,15 +28,22 @@ enum : int {
     kFlagChebTail = 16,   // complement expansion coefficients not decayed at the recorded degree
     kFlagChebBound = 32,  // complement expansion not bounded (spectrum outside its interval)
     kFlagJacobi = 64,     // full Jacobi eigensolve still rotating at its sweep cap
+    kFlagTransfer = 128,  // scheme (b): dominant eigenvalue of the transfer matrix not resolved
 };
 // the flags that fail a pass (kFlagChol is a diagnostic: the shifted pass absorbs it)
-constexpr int kFlagErrorMask = kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail | kFlagChebBound | kFlagJacobi;
+constexpr int kFlagErrorMask =
+    kFlagNonPos | kFlagNonFinite | kFlagSubspace | kFlagChebTail | kFlagChebBound | kFlagJacobi | kFlagTransfer;
 
 // Per-instance FP64 scalars: one row of kScPlan + kScStep * n_steps doubles per instance.
-constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace, 5 <T0bar, dT0>, 6 c0, 7 1/c0
+// scheme (b): weight of the current isometry added to its environment before the polar factor
+constexpr double kPolarTieBreak = 1e-6;
+constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace (scheme (b): the final transfer matrix's
+                              // dominant eigenvalue), 5 <T0bar, dT0>, 6 c0, 7 1/c0
 constexpr int kScStep = 12;   // per step: 0 c_k, 1 1/c_k, 2 trace of the Gram, 3 residual of the first
                               // unresolved Ritz pair, 4 lo, 5 hi (complement interval), 6 |v_0|,
-                              // 7 |v_m|, 8 largest resolved residual, 9 coefficient tail ratio
+                              // 7 |v_m|, 8 largest resolved residual, 9 coefficient tail ratio;
+                              // scheme (b): 10 ln Z per cell per slice closed after the step,
+                              // 11 the dominant eigenvalue of that step's transfer matrix
 
 struct StepShape {
     int X = 0, Y = 0, K = 0, n = 0, b = 0;
@@ -100,6 +107,10 @@ struct StepCk {
 
 struct dtrg_plan {
     int D = 0, chi = 0, nsteps = 0, nb = 1;
+    int phys = 0;               // scheme (b): physical dimension of the MPO input (0: scheme (a))
+    bool chain() const { return phys > 0; }
+    // elements of one instance's input (D^4, or D^2 d^2 for an MPO)
+    dtrg::i64 t0_elems() const { return chain() ? (dtrg::i64)D * D * phys * phys : (dtrg::i64)D * D * D * D; }
     dtrg_options opt{};
     dtrg::Prec prec = dtrg::Prec::F64;
     hipStream_t s = nullptr;
@@ -133,6 +144,7 @@ struct dtrg_plan {
     bool ctab_ready = false;
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
     dtrg::DevBuf<double> polS, polV, pollam;   // polar factor of an isometry gradient (2K x 2K, 2K)
+    dtrg::DevBuf<double> chain_lr;             // scheme (b): right and left dominant eigenvectors [r | l]
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)
     int tuned_seen = -1;          // size of the process table when the file was last written
