@@ -34,7 +34,18 @@ Workloads (--workload):
       beside it under "with_kept_intermediates".  The fixed tile heuristic (no autotuner, whose
       trial buffers would add to the reported peak device memory).
 
-    python bench.py [--workload chi48|batch256|ising_chi64] [--steps K] [--warmup W]
+  xy_chain
+      The paper's scheme (b) on the infinite spin-1/2 XY chain: the second-order Trotter MPO of
+      rho(tau) in two-spin cells, squared n = 18 times to beta = 12.8 (tau = 12.8 / 2^18 = 4.9e-5, the
+      paper's Fig. 3 setting), bonds truncated to D = 32, the chain closed by its transfer matrix after
+      every squaring (the whole free-energy curve beta = 2^k tau in one pass); FP64 contractions;
+      value = RG-steps (squarings) per second, forward + backward.  Reported beside it: the free
+      energy against the Jordan-Wigner solution at every beta >= 0.1 and at beta = 12.8, and the
+      differentiable-TRG optimisation of the last layers (depth n_d, n_i MERA updates per layer,
+      n_s sweeps): its wall time and the free-energy error before and after, and the FP64 oracle
+      timed on the host on one forward + backward pass.
+
+    python bench.py [--workload chi48|batch256|ising_chi64|xy_chain] [--steps K] [--warmup W]
                     [--contract fp32|fp64|bf16x3|bf16x6] [--checkpoint-gib G] [--autotune 0|1]
                     [--no-cpu-baseline]
 """
@@ -57,7 +68,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0} 
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (2 bf16 planes, 3 products, fp32 accumulate)",
          "bf16x6": "bf16x6 (3 bf16 planes, 6 products, fp32 accumulate)"}
-DEFAULT_CONTRACT = {"chi48": "bf16x6", "batch256": "bf16x6", "ising_chi64": "bf16x6"}
+DEFAULT_CONTRACT = {"chi48": "bf16x6", "batch256": "bf16x6", "ising_chi64": "bf16x6", "xy_chain": "fp64"}
 # chi = 64 at beta_c: FP32 accumulation chains of at most 512 products in the contractions with outputs
 # of at most chi^4 (the long-K adjoints; FP64 sums of the chunks), which brings d(lnZ/N)/dbeta from
 # 1.1e-5 to 5.5e-6 of the FP64 result for 2% of the pass
@@ -361,9 +372,11 @@ def bench_chi48(args, B, I, torch, np, dev):
         sub_args = argparse.Namespace(**vars(args))
         sub_args.steps, sub_args.warmup, sub_args.compact = 2, 1, True
         sub_args.checkpoint_gib = None
-        for name, fn, chi_s, n_s in (("batch256", bench_batch256, 48, 24), ("ising_chi64", bench_ising_chi64, 64, 30)):
+        for name, fn, chi_s, n_s in (("batch256", bench_batch256, 48, 24), ("ising_chi64", bench_ising_chi64, 64, 30),
+                                     ("xy_chain", bench_xy_chain, 32, 18)):
             _progress(f"compact {name}")
             sub_args.chi, sub_args.n_steps = chi_s, n_s
+            sub_args.contract = args.contract if name != "xy_chain" else DEFAULT_CONTRACT["xy_chain"]
             out[name] = fn(sub_args, B, I, torch, np, dev)
             torch.cuda.empty_cache()
     return out
@@ -554,12 +567,78 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     }
 
 
+def bench_xy_chain(args, B, I, torch, np, dev):
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_xy as X
+    n, D, beta = args.n_steps, args.chi, 12.8
+    tau = beta / 2 ** n
+    compact = getattr(args, "compact", False)
+    depth, n_inner, n_sweeps = (2, 5, 2) if compact else (4, 10, 3)
+    Mh = I.xy_trotter_mpo(tau)
+    M = torch.from_numpy(Mh).to(dev)
+    plan = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n,
+                                    B.default_options(contract=args.contract, profile=1), dev)
+
+    def one_step():
+        L = B.dtrg_plan_forward(plan, M)
+        B.dtrg_hotrg_backward(plan, 1.0)
+        return L
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    plan.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L = one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, ms, flops = plan.profile(reset=True)
+
+    def f_err(L_k, k):
+        return abs(math.ldexp(L_k, k) / 2.0 / X.lnZ_per_spin_infinite(math.ldexp(tau, k)) - 1.0)
+
+    at = [plan.step_info(k)["lnZ_at_step"] for k in range(1, n + 1)]
+    curve = [(math.ldexp(tau, k), f_err(at[k - 1], k)) for k in range(1, n + 1) if math.ldexp(tau, k) >= 0.1]
+    plan.close()
+    _progress("xy chain: isometry optimisation")
+    p2 = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n, B.default_options(contract=args.contract), dev)
+    t1 = time.perf_counter()
+    L0, L1, hist = B.dtrg_isometry_optimize(p2, M, layers=depth, n_inner=n_inner, n_sweeps=n_sweeps)
+    t_opt = time.perf_counter() - t1
+    p2.close()
+    out = {
+        "metric": "scheme (b) squarings/s (forward + backward), infinite XY chain to beta = 12.8",
+        "value": n * args.steps / wall, "unit": "RG-steps/s", "ms_per_step": wall / args.steps * 1e3,
+        "config": {"workload": (f"infinite XY chain, second-order Trotter MPO (two-spin cells, bond 4, tau = {tau:.3e}), "
+                                f"{n} squarings to beta = {beta}, D = {D}, forward + backward"),
+                   "D": D, "n_steps": n, "tau": tau, "beta": beta, "contract": args.contract, "eig": "fp64"},
+        "lnZ_per_tensor": L,
+        "f_rel_err_vs_jordan_wigner": {"beta_12.8": f_err(L, n), "max_beta_ge_0.1": max(e for _, e in curve),
+                                       "curve": [[b, e] for b, e in curve]},
+        "dtrg": {"depth_n_d": depth, "n_i": n_inner, "n_s": n_sweeps, "mera_updates": len(hist), "wall_s": t_opt,
+                 "f_rel_err_plain": f_err(L0, n), "f_rel_err_optimised": f_err(L1, n)},
+        "roofline": roofline(launches, ms, flops, args.contract, "join contraction (gemm kernel, tag 7)"),
+    }
+    if not args.no_cpu_baseline and not compact:
+        from oracle import xtrg as C
+        _progress("xy chain: the oracle on the host")
+        t2 = time.perf_counter()
+        fo = C.chain_forward(Mh, D, n)
+        C.chain_backward(fo)
+        t_cpu = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": n / t_cpu, "unit": "RG-steps/s", "cores": _threads(), "kind": "oracle",
+                               "sample": f"one forward + backward pass of the same workload ({t_cpu:.1f} s)",
+                               "lnZ_rel_err_gpu_vs_oracle": abs(L / fo.lnZ_per_tensor - 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chi48", choices=["chi48", "batch256", "ising_chi64"])
+    ap.add_argument("--workload", default="chi48", choices=["chi48", "batch256", "ising_chi64", "xy_chain"])
     # default per workload: chi48 runs the fastest path that meets both accuracy targets
     # (ln Z / N <= 1e-6, gradient <= 1e-5)
     ap.add_argument("--contract", default=None, choices=sorted(PEAK_TFLOPS))
@@ -581,7 +660,7 @@ def main():
     ap.add_argument("--no-library-reference", action="store_true",
                     help="skip timing the vendor library (torch.matmul) on the join's MFMA work")
     ap.add_argument("--no-extra-workloads", action="store_true",
-                    help="chi48: skip the compact batch256 and ising_chi64 legs")
+                    help="chi48: skip the compact batch256, ising_chi64 and xy_chain legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -592,9 +671,9 @@ def main():
     if args.contract is None:
         args.contract = DEFAULT_CONTRACT[args.workload]
     if args.chi is None:
-        args.chi = 64 if args.workload == "ising_chi64" else 48
+        args.chi = {"ising_chi64": 64, "xy_chain": 32}.get(args.workload, 48)
     if args.n_steps is None:
-        args.n_steps = 30 if args.workload == "ising_chi64" else 24
+        args.n_steps = {"ising_chi64": 30, "xy_chain": 18}.get(args.workload, 24)
 
     import numpy as np
     import torch
@@ -612,7 +691,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst, s
-    fn = {"chi48": bench_chi48, "batch256": bench_batch256, "ising_chi64": bench_ising_chi64}[args.workload]
+    fn = {"chi48": bench_chi48, "batch256": bench_batch256, "ising_chi64": bench_ising_chi64,
+          "xy_chain": bench_xy_chain}[args.workload]
     res = fn(args, B, I, torch, np, dev)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),

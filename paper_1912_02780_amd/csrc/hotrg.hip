@@ -534,7 +534,12 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
             if (stall >= 3 && mx <= kSubspaceAccept) break;      // rounding floor reached
         }
         if (it == it_max) break;
-        // next block: G V with columns rescaled to unit norm, re-orthonormalised
+        // next block: G V with columns rescaled to unit norm, re-orthonormalised.  Scheme (b): (G + s I) V
+        // (s = 2^-45 of the unit trace), because the Grams of a squared Trotter operator have far
+        // fewer non-negligible eigenvalues than chi' (rank 6 of 256 at tau = 5e-5), and G V alone would
+        // collapse the block onto that range and break its Cholesky factorisation; the shift leaves the
+        // eigenvectors unchanged and keeps the block's null-space directions at norm s.
+        if (P->chain()) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, kChainGramShift, c.s);
         col_norms(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, c.s);
         col_normalise(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, seed + 7919ULL * it, c.s);
         std::swap(P->V1, P->Y1);

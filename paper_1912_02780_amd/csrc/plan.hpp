@@ -37,6 +37,8 @@ constexpr int kFlagErrorMask =
 // Per-instance FP64 scalars: one row of kScPlan + kScStep * n_steps doubles per instance.
 // scheme (b): weight of the current isometry added to its environment before the polar factor
 constexpr double kPolarTieBreak = 1e-6;
+// scheme (b): shift of the trace-normalised Gram in the subspace iteration's block update
+constexpr double kChainGramShift = 0x1p-45;
 constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace (scheme (b): the final transfer matrix's
                               // dominant eigenvalue), 5 <T0bar, dT0>, 6 c0, 7 1/c0
 constexpr int kScStep = 12;   // per step: 0 c_k, 1 1/c_k, 2 trace of the Gram, 3 residual of the first
