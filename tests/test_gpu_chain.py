@@ -9,8 +9,9 @@ Jordan-Wigner free energy of the XY chain.
   exact symmetry multiplets in the Gram spectra leave the symmetry-breaking part of the gradient to
   each eigensolver's rotation inside them.
 * Six-product split-bf16 path at sizes where the projections run mixed: ln Z within 1e-6 of the
-  oracle; the gradient within 1e-5 for the random MPO, and within 1e-3 for the XY chain, whose
-  symmetry multiplets make it ill-conditioned in the symmetry-breaking directions (see MIXED_CASES).
+  oracle; the gradient within 1e-5 normwise; entry by entry within 1e-5 for the random MPO and 1e-2
+  for the XY chain, whose symmetry multiplets make single entries ill-conditioned in the
+  symmetry-breaking directions (see MIXED_CASES).
 * The isometry optimisation of the last layers (depth 2): ln Z after every MERA update within 1e-10
   of the oracle's trajectory (the update is gauge covariant), and the free energy closer to
   Jordan-Wigner than the local truncation.
@@ -85,10 +86,11 @@ def test_gpu_chain_fp64_vs_oracle(B, name):
 # Inside a kept multiplet the split-bf16 rounding splits the eigenvalues by ~1e-8 of the spectrum,
 # where the broadened inverse gaps d / (d^2 + 1e-12) reach 1e4 and turn the arbitrary rotation of the
 # multiplet's eigenvectors into gradient differences in the symmetry-breaking directions (the FP64 path
-# shows the same amplification at its rounding level: 1e-9 entry-wise): the full gradient of the XY
-# case is bounded at 1e-3 there, ln Z at 1e-6.  The random MPO has no multiplets (smallest relative gap
-# at a cut 6e-4 at chi = 9): its full gradient meets 1e-5.
-MIXED_CASES = {"xy_chi25": (("xy", 0.05), 25, 7, 1e-3), "random_chi9": (("random", 4), 9, 8, 1e-5)}
+# shows the same amplification at its rounding level: 1e-9 entry-wise).  Those directions carry little
+# of the gradient's norm (measured 4.7e-6 normwise against 3.8e-3 on the worst single entry), so the
+# XY case meets 1e-5 normwise and its entries are bounded at 1e-2; ln Z at 1e-6.  The random MPO has no
+# multiplets (smallest relative gap at a cut 6e-4 at chi = 9): its gradient meets 1e-5 entry by entry.
+MIXED_CASES = {"xy_chi25": (("xy", 0.05), 25, 7, 1e-2), "random_chi9": (("random", 4), 9, 8, 1e-5)}
 
 
 @pytest.mark.parametrize("name", sorted(MIXED_CASES))
@@ -113,7 +115,8 @@ def test_gpu_chain_mixed_vs_oracle(B, name):
          f"mixed steps {sum(mixed)}")
     assert sum(mixed) >= 3
     assert abs(L / fwd.lnZ_per_tensor - 1) < 1e-6
-    assert rel < gtol
+    assert rel < 1e-5
+    assert _elem(g, go, 1e-3) < gtol
 
 
 def test_gpu_chain_isometry_gradient_vs_oracle(B):
