@@ -35,6 +35,18 @@ Readings where the paper is silent (each is also listed in the design notes):
     trace 2^-n (N = 2^n sites);
   * the first step merges a vertical pair (the paper's figure), later steps alternate by the
     permutation (u, d, l, r) of the previous step's output.
+
+The side rule (option side_rule="min"; the default "left" is the reading above).  The local HOSVD
+of SM B can be taken on either unfolding of the pair: the left legs (x1, x2) or the right legs
+(x1', x2').  For a tensor with the left/right mirror symmetry the two Grams have the same spectrum,
+but a chiral tensor (invariant under quarter turns only) gives two different ones.  One bond between
+two columns carries a single projector w w^T, so one w serves both sides; the rule takes it from the
+unfolding whose discarded eigenvalues weigh less, the truncated weight 1 - sum of the kept
+trace-normalised eigenvalues (the choice of the original HOTRG between its two environments).  The
+right side wins only when its weight is below the left's by more than SIDE_MARGIN (absolute, on the
+trace-normalised spectrum), so that ties decided by rounding always go left.  The right unfolding's
+Gram is the left unfolding's Gram of the mirrored step input T[x'][x][y][y'], and its adjoint goes
+back through the same transpose.
 """
 
 from __future__ import annotations
@@ -45,6 +57,8 @@ from dataclasses import dataclass
 import numpy as np
 
 DEFAULT_BROADENING = 1e-12
+SIDE_MARGIN = 1e-12
+SIDE_RULES = ("left", "min")
 
 
 def _es(spec, *ops):
@@ -66,6 +80,8 @@ class StepRecord:
     P: np.ndarray | None = None
     Q: np.ndarray | None = None
     w_fixed: np.ndarray | None = None   # the step's given isometry (then U, lam, A, B, G_hat are None)
+    side: str = "L"      # unfolding the isometry came from: "L" (x1, x2) or "R" (x1', x2')
+    trunc_LR: tuple | None = None       # side_rule "min": the truncated weights of both unfoldings
 
 
 @dataclass
@@ -114,6 +130,16 @@ def isometry(G: np.ndarray, chi: int):
     return G_hat, t, lam, U, chi_kept
 
 
+def mirror_lr(T: np.ndarray) -> np.ndarray:
+    """T[x][x'][y][y'] -> T[x'][x][y][y']: the step input seen from its right legs."""
+    return np.ascontiguousarray(np.transpose(T, (1, 0, 2, 3)))
+
+
+def truncated_weight(lam: np.ndarray, chi_kept: int) -> float:
+    """1 - sum of the kept eigenvalues of the trace-normalised Gram."""
+    return 1.0 - float(np.sum(lam[:chi_kept]))
+
+
 def project(T: np.ndarray, w: np.ndarray):
     """The HOTRG step with isometry w[x1][x2][a] on both sides, in three pairwise contractions.
 
@@ -138,7 +164,7 @@ def _spill(arr: np.ndarray, spill_dir, tag: str):
 
 
 def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = False,
-                  spill_dir=None, progress=None, w_fixed=None) -> ForwardResult:
+                  spill_dir=None, progress=None, w_fixed=None, side_rule: str = "left") -> ForwardResult:
     """ln Z / N of the periodic 2^n-site network built from T0 with chi-truncated HOTRG steps.
 
     spill_dir (optional) keeps each step's record on disk as read-only memory maps instead of in
@@ -146,7 +172,11 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
     progress (optional) is called as progress("forward", k) after each step.
     w_fixed (optional) maps step numbers k to given isometries w[x1][x2][a] (chi' = min(chi, X^2)
     columns): those steps project with them instead of the leading eigenvectors of their Gram.
+    side_rule: "left" (the (x1, x2) unfolding) or "min" (the unfolding with the smaller truncated
+    weight; module notes).
     """
+    if side_rule not in SIDE_RULES:
+        raise ValueError(f"side_rule must be one of {SIDE_RULES}")
     T0 = np.asarray(T0_lurd, dtype=np.float64)
     if T0.ndim != 4 or len(set(T0.shape)) != 1:
         raise ValueError("T0 must be a D x D x D x D tensor")
@@ -172,9 +202,20 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
                 raise ValueError(f"step {k}: isometry must have shape {(X, X, chi_kept)}")
             A = B = G_hat = U = lam = None
             t = math.nan
+            side, trunc_LR = "L", None
         else:
             A, B = half_environments(T)
             G_hat, t, lam, U, chi_kept = isometry(gram(A, B), chi)
+            side, trunc_LR = "L", None
+            if side_rule == "min":
+                A_r, B_r = half_environments(mirror_lr(T))
+                right = isometry(gram(A_r, B_r), chi)
+                trunc_LR = (truncated_weight(lam, chi_kept), truncated_weight(right[2], chi_kept))
+                if trunc_LR[1] < trunc_LR[0] - SIDE_MARGIN:
+                    side = "R"
+                    A, B = A_r, B_r
+                    G_hat, t, lam, U, _ = right
+                del A_r, B_r, right
             w = U[:, :chi_kept].reshape(X, X, chi_kept)
         P, Q, Tn = project(T, w)
         if not keep_PQ:
@@ -190,7 +231,7 @@ def hotrg_forward(T0_lurd: np.ndarray, chi: int, n_steps: int, keep_PQ: bool = F
                                 G_hat=None if G_hat is None else _spill(G_hat, spill_dir, tag + "Ghat"),
                                 A=None if A is None else _spill(A, spill_dir, tag + "A"),
                                 B=None if B is None else _spill(B, spill_dir, tag + "B"),
-                                chi_kept=chi_kept, P=P, Q=Q, w_fixed=fixed))
+                                chi_kept=chi_kept, P=P, Q=Q, w_fixed=fixed, side=side, trunc_LR=trunc_LR))
         del A, B, G_hat, U
         T = Tn / c
         L += math.ldexp(math.log(c), -k)
@@ -273,11 +314,16 @@ def step_adjoint(rec: StepRecord, Tn_bar: np.ndarray, eps: float) -> np.ndarray:
     G4_bar = G_bar.reshape(X, X, X, X)          # [a][c][b][d]
     A_bar = _es("acbd,cdjk->abjk", G4_bar, rec.B)
     B_bar = _es("acbd,abjk->cdjk", G4_bar, rec.A)
+    # the Gram's tensor: T itself, or its mirror when the isometry came from the right unfolding
+    Tg = T if rec.side == "L" else mirror_lr(T)
     # A[a,b,j,k] = sum T[a,x,y,j] T[b,x,y,k]  (both factors are the same tensor)
-    T_bar_A = _es("abjk,bxyk->axyj", A_bar, T) + _es("abjk,axyj->bxyk", A_bar, T)
+    T_bar_A = _es("abjk,bxyk->axyj", A_bar, Tg) + _es("abjk,axyj->bxyk", A_bar, Tg)
     # B[a,b,j,k] = sum T[a,x,j,y] T[b,x,k,y]
-    T_bar_B = _es("abjk,bxky->axjy", B_bar, T) + _es("abjk,axjy->bxky", B_bar, T)
-    return T_bar_proj + T_bar_A + T_bar_B
+    T_bar_B = _es("abjk,bxky->axjy", B_bar, Tg) + _es("abjk,axjy->bxky", B_bar, Tg)
+    T_bar_G = T_bar_A + T_bar_B
+    if rec.side == "R":
+        T_bar_G = mirror_lr(T_bar_G)
+    return T_bar_proj + T_bar_G
 
 
 def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_BROADENING,
@@ -309,8 +355,9 @@ def hotrg_backward(fwd: ForwardResult, gbar: float = 1.0, eps: float = DEFAULT_B
     return np.ascontiguousarray(np.transpose(T_bar, (0, 2, 1, 3)))
 
 
-def lnZ_and_grad(T0_lurd: np.ndarray, chi: int, n_steps: int, eps: float = DEFAULT_BROADENING):
-    fwd = hotrg_forward(T0_lurd, chi, n_steps)
+def lnZ_and_grad(T0_lurd: np.ndarray, chi: int, n_steps: int, eps: float = DEFAULT_BROADENING,
+                 side_rule: str = "left"):
+    fwd = hotrg_forward(T0_lurd, chi, n_steps, side_rule=side_rule)
     return fwd.lnZ_per_site, hotrg_backward(fwd, 1.0, eps), fwd
 
 

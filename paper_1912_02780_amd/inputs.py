@@ -16,6 +16,8 @@ C-contiguous.
   averaged over the eight leg permutations of the square's point group (four rotations, each
   with and without the left/right mirror), so that it is invariant under the lattice
   symmetries.
+* Chiral random tensor: the same entries averaged over the four rotations only, so that the
+  tensor has no mirror symmetry and the Grams of the left and right unfoldings of a pair differ.
 * Quantum XY chain H = sum_i S^x_i S^x_{i+1} + S^y_i S^y_{i+1} (spin 1/2, J = 1; paper, main text
   "Infinite quantum XY chain" and Supplemental Material F): the matrix-product operator of the
   second-order Trotter-Suzuki density operator rho(tau) = exp(-tau/2 H_o) exp(-tau H_e)
@@ -108,6 +110,25 @@ def random_d4_T0(seed: int = 0, D: int = 4) -> np.ndarray:
     for img in square_group_images(T):
         acc += img
     return np.ascontiguousarray(acc / 8.0)
+
+
+def random_c4_T0(seed: int = 0, D: int = 4) -> np.ndarray:
+    """Random non-negative [l][u][r][d] tensor, uniform [0,1) entries, averaged over the four
+    rotations only: invariant under quarter turns but not under the mirror (a chiral tensor)."""
+    rng = np.random.default_rng(seed)
+    T = rng.random((D, D, D, D))
+    acc = np.zeros_like(T)
+    cur = T
+    for _ in range(4):
+        acc += cur
+        cur = np.transpose(cur, (1, 2, 3, 0))
+    return np.ascontiguousarray(acc / 4.0)
+
+
+def mirror_T0(T0: np.ndarray) -> np.ndarray:
+    """The left/right mirror image of a [l][u][r][d] tensor (the lattice reflected about a vertical
+    line has the same partition function)."""
+    return np.ascontiguousarray(np.transpose(T0, (2, 1, 0, 3)))
 
 
 def batch_betas(n: int = 256, lo: float = 0.30, hi: float = 0.60) -> np.ndarray:
