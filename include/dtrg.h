@@ -148,6 +148,18 @@ typedef struct {
                                  ln Z per cell per Trotter slice, and dtrg_step_info.lnZ_at_step
                                  gives it after every step.  0 <= d <= 16; batches take 0 only.
                                  Default 0 */
+    int side_rule;            /* which unfolding of the pair gives each step's isometry (SM B: the
+                                 local higher-order SVD of the pair).  0: the left legs (x1, x2).
+                                 1: whichever of the left legs (x1, x2) and the right legs
+                                 (x1', x2') has the smaller truncated weight (1 - the sum of the kept
+                                 eigenvalues of its trace-normalised Gram), the right one only when
+                                 lighter by more than 1e-12; one isometry still serves both sides,
+                                 as a bond carries one projector.  Rule 1 eigensolves both Grams in
+                                 the forward pass (the backward differentiates the chosen one); it
+                                 matters for tensors without the left/right mirror symmetry
+                                 (chiral or generic), while mirror-symmetric inputs keep the left
+                                 side.  Single-instance plans of scheme (a) only (DTRG_EINVAL for
+                                 batches and chain_phys > 0).  Default 0 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -171,6 +183,9 @@ typedef struct {
                                  format, 0 if in FP64 */
     double lnZ_at_step;       /* scheme (b) (chain_phys > 0): ln Z per cell per Trotter slice of the
                                  chain closed after this step (rho(2^k tau)); NaN for scheme (a) */
+    int side;                 /* unfolding the step's isometry came from: 0 left, 1 right */
+    double trunc_weight_left; /* side_rule 1: truncated weights of the left and right unfoldings */
+    double trunc_weight_right;/* (NaN with side_rule 0 and on steps with a given isometry) */
 } dtrg_step_info;
 
 typedef struct dtrg_plan dtrg_plan;

@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double), ("oversample", c_int),
                 ("max_fp32_chain", c_int), ("max_fp32_chain_wide", c_int),
                 ("tile_table", ctypes.c_char_p), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
-                ("alloc_user", c_void_p), ("chain_phys", c_int)]
+                ("alloc_user", c_void_p), ("chain_phys", c_int), ("side_rule", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -51,7 +51,8 @@ class StepInfo(ctypes.Structure):
                 ("c", c_double), ("trace_G", c_double), ("lam_last_kept", c_double),
                 ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int),
                 ("trunc_weight", c_double), ("cut_gap", c_double), ("min_kept_gap", c_double), ("mixed", c_int),
-                ("lnZ_at_step", c_double)]
+                ("lnZ_at_step", c_double), ("side", c_int), ("trunc_weight_left", c_double),
+                ("trunc_weight_right", c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -49,6 +49,8 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE((o.alloc_fn == nullptr) == (o.free_fn == nullptr), DTRG_EINVAL,
                  "alloc_fn and free_fn must both be set or both be NULL");
     DTRG_REQUIRE(o.chain_phys >= 0 && o.chain_phys <= 16, DTRG_EINVAL, "chain_phys out of range [0, 16]");
+    DTRG_REQUIRE(o.side_rule == 0 || o.side_rule == 1, DTRG_EINVAL, "side_rule must be 0 or 1");
+    DTRG_REQUIRE(o.side_rule == 0 || o.chain_phys == 0, DTRG_EINVAL, "the side rule is for scheme (a) (chain_phys 0)");
 }
 
 void validate_sizes(int D, int chi, int n_steps) {
@@ -120,12 +122,16 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->min_kept_gap = st.sh.K > 1 ? gmin : 0.0;
     info->mixed = st.sh.mixed ? 1 : 0;
     info->lnZ_at_step = P->chain() ? sc[10] : NAN;
+    info->side = st.side;
+    info->trunc_weight_left = st.tw_left;
+    info->trunc_weight_right = st.tw_right;
     if (st.fixed) {   // a given isometry: no Gram, no spectrum
         info->full_eig = 0;
         info->iters = -1;
         info->trace_G = info->lam_last_kept = info->lam_first_dropped = info->resid = 0.0;
         info->trunc_weight = info->cut_gap = info->min_kept_gap = 0.0;
         info->cheb_degree = 0;
+        info->trunc_weight_left = info->trunc_weight_right = NAN;
     }
 }
 
@@ -362,6 +368,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->free_fn = nullptr;
     o->alloc_user = nullptr;
     o->chain_phys = 0;
+    o->side_rule = 0;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {
@@ -600,6 +607,7 @@ dtrg_status dtrg_batch_create(int n_inst, int D, const int* chi_host, int n_step
         Bt->n_inst = n_inst; Bt->D = D; Bt->nsteps = n_steps;
         if (opt) validate_options(*opt);
         DTRG_REQUIRE(!opt || opt->chain_phys == 0, DTRG_EINVAL, "batches run scheme (a) only (chain_phys must be 0)");
+        DTRG_REQUIRE(!opt || opt->side_rule == 0, DTRG_EINVAL, "batches take the left unfolding only (side_rule must be 0)");
         Bt->alloc = allocator_of(opt, nullptr);
         AllocScope scope(&Bt->alloc);
         std::map<int, size_t> group_of;

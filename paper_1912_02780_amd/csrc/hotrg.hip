@@ -223,12 +223,17 @@ void gram(Ctx& c, const DevBuf<double>& A, const DevBuf<double>& B, DevBuf<doubl
 
 // Gram of step input T (checkpoint), normalised: TA, TB, A, B, then G in Gw with its trace in
 // sc(k, 2).  Shared by the forward pass and the backward recompute.
-// TA and TB, the two layouts of the step input that the half-environments contract
-void step_operands_TA_TB(Ctx& c, const StepCk& st) {
+// TA and TB, the two layouts of the step input that the half-environments contract:
+// TA[(a,j)][(x,y)] = T[a][x][y][j] and TB[(a,j)][(x,y)] = T[a][x][j][y] for the left unfolding;
+// the right unfolding (right = true) is the left one of the mirrored input T[x'][x][y][y'], so
+// TA[(a,j)][(x,y)] = T[x][a][y][j] and TB[(a,j)][(x,y)] = T[x][a][j][y]
+void step_operands_TA_TB(Ctx& c, const StepCk& st, bool right) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y;
-    permute_checked(P, st.T, P->TA.p, P->TA.bs, pd4(X, X, Y, Y, 0, 3, 1, 2), 1.0, nullptr, c.s);
-    permute_checked(P, st.T, P->TB.p, P->TB.bs, pd4(X, X, Y, Y, 0, 2, 1, 3), 1.0, nullptr, c.s);
+    permute_checked(P, st.T, P->TA.p, P->TA.bs, right ? pd4(X, X, Y, Y, 1, 3, 0, 2) : pd4(X, X, Y, Y, 0, 3, 1, 2),
+                    1.0, nullptr, c.s);
+    permute_checked(P, st.T, P->TB.p, P->TB.bs, right ? pd4(X, X, Y, Y, 1, 2, 0, 3) : pd4(X, X, Y, Y, 0, 2, 1, 3),
+                    1.0, nullptr, c.s);
 }
 
 // copy A, B and the normalised Gram of a step into its kept buffers (save) or back (!save)
@@ -245,10 +250,10 @@ void keep_gram(Ctx& c, const StepCk& st, bool save) {
     }
 }
 
-void gram_of_step(Ctx& c, const StepCk& st, int k) {
+void gram_of_step(Ctx& c, const StepCk& st, int k, bool right) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y, n = st.sh.n;
-    step_operands_TA_TB(c, st);
+    step_operands_TA_TB(c, st, right);
     half_env(c, P->TA, P->A, X, Y);
     half_env(c, P->TB, P->B, X, Y);
     gram(c, P->A, P->B, P->Gw, X, Y);
@@ -566,6 +571,51 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     copy2d(P->th.p, b, P->th.bs, st.lam.p, b, st.lam.bs, 1, b, nb, c.s);
 }
 
+// Truncated weight 1 - sum of the kept eigenvalues of a step's normalised Gram, from st.lam
+// (single-instance plans; synchronises the stream).
+double host_trunc_weight(Ctx& c, const StepCk& st) {
+    std::vector<double> lam(st.sh.K);
+    DTRG_HIP(hipMemcpyAsync(lam.data(), st.lam.p, lam.size() * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    DTRG_HIP(hipStreamSynchronize(c.s));
+    double kept = 0.0;
+    for (double v : lam) kept += v;
+    return st.sh.K < st.sh.n ? 1.0 - kept : 0.0;
+}
+
+// The side rule (SM B: the local HOSVD of the pair on either of its unfoldings).  Both the right
+// and the left unfolding's Grams are eigensolved; the isometry comes from the one whose discarded
+// eigenvalues weigh less, the right one only when lighter by more than kSideMargin.  The right
+// unfolding runs first and its eigenpairs and scalars are set aside, so that the usual outcome (the
+// left one, always for mirror-symmetric inputs) needs no copies back.
+void eigensolve_sides(Ctx& c, StepCk& st, int k, const StepCk* warm) {
+    dtrg_plan* P = c.P;
+    const int n = st.sh.n, b = st.sh.b, nb = P->nb;
+    DTRG_REQUIRE(nb == 1 && c.adaptive(), DTRG_EINVAL, "the side rule runs on single-instance plans");
+    const std::string where = "step " + std::to_string(k) + ": Gram trace";
+    gram_of_step(c, st, k, true);
+    check_flags(P, kFlagNonPos | kFlagNonFinite, where + " (right unfolding)");
+    eigensolve(c, st, k, warm);
+    const int iters_right = st.iters;
+    st.tw_right = host_trunc_weight(c, st);
+    copy2d(st.U.p, b, st.U.bs, P->side_U.p, b, P->side_U.bs, n, b, nb, c.s);
+    copy2d(st.lam.p, b, st.lam.bs, P->side_lam.p, b, P->side_lam.bs, 1, b, nb, c.s);
+    const int slots[3] = {2, 3, 8};
+    for (int i = 0; i < 3; ++i) copy2d(P->sc(k, slots[i]), 1, P->S, P->sp(9 + i), 1, P->S, 1, 1, nb, c.s);
+    gram_of_step(c, st, k, false);
+    check_flags(P, kFlagNonPos | kFlagNonFinite, where);
+    eigensolve(c, st, k, warm);
+    st.tw_left = host_trunc_weight(c, st);
+    st.side = st.tw_right < st.tw_left - kSideMargin ? 1 : 0;
+    if (st.side == 1) {
+        copy2d(P->side_U.p, b, P->side_U.bs, st.U.p, b, st.U.bs, n, b, nb, c.s);
+        copy2d(P->side_lam.p, b, P->side_lam.bs, st.lam.p, b, st.lam.bs, 1, b, nb, c.s);
+        for (int i = 0; i < 3; ++i) copy2d(P->sp(9 + i), 1, P->S, P->sc(k, slots[i]), 1, P->S, 1, 1, nb, c.s);
+        st.iters = iters_right;
+        if (st.keep_gram) gram_of_step(c, st, k, true);
+    }
+    if (st.keep_gram) keep_gram(c, st, true);
+}
+
 // Scheme (b): close the chain after step k.  E = transfer matrix of T'_k / c_k (Tn, [K][K][Y][Y]) in
 // Gw; its powers E^(2^j), each rescaled by its largest entry, alternate between Gt and Sm (FP64 MFMA
 // products); the dominant eigenvalue goes to sc(k, 11) and [r | l] to chain_lr, and ln Z per cell per
@@ -712,6 +762,10 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     }
     P->Gw.alloc_inst(nb, n2); P->Gt.alloc_inst(nb, n2);
     for (DevBuf<double>* b : {&P->V1, &P->V2, &P->Y1, &P->Y2}) b->alloc_inst(nb, nbk);
+    if (P->side_rule()) {
+        P->side_U.alloc_inst(nb, nbk);
+        P->side_lam.alloc_inst(nb, bmax);
+    }
     for (DevBuf<double>* b : {&P->H, &P->Z, &P->Rinv, &P->Sg}) b->alloc_inst(nb, bmax * bmax);
     for (DevBuf<double>* b : {&P->th, &P->res, &P->nrm}) b->alloc_inst(nb, bmax);
     // eigen-adjoint: every n x K block shares one instance stride (the Chebyshev step reads
@@ -1012,14 +1066,18 @@ void plan_forward(dtrg_plan* P, Mode mode) {
                             P->sc(k - 1, 1), c.s);
         }
         if (!st.fixed) {
-            gram_of_step(c, st, k);
-            if (st.keep_gram) keep_gram(c, st, true);
-            if (c.adaptive())
-                check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
             // warm start from the previous step in the same direction
             const int kw = P->chain() ? k - 1 : k - 2;
             const StepCk* warm = (kw >= 1 && !P->steps[kw - 1].fixed) ? &P->steps[kw - 1] : nullptr;
-            eigensolve(c, st, k, warm);
+            if (P->side_rule()) {
+                eigensolve_sides(c, st, k, warm);
+            } else {
+                gram_of_step(c, st, k, false);
+                if (st.keep_gram) keep_gram(c, st, true);
+                if (c.adaptive())
+                    check_flags(P, kFlagNonPos | kFlagNonFinite, "step " + std::to_string(k) + ": Gram trace");
+                eigensolve(c, st, k, warm);
+            }
         }
         // projection (in the step's contraction format; the output T' is FP64)
         const OpSet& o = P->ops[st.sh.mixed ? 1 : 0];
@@ -1180,11 +1238,12 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             continue;
         }
         // the step's half-environments and normalised Gram: kept, or recomputed from its checkpoint
+        const bool right = st.side == 1;
         if (st.keep_gram) {
-            step_operands_TA_TB(c, st);
+            step_operands_TA_TB(c, st, right);
             keep_gram(c, st, false);
         } else {
-            gram_of_step(c, st, k);
+            gram_of_step(c, st, k, right);
         }
         // eigensolver adjoint -> G_bar, in Gt[(a,b)][(c,d)]
         eig_adjoint(c, st, k);
@@ -1208,23 +1267,25 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             set_bs(g, P->Gt.bs, P->A.bs, Bbar.bs);
             c.gemm(g);
         }
-        // Tbar[a][x][y][j] += 2 sum_{(b,k)} Abar'[(a,j)][(b,k)] TA[(b,k)][(x,y)]
+        // Tbar[a][x][y][j] += 2 sum_{(b,k)} Abar'[(a,j)][(b,k)] TA[(b,k)][(x,y)]   (the right
+        // unfolding's tensor is the mirrored input: its gradient lands on Tbar[x][a][y][j])
+        const i64 s1 = (i64)X * Y * Y, s0 = (i64)Y * Y;
         {
             GemmOp g;
             g.M = X * Y; g.N = X * Y; g.K = X * Y;
             g.A = Abar.p; g.lda = X * Y;
             g.B = P->TA.p; g.ldb = X * Y; g.b_kmajor = true;
             g.C = P->Tbar2.p;
-            g.rmap = IdxMap::split(Y, (i64)X * Y * Y, 1);
-            g.cmap = IdxMap::split(Y, (i64)Y * Y, Y);
+            g.rmap = IdxMap::split(Y, right ? s0 : s1, 1);
+            g.cmap = IdxMap::split(Y, right ? s1 : s0, Y);
             g.alpha = 2.0; g.beta = 1.0;
             set_bs(g, Abar.bs, P->TA.bs, P->Tbar2.bs);
             c.gemm(g);
-            // Tbar[a][x][j][y] += 2 sum_{(b,k)} Bbar'[(a,j)][(b,k)] TB[(b,k)][(x,y)]
+            // Tbar[a][x][j][y] += 2 sum_{(b,k)} Bbar'[(a,j)][(b,k)] TB[(b,k)][(x,y)]   (right: Tbar[x][a][j][y])
             g.A = Bbar.p;
             g.B = P->TB.p;
-            g.rmap = IdxMap::split(Y, (i64)X * Y * Y, Y);
-            g.cmap = IdxMap::split(Y, (i64)Y * Y, 1);
+            g.rmap = IdxMap::split(Y, right ? s0 : s1, Y);
+            g.cmap = IdxMap::split(Y, right ? s1 : s0, 1);
             set_bs(g, Bbar.bs, P->TB.bs, P->Tbar2.bs);
             c.gemm(g);
         }

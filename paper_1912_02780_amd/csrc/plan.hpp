@@ -39,8 +39,12 @@ constexpr int kFlagErrorMask =
 constexpr double kPolarTieBreak = 1e-6;
 // scheme (b): shift of the trace-normalised Gram in the subspace iteration's block update
 constexpr double kChainGramShift = 0x1p-45;
+// side rule: the right unfolding wins only when its truncated weight is below the left one's by
+// more than this (absolute, on the trace-normalised spectrum): ties decided by rounding go left
+constexpr double kSideMargin = 1e-12;
 constexpr int kScPlan = 16;   // 0 L (ln Z / N), 4 final trace (scheme (b): the final transfer matrix's
-                              // dominant eigenvalue), 5 <T0bar, dT0>, 6 c0, 7 1/c0
+                              // dominant eigenvalue), 5 <T0bar, dT0>, 6 c0, 7 1/c0, 8 polar tie-break
+                              // norm; 9-11 the side rule's copy of a step's slots 2, 3 and 8
 constexpr int kScStep = 12;   // per step: 0 c_k, 1 1/c_k, 2 trace of the Gram, 3 residual of the first
                               // unresolved Ritz pair, 4 lo, 5 hi (complement interval), 6 |v_0|,
                               // 7 |v_m|, 8 largest resolved residual, 9 coefficient tail ratio;
@@ -103,6 +107,10 @@ struct StepCk {
     // backward stops at the projection adjoint and leaves d(gbar lnZ/N)/dw in wbar [n][K]
     bool fixed = false;
     DevBuf<double> wbar;
+    // side rule: the unfolding the isometry came from (0: left legs (x1, x2), 1: right legs
+    // (x1', x2')) and the truncated weights of both (NaN unless the rule ran on this step)
+    int side = 0;
+    double tw_left = NAN, tw_right = NAN;
 };
 
 }  // namespace dtrg
@@ -147,6 +155,8 @@ struct dtrg_plan {
     dtrg::DevBuf<double> tune_c;  // autotuner output scratch
     dtrg::DevBuf<double> polS, polV, pollam;   // polar factor of an isometry gradient (2K x 2K, 2K)
     dtrg::DevBuf<double> chain_lr;             // scheme (b): right and left dominant eigenvectors [r | l]
+    dtrg::DevBuf<double> side_U, side_lam;     // side rule: the other unfolding's eigenvectors and values
+    bool side_rule() const { return opt.side_rule != 0; }
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)
     int tuned_seen = -1;          // size of the process table when the file was last written

@@ -119,6 +119,7 @@ def test_default_options():
     assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1 and o.checkpoint_gib == 64.0
     assert o.oversample == 0 and o.max_fp32_chain == 4096 and o.max_fp32_chain_wide == 4096
     assert o.tile_table is None and o.alloc_fn is None and o.free_fn is None
+    assert o.chain_phys == 0 and o.side_rule == 0
     # a checkpoint budget that is negative or not finite is rejected before any allocation
     lib.dtrg_plan_create.restype = ctypes.c_int
     lib.dtrg_last_error.restype = ctypes.c_char_p
@@ -127,6 +128,28 @@ def test_default_options():
         o.checkpoint_gib = bad
         assert lib.dtrg_plan_create(2, 4, 3, ctypes.byref(o), ctypes.byref(plan)) == 1 and plan.value is None
         assert b"checkpoint_gib" in lib.dtrg_last_error()
+
+
+def test_side_rule_validation_without_device_work():
+    lib = _lib()
+    lib.dtrg_plan_create.restype = ctypes.c_int
+    lib.dtrg_batch_create.restype = ctypes.c_int
+    lib.dtrg_last_error.restype = ctypes.c_char_p
+    Options = _struct("dtrg_options")
+    plan = ctypes.c_void_p()
+    for rule, phys, msg in ((2, 0, b"side_rule"), (-1, 0, b"side_rule"), (1, 2, b"scheme (a)")):
+        o = Options()
+        lib.dtrg_default_options(ctypes.byref(o))
+        o.side_rule, o.chain_phys = rule, phys
+        assert lib.dtrg_plan_create(2, 4, 3, ctypes.byref(o), ctypes.byref(plan)) == 1 and plan.value is None
+        assert msg in lib.dtrg_last_error()
+    o = Options()
+    lib.dtrg_default_options(ctypes.byref(o))
+    o.side_rule = 1
+    b = ctypes.c_void_p()
+    chis = (ctypes.c_int * 2)(8, 8)
+    assert lib.dtrg_batch_create(2, 2, chis, 4, ctypes.byref(o), ctypes.byref(b)) == 1
+    assert b"side_rule" in lib.dtrg_last_error() and b.value is None
 
 
 def test_batch_argument_validation_without_device_work():
