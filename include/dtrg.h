@@ -88,7 +88,11 @@ typedef struct {
                                  residual stops decreasing above it, the step is accepted when the
                                  residual is below 1e-12 and fails with DTRG_ENOCONV otherwise. */
     int block_size;           /* subspace block b (> chi', <= 96); 0 = automatic (min(96, max(chi' + 16,
-                                 2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates */
+                                 2 chi'))).  DTRG_EINVAL if b <= chi' on a step that iterates.
+                                 Scheme (b): a block_size of at most chi' + 8 selects the block-locked
+                                 eigensolve with blocks of that width (which is automatic, with 96
+                                 columns, for chi' > 80); each block resolves all but max(8, b/4)
+                                 of its columns */
     int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
                                  (64 x 64, 128 x 128, and for the bf16-plane precisions 256 x 128,
                                  64 x 64 on full-width waves for outputs of at most 64 columns and
@@ -198,7 +202,10 @@ void dtrg_default_options(dtrg_options* opt);
  *   T0_dev        device, D^4 doubles, [l][u][r][d] (with opt->chain_phys = d > 0: one MPO cell,
  *                 D x d x D x d doubles); read only; all entries finite, not all 0.
  *   D             bond dimension of T0, 1 <= D <= 64.
- *   chi           truncation bond dimension, 1 <= chi <= 80.
+ *   chi           truncation bond dimension, 1 <= chi <= 80 (scheme (b), opt->chain_phys > 0:
+ *                 1 <= chi <= 255; chi' beyond one 96-column Rayleigh-Ritz block is found by the
+ *                 block-locked eigensolve, blocks of 96 or of opt->block_size columns, each deflated
+ *                 against the eigenvectors resolved before it).
  *   n_steps       number of single-direction HOTRG steps, 1 <= n_steps <= 62.
  *   opt           options or NULL for the defaults.
  *   stream        hipStream_t or NULL.

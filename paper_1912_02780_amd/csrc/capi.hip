@@ -53,9 +53,13 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE(o.side_rule == 0 || o.chain_phys == 0, DTRG_EINVAL, "the side rule is for scheme (a) (chain_phys 0)");
 }
 
-void validate_sizes(int D, int chi, int n_steps) {
+void validate_sizes(int D, int chi, int n_steps, bool chain = false) {
     DTRG_REQUIRE(D >= 1 && D <= 64, DTRG_EINVAL, "D out of range [1, 64]");
-    DTRG_REQUIRE(chi >= 1 && chi <= 80, DTRG_EINVAL, "chi out of range [1, 80]");
+    if (chain)
+        DTRG_REQUIRE(chi >= 1 && chi <= kChainMaxChi, DTRG_EINVAL,
+                     "chi out of range [1, " + std::to_string(kChainMaxChi) + "] for scheme (b)");
+    else
+        DTRG_REQUIRE(chi >= 1 && chi <= 80, DTRG_EINVAL, "chi out of range [1, 80]");
     DTRG_REQUIRE(n_steps >= 1 && n_steps <= 62, DTRG_EINVAL, "n_steps out of range [1, 62]");
 }
 
@@ -74,7 +78,7 @@ Allocator allocator_of(const dtrg_options* opt, hipStream_t s) {
 // stream handed to the caller's allocator
 std::unique_ptr<dtrg_plan> make_plan(int D, int chi, int n_steps, int nb, const dtrg_options* opt,
                                      double share = 1.0, hipStream_t s = nullptr) {
-    validate_sizes(D, chi, n_steps);
+    validate_sizes(D, chi, n_steps, opt && opt->chain_phys > 0);
     std::unique_ptr<dtrg_plan> P(new dtrg_plan());
     dtrg_default_options(&P->opt);
     if (opt) P->opt = *opt;

@@ -289,6 +289,8 @@ void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_
 // chain.hip (scheme (b): closing the infinite chain of cells)
 // largest transfer matrix the closing kernel takes, its residual bound, and the squarings of E
 constexpr int kChainMaxK = 2048;
+// largest chi of a scheme (b) plan (the Gram of the doubled bond is chi^2 x chi^2 doubles)
+constexpr int kChainMaxChi = 255;
 constexpr double kChainResidual = 1e-8;
 constexpr int kChainSquarings = 24;
 // E[l][r] = scale * sum_u T[l][r][u][u] for T [K][K][Y][Y] (scale from scale_dev[i * sc_bs], or 1)

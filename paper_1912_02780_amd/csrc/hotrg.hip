@@ -34,7 +34,7 @@ void for_each_buf(const dtrg_plan& P, F f) {
                                  &P.Xe, &P.Xc, &P.Re, &P.Om, &P.Sm, &P.Vc, &P.Vp, &P.Vn, &P.Ye, &P.We, &P.V1, &P.V2,
                                  &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
                                  &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red,
-                                 &P.polS, &P.polV, &P.pollam, &P.chain_lr};
+                                 &P.polS, &P.polV, &P.pollam, &P.chain_lr, &P.side_U, &P.side_lam, &P.lockW};
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
@@ -472,6 +472,128 @@ void gemm_GV(Ctx& c, const DevBuf<double>& G, const double* V, double* C, i64 vb
     c.gemm(g);
 }
 
+// V -= U_L (U_L^T V) with U_L the first `cols` columns of U (n rows, ld ldu) and V n x w (ld w),
+// twice, so that V leaves the locked vectors' span to working accuracy whatever its start
+void deflate(Ctx& c, const double* U, int ldu, i64 ubs, int cols, double* V, int w, i64 vbs, int n) {
+    if (cols == 0) return;
+    dtrg_plan* P = c.P;
+    for (int pass = 0; pass < 2; ++pass) {
+        GemmOp g;   // W = U_L^T V  (cols x w, in lockW)
+        g.M = cols; g.N = w; g.K = n;
+        g.A = U; g.lda = ldu; g.a_kmajor = true;
+        g.B = V; g.ldb = w; g.b_kmajor = true;
+        g.C = P->lockW.p; g.rmap = IdxMap::linear(w); g.cmap = IdxMap::linear(1);
+        set_bs(g, ubs, vbs, P->lockW.bs);
+        c.gemm(g);
+        GemmOp h;   // V -= U_L W
+        h.M = n; h.N = w; h.K = cols;
+        h.A = U; h.lda = ldu;
+        h.B = P->lockW.p; h.ldb = w; h.b_kmajor = true;
+        h.C = V; h.rmap = IdxMap::linear(w); h.cmap = IdxMap::linear(1);
+        h.alpha = -1.0; h.beta = 1.0;
+        set_bs(h, ubs, P->lockW.bs, vbs);
+        c.gemm(h);
+    }
+}
+
+// Truncated eigensolve for chi' beyond one Rayleigh-Ritz block (scheme (b) at large bond
+// dimension): the leading eigenpairs are found lock_n blocks at a time by the block subspace
+// iteration of eigensolve, each block of lock_bw columns deflated against the eigenvectors that the
+// blocks before it resolved (they are eigenvectors of the Gram, so the deflated Gram has the
+// remaining spectrum).  Each block resolves lock_r pairs to the tolerance; the last block's guard
+// columns complete U, its first unresolved pair bounds the complement of the eigen-adjoint.
+// Adaptive passes only (scheme (b) plans are not batched).
+void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
+    dtrg_plan* P = c.P;
+    const StepShape& s = st.sh;
+    const int n = s.n, bw = s.lock_bw, er = s.lock_r, nblk = s.lock_n, b = s.b, nb = P->nb;
+    DTRG_REQUIRE(c.adaptive(), DTRG_EINVAL, "the block-locked eigensolve runs in adaptive passes only");
+    const i64 vbs = P->V1.bs, ubs = st.U.bs;
+    const uint64_t seed = 0x5eedULL * (uint64_t)k + 17ULL;
+    const bool warm_used = warm && warm->sh.n == n && warm->sh.b == b && warm->sh.lock_bw == bw;
+    const double tol = P->opt.subspace_tol;
+    const int it_max = P->opt.max_subspace_iters;
+    std::vector<double> resh((size_t)nb * P->res.bs);
+    int total = 0;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int c0 = blk * er;
+        const bool last = blk == nblk - 1;
+        if (warm_used)
+            copy2d(warm->U.p + c0, b, warm->U.bs, P->V1.p, bw, vbs, n, bw, nb, c.s);
+        else
+            hash_fill(P->V1.p, vbs, (i64)n * bw, nb, seed + 977ULL * (uint64_t)(blk + 1), c.s);
+        deflate(c, st.U.p, b, ubs, c0, P->V1.p, bw, vbs, n);
+        orthonormalise(c, P->V1.p, P->V2.p, vbs, n, bw);
+        double prev = INFINITY, mx = INFINITY;
+        int stall = 0, it = 0;
+        for (it = 1; it <= it_max; ++it) {
+            gemm_GV(c, P->Gw, P->V1.p, P->Y1.p, vbs, n, bw);
+            deflate(c, st.U.p, b, ubs, c0, P->Y1.p, bw, vbs, n);
+            // H = V^T Y, its eigenvectors Z, V <- V Z, Y <- Y Z, residuals of the resolved pairs
+            GemmOp g;
+            g.M = g.N = bw; g.K = n;
+            g.A = P->V1.p; g.lda = bw; g.a_kmajor = true;
+            g.B = P->Y1.p; g.ldb = bw; g.b_kmajor = true;
+            g.C = P->H.p;
+            g.rmap = IdxMap::linear(bw); g.cmap = IdxMap::linear(1);
+            set_bs(g, vbs, vbs, P->H.bs);
+            c.gemm(g);
+            jacobi_eig(P->H.p, bw, bw, P->H.bs, P->th.p, P->th.bs, P->Z.p, bw, P->Z.bs, nb, kJacobiSweeps, P->misc.p,
+                       c.s);
+            GemmOp r;
+            r.M = n; r.N = bw; r.K = bw;
+            r.B = P->Z.p; r.ldb = bw; r.b_kmajor = true;
+            r.rmap = IdxMap::linear(bw); r.cmap = IdxMap::linear(1);
+            r.A = P->V1.p; r.lda = bw; r.C = P->V2.p; set_bs(r, vbs, P->Z.bs, vbs); c.gemm(r);
+            r.A = P->Y1.p; r.lda = bw; r.C = P->Y2.p; c.gemm(r);
+            std::swap(P->V1, P->V2);
+            std::swap(P->Y1, P->Y2);
+            ritz_residuals(P->V1.p, P->Y1.p, n, er, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb, c.s);
+            DTRG_HIP(hipMemcpyAsync(resh.data(), P->res.p, resh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                    c.s));
+            DTRG_HIP(hipStreamSynchronize(c.s));
+            mx = 0.0;
+            for (int i = 0; i < nb; ++i)
+                for (int j = 0; j < er; ++j) {
+                    const double v = resh[(size_t)i * P->res.bs + j];
+                    mx = std::max(mx, std::isfinite(v) ? v : INFINITY);
+                }
+            if (mx <= tol) break;
+            if (mx > 0.5 * prev) ++stall; else stall = 0;
+            prev = mx;
+            if (stall >= 3 && mx <= kSubspaceAccept) break;      // rounding floor reached
+            if (it == it_max) break;
+            // next block: (G + s I) V with columns rescaled to unit norm (the shift of eigensolve),
+            // deflated and re-orthonormalised
+            axpy(P->V1.p, P->Y1.p, vbs, (i64)n * bw, nb, kChainGramShift, c.s);
+            col_norms(P->Y1.p, n, bw, bw, vbs, P->nrm.p, P->nrm.bs, nb, c.s);
+            col_normalise(P->Y1.p, n, bw, bw, vbs, P->nrm.p, P->nrm.bs, nb,
+                          seed + 7919ULL * it + 104729ULL * (uint64_t)blk, c.s);
+            std::swap(P->V1, P->Y1);
+            deflate(c, st.U.p, b, ubs, c0, P->V1.p, bw, vbs, n);
+            orthonormalise(c, P->V1.p, P->V2.p, vbs, n, bw);
+        }
+        total += std::min(it, it_max);
+        // lock the resolved pairs (and, for the last block, its guard) into U and lam
+        const int keep = last ? bw : er;
+        copy2d(P->V1.p, bw, vbs, st.U.p + c0, b, ubs, n, keep, nb, c.s);
+        copy2d(P->th.p, bw, P->th.bs, st.lam.p + c0, b, st.lam.bs, 1, keep, nb, c.s);
+        if (last) {
+            // residual of the first unresolved pair (it bounds the complement of the eigen-adjoint)
+            ritz_residuals(P->V1.p, P->Y1.p, n, er + 1, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb, c.s);
+            copy2d(P->res.p + er, 1, P->res.bs, P->sc(k, 3), 1, P->S, 1, 1, nb, c.s);
+        }
+        max_check(P->res.p, P->res.bs, er, nb, kSubspaceAccept, P->sc(k, 8), P->S, P->flags.p, kFlagSubspace, c.s);
+        const std::vector<int> f = read_flags(P);
+        for (int i = 0; i < nb; ++i)
+            if (f[i] & kFlagSubspace)
+                throw Error(DTRG_ENOCONV, inst_name(P, i) + "step " + std::to_string(k) + ", locked block " +
+                                              std::to_string(blk) + ": truncated eigensolve residual " +
+                                              std::to_string(mx) + " after " + std::to_string(it) + " iterations");
+    }
+    st.iters = total;
+}
+
 void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     dtrg_plan* P = c.P;
     const int n = st.sh.n, b = st.sh.b, E = st.sh.e, nb = P->nb;
@@ -482,6 +604,10 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
         jacobi_eig(P->Gw.p, n, n, P->Gw.bs, st.lam.p, st.lam.bs, st.U.p, n, st.U.bs, nb, kJacobiSweeps, P->misc.p,
                    c.s, P->flags.p, kFlagJacobi);
         st.iters = 0;
+        return;
+    }
+    if (st.sh.lock_n) {
+        eigensolve_locked(c, st, k, warm);
         return;
     }
     // block subspace iteration with Rayleigh-Ritz on the normalised Gram
@@ -662,7 +788,21 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversam
         s.X = X; s.Y = Y; s.n = X * X;
         s.K = std::min(chi, s.n);
         if (s.n <= kJacobiMax) { s.full = true; s.b = s.n; s.e = s.n; }
-        else {
+        else if (phys > 0 && (s.K + 16 > kJacobiMax || (block > 0 && block <= s.K + 8))) {
+            // scheme (b) beyond one Rayleigh-Ritz block: the eigenpairs are found lock_n blocks at a
+            // time, each block deflated against the ones before (block_size, when set, is the
+            // block width)
+            DTRG_REQUIRE(s.K < s.n, DTRG_EINVAL,
+                         "an untruncated step wider than " + std::to_string(kJacobiMax) + " (chi' = X^2)");
+            s.lock_bw = block > 0 ? std::min(block, kJacobiMax) : kJacobiMax;
+            const int guard = std::max(8, s.lock_bw / 4);   // each block converges at lam_bw / lam_r
+            s.lock_r = s.lock_bw - guard;
+            DTRG_REQUIRE(s.lock_r >= 8, DTRG_EINVAL, "block size too small for the locked eigensolve");
+            s.lock_n = (s.K + 8 + s.lock_r - 1) / s.lock_r;   // at least 8 resolved pairs beyond the cut
+            s.e = s.lock_n * s.lock_r;
+            s.b = s.e + guard;
+            DTRG_REQUIRE(s.b < s.n, DTRG_EINVAL, "chi' too close to X^2 for the locked eigensolve");
+        } else {
             int b = block > 0 ? block : (oversample > 0 ? s.K + oversample : std::max(s.K + 16, 2 * s.K));
             b = std::min(b, kJacobiMax);
             b = std::min(b, s.n - 1);
@@ -726,15 +866,16 @@ void alloc_kept(dtrg_plan* P) {
 void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
     const i64 D4 = P->t0_elems();
-    i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1;
+    i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1, lockw = 1;
     i64 osz[2][12] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
     bool used[2] = {false, false};
     for (auto& s : sh) {
         const i64 a4 = std::max<i64>((i64)s.X * s.X * s.Y * s.Y, (i64)s.K * s.K * s.Y * s.Y);
         t4 = std::max(t4, a4);
         n2 = std::max<i64>(n2, (i64)s.n * s.n);
-        nbk = std::max<i64>(nbk, (i64)s.n * s.b);
-        bmax = std::max<i64>(bmax, s.b);
+        nbk = std::max<i64>(nbk, (i64)s.n * s.rr());
+        bmax = std::max<i64>(bmax, s.rr());
+        lockw = std::max<i64>(lockw, s.lock_n ? (i64)s.b * s.lock_bw : 1);
         nK = std::max<i64>(nK, (i64)s.n * s.K);
         bK = std::max<i64>(bK, (i64)s.b * s.K);
         KK = std::max<i64>(KK, (i64)s.K * s.K);
@@ -766,6 +907,7 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         P->side_U.alloc_inst(nb, nbk);
         P->side_lam.alloc_inst(nb, bmax);
     }
+    if (lockw > 1) P->lockW.alloc_inst(nb, lockw);
     for (DevBuf<double>* b : {&P->H, &P->Z, &P->Rinv, &P->Sg}) b->alloc_inst(nb, bmax * bmax);
     for (DevBuf<double>* b : {&P->th, &P->res, &P->nrm}) b->alloc_inst(nb, bmax);
     // eigen-adjoint: every n x K block shares one instance stride (the Chebyshev step reads

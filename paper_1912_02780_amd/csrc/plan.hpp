@@ -57,6 +57,11 @@ struct StepShape {
                         // discarded ones nearest the cut (the rest of the block is a guard)
     bool full = false;
     bool mixed = false; // projection contractions of this step in the mixed precision
+    // block-locked eigensolve (scheme (b) with chi' beyond one Rayleigh-Ritz block): lock_n blocks
+    // of lock_bw columns, each resolving lock_r eigenpairs; then e = lock_n * lock_r and the last
+    // block's lock_bw - lock_r guard columns complete U (b = e + guard)
+    int lock_bw = 0, lock_r = 0, lock_n = 0;
+    int rr() const { return lock_n ? lock_bw : b; }   // width of the Rayleigh-Ritz problems
     double join_flops() const { return 2.0 * K * Y * X * (double)(Y * X) * (X * Y); }
 };
 
@@ -156,6 +161,7 @@ struct dtrg_plan {
     dtrg::DevBuf<double> polS, polV, pollam;   // polar factor of an isometry gradient (2K x 2K, 2K)
     dtrg::DevBuf<double> chain_lr;             // scheme (b): right and left dominant eigenvectors [r | l]
     dtrg::DevBuf<double> side_U, side_lam;     // side rule: the other unfolding's eigenvectors and values
+    dtrg::DevBuf<double> lockW;                // block-locked eigensolve: projections on the locked vectors
     bool side_rule() const { return opt.side_rule != 0; }
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)
