@@ -567,6 +567,43 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     }
 
 
+def chain_sweep(args, B, I, torch, dev, X, n, tau):
+    """Scheme (b) forward + backward time against the bond dimension D (the paper's Fig. 3(b) measures
+    its wall time at beta = 12.8 against D): one warm-up and args.steps timed passes per D, with the
+    free-energy error at beta = 12.8, the subspace iterations and the complement expansion degrees."""
+    Mh = I.xy_trotter_mpo(tau)
+    M = torch.from_numpy(Mh).to(dev)
+    rows = []
+    for D in [int(v) for v in args.chain_sweep.split(",")]:
+        _progress(f"xy chain sweep: D = {D}")
+        # at beta = 12.8 the gapless chain's Gram spectrum is flat near the cut (lam_96 / lam_80 = 0.76 at
+        # D = 64), so the subspace iteration needs more than the default 60 products
+        plan = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n,
+                                        B.default_options(contract=args.contract, max_subspace_iters=400), dev)
+        L = B.dtrg_plan_forward(plan, M)
+        B.dtrg_hotrg_backward(plan, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L = B.dtrg_plan_forward(plan, M)
+            B.dtrg_hotrg_backward(plan, 1.0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        info = [plan.step_info(k) for k in range(1, n + 1)]
+        err = abs(math.ldexp(L, n) / 2.0 / X.lnZ_per_spin_infinite(math.ldexp(tau, n)) - 1.0)
+        rows.append({"D": D, "ms_per_pass": ms, "f_rel_err_beta_12.8": err,
+                     "max_subspace_iters": max(i["iters"] for i in info),
+                     "max_cheb_degree": max(i["cheb_degree"] for i in info),
+                     "plan_device_GB": plan.device_bytes() / 1e9})
+        _progress(f"    {ms:.1f} ms per pass, f err {err:.2e}")
+        plan.close()
+    for r in rows:
+        r["exponent_to_next"] = None
+    for r0, r1 in zip(rows, rows[1:]):
+        r0["exponent_to_next"] = math.log(r1["ms_per_pass"] / r0["ms_per_pass"]) / math.log(r1["D"] / r0["D"])
+    return rows
+
+
 def bench_xy_chain(args, B, I, torch, np, dev):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import exact_xy as X
@@ -620,6 +657,8 @@ def bench_xy_chain(args, B, I, torch, np, dev):
                  "f_rel_err_plain": f_err(L0, n), "f_rel_err_optimised": f_err(L1, n)},
         "roofline": roofline(launches, ms, flops, args.contract, "join contraction (gemm kernel, tag 7)"),
     }
+    if args.chain_sweep:
+        out["scaling_vs_D"] = chain_sweep(args, B, I, torch, dev, X, n, tau)
     if not args.no_cpu_baseline and not compact:
         from oracle import xtrg as C
         _progress("xy chain: the oracle on the host")
@@ -643,6 +682,8 @@ def main():
     # (ln Z / N <= 1e-6, gradient <= 1e-5)
     ap.add_argument("--contract", default=None, choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--chi", type=int, default=None, help="chi48: 48 by default; ising_chi64: 64")
+    ap.add_argument("--chain-sweep", default="",
+                    help="xy_chain: comma-separated bond dimensions D to time forward + backward at (e.g. 32,64,128)")
     ap.add_argument("--n-steps", type=int, default=None, help="chi48: 24 by default; ising_chi64: 30")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],

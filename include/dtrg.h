@@ -92,7 +92,8 @@ typedef struct {
                                  Scheme (b): a block_size of at most chi' + 8 selects the block-locked
                                  eigensolve with blocks of that width (which is automatic, with 96
                                  columns, for chi' > 80); each block resolves all but max(8, b/4)
-                                 of its columns */
+                                 of its columns, and together they resolve max(8, chi'/2) pairs
+                                 beyond the cut where X^2 leaves room (at least 8) */
     int autotune;             /* 1: the first time a contraction shape is met, time every tile shape
                                  (64 x 64, 128 x 128, and for the bf16-plane precisions 256 x 128,
                                  64 x 64 on full-width waves for outputs of at most 64 columns and

@@ -518,6 +518,7 @@ void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     for (int blk = 0; blk < nblk; ++blk) {
         const int c0 = blk * er;
         const bool last = blk == nblk - 1;
+        const int res_n = last ? s.e - c0 : er;   // pairs this block resolves
         if (warm_used)
             copy2d(warm->U.p + c0, b, warm->U.bs, P->V1.p, bw, vbs, n, bw, nb, c.s);
         else
@@ -548,13 +549,13 @@ void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
             r.A = P->Y1.p; r.lda = bw; r.C = P->Y2.p; c.gemm(r);
             std::swap(P->V1, P->V2);
             std::swap(P->Y1, P->Y2);
-            ritz_residuals(P->V1.p, P->Y1.p, n, er, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb, c.s);
+            ritz_residuals(P->V1.p, P->Y1.p, n, res_n, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb, c.s);
             DTRG_HIP(hipMemcpyAsync(resh.data(), P->res.p, resh.size() * sizeof(double), hipMemcpyDeviceToHost,
                                     c.s));
             DTRG_HIP(hipStreamSynchronize(c.s));
             mx = 0.0;
             for (int i = 0; i < nb; ++i)
-                for (int j = 0; j < er; ++j) {
+                for (int j = 0; j < res_n; ++j) {
                     const double v = resh[(size_t)i * P->res.bs + j];
                     mx = std::max(mx, std::isfinite(v) ? v : INFINITY);
                 }
@@ -580,10 +581,12 @@ void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
         copy2d(P->th.p, bw, P->th.bs, st.lam.p + c0, b, st.lam.bs, 1, keep, nb, c.s);
         if (last) {
             // residual of the first unresolved pair (it bounds the complement of the eigen-adjoint)
-            ritz_residuals(P->V1.p, P->Y1.p, n, er + 1, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb, c.s);
-            copy2d(P->res.p + er, 1, P->res.bs, P->sc(k, 3), 1, P->S, 1, 1, nb, c.s);
+            ritz_residuals(P->V1.p, P->Y1.p, n, res_n + 1, bw, vbs, P->th.p, P->th.bs, P->res.p, P->res.bs, nb,
+                           c.s);
+            copy2d(P->res.p + res_n, 1, P->res.bs, P->sc(k, 3), 1, P->S, 1, 1, nb, c.s);
         }
-        max_check(P->res.p, P->res.bs, er, nb, kSubspaceAccept, P->sc(k, 8), P->S, P->flags.p, kFlagSubspace, c.s);
+        max_check(P->res.p, P->res.bs, res_n, nb, kSubspaceAccept, P->sc(k, 8), P->S, P->flags.p, kFlagSubspace,
+                  c.s);
         const std::vector<int> f = read_flags(P);
         for (int i = 0; i < nb; ++i)
             if (f[i] & kFlagSubspace)
@@ -795,13 +798,29 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversam
             DTRG_REQUIRE(s.K < s.n, DTRG_EINVAL,
                          "an untruncated step wider than " + std::to_string(kJacobiMax) + " (chi' = X^2)");
             s.lock_bw = block > 0 ? std::min(block, kJacobiMax) : kJacobiMax;
-            const int guard = std::max(8, s.lock_bw / 4);   // each block converges at lam_bw / lam_r
-            s.lock_r = s.lock_bw - guard;
-            DTRG_REQUIRE(s.lock_r >= 8, DTRG_EINVAL, "block size too small for the locked eigensolve");
-            s.lock_n = (s.K + 8 + s.lock_r - 1) / s.lock_r;   // at least 8 resolved pairs beyond the cut
-            s.e = s.lock_n * s.lock_r;
-            s.b = s.e + guard;
-            DTRG_REQUIRE(s.b < s.n, DTRG_EINVAL, "chi' too close to X^2 for the locked eigensolve");
+            DTRG_REQUIRE(s.lock_bw >= 16, DTRG_EINVAL, "block size too small for the locked eigensolve");
+            // Resolved pairs beyond the cut: max(8, chi'/2), so that the complement of the
+            // eigen-adjoint starts well below the kept eigenvalues (a gapless chain's spectrum is flat
+            // near the cut: with 16 beyond it the complement expansion needed degrees beyond 1024 at
+            // chi' = 128).  A block converges at the ratio lam_bw / lam_r of its width to the pairs it
+            // resolves, so each keeps a guard of max(8, bw/4) columns; the last block resolves what
+            // remains and keeps its whole width, so U has b = (lock_n - 1) lock_r + lock_bw < n
+            // columns.  Where the Gram is too small for that (chi' near X^2), the guard shrinks to
+            // 8 and the pairs beyond the cut to what fits, at least 8.
+            const int e_want = s.K + std::max(8, s.K / 2);
+            int best_e = -1;
+            for (int g = std::max(8, s.lock_bw / 4); g >= 8 && best_e < e_want; --g) {
+                const int r = s.lock_bw - g;
+                for (int m = 1;; ++m) {
+                    if ((m - 1) * r + s.lock_bw >= s.n) break;
+                    const int e = std::min(e_want, m * r);
+                    if (e > best_e) { best_e = e; s.lock_r = r; s.lock_n = m; }
+                    if (m * r >= e_want) break;
+                }
+            }
+            DTRG_REQUIRE(best_e >= s.K + 8, DTRG_EINVAL, "chi' too close to X^2 for the locked eigensolve");
+            s.e = best_e;
+            s.b = (s.lock_n - 1) * s.lock_r + s.lock_bw;
         } else {
             int b = block > 0 ? block : (oversample > 0 ? s.K + oversample : std::max(s.K + 16, 2 * s.K));
             b = std::min(b, kJacobiMax);
