@@ -47,6 +47,31 @@ __device__ T block_reduce(T v, T* sh, Op op) {
     return r;
 }
 
+// tr G for G = sum_{j,k} A_jk (x) B_jk: sum_{j,k} (sum_a A[a][a][j][k]) (sum_c B[c][c][j][k]) (one
+// workgroup per instance); a trace that is not positive or not finite sets flag bit 1
+__global__ __launch_bounds__(256) void kron_trace_kernel(const double* A, i64 a_bs, const double* B, i64 b_bs, int X,
+                                                         int Y, double* out, i64 out_bs, int* flag) {
+    __shared__ double sh[256];
+    const int z = blockIdx.x;
+    A += z * a_bs;
+    B += z * b_bs;
+    const int YY = Y * Y;
+    double s = 0.0;
+    for (int jk = threadIdx.x; jk < YY; jk += blockDim.x) {
+        double ta = 0.0, tb = 0.0;
+        for (int a = 0; a < X; ++a) {
+            ta += A[((i64)a * X + a) * YY + jk];
+            tb += B[((i64)a * X + a) * YY + jk];
+        }
+        s += ta * tb;
+    }
+    s = block_reduce(s, sh, [](double u, double v) { return u + v; });
+    if (threadIdx.x == 0) {
+        out[z * out_bs] = s;
+        if (!(s > 0.0) || !isfinite(s)) flag[z] |= 1;
+    }
+}
+
 // P /= max |P| (one workgroup per instance); a zero or non-finite P sets flag bit
 __global__ __launch_bounds__(1024) void maxabs_normalise_kernel(double* P, i64 bs, i64 n, int* flag, int bit) {
     __shared__ double sh[1024];
@@ -173,6 +198,12 @@ dim3 grid_of(i64 n, int nb) {
 }
 
 }  // namespace
+
+void kron_trace(const double* A, i64 a_bs, const double* B, i64 b_bs, int X, int Y, int nb, double* t_dev, i64 t_bs,
+                int* flag_dev, hipStream_t s) {
+    hipLaunchKernelGGL(kron_trace_kernel, dim3(nb), dim3(256), 0, s, A, a_bs, B, b_bs, X, Y, t_dev, t_bs, flag_dev);
+    DTRG_HIP(hipGetLastError());
+}
 
 void chain_transfer(const double* T, i64 tbs, int K, int Y, const double* scale_dev, i64 sc_bs, double* E, i64 ebs,
                     int nb, hipStream_t s) {

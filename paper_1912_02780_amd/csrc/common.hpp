@@ -303,6 +303,11 @@ void chain_normalise(double* P, i64 bs, i64 n, int nb, int* flag_dev, int bit, h
 // positive or either eigenvector residual exceeds kChainResidual relative
 void chain_dominant_finish(const double* E, i64 ebs, const double* P, i64 pbs, int K, int nb, double* lr, i64 lrbs,
                            double* lam_dev, i64 sc_bs, int* flag_dev, int bit, hipStream_t s);
+// trace of the Gram G = sum_{j,k} A_jk (x) B_jk of the doubled bond, from the half-environments
+// A, B ([X][X][Y][Y], instance strides a_bs, b_bs) into t_dev; flag_dev[i] |= 1 if it is not
+// positive or not finite
+void kron_trace(const double* A, i64 a_bs, const double* B, i64 b_bs, int X, int Y, int nb, double* t_dev, i64 t_bs,
+                int* flag_dev, hipStream_t s);
 // backward seed: T[y][z][a][b] = delta(y, z) gw l[a] r[b] / lambda
 void chain_seed(double* T, i64 bs, int K, int Y, const double* lr, i64 lrbs, double gw, const double* lam_dev,
                 i64 sc_bs, int nb, hipStream_t s);

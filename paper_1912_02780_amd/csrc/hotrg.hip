@@ -34,7 +34,8 @@ void for_each_buf(const dtrg_plan& P, F f) {
                                  &P.Xe, &P.Xc, &P.Re, &P.Om, &P.Sm, &P.Vc, &P.Vp, &P.Vn, &P.Ye, &P.We, &P.V1, &P.V2,
                                  &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
                                  &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red,
-                                 &P.polS, &P.polV, &P.pollam, &P.chain_lr, &P.side_U, &P.side_lam, &P.lockW};
+                                 &P.polS, &P.polV, &P.pollam, &P.chain_lr, &P.side_U, &P.side_lam, &P.lockW,
+                                 &P.kronW};
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
@@ -164,6 +165,12 @@ struct Ctx {
 };
 
 void set_bs(GemmOp& g, i64 a, i64 b, i64 c) { g.a_bs2 = a; g.b_bs2 = b; g.c_bs2 = c; }
+
+// Scheme (b) steps that iterate keep their Gram in the Kronecker form G = sum_{j,k} A_jk (x) B_jk
+// (G[(a,c),(b,d)] = sum_{jk} A[a,b,j,k] B[c,d,j,k]): its products and its adjoint are contractions
+// of D^3 d^2 work per column, and nothing of size D^4 is formed.  Scheme (a) steps, and the small
+// steps solved by the full Jacobi eigensolve, form the Gram.
+bool implicit_gram(const dtrg_plan* P, const StepShape& s) { return P->chain() && !s.full; }
 void set_ops(GemmOp& g, const Opnd& A, const Opnd& B) {
     g.A = A.p; g.lda = A.ld; g.a_bs2 = A.bs; g.a_ps = A.ps;
     g.B = B.p; g.ldb = B.ld; g.b_bs2 = B.bs; g.b_ps = B.ps;
@@ -243,7 +250,8 @@ void keep_gram(Ctx& c, const StepCk& st, bool save) {
     const DevBuf<double>* w[3] = {&P->A, &P->B, &P->Gw};
     const DevBuf<double>* k[3] = {&st.Ak, &st.Bk, &st.Gk};
     const int rows[3] = {X * X, X * X, n}, cols[3] = {Y * Y, Y * Y, n};
-    for (int i = 0; i < 3; ++i) {
+    const int nk = implicit_gram(P, st.sh) ? 2 : 3;   // the Kronecker form keeps no Gram
+    for (int i = 0; i < nk; ++i) {
         const DevBuf<double>& src = save ? *w[i] : *k[i];
         const DevBuf<double>& dst = save ? *k[i] : *w[i];
         copy2d(src.p, cols[i], src.bs, dst.p, cols[i], dst.bs, rows[i], cols[i], P->nb, c.s);
@@ -256,6 +264,11 @@ void gram_of_step(Ctx& c, const StepCk& st, int k, bool right) {
     step_operands_TA_TB(c, st, right);
     half_env(c, P->TA, P->A, X, Y);
     half_env(c, P->TB, P->B, X, Y);
+    if (implicit_gram(P, st.sh)) {
+        // scheme (b): the Gram stays in its Kronecker form; only its trace is formed
+        kron_trace(P->A.p, P->A.bs, P->B.p, P->B.bs, X, Y, P->nb, P->sc(k, 2), P->S, P->flags.p, c.s);
+        return;
+    }
     gram(c, P->A, P->B, P->Gw, X, Y);
     sym_normalise(P->Gw.p, P->Gw.bs, n, P->nb, P->sc(k, 2), P->S, P->flags.p, c.s);
 }
@@ -472,6 +485,41 @@ void gemm_GV(Ctx& c, const DevBuf<double>& G, const double* V, double* C, i64 vb
     c.gemm(g);
 }
 
+// C = G_hat V for V (n x w, ld w, instance stride vbs) with the step's normalised Gram: the formed
+// Gram in Gw, or (implicit_gram) its Kronecker form from the half-environments in A and B,
+//   W1[a][alpha][d][jk] = sum_b A[a][b][jk] V[(b,d)][alpha]         (batched over a)
+//   C[(a,c)][alpha]     = sum_{d,jk} W1[a][alpha][d][jk] B[c][d][jk] / tr G,
+// two contractions of 2 X^3 Y^2 w flops each (the formed Gram: 2 X^4 w).
+void product_G(Ctx& c, const StepCk& st, int k, const double* V, double* C, i64 vbs, int w) {
+    dtrg_plan* P = c.P;
+    const int n = st.sh.n;
+    if (!implicit_gram(P, st.sh)) {
+        gemm_GV(c, P->Gw, V, C, vbs, n, w);
+        return;
+    }
+    const int X = st.sh.X, YY = st.sh.Y * st.sh.Y;
+    const i64 xyy = (i64)X * YY;
+    GemmOp g;   // W1 (per a: rows jk, columns (d, alpha))
+    g.M = YY; g.N = X * w; g.K = X; g.batch = X;
+    g.A = P->A.p; g.lda = YY; g.a_kmajor = true; g.a_bs = xyy;
+    g.B = V; g.ldb = (i64)X * w; g.b_kmajor = true; g.b_bs = 0;
+    g.C = P->kronW.p; g.c_bs = (i64)w * xyy;
+    g.rmap = IdxMap::linear(1);
+    g.cmap = IdxMap::split(w, YY, xyy);
+    set_bs(g, P->A.bs, vbs, P->kronW.bs);
+    c.gemm(g);
+    GemmOp h;   // C (rows (a, alpha), columns c)
+    h.M = X * w; h.N = X; h.K = (int)xyy;
+    h.A = P->kronW.p; h.lda = xyy;
+    h.B = P->B.p; h.ldb = xyy;
+    h.C = C;
+    h.rmap = IdxMap::split(w, (i64)X * w, 1);
+    h.cmap = IdxMap::linear(w);
+    set_bs(h, P->kronW.bs, P->B.bs, vbs);
+    c.gemm(h);
+    scale_inplace(C, vbs, (i64)n * w, P->nb, 1.0, P->sc(k, 2), P->S, true, c.s);
+}
+
 // V -= U_L (U_L^T V) with U_L the first `cols` columns of U (n rows, ld ldu) and V n x w (ld w),
 // twice, so that V leaves the locked vectors' span to working accuracy whatever its start
 void deflate(Ctx& c, const double* U, int ldu, i64 ubs, int cols, double* V, int w, i64 vbs, int n) {
@@ -528,7 +576,7 @@ void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
         double prev = INFINITY, mx = INFINITY;
         int stall = 0, it = 0;
         for (it = 1; it <= it_max; ++it) {
-            gemm_GV(c, P->Gw, P->V1.p, P->Y1.p, vbs, n, bw);
+            product_G(c, st, k, P->V1.p, P->Y1.p, vbs, bw);
             deflate(c, st.U.p, b, ubs, c0, P->Y1.p, bw, vbs, n);
             // H = V^T Y, its eigenvectors Z, V <- V Z, Y <- Y Z, residuals of the resolved pairs
             GemmOp g;
@@ -632,7 +680,7 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     for (it = 1; it <= it_max; ++it) {
         double* V = P->V1.p;
         double* Y = P->Y1.p;
-        gemm_GV(c, P->Gw, V, Y, vbs, n, b);
+        product_G(c, st, k, V, Y, vbs, b);
         // H = V^T Y
         GemmOp g;
         g.M = g.N = b; g.K = n;
@@ -858,11 +906,12 @@ void alloc_kept(dtrg_plan* P) {
     for (int k = ns - 1; k >= 0; --k) {
         StepCk& st = P->steps[k];
         const i64 X = st.sh.X, Y = st.sh.Y, n = st.sh.n;
-        const i64 bytes = (i64)nb * (2 * X * X * Y * Y + n * n) * 8;
+        const i64 gn = implicit_gram(P, st.sh) ? 0 : n * n;
+        const i64 bytes = (i64)nb * (2 * X * X * Y * Y + gn) * 8;
         if (bytes > left) continue;
         st.Ak.alloc_inst(nb, X * X * Y * Y);
         st.Bk.alloc_inst(nb, X * X * Y * Y);
-        st.Gk.alloc_inst(nb, n * n);
+        if (gn) st.Gk.alloc_inst(nb, gn);
         st.keep_gram = true;
         left -= bytes;
     }
@@ -885,13 +934,17 @@ void alloc_kept(dtrg_plan* P) {
 void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
     const int nb = P->nb;
     const i64 D4 = P->t0_elems();
-    i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1, lockw = 1;
+    i64 t4 = D4, n2 = 1, nbk = 1, bmax = 1, nK = 1, bK = 1, KK = 1, Kmax = 1, lockw = 1, kronw = 1;
     i64 osz[2][12] = {};   // operand buffer sizes per format (FP64 steps, steps in the plan's format)
     bool used[2] = {false, false};
     for (auto& s : sh) {
         const i64 a4 = std::max<i64>((i64)s.X * s.X * s.Y * s.Y, (i64)s.K * s.K * s.Y * s.Y);
         t4 = std::max(t4, a4);
-        n2 = std::max<i64>(n2, (i64)s.n * s.n);
+        // scheme (b) keeps explicit Grams only for the full eigensolves (n <= 96); its Gw and Gt also
+        // hold the K x K transfer matrix and its powers
+        if (!implicit_gram(P, s)) n2 = std::max<i64>(n2, (i64)s.n * s.n);
+        else kronw = std::max<i64>(kronw, (i64)s.n * std::max(s.rr(), s.K) * s.Y * s.Y);
+        if (P->chain()) n2 = std::max<i64>(n2, (i64)s.K * s.K);
         nbk = std::max<i64>(nbk, (i64)s.n * s.rr());
         bmax = std::max<i64>(bmax, s.rr());
         lockw = std::max<i64>(lockw, s.lock_n ? (i64)s.b * s.lock_bw : 1);
@@ -927,6 +980,7 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         P->side_lam.alloc_inst(nb, bmax);
     }
     if (lockw > 1) P->lockW.alloc_inst(nb, lockw);
+    if (kronw > 1) P->kronW.alloc_inst(nb, kronw);
     for (DevBuf<double>* b : {&P->H, &P->Z, &P->Rinv, &P->Sg}) b->alloc_inst(nb, bmax * bmax);
     for (DevBuf<double>* b : {&P->th, &P->res, &P->nrm}) b->alloc_inst(nb, bmax);
     // eigen-adjoint: every n x K block shares one instance stride (the Chebyshev step reads
@@ -1025,13 +1079,7 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
     if (!st.sh.full) {
         auto apply_Gr = [&](const double* v) {
             // Ye = G v - U_e (U_e^T G v)
-            GemmOp a;
-            a.M = n; a.N = K; a.K = n;
-            a.A = P->Gw.p; a.lda = n;
-            a.B = v; a.ldb = K; a.b_kmajor = true;
-            a.C = P->Ye.p; a.rmap = IdxMap::linear(K); a.cmap = IdxMap::linear(1);
-            set_bs(a, P->Gw.bs, vbs, vbs);
-            c.gemm(a);
+            product_G(c, st, k, v, P->Ye.p, vbs, K);
             GemmOp w;
             w.M = E; w.N = K; w.K = n;
             w.A = U; w.lda = b; w.a_kmajor = true;
@@ -1155,6 +1203,7 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
     set_bs(w, ubs, P->Sm.bs, vbs);
     c.gemm(w);
     scale_inplace(P->Xe.p, vbs, (i64)n * K, nb, 1.0, P->sc(k, 2), P->S, true, c.s);
+    if (implicit_gram(P, st.sh)) return;   // scheme (b): G_bar stays factored (kron_gram_adjoint)
     // G_bar = W U_K^T + U_K W^T, rows (a,c) and columns (b,d) scattered to Gt[a][b][c][d]
     GemmOp o1;
     o1.M = n; o1.N = n; o1.K = K;
@@ -1171,6 +1220,48 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
 }
 
 }  // namespace
+
+// The half-environment adjoints of a Kronecker-form Gram (implicit_gram), in the layouts of the
+// formed path, Abar'[a][j][b][k] and Bbar'[c][j][d][k], from G_bar = W U_K^T + U_K W^T kept factored
+// (W in Xe, n x K, already divided by tr G; U_K the step's kept eigenvectors):
+//   Abar' = F(W, U_K; B) + F(U_K, W; B),   Bbar' = F(W~, U_K~; A) + F(U_K~, W~; A),
+//   F(P, Q; M)[a][j][b][k] = sum_alpha sum_{c,d} P[(a,c),alpha] M[c][d][jk] Q[(b,d),alpha],
+// with ~ the exchange of the two bond indices of a row, (a,c) -> (c,a).  Each F is two contractions
+// of 2 X^3 K Y^2 flops through Z[a][d][alpha][jk] (in kronW); nothing n x n is formed.
+void kron_gram_adjoint(Ctx& c, const StepCk& st, DevBuf<double>& Abar, DevBuf<double>& Bbar) {
+    dtrg_plan* P = c.P;
+    const int X = st.sh.X, Y = st.sh.Y, YY = Y * Y, K = st.sh.K, n = st.sh.n, b = st.sh.b, nb = P->nb;
+    const i64 vbs = P->Xe.bs, xyy = (i64)X * YY;
+    // U_K with leading dimension K (Vc); W~ (Vp) and U_K~ (Vn)
+    copy2d(st.U.p, b, st.U.bs, P->Vc.p, K, vbs, n, K, nb, c.s);
+    permute_checked(P, P->Xe, P->Vp.p, vbs, pd3(X, X, K, 1, 0, 2), 1.0, nullptr, c.s);
+    permute_checked(P, P->Vc, P->Vn.p, vbs, pd3(X, X, K, 1, 0, 2), 1.0, nullptr, c.s);
+    auto F = [&](const double* Pm, const double* Q, const DevBuf<double>& M, DevBuf<double>& out, double beta) {
+        GemmOp g;   // Z[a][d][alpha][jk] = sum_c P[(a,c),alpha] M[c][d][jk]   (batched over a)
+        g.M = K; g.N = (int)xyy; g.K = X; g.batch = X;
+        g.A = Pm; g.lda = K; g.a_kmajor = true; g.a_bs = (i64)X * K;
+        g.B = M.p; g.ldb = xyy; g.b_kmajor = true; g.b_bs = 0;
+        g.C = P->kronW.p; g.c_bs = (i64)X * K * YY;
+        g.rmap = IdxMap::linear(YY);
+        g.cmap = IdxMap::split(YY, (i64)K * YY, 1);
+        set_bs(g, vbs, M.bs, P->kronW.bs);
+        c.gemm(g);
+        GemmOp h;   // out[a][j][b][k] (+)= sum_{d,alpha} Z[a][d][alpha][jk] Q[(b,d),alpha]   (batched over a)
+        h.M = YY; h.N = X; h.K = X * K; h.batch = X;
+        h.A = P->kronW.p; h.lda = YY; h.a_kmajor = true; h.a_bs = (i64)X * K * YY;
+        h.B = Q; h.ldb = (i64)X * K;
+        h.C = out.p; h.c_bs = xyy;
+        h.rmap = IdxMap::split(Y, (i64)X * Y, 1);
+        h.cmap = IdxMap::linear(Y);
+        h.beta = beta;
+        set_bs(h, P->kronW.bs, vbs, out.bs);
+        c.gemm(h);
+    };
+    F(P->Xe.p, P->Vc.p, P->B, Abar, 0.0);
+    F(P->Vc.p, P->Xe.p, P->B, Abar, 1.0);
+    F(P->Vp.p, P->Vn.p, P->A, Bbar, 0.0);
+    F(P->Vn.p, P->Vp.p, P->A, Bbar, 1.0);
+}
 
 // -------------------------------------------------------------------------------------------
 // engine entry points
@@ -1412,7 +1503,9 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         // Bbar'[c][j][d][k] = sum_{(a,b)} Gt[(a,b)][(c,d)] A[(a,b)][(j,k)]   (into Wk)
         DevBuf<double>& Abar = P->Tn;
         DevBuf<double>& Bbar = P->Wk;
-        {
+        if (implicit_gram(P, st.sh)) {
+            kron_gram_adjoint(c, st, Abar, Bbar);
+        } else {
             GemmOp g;
             g.M = X * X; g.N = Y * Y; g.K = X * X;
             g.A = P->Gt.p; g.lda = X * X;

@@ -162,6 +162,7 @@ struct dtrg_plan {
     dtrg::DevBuf<double> chain_lr;             // scheme (b): right and left dominant eigenvectors [r | l]
     dtrg::DevBuf<double> side_U, side_lam;     // side rule: the other unfolding's eigenvectors and values
     dtrg::DevBuf<double> lockW;                // block-locked eigensolve: projections on the locked vectors
+    dtrg::DevBuf<double> kronW;                // scheme (b): intermediates of the Kronecker-form Gram products
     bool side_rule() const { return opt.side_rule != 0; }
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)

@@ -9,9 +9,9 @@ Jordan-Wigner free energy of the XY chain.
   exact symmetry multiplets in the Gram spectra leave the symmetry-breaking part of the gradient to
   each eigensolver's rotation inside them.
 * Six-product split-bf16 path at sizes where the projections run mixed: ln Z within 1e-6 of the
-  oracle; the gradient within 1e-5 normwise; entry by entry within 1e-5 for the random MPO and 1e-2
-  for the XY chain, whose symmetry multiplets make single entries ill-conditioned in the
-  symmetry-breaking directions (see MIXED_CASES).
+  oracle; the gradient within 1e-5 normwise and entry by entry for the random MPO, and within 1e-4
+  normwise (5e-2 entry-wise) for the XY chain, whose symmetry multiplets make the gradient
+  ill-conditioned in the symmetry-breaking directions (see MIXED_CASES).
 * The isometry optimisation of the last layers (depth 2): ln Z after every MERA update within 1e-10
   of the oracle's trajectory (the update is gauge covariant), and the free energy closer to
   Jordan-Wigner than the local truncation.
@@ -88,18 +88,22 @@ def test_gpu_chain_fp64_vs_oracle(B, name):
 # Inside a kept multiplet the split-bf16 rounding splits the eigenvalues by ~1e-8 of the spectrum,
 # where the broadened inverse gaps d / (d^2 + 1e-12) reach 1e4 and turn the arbitrary rotation of the
 # multiplet's eigenvectors into gradient differences in the symmetry-breaking directions (the FP64 path
-# shows the same amplification at its rounding level: 1e-9 entry-wise).  Those directions carry little
-# of the gradient's norm (measured 4.7e-6 normwise against 3.8e-3 on the worst single entry), so the
-# XY case meets 1e-5 normwise and its entries are bounded at 1e-2; ln Z at 1e-6.  The random MPO has no
-# multiplets (smallest relative gap at a cut 6e-4 at chi = 9): its gradient meets 1e-5 entry by entry.
-MIXED_CASES = {"xy_chi25": (("xy", 0.05), 25, 7, 1e-2), "random_chi9": (("random", 4), 9, 8, 1e-5)}
+# shows the same amplification at its rounding level: 1e-9 entry-wise).  How much of the gradient's
+# norm that moves depends on how the rounding splits the multiplets: 4.7e-6 normwise (3.8e-3 on the
+# worst entry) with the formed Gram, 2.5e-5 (2.1e-2) with its Kronecker form, whose products round
+# differently; the XY case is therefore held to 1e-4 normwise and 5e-2 entry-wise, ln Z to 1e-6.  The
+# random MPO has no multiplets (smallest relative gap at a cut 6e-4 at chi = 9): its gradient meets
+# 1e-5 normwise and entry by entry, on full-Jacobi steps (chi = 9) and on steps whose Gram stays in
+# its Kronecker form (chi = 12, X^2 = 144).
+MIXED_CASES = {"xy_chi25": (("xy", 0.05), 25, 7, 1e-4, 5e-2), "random_chi9": (("random", 4), 9, 8, 1e-5, 1e-5),
+               "random_chi12": (("random", 4), 12, 8, 1e-5, 1e-5)}
 
 
 @pytest.mark.parametrize("name", sorted(MIXED_CASES))
 def test_gpu_chain_mixed_vs_oracle(B, name):
     from oracle import xtrg as C
     from paper_1912_02780_amd import inputs as I
-    (kind, p), chi, n, gtol = MIXED_CASES[name]
+    (kind, p), chi, n, gtol, etol = MIXED_CASES[name]
     M = I.xy_trotter_mpo(p) if kind == "xy" else I.random_mpo(p, 3, 2)
     fwd = C.chain_forward(M, chi, n)
     cuts = [(r.lam[r.chi_kept - 1] - r.lam[r.chi_kept]) / r.lam[r.chi_kept - 1] for r in fwd.steps
@@ -117,8 +121,8 @@ def test_gpu_chain_mixed_vs_oracle(B, name):
          f"mixed steps {sum(mixed)}")
     assert sum(mixed) >= 3
     assert abs(L / fwd.lnZ_per_tensor - 1) < 1e-6
-    assert rel < 1e-5
-    assert _elem(g, go, 1e-3) < gtol
+    assert rel < gtol
+    assert _elem(g, go, 1e-3) < etol
 
 
 def test_gpu_chain_isometry_gradient_vs_oracle(B):
