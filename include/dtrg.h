@@ -204,9 +204,11 @@ void dtrg_default_options(dtrg_options* opt);
  *                 D x d x D x d doubles); read only; all entries finite, not all 0.
  *   D             bond dimension of T0, 1 <= D <= 64.
  *   chi           truncation bond dimension, 1 <= chi <= 80 (scheme (b), opt->chain_phys > 0:
- *                 1 <= chi <= 255; chi' beyond one 96-column Rayleigh-Ritz block is found by the
+ *                 1 <= chi <= 512; chi' beyond one 96-column Rayleigh-Ritz block is found by the
  *                 block-locked eigensolve, blocks of 96 or of opt->block_size columns, each deflated
- *                 against the eigenvectors resolved before it).
+ *                 against the eigenvectors resolved before it; a step that keeps everything
+ *                 (chi' = X^2 > 96) projects with the identity; a step whose chi' leaves fewer than
+ *                 8 resolved pairs and a guard below X^2 gives DTRG_EINVAL).
  *   n_steps       number of single-direction HOTRG steps, 1 <= n_steps <= 62.
  *   opt           options or NULL for the defaults.
  *   stream        hipStream_t or NULL.

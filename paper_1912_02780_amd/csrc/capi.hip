@@ -129,7 +129,7 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->side = st.side;
     info->trunc_weight_left = st.tw_left;
     info->trunc_weight_right = st.tw_right;
-    if (st.fixed) {   // a given isometry: no Gram, no spectrum
+    if (st.fixed || st.sh.ident) {   // a given isometry (or the identity): no Gram, no spectrum
         info->full_eig = 0;
         info->iters = -1;
         info->trace_G = info->lam_last_kept = info->lam_first_dropped = info->resid = 0.0;
@@ -514,6 +514,7 @@ dtrg_status dtrg_plan_fix_isometry(dtrg_plan* plan, int k, const double* w_dev, 
     g_last_error.clear();
     try {
         StepCk& st = plan_step(plan, k);
+        DTRG_REQUIRE(!st.sh.ident, DTRG_EINVAL, "step keeps everything (chi' = X^2): its isometry is the identity");
         plan->s = (hipStream_t)stream;
         plan->alloc.stream = plan->s;
         AllocScope scope(&plan->alloc);

@@ -289,8 +289,8 @@ void max_check(const double* v, i64 v_bs, int k, int nb, double thr, double* mx_
 // chain.hip (scheme (b): closing the infinite chain of cells)
 // largest transfer matrix the closing kernel takes, its residual bound, and the squarings of E
 constexpr int kChainMaxK = 2048;
-// largest chi of a scheme (b) plan (the Gram of the doubled bond is chi^2 x chi^2 doubles)
-constexpr int kChainMaxChi = 255;
+// largest chi of a scheme (b) plan
+constexpr int kChainMaxChi = 512;
 constexpr double kChainResidual = 1e-8;
 constexpr int kChainSquarings = 24;
 // E[l][r] = scale * sum_u T[l][r][u][u] for T [K][K][Y][Y] (scale from scale_dev[i * sc_bs], or 1)
@@ -303,6 +303,8 @@ void chain_normalise(double* P, i64 bs, i64 n, int nb, int* flag_dev, int bit, h
 // positive or either eigenvector residual exceeds kChainResidual relative
 void chain_dominant_finish(const double* E, i64 ebs, const double* P, i64 pbs, int K, int nb, double* lr, i64 lrbs,
                            double* lam_dev, i64 sc_bs, int* flag_dev, int bit, hipStream_t s);
+// p[i][j] = (i == j) for a rows x cols row-major block per instance
+void eye(double* p, i64 bs, int rows, int cols, int nb, hipStream_t s);
 // trace of the Gram G = sum_{j,k} A_jk (x) B_jk of the doubled bond, from the half-environments
 // A, B ([X][X][Y][Y], instance strides a_bs, b_bs) into t_dev; flag_dev[i] |= 1 if it is not
 // positive or not finite

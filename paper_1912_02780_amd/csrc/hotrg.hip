@@ -839,12 +839,11 @@ std::vector<StepShape> shapes(int D, int chi, int nsteps, int block, int oversam
         s.X = X; s.Y = Y; s.n = X * X;
         s.K = std::min(chi, s.n);
         if (s.n <= kJacobiMax) { s.full = true; s.b = s.n; s.e = s.n; }
+        else if (phys > 0 && s.K == s.n) { s.ident = true; s.b = s.n; s.e = s.n; }
         else if (phys > 0 && (s.K + 16 > kJacobiMax || (block > 0 && block <= s.K + 8))) {
             // scheme (b) beyond one Rayleigh-Ritz block: the eigenpairs are found lock_n blocks at a
             // time, each block deflated against the ones before (block_size, when set, is the
             // block width)
-            DTRG_REQUIRE(s.K < s.n, DTRG_EINVAL,
-                         "an untruncated step wider than " + std::to_string(kJacobiMax) + " (chi' = X^2)");
             s.lock_bw = block > 0 ? std::min(block, kJacobiMax) : kJacobiMax;
             DTRG_REQUIRE(s.lock_bw >= 16, DTRG_EINVAL, "block size too small for the locked eigensolve");
             // Resolved pairs beyond the cut: max(8, chi'/2), so that the complement of the
@@ -1317,10 +1316,15 @@ void plan_forward(dtrg_plan* P, Mode mode) {
             permute_checked(P, P->Tn, st.T.p, st.T.bs, pd4(ps.K, ps.K, ps.Y, ps.Y, 2, 3, 0, 1), 1.0,
                             P->sc(k - 1, 1), c.s);
         }
-        if (!st.fixed) {
+        if (st.sh.ident) {
+            eye(st.U.p, st.U.bs, st.sh.n, st.sh.b, nb, c.s);
+            fill(st.lam.p, st.lam.bs, st.sh.b, nb, 0.0, c.s);
+        }
+        if (!st.fixed && !st.sh.ident) {
             // warm start from the previous step in the same direction
             const int kw = P->chain() ? k - 1 : k - 2;
-            const StepCk* warm = (kw >= 1 && !P->steps[kw - 1].fixed) ? &P->steps[kw - 1] : nullptr;
+            const StepCk* warm =
+                (kw >= 1 && !P->steps[kw - 1].fixed && !P->steps[kw - 1].sh.ident) ? &P->steps[kw - 1] : nullptr;
             if (P->side_rule()) {
                 eigensolve_sides(c, st, k, warm);
             } else {
@@ -1481,10 +1485,10 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
             g.beta = 1.0;
             c.run(g, pr, Out::F64);
         }
-        if (st.fixed) {
+        if (st.fixed || st.sh.ident) {
             // the isometry is a parameter of its own: its gradient is kept, and nothing flows
-            // through the Gram of the step
-            copy2d(P->Ub.p, K, P->Ub.bs, st.wbar.p, K, st.wbar.bs, n, K, nb, c.s);
+            // through the Gram of the step (an untruncated step's identity has no gradient at all)
+            if (st.fixed) copy2d(P->Ub.p, K, P->Ub.bs, st.wbar.p, K, st.wbar.bs, n, K, nb, c.s);
             std::swap(P->Tbar, P->Tbar2);
             if (c.adaptive()) check_flags(P, kFlagErrors, "backward step " + std::to_string(k));
             continue;

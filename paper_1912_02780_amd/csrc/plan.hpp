@@ -62,6 +62,9 @@ struct StepShape {
     // block's lock_bw - lock_r guard columns complete U (b = e + guard)
     int lock_bw = 0, lock_r = 0, lock_n = 0;
     int rr() const { return lock_n ? lock_bw : b; }   // width of the Rayleigh-Ritz problems
+    // scheme (b): an untruncated step (chi' = X^2 > 96) projects with the identity: Z does not depend
+    // on an orthogonal isometry that keeps everything, so no Gram is needed, forward or backward
+    bool ident = false;
     double join_flops() const { return 2.0 * K * Y * X * (double)(Y * X) * (X * Y); }
 };
 

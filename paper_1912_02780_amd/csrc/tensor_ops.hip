@@ -386,6 +386,18 @@ void convert_f64_to_f32(const double* in, i64 in_bs, float* out, i64 out_bs, i64
     DTRG_HIP(hipGetLastError());
 }
 
+__global__ __launch_bounds__(256) void eye_kernel(double* p, i64 bs, int rows, int cols) {
+    p += blockIdx.y * bs;
+    const i64 total = (i64)rows * cols;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < total; i += (i64)gridDim.x * blockDim.x)
+        p[i] = (i / cols == i % cols) ? 1.0 : 0.0;
+}
+
+void eye(double* p, i64 bs, int rows, int cols, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(eye_kernel, grid2((i64)rows * cols, nb), dim3(256), 0, s, p, bs, rows, cols);
+    DTRG_HIP(hipGetLastError());
+}
+
 void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(fill_kernel, grid2(n, nb), dim3(256), 0, s, p, bs, n, v);
