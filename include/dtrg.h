@@ -165,6 +165,10 @@ typedef struct {
                                  (chiral or generic), while mirror-symmetric inputs keep the left
                                  side.  Single-instance plans of scheme (a) only (DTRG_EINVAL for
                                  batches and chain_phys > 0).  Default 0 */
+    int polar_newton;         /* polar factor of the MERA update (dtrg_isometry_optimize): 0 = the
+                                 Jacobi eigensolve of [[0, R], [R^T, 0]] for chi' <= 48 and the
+                                 Newton-Schulz iteration X <- X (3 I - X^T X) / 2 above (chi' <= 80);
+                                 1 = Newton-Schulz for every chi'.  Default 0 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -268,8 +272,9 @@ dtrg_status dtrg_hotrg_backward(dtrg_plan* plan, double gbar, double* T0bar_dev,
  *   the isometries above the optimised steps remain HOTRG's local ones, recomputed every pass.
  *   ln Z / N after every update goes to history_host (host, n_sweeps * layers * n_inner doubles,
  *   nullable), the last to *lnZ_host.  The optimised isometries stay fixed in the plan, whose last
- *   forward pass is valid (a backward pass may follow).  chi' <= 48 on the optimised steps
- *   (DTRG_EINVAL otherwise); DTRG_EINVAL if fewer steps truncate than `layers`.
+ *   forward pass is valid (a backward pass may follow).  The optimised steps need chi' <= 80 and
+ *   one Rayleigh-Ritz block (DTRG_EINVAL otherwise; see polar_newton for the polar factor);
+ *   DTRG_EINVAL if fewer steps truncate than `layers`.
  * All four synchronise `stream`.
  */
 dtrg_status dtrg_plan_isometry(dtrg_plan* plan, int k, double* w_dev, void* stream);

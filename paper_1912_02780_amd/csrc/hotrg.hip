@@ -1563,18 +1563,70 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
     }
 }
 
+// polar(R) of the K x K matrix R in P->H into P->Rinv by the Newton-Schulz iteration
+// X_0 = R / |R|_F, X <- X (3 I - X^T X) / 2: every singular value below 1 grows by a factor of up to
+// 3/2 a step and they converge quadratically once near 1, while the singular vectors stay those of
+// R.  Stops when |X^T X - I|_F <= 1e-13 (checked every 8 steps), at most 256 steps (then
+// DTRG_ENOCONV: R numerically rank deficient).
+void polar_newton(Ctx& c, int K) {
+    dtrg_plan* P = c.P;
+    const int nb = P->nb;
+    const i64 kk = (i64)K * K;
+    norm2(P->H.p, P->H.bs, kk, nb, P->sp(12), P->S, c.s, P->ws);
+    copy2d(P->H.p, K, P->H.bs, P->Rinv.p, K, P->Rinv.bs, K, K, nb, c.s);
+    scale_inplace(P->Rinv.p, P->Rinv.bs, kk, nb, 1.0, P->sp(12), P->S, true, c.s);
+    auto gram = [&]() {   // polS = X^T X
+        GemmOp g;
+        g.M = g.N = K; g.K = K;
+        g.A = P->Rinv.p; g.lda = K; g.a_kmajor = true;
+        g.B = P->Rinv.p; g.ldb = K; g.b_kmajor = true;
+        g.C = P->polS.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+        set_bs(g, P->Rinv.bs, P->Rinv.bs, P->polS.bs);
+        c.gemm(g);
+    };
+    for (int it = 1;; ++it) {
+        gram();
+        // polV = 1.5 X - 0.5 X (X^T X), then X = polV
+        copy2d(P->Rinv.p, K, P->Rinv.bs, P->polV.p, K, P->polV.bs, K, K, nb, c.s);
+        GemmOp h;
+        h.M = h.N = K; h.K = K;
+        h.A = P->Rinv.p; h.lda = K;
+        h.B = P->polS.p; h.ldb = K; h.b_kmajor = true;
+        h.C = P->polV.p; h.rmap = IdxMap::linear(K); h.cmap = IdxMap::linear(1);
+        h.alpha = -0.5; h.beta = 1.5;
+        set_bs(h, P->Rinv.bs, P->polS.bs, P->polV.bs);
+        c.gemm(h);
+        copy2d(P->polV.p, K, P->polV.bs, P->Rinv.p, K, P->Rinv.bs, K, K, nb, c.s);
+        if (it % 8 != 0) continue;
+        gram();
+        eye(P->polV.p, P->polV.bs, K, K, nb, c.s);
+        axpy(P->polV.p, P->polS.p, P->polS.bs, kk, nb, -1.0, c.s);   // polS = X^T X - I
+        norm2(P->polS.p, P->polS.bs, kk, nb, P->sp(13), P->S, c.s, P->ws);
+        const std::vector<double> dev = read_scalar(P, P->sp(13));
+        double mx = 0.0;
+        for (double v : dev) mx = std::max(mx, std::isfinite(v) ? v : INFINITY);
+        if (mx <= 1e-13) break;
+        DTRG_REQUIRE(it < 256, DTRG_ENOCONV,
+                     "polar factor: Newton-Schulz iteration did not converge (environment numerically rank "
+                     "deficient, |X^T X - I| = " + std::to_string(mx) + ")");
+    }
+}
+
 // MERA update of step k's fixed isometry (paper, main text: the SVD E = U S V^T of the environment
 // and w <- U V^T, which maximises Tr(E^T w)) from the gradient in st.wbar, which is E up to a
 // positive factor.  The polar factor is formed without squaring E's condition number (the
 // environments reach condition numbers of 1e8): E = Q R with the shifted CholeskyQR3 of the
 // eigensolver (orthonormal to working accuracy for condition numbers up to ~1/u), R = Q^T E, and
 // polar(R) = sum_j u_j v_j^T from the positive eigenpairs of [[0, R], [R^T, 0]] (Jacobi), whose
-// eigenvectors are (u_j, v_j) / sqrt 2; then w = Q polar(R).  K <= 48 (2K within the Jacobi kernel).
+// eigenvectors are (u_j, v_j) / sqrt 2; then w = Q polar(R).  For K > 48 (2K beyond the Jacobi kernel),
+// or with the polar_newton option, polar(R) comes from the Newton-Schulz iteration instead.
 void polar_update(dtrg_plan* P, int k) {
     StepCk& st = P->steps[k - 1];
     const int n = st.sh.n, K = st.sh.K, b = st.sh.b, nb = P->nb, m = 2 * K;
     DTRG_REQUIRE(st.fixed, DTRG_ESTATE, "polar update of a step without a fixed isometry");
-    DTRG_REQUIRE(m <= kJacobiMax, DTRG_EINVAL, "isometry optimisation needs chi' <= 48 on the optimised steps");
+    DTRG_REQUIRE(K <= kJacobiMax && !st.sh.lock_n && !st.sh.ident, DTRG_EINVAL,
+                 "isometry optimisation needs chi' <= 80 (one Rayleigh-Ritz block) on the optimised steps");
+    const bool newton = m > kJacobiMax || P->opt.polar_newton;
     Ctx c{P, P->s, Mode::Adaptive};
     if (P->polS.n < (size_t)m * m * nb) {
         P->polS.alloc_inst(nb, (i64)m * m);
@@ -1609,22 +1661,26 @@ void polar_update(dtrg_plan* P, int k) {
         set_bs(g, vbs, ebs, P->H.bs);
         c.gemm(g);
     }
-    sym_augment(P->H.p, P->H.bs, K, P->polS.p, P->polS.bs, nb, c.s);
-    // floor at the rounding level of [[0, R], [R^T, 0]]: the polar factor needs the singular vectors
-    // to working accuracy only, and rotations among its large entries leave residues of about u |R|
-    // next to the small singular values, which a lower floor keeps rotating
-    jacobi_eig(P->polS.p, m, m, P->polS.bs, P->pollam.p, P->pollam.bs, P->polV.p, m, P->polV.bs, nb, kJacobiSweeps,
-               P->misc.p, c.s, P->flags.p, kFlagJacobi, 0x1p-50);
-    // polar(R)[r][c] = 2 sum_{j < K} V[r][j] V[K + c][j]   (into Rinv, K x K)
-    {
-        GemmOp g;
-        g.M = K; g.N = K; g.K = K;
-        g.A = P->polV.p; g.lda = m;
-        g.B = P->polV.p + (i64)K * m; g.ldb = m;
-        g.C = P->Rinv.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
-        g.alpha = 2.0;
-        set_bs(g, P->polV.bs, P->polV.bs, P->Rinv.bs);
-        c.gemm(g);
+    if (newton) {
+        polar_newton(c, K);
+    } else {
+        sym_augment(P->H.p, P->H.bs, K, P->polS.p, P->polS.bs, nb, c.s);
+        // floor at the rounding level of [[0, R], [R^T, 0]]: the polar factor needs the singular vectors
+        // to working accuracy only, and rotations among its large entries leave residues of about u |R|
+        // next to the small singular values, which a lower floor keeps rotating
+        jacobi_eig(P->polS.p, m, m, P->polS.bs, P->pollam.p, P->pollam.bs, P->polV.p, m, P->polV.bs, nb, kJacobiSweeps,
+                   P->misc.p, c.s, P->flags.p, kFlagJacobi, 0x1p-50);
+        // polar(R)[r][c] = 2 sum_{j < K} V[r][j] V[K + c][j]   (into Rinv, K x K)
+        {
+            GemmOp g;
+            g.M = K; g.N = K; g.K = K;
+            g.A = P->polV.p; g.lda = m;
+            g.B = P->polV.p + (i64)K * m; g.ldb = m;
+            g.C = P->Rinv.p; g.rmap = IdxMap::linear(K); g.cmap = IdxMap::linear(1);
+            g.alpha = 2.0;
+            set_bs(g, P->polV.bs, P->polV.bs, P->Rinv.bs);
+            c.gemm(g);
+        }
     }
     // w = Q polar(R), into the first K columns of U (ld b)
     {
@@ -1659,7 +1715,8 @@ void plan_isometry_optimize(dtrg_plan* P, int layers, int n_inner, int n_sweeps,
     DTRG_REQUIRE((int)opt.size() == layers, DTRG_EINVAL, "fewer truncating steps than layers to optimise");
     for (int k : opt) {
         StepCk& st = P->steps[k - 1];
-        DTRG_REQUIRE(2 * st.sh.K <= kJacobiMax, DTRG_EINVAL, "isometry optimisation needs chi' <= 48 on the optimised steps");
+        DTRG_REQUIRE(st.sh.K <= kJacobiMax && !st.sh.lock_n && !st.sh.ident, DTRG_EINVAL,
+                     "isometry optimisation needs chi' <= 80 (one Rayleigh-Ritz block) on the optimised steps");
         if (st.wbar.n == 0) st.wbar.alloc_inst(1, (i64)st.sh.n * st.sh.K);
         st.fixed = true;   // U already holds HOTRG's isometry of the step
     }

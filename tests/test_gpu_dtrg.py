@@ -68,14 +68,17 @@ def test_gpu_isometry_gradient_vs_oracle(B, case):
 
 
 @pytest.mark.parametrize("case", ["ising_bc", "random_d3"])
-def test_gpu_isometry_optimisation_trajectory_vs_oracle(B, case):
+@pytest.mark.parametrize("polar", ["jacobi", "newton"])
+def test_gpu_isometry_optimisation_trajectory_vs_oracle(B, case, polar):
+    """Both polar factors of the MERA update (the Jacobi eigensolve of [[0, R], [R^T, 0]], and the
+    Newton-Schulz iteration the library uses above chi' = 48) against the oracle's SVD."""
     from oracle import dtrg as DT
     T0, chi, n = _inputs(case)
     layers, n_inner, n_sweeps = 2, 4, 2
     L0o, Lo, hist_o, _ = DT.optimize(T0, chi, n, layers=layers, n_inner=n_inner, n_sweeps=n_sweeps)
-    _say(f"[gpu] isometry optimisation {case}: layers {layers}, n_inner {n_inner}, sweeps {n_sweeps}")
+    _say(f"[gpu] isometry optimisation {case} ({polar}): layers {layers}, n_inner {n_inner}, sweeps {n_sweeps}")
     dev = torch.device("cuda:0")
-    plan = B.dtrg_plan_create(T0.shape[0], chi, n, None, dev)
+    plan = B.dtrg_plan_create(T0.shape[0], chi, n, B.default_options(polar_newton=int(polar == "newton")), dev)
     L0, L, hist = B.dtrg_isometry_optimize(plan, torch.from_numpy(T0).to(dev), layers, n_inner, n_sweeps)
     rel = np.abs(np.array(hist) / np.array(hist_o) - 1)
     _say(f"    HOTRG {L0:.15f} (oracle {L0o:.15f}); optimised {L:.15f} (oracle {Lo:.15f}); "
