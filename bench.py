@@ -657,6 +657,17 @@ def bench_xy_chain(args, B, I, torch, np, dev):
                  "f_rel_err_plain": f_err(L0, n), "f_rel_err_optimised": f_err(L1, n)},
         "roofline": roofline(launches, ms, flops, args.contract, "join contraction (gemm kernel, tag 7)"),
     }
+    if not compact and D < 64:
+        # the same optimisation at D = 64 (the polar factor by Newton-Schulz beyond chi' = 48)
+        _progress("xy chain: isometry optimisation at D = 64")
+        p3 = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], 64, n,
+                                      B.default_options(contract=args.contract, max_subspace_iters=400), dev)
+        t3 = time.perf_counter()
+        L0b, L1b, hist_b = B.dtrg_isometry_optimize(p3, M, layers=depth, n_inner=n_inner, n_sweeps=n_sweeps)
+        t_opt64 = time.perf_counter() - t3
+        p3.close()
+        out["dtrg_D64"] = {"depth_n_d": depth, "n_i": n_inner, "n_s": n_sweeps, "mera_updates": len(hist_b),
+                           "wall_s": t_opt64, "f_rel_err_plain": f_err(L0b, n), "f_rel_err_optimised": f_err(L1b, n)}
     if args.chain_sweep:
         out["scaling_vs_D"] = chain_sweep(args, B, I, torch, dev, X, n, tau)
     if not args.no_cpu_baseline and not compact:
