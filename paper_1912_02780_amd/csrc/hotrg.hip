@@ -168,9 +168,12 @@ void set_bs(GemmOp& g, i64 a, i64 b, i64 c) { g.a_bs2 = a; g.b_bs2 = b; g.c_bs2 
 
 // Scheme (b) steps that iterate keep their Gram in the Kronecker form G = sum_{j,k} A_jk (x) B_jk
 // (G[(a,c),(b,d)] = sum_{jk} A[a,b,j,k] B[c,d,j,k]): its products and its adjoint are contractions
-// of D^3 d^2 work per column, and nothing of size D^4 is formed.  Scheme (a) steps, and the small
-// steps solved by the full Jacobi eigensolve, form the Gram.
-bool implicit_gram(const dtrg_plan* P, const StepShape& s) { return P->chain() && !s.full; }
+// of 4 X^3 d^2 work per column against 2 X^4 for the formed Gram, and nothing of size X^4 is formed.
+// That pays from X > 2 d^2 on (below, the formed Gram's single product per column is cheaper to
+// launch).  Scheme (a) steps, and the small steps solved by the full Jacobi eigensolve, form the Gram.
+bool implicit_gram(const dtrg_plan* P, const StepShape& s) {
+    return P->chain() && !s.full && s.X > 2 * s.Y * s.Y;
+}
 void set_ops(GemmOp& g, const Opnd& A, const Opnd& B) {
     g.A = A.p; g.lda = A.ld; g.a_bs2 = A.bs; g.a_ps = A.ps;
     g.B = B.p; g.ldb = B.ld; g.b_bs2 = B.bs; g.b_ps = B.ps;
