@@ -377,6 +377,8 @@ def bench_chi48(args, B, I, torch, np, dev):
             _progress(f"compact {name}")
             sub_args.chi, sub_args.n_steps = chi_s, n_s
             sub_args.contract = args.contract if name != "xy_chain" else DEFAULT_CONTRACT["xy_chain"]
+            # the chain also at D = 64 and 128 (the Kronecker-form Gram and the locked eigensolve)
+            sub_args.chain_sweep = "64,128" if name == "xy_chain" else ""
             out[name] = fn(sub_args, B, I, torch, np, dev)
             torch.cuda.empty_cache()
     return out
@@ -579,22 +581,27 @@ def chain_sweep(args, B, I, torch, dev, X, n, tau):
         # at beta = 12.8 the gapless chain's Gram spectrum is flat near the cut (lam_96 / lam_80 = 0.76 at
         # D = 64), so the subspace iteration needs more than the default 60 products
         plan = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n,
-                                        B.default_options(contract=args.contract, max_subspace_iters=400), dev)
+                                        B.default_options(contract=args.contract, max_subspace_iters=400, profile=1),
+                                        dev)
         L = B.dtrg_plan_forward(plan, M)
         B.dtrg_hotrg_backward(plan, 1.0)
         torch.cuda.synchronize()
+        plan.profile(reset=True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             L = B.dtrg_plan_forward(plan, M)
             B.dtrg_hotrg_backward(plan, 1.0)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / args.steps * 1e3
+        g_launches, g_ms, g_flops = plan.profile(reset=True)
         info = [plan.step_info(k) for k in range(1, n + 1)]
         err = abs(math.ldexp(L, n) / 2.0 / X.lnZ_per_spin_infinite(math.ldexp(tau, n)) - 1.0)
         rows.append({"D": D, "ms_per_pass": ms, "f_rel_err_beta_12.8": err,
                      "max_subspace_iters": max(i["iters"] for i in info),
                      "max_cheb_degree": max(i["cheb_degree"] for i in info),
-                     "plan_device_GB": plan.device_bytes() / 1e9})
+                     "plan_device_GB": plan.device_bytes() / 1e9,
+                     "gram_products": {"launches": g_launches, "ms_per_pass": g_ms / args.steps,
+                                       "TFLOP/s": g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None}})
         _progress(f"    {ms:.1f} ms per pass, f err {err:.2e}")
         plan.close()
     for r in rows:
@@ -655,7 +662,9 @@ def bench_xy_chain(args, B, I, torch, np, dev):
                                        "curve": [[b, e] for b, e in curve]},
         "dtrg": {"depth_n_d": depth, "n_i": n_inner, "n_s": n_sweeps, "mera_updates": len(hist), "wall_s": t_opt,
                  "f_rel_err_plain": f_err(L0, n), "f_rel_err_optimised": f_err(L1, n)},
-        "roofline": roofline(launches, ms, flops, args.contract, "join contraction (gemm kernel, tag 7)"),
+        "roofline": roofline(launches, ms, flops, args.contract,
+                             "products with the steps' Grams (subspace iteration and eigen-adjoint; FP64 MFMA "
+                             "contractions, in Kronecker form above X = 2 d^2)"),
     }
     if not compact and D < 64:
         # the same optimisation at D = 64 (the polar factor by Newton-Schulz beyond chi' = 48)

@@ -103,8 +103,9 @@ typedef struct {
                                  12, 16, 24 and 32 above it) of the MFMA kernels on a scratch output
                                  (the least of three timed runs) and keep the fastest for that shape (a table shared by all plans of the
                                  process); 0: fixed heuristic.  Default 0 */
-    int profile;              /* 1: time the chi^7 join contractions with HIP events on the plan's
-                                 stream (read with dtrg_plan_profile); default 0 */
+    int profile;              /* 1: time the chi^7 join contractions (scheme (b): the Gram products)
+                                 with HIP events on the plan's stream (read with dtrg_plan_profile);
+                                 default 0 */
     double checkpoint_gib;    /* device memory (GiB) the plan may spend keeping forward-pass
                                  intermediates that the backward pass would otherwise recompute:
                                  first each step's half-environments and normalised Gram (FP64),
@@ -294,7 +295,9 @@ dtrg_status dtrg_plan_step_info(const dtrg_plan* plan, int k, dtrg_step_info* in
  * created with opt.profile = 1: number of launches, summed milliseconds and summed algorithmic
  * flops (2 M N K per launch).  Only launches in the plan's contraction precision on the 128 x 128
  * tile are timed (all launches of that kernel), so the average matches that kernel's average in a
- * kernel trace.  Synchronises on the recorded events; reset != 0 clears the record.
+ * kernel trace.  Scheme (b) plans (whose passes the eigensolver dominates) time instead every
+ * product with a step's Gram (the subspace iteration's and the eigen-adjoint's, FP64; in Kronecker
+ * form two contractions each).  Synchronises on the recorded events; reset != 0 clears the record.
  */
 dtrg_status dtrg_plan_profile(dtrg_plan* plan, long long* launches, double* total_ms, double* flops, int reset);
 

@@ -203,7 +203,8 @@ struct GemmOp {
     int max_chain = 4096;
     int tag = 0;   // own kernel symbol for the chi^7 contractions: 7 the join of the two copies
                    // (forward and its backward recompute; timed when profiling), 8 its adjoint
-                   // with respect to the upper copy's product P, 9 with respect to the lower copy
+                   // with respect to the upper copy's product P, 9 with respect to the lower copy;
+                   // 10: the products with the step's Gram (timed when profiling scheme (b))
 };
 
 // Scratch owned by a plan, grown on demand (not shrunk) and reused by every contraction.

@@ -35,7 +35,7 @@ void for_each_buf(const dtrg_plan& P, F f) {
                                  &P.Y1, &P.Y2, &P.H, &P.Z, &P.Rinv, &P.Sg, &P.th, &P.res, &P.nrm, &P.coef, &P.fv,
                                  &P.ctab, &P.scal, &P.T0buf, &P.T0barbuf, &P.dT0buf, &P.tune_c, &P.ws.splitk, &P.ws.red,
                                  &P.polS, &P.polV, &P.pollam, &P.chain_lr, &P.side_U, &P.side_lam, &P.lockW,
-                                 &P.kronW};
+                                 &P.kronW, &P.Akr};
     for (auto* b : w) f(b->p, b->bytes());
     for (const OpSet& o : P.ops) {
         const OpBuf* v[] = {&o.Wt, &o.Wt2, &o.UT, &o.Us, &o.Tp, &o.Tb, &o.Tb2, &o.TpT, &o.Tpb, &o.Tpb2,
@@ -142,9 +142,11 @@ struct Ctx {
         if (g.c_cap < 0) g.c_cap = P->cap_of(g.C, eout);
         if (P->opt.autotune) g.cfg = tuned_cfg(pr, out, g, adaptive(), s, P->ws, P->tune_c);
         // timed: the joins in the plan's contraction precision on the large tiles, i.e. every
-        // launch of that one kernel symbol (the small early steps stay FP64 on mixed plans)
-        const bool timed = P->opt.profile && g.tag == 7 && adaptive() && pr == P->prec &&
-                           gemm_resolve(pr, g).tile >= 2;
+        // launch of that one kernel symbol (the small early steps stay FP64 on mixed plans); for
+        // scheme (b), whose passes the eigensolver dominates, the Gram products instead (tag 10)
+        const bool timed = P->opt.profile && adaptive() &&
+                           (P->chain() ? g.tag == 10
+                                       : (g.tag == 7 && pr == P->prec && gemm_resolve(pr, g).tile >= 2));
         if (timed) {
             while (P->ev_pool.size() < P->ev_used + 2) {
                 hipEvent_t e;
@@ -479,6 +481,7 @@ void orthonormalise(Ctx& c, double* V, double* Vtmp, i64 vbs, int n, int b) {
 // C (n x b) = G (n x n) V (n x b)
 void gemm_GV(Ctx& c, const DevBuf<double>& G, const double* V, double* C, i64 vbs, int n, int b) {
     GemmOp g;
+    g.tag = 10;
     g.M = n; g.N = b; g.K = n;
     g.A = G.p; g.lda = n;
     g.B = V; g.ldb = b; g.b_kmajor = true;
@@ -490,9 +493,11 @@ void gemm_GV(Ctx& c, const DevBuf<double>& G, const double* V, double* C, i64 vb
 
 // C = G_hat V for V (n x w, ld w, instance stride vbs) with the step's normalised Gram: the formed
 // Gram in Gw, or (implicit_gram) its Kronecker form from the half-environments in A and B,
-//   W1[a][alpha][d][jk] = sum_b A[a][b][jk] V[(b,d)][alpha]         (batched over a)
+//   W1[a][alpha][d][jk] = sum_b A'[b][(a,jk)] V[(b,d)][alpha]      (A'[b][a][jk] = A[a][b][jk])
 //   C[(a,c)][alpha]     = sum_{d,jk} W1[a][alpha][d][jk] B[c][d][jk] / tr G,
-// two contractions of 2 X^3 Y^2 w flops each (the formed Gram: 2 X^4 w).
+// two contractions of 2 X^3 Y^2 w flops each (the formed Gram: 2 X^4 w), both with every dimension
+// at least X (the first contraction's rows are (a, jk), not jk alone per a, which would leave most
+// rows of each MFMA tile empty).
 void product_G(Ctx& c, const StepCk& st, int k, const double* V, double* C, i64 vbs, int w) {
     dtrg_plan* P = c.P;
     const int n = st.sh.n;
@@ -502,16 +507,19 @@ void product_G(Ctx& c, const StepCk& st, int k, const double* V, double* C, i64 
     }
     const int X = st.sh.X, YY = st.sh.Y * st.sh.Y;
     const i64 xyy = (i64)X * YY;
-    GemmOp g;   // W1 (per a: rows jk, columns (d, alpha))
-    g.M = YY; g.N = X * w; g.K = X; g.batch = X;
-    g.A = P->A.p; g.lda = YY; g.a_kmajor = true; g.a_bs = xyy;
-    g.B = V; g.ldb = (i64)X * w; g.b_kmajor = true; g.b_bs = 0;
-    g.C = P->kronW.p; g.c_bs = (i64)w * xyy;
-    g.rmap = IdxMap::linear(1);
+    permute_checked(P, P->A, P->Akr.p, P->Akr.bs, pd3(X, X, YY, 1, 0, 2), 1.0, nullptr, c.s);
+    GemmOp g;   // W1 (rows (a, jk), columns (d, alpha))
+    g.tag = 10;
+    g.M = (int)xyy; g.N = X * w; g.K = X;
+    g.A = P->Akr.p; g.lda = xyy; g.a_kmajor = true;
+    g.B = V; g.ldb = (i64)X * w; g.b_kmajor = true;
+    g.C = P->kronW.p;
+    g.rmap = IdxMap::split(YY, (i64)w * xyy, 1);
     g.cmap = IdxMap::split(w, YY, xyy);
-    set_bs(g, P->A.bs, vbs, P->kronW.bs);
+    set_bs(g, P->Akr.bs, vbs, P->kronW.bs);
     c.gemm(g);
     GemmOp h;   // C (rows (a, alpha), columns c)
+    h.tag = 10;
     h.M = X * w; h.N = X; h.K = (int)xyy;
     h.A = P->kronW.p; h.lda = xyy;
     h.B = P->B.p; h.ldb = xyy;
@@ -982,7 +990,10 @@ void alloc_plan(dtrg_plan* P, const std::vector<StepShape>& sh) {
         P->side_lam.alloc_inst(nb, bmax);
     }
     if (lockw > 1) P->lockW.alloc_inst(nb, lockw);
-    if (kronw > 1) P->kronW.alloc_inst(nb, kronw);
+    if (kronw > 1) {
+        P->kronW.alloc_inst(nb, kronw);
+        P->Akr.alloc_inst(nb, t4);
+    }
     for (DevBuf<double>* b : {&P->H, &P->Z, &P->Rinv, &P->Sg}) b->alloc_inst(nb, bmax * bmax);
     for (DevBuf<double>* b : {&P->th, &P->res, &P->nrm}) b->alloc_inst(nb, bmax);
     // eigen-adjoint: every n x K block shares one instance stride (the Chebyshev step reads
@@ -1229,7 +1240,8 @@ void eig_adjoint(Ctx& c, StepCk& st, int k) {
 //   Abar' = F(W, U_K; B) + F(U_K, W; B),   Bbar' = F(W~, U_K~; A) + F(U_K~, W~; A),
 //   F(P, Q; M)[a][j][b][k] = sum_alpha sum_{c,d} P[(a,c),alpha] M[c][d][jk] Q[(b,d),alpha],
 // with ~ the exchange of the two bond indices of a row, (a,c) -> (c,a).  Each F is two contractions
-// of 2 X^3 K Y^2 flops through Z[a][d][alpha][jk] (in kronW); nothing n x n is formed.
+// of 2 X^3 K Y^2 flops, through Z'[(d,alpha)][(a,jk)] (kronW) into F'[(a,jk)][b] (Akr), whose rows
+// (a, jk) keep every dimension at least X; nothing n x n is formed.
 void kron_gram_adjoint(Ctx& c, const StepCk& st, DevBuf<double>& Abar, DevBuf<double>& Bbar) {
     dtrg_plan* P = c.P;
     const int X = st.sh.X, Y = st.sh.Y, YY = Y * Y, K = st.sh.K, n = st.sh.n, b = st.sh.b, nb = P->nb;
@@ -1238,31 +1250,35 @@ void kron_gram_adjoint(Ctx& c, const StepCk& st, DevBuf<double>& Abar, DevBuf<do
     copy2d(st.U.p, b, st.U.bs, P->Vc.p, K, vbs, n, K, nb, c.s);
     permute_checked(P, P->Xe, P->Vp.p, vbs, pd3(X, X, K, 1, 0, 2), 1.0, nullptr, c.s);
     permute_checked(P, P->Vc, P->Vn.p, vbs, pd3(X, X, K, 1, 0, 2), 1.0, nullptr, c.s);
-    auto F = [&](const double* Pm, const double* Q, const DevBuf<double>& M, DevBuf<double>& out, double beta) {
-        GemmOp g;   // Z[a][d][alpha][jk] = sum_c P[(a,c),alpha] M[c][d][jk]   (batched over a)
+    auto F = [&](const double* Pm, const double* Q, const DevBuf<double>& M, double beta) {
+        GemmOp g;   // Z'[(d,alpha)][(a,jk)] = sum_c P[(a,c),alpha] M[c][(d,jk)]   (batched over a)
         g.M = K; g.N = (int)xyy; g.K = X; g.batch = X;
         g.A = Pm; g.lda = K; g.a_kmajor = true; g.a_bs = (i64)X * K;
         g.B = M.p; g.ldb = xyy; g.b_kmajor = true; g.b_bs = 0;
-        g.C = P->kronW.p; g.c_bs = (i64)X * K * YY;
-        g.rmap = IdxMap::linear(YY);
-        g.cmap = IdxMap::split(YY, (i64)K * YY, 1);
+        g.C = P->kronW.p; g.c_bs = YY;
+        g.rmap = IdxMap::linear(xyy);
+        g.cmap = IdxMap::split(YY, (i64)K * xyy, 1);
         set_bs(g, vbs, M.bs, P->kronW.bs);
         c.gemm(g);
-        GemmOp h;   // out[a][j][b][k] (+)= sum_{d,alpha} Z[a][d][alpha][jk] Q[(b,d),alpha]   (batched over a)
-        h.M = YY; h.N = X; h.K = X * K; h.batch = X;
-        h.A = P->kronW.p; h.lda = YY; h.a_kmajor = true; h.a_bs = (i64)X * K * YY;
+        GemmOp h;   // F'[(a,jk)][b] (+)= sum_{(d,alpha)} Z'[(d,alpha)][(a,jk)] Q[b][(d,alpha)]
+        h.M = (int)xyy; h.N = X; h.K = X * K;
+        h.A = P->kronW.p; h.lda = xyy; h.a_kmajor = true;
         h.B = Q; h.ldb = (i64)X * K;
-        h.C = out.p; h.c_bs = xyy;
-        h.rmap = IdxMap::split(Y, (i64)X * Y, 1);
-        h.cmap = IdxMap::linear(Y);
+        h.C = P->Akr.p;
+        h.rmap = IdxMap::linear(X);
+        h.cmap = IdxMap::linear(1);
         h.beta = beta;
-        set_bs(h, P->kronW.bs, vbs, out.bs);
+        set_bs(h, P->kronW.bs, vbs, P->Akr.bs);
         c.gemm(h);
     };
-    F(P->Xe.p, P->Vc.p, P->B, Abar, 0.0);
-    F(P->Vc.p, P->Xe.p, P->B, Abar, 1.0);
-    F(P->Vp.p, P->Vn.p, P->A, Bbar, 0.0);
-    F(P->Vn.p, P->Vp.p, P->A, Bbar, 1.0);
+    // F'[a][j][k][b] -> out[a][j][b][k]
+    const PermDesc to_out = pd4(X, Y, Y, X, 0, 1, 3, 2);
+    F(P->Xe.p, P->Vc.p, P->B, 0.0);
+    F(P->Vc.p, P->Xe.p, P->B, 1.0);
+    permute_checked(P, P->Akr, Abar.p, Abar.bs, to_out, 1.0, nullptr, c.s);
+    F(P->Vp.p, P->Vn.p, P->A, 0.0);
+    F(P->Vn.p, P->Vp.p, P->A, 1.0);
+    permute_checked(P, P->Akr, Bbar.p, Bbar.bs, to_out, 1.0, nullptr, c.s);
 }
 
 // -------------------------------------------------------------------------------------------

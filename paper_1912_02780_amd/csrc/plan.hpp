@@ -166,6 +166,7 @@ struct dtrg_plan {
     dtrg::DevBuf<double> side_U, side_lam;     // side rule: the other unfolding's eigenvectors and values
     dtrg::DevBuf<double> lockW;                // block-locked eigensolve: projections on the locked vectors
     dtrg::DevBuf<double> kronW;                // scheme (b): intermediates of the Kronecker-form Gram products
+    dtrg::DevBuf<double> Akr;                  // ... and the permuted half-environment / adjoint (X^2 Y^2)
     bool side_rule() const { return opt.side_rule != 0; }
     dtrg::i64 ck_budget = 0;      // bytes the kept forward intermediates may take
     std::string tile_table;       // persisted autotuning table ("" = none)
