@@ -155,21 +155,40 @@ def xy_bond_gate(t: float) -> np.ndarray:
     return g.reshape(2, 2, 2, 2)
 
 
+def xy_bond_split(tau: float):
+    """The gate exp(-tau h) of one XY bond as sum_k L[a_out][a_in][k] R[b_out][b_in][k] (k < 4).
+
+    h = (X X + Y Y) / 4 = (X X - J J) / 4 with X = sigma_x and J = i sigma_y = [[0, 1], [-1, 0]]
+    (real); the two terms commute and square to the identity, so with c = cosh(tau/4),
+    s = sinh(tau/4):  exp(-tau h) = (c - s X X)(c + s J J) = c^2 I I - c s X X + c s J J - s^2 Z Z.
+    I, X, J, Z are orthogonal with norm sqrt 2 under the Frobenius inner product of the
+    (a_out a_in) x (b_out b_in) unfolding, so this is its singular value decomposition with the
+    singular values 2 (c^2, c s, c s, s^2) shared as square roots, written in one fixed basis: a
+    numerical SVD may rotate the degenerate pair (c s, c s) arbitrarily from one tau to the next,
+    while this factorisation is smooth in tau."""
+    c, s = math.cosh(0.25 * tau), math.sinh(0.25 * tau)
+    ops = [np.eye(2), np.array([[0.0, 1.0], [1.0, 0.0]]), np.array([[0.0, 1.0], [-1.0, 0.0]]),
+           np.array([[1.0, 0.0], [0.0, -1.0]])]
+    coef = [c * c, -c * s, c * s, -s * s]
+    Lg = np.empty((2, 2, 4))
+    Rg = np.empty((2, 2, 4))
+    for k, (o, a) in enumerate(zip(ops, coef)):
+        r = math.sqrt(abs(a))
+        Lg[:, :, k] = r * o
+        Rg[:, :, k] = math.copysign(r, a) * o
+    return Lg, Rg
+
+
 def xy_trotter_mpo(tau: float) -> np.ndarray:
     """MPO tensor M[l][u][r][d] of rho(tau) for the infinite XY chain in two-spin cells.
 
     The gate exp(-tau h) on the bond between cells (spin 2 of one cell, spin 1 of the next) is split
-    by an SVD of its (a_out a_in) x (b_out b_in) unfolding into sum_k L[a_out, a_in, k] R[b_out, b_in, k]
-    (singular values shared as square roots, all four kept); the cell's tensor applies
-    exp(-tau/2 h) on its inner bond, then R on spin 1 (bond l) and L on spin 2 (bond r), then
-    exp(-tau/2 h) again."""
+    as sum_k L[a_out, a_in, k] R[b_out, b_in, k] (xy_bond_split, all four terms kept); the cell's
+    tensor applies exp(-tau/2 h) on its inner bond, then R on spin 1 (bond l) and L on spin 2
+    (bond r), then exp(-tau/2 h) again."""
     if not tau > 0.0:
         raise ValueError("tau must be positive")
-    G = xy_bond_gate(tau)
-    Gm = np.transpose(G, (0, 2, 1, 3)).reshape(4, 4)     # [(a_out a_in), (b_out b_in)]
-    U, sv, Vt = np.linalg.svd(Gm)
-    Lg = (U * np.sqrt(sv)).reshape(2, 2, 4)              # [a_out][a_in][k]
-    Rg = (np.sqrt(sv)[:, None] * Vt).T.reshape(2, 2, 4)  # [b_out][b_in][k]
+    Lg, Rg = xy_bond_split(tau)
     gh = xy_bond_gate(0.5 * tau).reshape(4, 4)           # inner bond, [(s1 s2)_out][(s1 s2)_in]
     # E[(s1 s2)_out, (s1 s2)_in, l, r] = R[s1_out, s1_in, l] L[s2_out, s2_in, r]
     E = np.einsum("acl,bdr->abcdlr", Rg, Lg).reshape(4, 4, 4, 4)

@@ -11,7 +11,8 @@ what the paper and the mathematics fix, independently of the oracle's own code.
 * The infinite chain against Jordan-Wigner: the error of the Trotter density operator is second
   order in tau (halving tau divides it by four) when nothing is truncated that matters.
 * The adjoint (transfer-matrix eigenvalue, vertical steps, isometry gradients) against central
-  finite differences; planted mistakes in the eigenvalue adjoint are caught.
+  finite differences, also along dM/dtau (the energy's direction; the MPO's bond split is smooth in
+  tau); planted mistakes in the eigenvalue adjoint are caught.
 * The paper's Fig. 3(a) claim as a property: optimising the isometries of the last layers (depth
   n_d) raises ln Z monotonically over the MERA updates and brings the free energy closer to the
   exact one than the plain local truncation, more so with larger depth.
@@ -112,6 +113,35 @@ def test_input_gradient_matches_finite_differences(case, chi, n):
         V = rng.standard_normal(M.shape)
         fd = _fd_input(M, chi, n, V)
         assert abs(float(np.sum(g * V)) / fd - 1) < 2e-6
+
+
+def test_mpo_is_smooth_in_tau_and_its_split_is_exact():
+    """The bond split of the MPO is the gate's SVD written in one fixed operator basis: it
+    reproduces the gate, and the MPO is smooth in tau (a numerical SVD may rotate the degenerate pair
+    of singular values from one tau to the next, which makes finite differences of M meaningless)."""
+    for tau in (1e-4, 0.05, 0.3):
+        L, R = I.xy_bond_split(tau)
+        G = np.transpose(I.xy_bond_gate(tau), (0, 2, 1, 3)).reshape(4, 4)
+        assert np.max(np.abs(np.einsum("abk,cdk->abcd", L, R).reshape(4, 4) - G)) < 1e-15
+    tau = 0.05
+    d5 = (I.xy_trotter_mpo(tau * (1 + 1e-5)) - I.xy_trotter_mpo(tau * (1 - 1e-5))) / (2e-5 * tau)
+    d6 = (I.xy_trotter_mpo(tau * (1 + 1e-6)) - I.xy_trotter_mpo(tau * (1 - 1e-6))) / (2e-6 * tau)
+    assert np.max(np.abs(d5 - d6)) < 1e-8 * np.max(np.abs(d5))
+
+
+@pytest.mark.parametrize("chi,n", [(10, 6), (12, 8)])
+def test_tau_derivative_of_lnZ(chi, n):
+    """The gradient contracted with dM/dtau (the internal energy's direction: ln Z per cell at
+    beta = 2^n tau is 2^n L) against central differences of L in tau, through the truncations."""
+    tau = 0.05
+    M = I.xy_trotter_mpo(tau)
+    g = C.chain_backward(C.chain_forward(M, chi, n))
+    h = 1e-6
+    dM = (I.xy_trotter_mpo(tau * (1 + h)) - I.xy_trotter_mpo(tau * (1 - h))) / (2 * h * tau)
+    ht = 1e-5 * tau
+    fd = (C.chain_forward(I.xy_trotter_mpo(tau + ht), chi, n).lnZ_per_tensor
+          - C.chain_forward(I.xy_trotter_mpo(tau - ht), chi, n).lnZ_per_tensor) / (2 * ht)
+    assert abs(float(np.sum(g * dM)) / fd - 1) < 1e-6
 
 
 def test_isometry_gradient_matches_finite_differences():
