@@ -581,7 +581,8 @@ def chain_sweep(args, B, I, torch, dev, X, n, tau):
         # at beta = 12.8 the gapless chain's Gram spectrum is flat near the cut (lam_96 / lam_80 = 0.76 at
         # D = 64), so the subspace iteration needs more than the default 60 products
         plan = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n,
-                                        B.default_options(contract=args.contract, max_subspace_iters=400, profile=1),
+                                        B.default_options(contract=args.contract, profile=1,
+                                                          max_subspace_iters=args.max_subspace_iters),
                                         dev)
         L = B.dtrg_plan_forward(plan, M)
         B.dtrg_hotrg_backward(plan, 1.0)
@@ -622,7 +623,8 @@ def bench_xy_chain(args, B, I, torch, np, dev):
     M = torch.from_numpy(Mh).to(dev)
     # max_subspace_iters 400: at beta = 12.8 the gapless chain's spectrum is flat near the cut
     plan = B.dtrg_chain_plan_create(Mh.shape[0], Mh.shape[1], D, n,
-                                    B.default_options(contract=args.contract, profile=1, max_subspace_iters=400), dev)
+                                    B.default_options(contract=args.contract, profile=1,
+                                                      max_subspace_iters=args.max_subspace_iters), dev)
 
     def one_step():
         L = B.dtrg_plan_forward(plan, M)
@@ -709,6 +711,9 @@ def main():
     ap.add_argument("--chain-sweep", default="",
                     help="xy_chain: comma-separated bond dimensions D to time forward + backward at (e.g. 32,64,128)")
     ap.add_argument("--n-steps", type=int, default=None, help="chi48: 24 by default; ising_chi64: 30")
+    ap.add_argument("--max-subspace-iters", type=int, default=400,
+                    help="xy_chain: subspace products per eigensolve block (the spectrum is flat near the cut at "
+                         "beta = 12.8, and more so as D grows)")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="chi48: time every contraction shape's tile configurations once (1) or use the fixed "

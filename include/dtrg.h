@@ -170,6 +170,14 @@ typedef struct {
                                  Jacobi eigensolve of [[0, R], [R^T, 0]] for chi' <= 48 and the
                                  Newton-Schulz iteration X <- X (3 I - X^T X) / 2 above (chi' <= 80);
                                  1 = Newton-Schulz for every chi'.  Default 0 */
+    int subspace_shift;       /* the block subspace iteration of scheme (a) (SM B: the isometry from
+                                 the leading eigenvectors of the pair's Gram): 0 = each new block from
+                                 G V; 1 = from (G - s I) V with s half the block's smallest Ritz
+                                 value, the first-degree Chebyshev filter on [0, s]: the eigenvalues
+                                 the block leaves out map into [-s, s], so a wanted pair converges at
+                                 the ratio s / (lambda - s) in place of lambda_b / lambda.  The
+                                 eigenvectors are those of G either way.  Scheme (b) plans build the
+                                 block from (G + 2^-45 I) V whatever the setting.  Default 1 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */

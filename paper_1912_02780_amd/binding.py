@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("autotune", c_int), ("profile", c_int), ("checkpoint_gib", c_double), ("oversample", c_int),
                 ("max_fp32_chain", c_int), ("max_fp32_chain_wide", c_int),
                 ("tile_table", ctypes.c_char_p), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
-                ("alloc_user", c_void_p), ("chain_phys", c_int), ("side_rule", c_int), ("polar_newton", c_int)]
+                ("alloc_user", c_void_p), ("chain_phys", c_int), ("side_rule", c_int), ("polar_newton", c_int),
+                ("subspace_shift", c_int)]
 
 
 class StepInfo(ctypes.Structure):

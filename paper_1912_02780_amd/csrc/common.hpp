@@ -254,7 +254,8 @@ void split_matrix(const float* in, i64 ld_in, bool kmajor, int rows, int cols, v
 void convert_f64_to_f32(const double* in, i64 in_bs, float* out, i64 out_bs, i64 n, int nb, hipStream_t s);
 void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s);
 // y += a * x
-void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s);
+void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s, const double* sc = nullptr,
+          i64 sc_bs = 0);
 // p *= alpha * (scale_dev[i * scale_bs], or its reciprocal)
 void scale_inplace(double* p, i64 bs, i64 n, int nb, double alpha, const double* scale_dev, i64 scale_bs,
                    bool reciprocal, hipStream_t s);

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     __shared__ double V[JM * JLD];
     __shared__ int rp[JM / 2], rq[JM / 2];
     __shared__ double rc[JM / 2], rs[JM / 2];
-    __shared__ int nrot, nact;
+    __shared__ int nrot, nact, any_active;
     __shared__ double fro;
     const int tid = threadIdx.x;
     Ain += blockIdx.x * a_bs;
@@ -73,6 +73,24 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
     const double abs_floor = floor_rel * fro + 1e-300;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
+        // A sweep in which no pair passes the rotation test leaves the matrix as it is, so every round
+        // of it sees the matrix the sweep started from: the test over all pairs at once decides that
+        // case without running the rounds (the result is the same as running them).
+        if (tid == 0) any_active = 0;
+        __syncthreads();
+        {
+            int mine = 0;
+            for (int i = tid; i < n * n && !mine; i += JT) {
+                const int p = i / n, q = i % n;
+                if (q <= p) continue;
+                const double apq = A[p * JLD + q];
+                const double app = A[p * JLD + p], aqq = A[q * JLD + q];
+                mine = fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), abs_floor);
+            }
+            if (mine) any_active = 1;
+        }
+        __syncthreads();
+        if (!any_active) break;
         if (tid == 0) nrot = 0;
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {

@@ -731,8 +731,11 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
         // (s = 2^-45 of the unit trace), because the Grams of a squared Trotter operator have far
         // fewer non-negligible eigenvalues than chi' (rank 6 of 256 at tau = 5e-5), and G V alone would
         // collapse the block onto that range and break its Cholesky factorisation; the shift leaves the
-        // eigenvectors unchanged and keeps the block's null-space directions at norm s.
+        // eigenvectors unchanged and keeps the block's null-space directions at norm s.  With
+        // subspace_shift: (G - s I) V, s = theta_{b-1} / 2 from the Ritz values on the device (V1, Y1
+        // hold the Ritz vectors and G times them).
         if (P->chain()) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, kChainGramShift, c.s);
+        else if (P->opt.subspace_shift) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, -0.5, c.s, P->th.p + (b - 1), P->th.bs);
         col_norms(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, c.s);
         col_normalise(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, seed + 7919ULL * it, c.s);
         std::swap(P->V1, P->Y1);

@@ -193,9 +193,11 @@ __global__ __launch_bounds__(256) void fill_kernel(double* p, i64 bs, i64 n, dou
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void axpy_kernel(const double* x, double* y, i64 bs, i64 n, double a) {
+__global__ __launch_bounds__(256) void axpy_kernel(const double* x, double* y, i64 bs, i64 n, double a,
+                                                   const double* sc, i64 sc_bs) {
     x += blockIdx.y * bs;
     y += blockIdx.y * bs;
+    if (sc) a *= sc[blockIdx.y * sc_bs];
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) y[i] += a * x[i];
 }
 
@@ -404,9 +406,9 @@ void fill(double* p, i64 bs, i64 n, int nb, double v, hipStream_t s) {
     DTRG_HIP(hipGetLastError());
 }
 
-void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s) {
+void axpy(const double* x, double* y, i64 bs, i64 n, int nb, double a, hipStream_t s, const double* sc, i64 sc_bs) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(axpy_kernel, grid2(n, nb), dim3(256), 0, s, x, y, bs, n, a);
+    hipLaunchKernelGGL(axpy_kernel, grid2(n, nb), dim3(256), 0, s, x, y, bs, n, a, sc, sc_bs);
     DTRG_HIP(hipGetLastError());
 }
 

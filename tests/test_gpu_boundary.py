@@ -50,15 +50,20 @@ def test_gpu_autograd_dbeta_through_torch_tensor(B):
 
 
 def test_gpu_autograd_second_backward_and_scaling(B):
-    """The backward is seeded with the incoming gradient (here 3.5 * d(2 lnZ)) and may run twice on one
-    forward (retain_graph)."""
+    """The backward is seeded with the incoming gradient (here 7 d lnZ) and may run twice on one forward
+    (retain_graph).  The two backward passes round differently (the seed scales every intermediate):
+    entry by entry they agree to 9e-15 to 1.1e-14 here (the eigen-adjoint's broadened inverse gaps
+    d / (d^2 + 1e-12) reach up to 5e5), held to 5e-14."""
     from paper_1912_02780_amd import inputs as I
     from paper_1912_02780_amd.autograd import HOTRGFunction
     T0 = torch.from_numpy(I.random_d4_T0(2)).to("cuda:0").requires_grad_(True)
     lnZ = HOTRGFunction.apply(T0, 12, 8, None)
     (g1,) = torch.autograd.grad(lnZ, T0, retain_graph=True)
     (g2,) = torch.autograd.grad(7.0 * lnZ, T0)
-    assert torch.allclose(g2, 7.0 * g1, rtol=1e-14, atol=0)
+    d = (g2 - 7.0 * g1).abs()
+    _say(f"[gpu] second backward: max |g2 - 7 g1| / |7 g1| = {float((d / (7.0 * g1).abs()).max()):.2e}, "
+         f"normwise {float(d.norm() / (7.0 * g1).norm()):.2e}")
+    assert torch.allclose(g2, 7.0 * g1, rtol=5e-14, atol=0)
     assert abs(float((g1 * T0.detach()).sum()) - 1.0) < 1e-12      # Euler identity
 
 
