@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
                 ("max_fp32_chain", c_int), ("max_fp32_chain_wide", c_int),
                 ("tile_table", ctypes.c_char_p), ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN),
                 ("alloc_user", c_void_p), ("chain_phys", c_int), ("side_rule", c_int), ("polar_newton", c_int),
-                ("subspace_shift", c_int)]
+                ("subspace_shift", c_int), ("rr_skip", c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -53,7 +53,7 @@ class StepInfo(ctypes.Structure):
                 ("lam_first_dropped", c_double), ("resid", c_double), ("cheb_degree", c_int),
                 ("trunc_weight", c_double), ("cut_gap", c_double), ("min_kept_gap", c_double), ("mixed", c_int),
                 ("lnZ_at_step", c_double), ("side", c_int), ("trunc_weight_left", c_double),
-                ("trunc_weight_right", c_double)]
+                ("trunc_weight_right", c_double), ("rr_stride", c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -52,6 +52,7 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE(o.side_rule == 0 || o.side_rule == 1, DTRG_EINVAL, "side_rule must be 0 or 1");
     DTRG_REQUIRE(o.polar_newton == 0 || o.polar_newton == 1, DTRG_EINVAL, "polar_newton must be 0 or 1");
     DTRG_REQUIRE(o.subspace_shift == 0 || o.subspace_shift == 1, DTRG_EINVAL, "subspace_shift must be 0 or 1");
+    DTRG_REQUIRE(o.rr_skip == 0 || o.rr_skip == 1, DTRG_EINVAL, "rr_skip must be 0 or 1");
     DTRG_REQUIRE(o.side_rule == 0 || o.chain_phys == 0, DTRG_EINVAL, "the side rule is for scheme (a) (chain_phys 0)");
 }
 
@@ -131,6 +132,7 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
     info->side = st.side;
     info->trunc_weight_left = st.tw_left;
     info->trunc_weight_right = st.tw_right;
+    info->rr_stride = st.sh.full ? 0 : st.rr_stride;
     if (st.fixed || st.sh.ident) {   // a given isometry (or the identity): no Gram, no spectrum
         info->full_eig = 0;
         info->iters = -1;
@@ -138,6 +140,7 @@ void step_info(const dtrg_plan* P, int i, int k, dtrg_step_info* info) {
         info->trunc_weight = info->cut_gap = info->min_kept_gap = 0.0;
         info->cheb_degree = 0;
         info->trunc_weight_left = info->trunc_weight_right = NAN;
+        info->rr_stride = 0;
     }
 }
 
@@ -377,6 +380,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->side_rule = 0;
     o->polar_newton = 0;
     o->subspace_shift = 1;
+    o->rr_skip = 1;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {

@@ -75,6 +75,9 @@ namespace {
 double ldexp1(int e) { return std::ldexp(1.0, e); }
 
 constexpr double kSubspaceAccept = 1e-12;   // largest accepted resolved residual (trace-normalised)
+// Rayleigh-Ritz after every second Gram product only where the first solve's Ritz values span less
+// than this ratio (smallest over largest, every instance)
+constexpr double kRrSkipRatio = 1e-6;
 constexpr double kChebTail = 1e-15;         // relative size of the last two expansion coefficients
 constexpr int kChebMaxDegree = 1024;
 // at the largest degree the expansion is accepted down to this tail (a relative error of the
@@ -656,6 +659,25 @@ void eigensolve_locked(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     st.iters = total;
 }
 
+// The next block of the scheme (a) subspace iteration from V1 and Y1 = G V1: G V with columns
+// rescaled to unit norm, re-orthonormalised.  Scheme (b): (G + s I) V (s = 2^-45 of the unit trace),
+// because the Grams of a squared Trotter operator have far fewer non-negligible eigenvalues than chi'
+// (rank 6 of 256 at tau = 5e-5), and G V alone would collapse the block onto that range and break its
+// Cholesky factorisation; the shift leaves the eigenvectors unchanged and keeps the block's
+// null-space directions at norm s.  With subspace_shift: (G - s I) V, s = theta_{b-1} / 2 from the
+// last Rayleigh-Ritz solve's values on the device.
+void next_block(Ctx& c, const StepShape& sh, int it, uint64_t seed) {
+    dtrg_plan* P = c.P;
+    const int n = sh.n, b = sh.b, nb = P->nb;
+    const i64 vbs = P->V1.bs;
+    if (P->chain()) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, kChainGramShift, c.s);
+    else if (P->opt.subspace_shift) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, -0.5, c.s, P->th.p + (b - 1), P->th.bs);
+    col_norms(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, c.s);
+    col_normalise(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, seed + 7919ULL * it, c.s);
+    std::swap(P->V1, P->Y1);
+    orthonormalise(c, P->V1.p, P->V2.p, vbs, n, b);
+}
+
 void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     dtrg_plan* P = c.P;
     const int n = st.sh.n, b = st.sh.b, E = st.sh.e, nb = P->nb;
@@ -688,10 +710,19 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
     double prev = INFINITY;
     int stall = 0, it = 0;
     std::vector<double> resh((size_t)nb * P->res.bs);
+    // Rayleigh-Ritz after every stride-th product (and after the first and the last): the adaptive
+    // pass starts at 1 and may raise it after the first solve; fixed passes replay it
+    int stride = c.adaptive() ? 1 : st.rr_stride;
     for (it = 1; it <= it_max; ++it) {
         double* V = P->V1.p;
         double* Y = P->Y1.p;
         product_G(c, st, k, V, Y, vbs, b);
+        if ((it - 1) % stride != 0 && it < it_max) {
+            // no Rayleigh-Ritz after this product: the next block comes from Y (and the shift of the
+            // last solve's Ritz values)
+            next_block(c, st.sh, it, seed);
+            continue;
+        }
         // H = V^T Y
         GemmOp g;
         g.M = g.N = b; g.K = n;
@@ -725,23 +756,28 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
             if (mx > 0.5 * prev) ++stall; else stall = 0;
             prev = mx;
             if (stall >= 3 && mx <= kSubspaceAccept) break;      // rounding floor reached
+            if (it == 1 && warm_used && P->opt.rr_skip && !P->chain()) {
+                // the spread of the first solve's Ritz values decides the stride (see kRrSkipRatio); a
+                // warm block is close to the Gram's eigenvectors, so they approximate its spectrum (a
+                // random block's would not: its Ritz values average over the spectrum)
+                std::vector<double> th((size_t)nb * P->th.bs);
+                DTRG_HIP(hipMemcpyAsync(th.data(), P->th.p, th.size() * sizeof(double), hipMemcpyDeviceToHost, c.s));
+                DTRG_HIP(hipStreamSynchronize(c.s));
+                double ratio = INFINITY;
+                for (int i = 0; i < nb; ++i) {
+                    const double* t = th.data() + (size_t)i * P->th.bs;
+                    ratio = std::min(ratio, t[0] > 0.0 ? t[b - 1] / t[0] : 0.0);
+                }
+                stride = ratio > kRrSkipRatio ? 2 : 1;
+            }
         }
         if (it == it_max) break;
-        // next block: G V with columns rescaled to unit norm, re-orthonormalised.  Scheme (b): (G + s I) V
-        // (s = 2^-45 of the unit trace), because the Grams of a squared Trotter operator have far
-        // fewer non-negligible eigenvalues than chi' (rank 6 of 256 at tau = 5e-5), and G V alone would
-        // collapse the block onto that range and break its Cholesky factorisation; the shift leaves the
-        // eigenvectors unchanged and keeps the block's null-space directions at norm s.  With
-        // subspace_shift: (G - s I) V, s = theta_{b-1} / 2 from the Ritz values on the device (V1, Y1
-        // hold the Ritz vectors and G times them).
-        if (P->chain()) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, kChainGramShift, c.s);
-        else if (P->opt.subspace_shift) axpy(P->V1.p, P->Y1.p, vbs, (i64)n * b, nb, -0.5, c.s, P->th.p + (b - 1), P->th.bs);
-        col_norms(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, c.s);
-        col_normalise(P->Y1.p, n, b, b, vbs, P->nrm.p, P->nrm.bs, nb, seed + 7919ULL * it, c.s);
-        std::swap(P->V1, P->Y1);
-        orthonormalise(c, P->V1.p, P->V2.p, vbs, n, b);
+        next_block(c, st.sh, it, seed);
     }
-    if (c.adaptive()) st.iters = std::min(it, it_max);
+    if (c.adaptive()) {
+        st.iters = std::min(it, it_max);
+        st.rr_stride = stride;
+    }
     // acceptance of the resolved pairs, on the device (the fixed pass reports it afterwards)
     max_check(P->res.p, P->res.bs, E, nb, kSubspaceAccept, P->sc(k, 8), P->S, P->flags.p, kFlagSubspace, c.s);
     if (c.adaptive()) {

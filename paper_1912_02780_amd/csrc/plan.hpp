@@ -108,6 +108,7 @@ struct StepCk {
     OpBuf P1k, Q2k;
     // schedule (written by adaptive passes, replayed by fixed passes)
     int iters = 0;         // subspace iterations
+    int rr_stride = 1;     // Gram products per Rayleigh-Ritz solve of the subspace iteration
     int cheb = 0;          // degree of the complement expansion (0: none)
     double hi_mult = 1.0;  // widening factor of the complement interval
     // a given isometry (the first K columns of U, set by the caller or by the isometry optimiser):

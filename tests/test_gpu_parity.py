@@ -181,19 +181,28 @@ FULL = ["ising_b0.4406868_chi24_n24", "ising_b0.30_chi32_n30", "ising_b0.4406868
         "ising_b0.50_chi32_n30", "random_d4_seed0_chi48_n24"]
 
 
-@pytest.mark.parametrize("shift", [1, 0])
+# forms of the subspace iteration: (subspace_shift, rr_skip)
+FORMS = {"default": (1, 1), "shift_rr_every_product": (1, 0), "plain": (0, 0)}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("name", FULL)
-def test_gpu_vs_golden_fp64(B, name, shift):
-    """Both forms of the subspace iteration (new blocks from G V, or from (G - s I) V) against the
-    golden."""
+def test_gpu_vs_golden_fp64(B, name, form):
+    """Every form of the subspace iteration (new blocks from G V or from (G - s I) V; Rayleigh-Ritz after
+    every product or after every second one where the block's spectrum allows) against the golden."""
     from paper_1912_02780_amd import inputs as I
     gd = _golden(name)
     if gd["input"] == "ising":
         T0, dT0 = I.ising_T0(gd["param"]), I.ising_dT0_dbeta(gd["param"])
     else:
         T0, dT0 = I.random_d4_T0(int(gd["param"])), None
-    _say(f"[gpu] golden parity {name} subspace_shift={shift}")
-    lnZ, g, d, plan = _gpu(B, T0, gd["chi"], gd["n_steps"], dT0, subspace_shift=shift)
+    shift, skip = FORMS[form]
+    _say(f"[gpu] golden parity {name} {form}")
+    lnZ, g, d, plan = _gpu(B, T0, gd["chi"], gd["n_steps"], dT0, subspace_shift=shift, rr_skip=skip)
+    info = [plan.step_info(k) for k in range(1, gd["n_steps"] + 1)]
+    _say(f"    products {[s['iters'] for s in info]} strides {''.join(str(s['rr_stride']) for s in info)}")
+    if not skip:
+        assert all(s["rr_stride"] <= 1 for s in info)
     go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
     tol_g = max(1e-10, 10.0 * gd.get("rounding_sensitivity_T0bar", 0.0))
     _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.3e}  T0bar rel {_rel(g, go):.3e} elem {_elem(g, go):.3e} "
@@ -486,21 +495,31 @@ def test_gpu_autotuned_plan(B):
     assert _rel(g1, g0) < 1e-5
 
 
-def test_gpu_subspace_shift_takes_fewer_products_at_criticality(B):
-    """Ising at beta_c, chi = 32, 30 steps: the spectrum near the cut decays slowly, and building each
-    new block from (G - s I) V (s half the smallest Ritz value) takes fewer Gram products than G V
-    (measured 350 against 442), with the same ln Z / N and d(lnZ/N)/dbeta to 1e-12."""
+def test_gpu_subspace_iteration_forms_at_criticality(B):
+    """Ising at beta_c, chi = 32, 30 steps: the spectrum near the cut decays slowly.  Building each new
+    block from (G - s I) V (s half the smallest Ritz value) takes fewer Gram products than G V
+    (measured 350 against 442); the warm-started steps' blocks span few decades, so the Rayleigh-Ritz
+    solve runs after every second product there.  ln Z / N and d(lnZ/N)/dbeta agree to 1e-12."""
     from paper_1912_02780_amd import inputs as I
     beta = 0.4406868
     T0, dT0 = I.ising_T0(beta), I.ising_dT0_dbeta(beta)
-    its, res = {}, {}
-    for shift in (0, 1):
-        L, _, d, plan = _gpu(B, T0, 32, 30, dT0, subspace_shift=shift)
-        its[shift] = sum(plan.step_info(k)["iters"] for k in range(1, 31))
-        res[shift] = (L, d)
-    _say(f"[gpu] subspace shift at beta_c: products {its[0]} (G V) / {its[1]} ((G - s I) V)")
-    assert its[1] < 0.9 * its[0]
-    assert abs(res[1][0] / res[0][0] - 1) < 1e-12 and abs(res[1][1] / res[0][1] - 1) < 1e-12
+    its, solves, res = {}, {}, {}
+    for form, (shift, skip) in FORMS.items():
+        L, _, d, plan = _gpu(B, T0, 32, 30, dT0, subspace_shift=shift, rr_skip=skip)
+        info = [plan.step_info(k) for k in range(1, 31)]
+        its[form] = sum(s["iters"] for s in info)
+        solves[form] = sum(len([it for it in range(1, s["iters"] + 1) if (it - 1) % s["rr_stride"] == 0
+                                or it == s["iters"]]) for s in info if s["iters"] > 0)
+        res[form] = (L, d)
+        if form == "default":
+            strides = [s["rr_stride"] for s in info if s["iters"] > 0]
+    _say(f"[gpu] subspace iteration at beta_c: products {its}, Rayleigh-Ritz solves {solves}, "
+         f"strides {strides}")
+    assert its["shift_rr_every_product"] < 0.9 * its["plain"]
+    assert sum(s == 2 for s in strides) >= len(strides) // 2
+    assert solves["default"] < 0.7 * solves["shift_rr_every_product"]
+    for form in FORMS:
+        assert abs(res[form][0] / res["plain"][0] - 1) < 1e-12 and abs(res[form][1] / res["plain"][1] - 1) < 1e-12
 
 
 @pytest.mark.parametrize("contract", ["fp64", "bf16x6"])
