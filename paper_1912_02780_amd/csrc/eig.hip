@@ -205,14 +205,24 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const double* __restrict__ A
 // parallel), then X = L^{-1} by the same elimination applied to the identity (row k of X is
 // final after step k, rows below get a parallel rank-1 update), Rinv = X^T to global.  The
 // updates run on a CG x CG thread grid, one barrier per column (or row).
+//
+// An unshifted S = I + E with |E|_F <= kCholSeries (the Gram of a block that one CholeskyQR pass has
+// made orthonormal to about that) takes the series instead: with G1 = Phi(E) and
+// Phi(M) = (strict lower part of M) + diag(M)/2, the factor is L = I + G1 - Phi(G1 G1^T) + O(|E|^3)
+// (from L L^T = I + E order by order), and its inverse
+//   X = I - G1 + Phi(G1 G1^T) + G1 G1 + O(|E|^3),
+// exact to rounding for |E|_F <= 2^-20 (|E|^3 <= 2^-60).  Two triangular b^3 products with no
+// barrier between columns, against 2b barriers of the elimination.
+constexpr double kCholSeries = 0x1p-20;
+
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ S, i64 s_bs, int b,
                                                        double shift_rel, double* __restrict__ Rinv, i64 r_bs,
                                                        int* flag, const int* __restrict__ skip, int* __restrict__ near,
                                                        double near_tol) {
     __shared__ double L[JM * JLD];
     __shared__ double Xs[JM * JLD];
-    __shared__ double tr;
-    __shared__ double wmax[CT / 64];
+    __shared__ double tr, efro2;
+    __shared__ double wmax[CT / 64], wsum[CT / 64];
     const int tid = threadIdx.x;
     S += blockIdx.x * s_bs;
     Rinv += blockIdx.x * r_bs;
@@ -222,20 +232,31 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
         for (int idx = tid; idx < b * b; idx += CT) Rinv[(i64)(idx / b) * b + idx % b] = (idx / b == idx % b) ? 1.0 : 0.0;
         return;
     }
-    double dev = 0.0;
+    double dev = 0.0, e2 = 0.0;
     for (int i = tid; i < b * b; i += CT) {
         const int r = i / b, c = i % b;
         const double v = 0.5 * (S[(i64)r * b + c] + S[(i64)c * b + r]);
         L[r * JLD + c] = v;
         Xs[r * JLD + c] = (r == c) ? 1.0 : 0.0;
-        dev = fmax(dev, fabs(v - (r == c ? 1.0 : 0.0)));   // fmax drops a NaN: checked below
+        const double e = v - (r == c ? 1.0 : 0.0);
+        dev = fmax(dev, fabs(e));   // fmax drops a NaN: checked below
+        e2 += e * e;                // a NaN stays: the series test below fails on it
         if (!isfinite(v)) dev = INFINITY;
     }
-    if (near) {
-        for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
-        if ((tid & 63) == 0) wmax[tid >> 6] = dev;
+    for (int o = 32; o > 0; o >>= 1) {
+        dev = fmax(dev, __shfl_xor(dev, o));
+        e2 += __shfl_xor(e2, o);
+    }
+    if ((tid & 63) == 0) {
+        wmax[tid >> 6] = dev;
+        wsum[tid >> 6] = e2;
     }
     __syncthreads();
+    if (tid == 0) {
+        double s2 = 0.0;
+        for (int w = 0; w < CT / 64; ++w) s2 += wsum[w];
+        efro2 = s2;
+    }
     if (near && tid == 0) {
         double m = 0.0;
         for (int w = 0; w < CT / 64; ++w) m = fmax(m, wmax[w]);
@@ -247,13 +268,37 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
         tr = s;
     }
     __syncthreads();
+    const int tx = tid % CG, ty = tid / CG;
+    if (shift_rel == 0.0 && efro2 <= kCholSeries * kCholSeries) {
+        // the series: G1 = Phi(S - I) in L (the strict upper part zeroed)
+        for (int i = tid; i < b * b; i += CT) {
+            const int r = i / b, c = i % b;
+            const double e = L[r * JLD + c] - (r == c ? 1.0 : 0.0);
+            L[r * JLD + c] = r > c ? e : (r == c ? 0.5 * e : 0.0);
+        }
+        __syncthreads();
+        // X[i][j] (i >= j) = delta_ij - G1[i][j] + Phi(M)[i][j] + (G1 G1)[i][j], with
+        // M[i][j] = sum_{k <= j} G1[i][k] G1[j][k] and (G1 G1)[i][j] = sum_{j <= k <= i} G1[i][k] G1[k][j]
+        for (int i = ty; i < b; i += CG)
+            for (int j = tx; j <= i; j += CG) {
+                double m = 0.0, p = 0.0;
+                for (int k = 0; k <= j; ++k) m += L[i * JLD + k] * L[j * JLD + k];
+                for (int k = j; k <= i; ++k) p += L[i * JLD + k] * L[k * JLD + j];
+                Xs[i * JLD + j] = (i == j ? 1.0 : 0.0) - L[i * JLD + j] + (i > j ? m : 0.5 * m) + p;
+            }
+        __syncthreads();
+        for (int idx = tid; idx < b * b; idx += CT) {
+            const int i = idx / b, j = idx % b;
+            Rinv[(i64)i * b + j] = (i <= j) ? Xs[j * JLD + i] : 0.0;
+        }
+        return;
+    }
     const double shift = shift_rel * tr;
     for (int i = tid; i < b; i += CT) L[i * JLD + i] += shift;
     __syncthreads();
     // Cholesky, right-looking, one barrier per column: phase k takes the pivot and column k as phase
     // k-1 left them, applies the rank-1 update with the scaled column to the trailing lower
     // triangle, and writes back the scaled column k-1, which phase k no longer reads
-    const int tx = tid % CG, ty = tid / CG;
     double dprev = 1.0, rprev = 1.0;
     for (int k = 0; k <= b; ++k) {
         if (k > 0) {
