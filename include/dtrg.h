@@ -178,16 +178,17 @@ typedef struct {
                                  the ratio s / (lambda - s) in place of lambda_b / lambda.  The
                                  eigenvectors are those of G either way.  Scheme (b) plans build the
                                  block from (G + 2^-45 I) V whatever the setting.  Default 1 */
-    int rr_skip;              /* Rayleigh-Ritz solves of the same subspace iteration: 0 = after every
-                                 Gram product; 1 = after every second product on steps that start
-                                 from the previous step's vectors and whose first solve finds the
-                                 block's Ritz values within six decades (the smallest above 1e-6 of
-                                 the largest, for every instance), where the product
-                                 of a block that is not aligned with eigenvectors loses no direction
-                                 to rounding; the iteration still ends on a solve, whose Ritz
-                                 residuals decide convergence.  The choice is made in the adaptive
-                                 pass and replayed.  Scheme (b) plans solve after every product.
-                                 Default 1 */
+    int rr_skip;              /* Rayleigh-Ritz solves of the same subspace iteration, 0 to 3: a solve
+                                 after every (rr_skip + 1)-th Gram product on steps that start from
+                                 the previous step's vectors and whose first solve finds the block's
+                                 Ritz values within eight decades (the smallest above 1e-8 of the
+                                 largest, for every instance), where the product of a block that is
+                                 not aligned with eigenvectors loses no direction to rounding (each
+                                 new block is still re-orthonormalised); after every product
+                                 elsewhere, and with 0.  The iteration still ends on a solve, whose
+                                 Ritz residuals decide convergence.  The choice is made in the
+                                 adaptive pass and replayed.  Scheme (b) plans solve after every
+                                 product.  Default 3 */
 } dtrg_options;
 
 /* Per-step diagnostics, all gauge invariant. */
@@ -214,8 +215,8 @@ typedef struct {
     int side;                 /* unfolding the step's isometry came from: 0 left, 1 right */
     double trunc_weight_left; /* side_rule 1: truncated weights of the left and right unfoldings */
     double trunc_weight_right;/* (NaN with side_rule 0 and on steps with a given isometry) */
-    int rr_stride;            /* Gram products per Rayleigh-Ritz solve of the subspace iteration (1 or
-                                 2, see rr_skip; 0 where the step does not iterate) */
+    int rr_stride;            /* Gram products per Rayleigh-Ritz solve of the subspace iteration (1 to
+                                 4, see rr_skip; 0 where the step does not iterate) */
 } dtrg_step_info;
 
 typedef struct dtrg_plan dtrg_plan;

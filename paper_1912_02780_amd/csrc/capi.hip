@@ -52,7 +52,7 @@ void validate_options(const dtrg_options& o) {
     DTRG_REQUIRE(o.side_rule == 0 || o.side_rule == 1, DTRG_EINVAL, "side_rule must be 0 or 1");
     DTRG_REQUIRE(o.polar_newton == 0 || o.polar_newton == 1, DTRG_EINVAL, "polar_newton must be 0 or 1");
     DTRG_REQUIRE(o.subspace_shift == 0 || o.subspace_shift == 1, DTRG_EINVAL, "subspace_shift must be 0 or 1");
-    DTRG_REQUIRE(o.rr_skip == 0 || o.rr_skip == 1, DTRG_EINVAL, "rr_skip must be 0 or 1");
+    DTRG_REQUIRE(o.rr_skip >= 0 && o.rr_skip <= 3, DTRG_EINVAL, "rr_skip must be 0 to 3");
     DTRG_REQUIRE(o.side_rule == 0 || o.chain_phys == 0, DTRG_EINVAL, "the side rule is for scheme (a) (chain_phys 0)");
 }
 
@@ -380,7 +380,7 @@ void dtrg_default_options(dtrg_options* o) {
     o->side_rule = 0;
     o->polar_newton = 0;
     o->subspace_shift = 1;
-    o->rr_skip = 1;
+    o->rr_skip = 3;
 }
 
 dtrg_status dtrg_plan_create(int D, int chi, int n_steps, const dtrg_options* opt, dtrg_plan** plan_out) {

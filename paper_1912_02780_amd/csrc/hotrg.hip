@@ -75,9 +75,9 @@ namespace {
 double ldexp1(int e) { return std::ldexp(1.0, e); }
 
 constexpr double kSubspaceAccept = 1e-12;   // largest accepted resolved residual (trace-normalised)
-// Rayleigh-Ritz after every second Gram product only where the first solve's Ritz values span less
-// than this ratio (smallest over largest, every instance)
-constexpr double kRrSkipRatio = 1e-6;
+// Rayleigh-Ritz after every (rr_skip + 1)-th Gram product only where the first solve's Ritz values
+// span less than this ratio (smallest over largest, every instance)
+constexpr double kRrSkipRatio = 1e-8;
 constexpr double kChebTail = 1e-15;         // relative size of the last two expansion coefficients
 constexpr int kChebMaxDegree = 1024;
 // at the largest degree the expansion is accepted down to this tail (a relative error of the
@@ -768,7 +768,7 @@ void eigensolve(Ctx& c, StepCk& st, int k, const StepCk* warm) {
                     const double* t = th.data() + (size_t)i * P->th.bs;
                     ratio = std::min(ratio, t[0] > 0.0 ? t[b - 1] / t[0] : 0.0);
                 }
-                stride = ratio > kRrSkipRatio ? 2 : 1;
+                stride = ratio > kRrSkipRatio ? 1 + P->opt.rr_skip : 1;
             }
         }
         if (it == it_max) break;

@@ -119,7 +119,7 @@ def test_default_options():
     assert o.autotune == 0 and o.profile == 0 and o.gram_fp64 == 1 and o.checkpoint_gib == 64.0
     assert o.oversample == 0 and o.max_fp32_chain == 4096 and o.max_fp32_chain_wide == 4096
     assert o.tile_table is None and o.alloc_fn is None and o.free_fn is None
-    assert o.chain_phys == 0 and o.side_rule == 0 and o.polar_newton == 0 and o.subspace_shift == 1 and o.rr_skip == 1
+    assert o.chain_phys == 0 and o.side_rule == 0 and o.polar_newton == 0 and o.subspace_shift == 1 and o.rr_skip == 3
     # a checkpoint budget that is negative or not finite is rejected before any allocation
     lib.dtrg_plan_create.restype = ctypes.c_int
     lib.dtrg_last_error.restype = ctypes.c_char_p

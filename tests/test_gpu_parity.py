@@ -182,14 +182,14 @@ FULL = ["ising_b0.4406868_chi24_n24", "ising_b0.30_chi32_n30", "ising_b0.4406868
 
 
 # forms of the subspace iteration: (subspace_shift, rr_skip)
-FORMS = {"default": (1, 1), "shift_rr_every_product": (1, 0), "plain": (0, 0)}
+FORMS = {"default": (1, 3), "shift_rr_every_product": (1, 0), "plain": (0, 0)}
 
 
 @pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("name", FULL)
 def test_gpu_vs_golden_fp64(B, name, form):
     """Every form of the subspace iteration (new blocks from G V or from (G - s I) V; Rayleigh-Ritz after
-    every product or after every second one where the block's spectrum allows) against the golden."""
+    every product or after every fourth one where the block's spectrum allows) against the golden."""
     from paper_1912_02780_amd import inputs as I
     gd = _golden(name)
     if gd["input"] == "ising":
@@ -499,7 +499,8 @@ def test_gpu_subspace_iteration_forms_at_criticality(B):
     """Ising at beta_c, chi = 32, 30 steps: the spectrum near the cut decays slowly.  Building each new
     block from (G - s I) V (s half the smallest Ritz value) takes fewer Gram products than G V
     (measured 350 against 442); the warm-started steps' blocks span few decades, so the Rayleigh-Ritz
-    solve runs after every second product there.  ln Z / N and d(lnZ/N)/dbeta agree to 1e-12."""
+    solve runs after every fourth product there (measured 137 solves against 350, for 386 products).
+    ln Z / N and d(lnZ/N)/dbeta agree to 1e-12."""
     from paper_1912_02780_amd import inputs as I
     beta = 0.4406868
     T0, dT0 = I.ising_T0(beta), I.ising_dT0_dbeta(beta)
@@ -516,8 +517,8 @@ def test_gpu_subspace_iteration_forms_at_criticality(B):
     _say(f"[gpu] subspace iteration at beta_c: products {its}, Rayleigh-Ritz solves {solves}, "
          f"strides {strides}")
     assert its["shift_rr_every_product"] < 0.9 * its["plain"]
-    assert sum(s == 2 for s in strides) >= len(strides) // 2
-    assert solves["default"] < 0.7 * solves["shift_rr_every_product"]
+    assert sum(s == 4 for s in strides) >= len(strides) // 2
+    assert solves["default"] < 0.5 * solves["shift_rr_every_product"]
     for form in FORMS:
         assert abs(res[form][0] / res["plain"][0] - 1) < 1e-12 and abs(res[form][1] / res["plain"][1] - 1) < 1e-12
 
