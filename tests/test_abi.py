@@ -302,7 +302,8 @@ def test_option_ranges_are_validated():
     lib = _lib()
     lib.dtrg_last_error.restype = ctypes.c_char_p
     for field, value in (("max_fp32_chain", 16), ("max_fp32_chain_wide", 1 << 21), ("oversample", 96),
-                         ("oversample", -1)):
+                         ("oversample", -1), ("subspace_shift", 2), ("subspace_shift", -1), ("rr_skip", 4),
+                         ("rr_skip", -1), ("polar_newton", 2)):
         st, plan = _plan_create(lib, FakeDeviceMemory(), **{field: value})
         assert st == 1 and plan.value is None, field
         assert field.encode() in lib.dtrg_last_error()
