@@ -201,6 +201,15 @@ struct GemmOp {
     // longest FP32 accumulation chain (products per output and K chunk) of the FP32 and bf16-plane
     // formats; longer K is split and the partials are summed in FP64
     int max_chain = 4096;
+    // Symmetric outputs (FP64 contractions only; beta = 0), which are computed on half their rows:
+    //   sym = 1: C(r, c) = C(c, r) (M == N).  Only the tiles on or below the diagonal are computed,
+    //            and every tile below it also writes its mirror image.
+    //   sym = 2: C(r, c) = C(r~, c~), where r = r1 rdig + r0 has r~ = r0 rdig + r1 and
+    //            c = c1 cdig + c0 has c~ = c0 cdig + c1 (N == cdig^2).  Only the rows with r1 >= r0
+    //            are computed: M = rdig (rdig + 1) / 2, packed row p standing for the row with
+    //            p = r1 (r1 + 1) / 2 + r0, read from A and written to C as that row, and every packed
+    //            row with r1 > r0 also writes the mirrored row.
+    int sym = 0, rdig = 0, cdig = 0;
     int tag = 0;   // own kernel symbol for the chi^7 contractions: 7 the join of the two copies
                    // (forward and its backward recompute; timed when profiling), 8 its adjoint
                    // with respect to the upper copy's product P, 9 with respect to the lower copy;

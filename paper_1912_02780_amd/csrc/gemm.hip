@@ -19,6 +19,9 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
     for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
         const i64 zb = idx / MN, rc = idx % MN;
         const int r = (int)(rc / p.N), c = (int)(rc % p.N);
+        // a symmetric output's tiles above the diagonal have no partials: they are written as the
+        // mirror images of the tiles below it
+        if (p.sym == 1 && r / p.sym_tile < c / p.sym_tile) continue;
         const TA* W = (const TA*)p.W + zb * p.splits * MN + rc;
         double s = 0.0;
         int q = 0;
@@ -30,7 +33,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
             for (int u = 0; u < U; ++u) s += (double)v[u];
         }
         for (; q < p.splits; ++q) s += (double)W[(i64)q * MN];
-        write_elem<OUT>(p, (int)zb, r, c, p.alpha * s);
+        write_out<OUT>(p, (int)zb, r, c, p.alpha * s);
     }
 }
 
@@ -77,9 +80,20 @@ constexpr i64 kMaxChainSplits = 256;
 
 int prec_planes(Prec p) { return p == Prec::BF16X3 ? 2 : (p == Prec::BF16X6 ? 3 : 1); }
 
+namespace {
+// rows of the full output (a symmetric output with packed rows has rdig^2)
+i64 full_rows(const GemmOp& op) { return op.sym == 2 ? (i64)op.rdig * op.rdig : op.M; }
+
+// output tiles a configuration computes per batch element (a sym = 1 output: the lower triangle)
+i64 tile_count(const GemmOp& op, int BM, int BN) {
+    const i64 tm = (op.M + BM - 1) / BM, tn = (op.N + BN - 1) / BN;
+    return op.sym == 1 ? tm * (tm + 1) / 2 : tm * tn;
+}
+}  // namespace
+
 i64 gemm_c_extent(const GemmOp& op) {
     if (op.M == 0 || op.N == 0) return 0;
-    return map_max(op.rmap, op.M) + map_max(op.cmap, op.N) + (i64)(op.batch - 1) * op.c_bs +
+    return map_max(op.rmap, full_rows(op)) + map_max(op.cmap, op.N) + (i64)(op.batch - 1) * op.c_bs +
            (i64)(op.batch2 - 1) * op.c_bs2 + 1;
 }
 
@@ -105,7 +119,7 @@ GemmCfg gemm_resolve(Prec prec, const GemmOp& op) {
     const int BK = bk_of(prec, c.tile);
     if (c.splits <= 0) {
         const i64 nz = (i64)op.batch * op.batch2;
-        const i64 tiles = (i64)((op.M + BM - 1) / BM) * ((op.N + BN - 1) / BN) * nz;
+        const i64 tiles = tile_count(op, BM, BN) * nz;
         c.splits = 1;
         // fill the 256 CUs (several blocks each) when the output is small and K is long
         if (tiles < 512) {
@@ -165,6 +179,14 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
         return;
     }
     DTRG_REQUIRE(prec != Prec::F64 || out == Out::F64, DTRG_EINVAL, "gemm: FP64 contraction must write FP64");
+    if (op.sym != 0) {
+        DTRG_REQUIRE(prec == Prec::F64 && op.beta == 0.0 && (op.sym == 1 || op.sym == 2), DTRG_EINVAL,
+                     "gemm: symmetric outputs are FP64 contractions with beta = 0");
+        DTRG_REQUIRE(op.sym != 1 || op.M == op.N, DTRG_EINVAL, "gemm: sym = 1 needs a square output");
+        DTRG_REQUIRE(op.sym != 2 || (op.rdig >= 1 && op.cdig >= 1 && (i64)op.M == (i64)op.rdig * (op.rdig + 1) / 2 &&
+                                     (i64)op.N == (i64)op.cdig * op.cdig),
+                     DTRG_EINVAL, "gemm: sym = 2 needs M = rdig (rdig + 1) / 2 packed rows and N = cdig^2");
+    }
     DTRG_REQUIRE(out != Out::Split || (split && op.beta == 0.0), DTRG_EINVAL,
                  "gemm: split output needs a split contraction and beta = 0");
     if (split) {
@@ -185,7 +207,8 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     // the kernels read whole 16-byte chunks of split rows: the row extent is padded to 8 elements
     auto ext = [&](i64 x) { return split ? round8(x) : x; };
     if (op.K > 0 && op.a_cap >= 0) {
-        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (ext(op.M) - 1) : (i64)(op.M - 1) * op.lda + (ext(op.K) - 1)) +
+        const i64 rows = full_rows(op);   // rows read from A (packed rows stand for rows below rdig^2)
+        const i64 mx = (op.a_kmajor ? (i64)(op.K - 1) * op.lda + (ext(rows) - 1) : (i64)(rows - 1) * op.lda + (ext(op.K) - 1)) +
                        (i64)(op.batch - 1) * op.a_bs + (i64)(op.batch2 - 1) * op.a_bs2 + (i64)(np - 1) * op.a_ps;
         DTRG_REQUIRE(mx < op.a_cap, DTRG_EINVAL, "gemm: operand A out of bounds");
     }
@@ -207,6 +230,7 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     a.alpha = op.alpha; a.beta = op.beta;
     a.batch = op.batch; a.batch2 = op.batch2;
     a.W = nullptr;
+    a.sym = op.sym; a.rdig = op.rdig; a.cdig = op.cdig; a.sym_tile = 1;
     {
         // 16-byte epilogue stores of bf16 planes: every aligned group of 8 output columns must be
         // contiguous and start on a multiple of 8 elements in every plane and batch element
@@ -223,6 +247,8 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     DTRG_REQUIRE(cfg.tile != 6 || (!op.a_kmajor && !op.b_kmajor && op.K % 16 == 0), DTRG_EINVAL,
                  "gemm: tile 6 takes K-contiguous operands and K a multiple of 16 only");
     const int BM = tile_rows(cfg.tile), BN = tile_cols(cfg.tile);
+    DTRG_REQUIRE(op.sym != 1 || BM == BN, DTRG_EINVAL, "gemm: sym = 1 needs square tiles");
+    a.sym_tile = BM;
     int splits = 1;
     resolve_chunks(prec, op, cfg, a.k_chunk, splits);
     a.splits = splits;
@@ -236,7 +262,7 @@ void gemm(Prec prec, Out out, const GemmOp& op, hipStream_t s, Scratch& ws) {
     }
     a.tiles_m = (op.M + BM - 1) / BM;
     a.tiles_n = (op.N + BN - 1) / BN;
-    const i64 total = (i64)a.tiles_m * a.tiles_n;
+    const i64 total = tile_count(op, BM, BN);
     const i64 chunk = (total + kXcds - 1) / kXcds;
     DTRG_REQUIRE(total < (1LL << 30), DTRG_EINVAL, "gemm: grid too large");
     dim3 grid((unsigned)(chunk * kXcds), 1, (unsigned)(nz * splits));

@@ -31,7 +31,28 @@ typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 constexpr int kXcds = 8;
 constexpr int kGroupM = 4;
 
-__device__ inline bool tile_of(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+// Packed index p of the pairs (r1, r0) with r1 >= r0, in the order (0,0), (1,0), (1,1), (2,0), ...:
+// p = r1 (r1 + 1) / 2 + r0.
+// (The root is off by at most one for the index range used here; one correction each way.)
+__host__ __device__ inline void tri_pair(int p, int& r1, int& r0) {
+    int a = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    a -= (a * (a + 1) / 2 > p) ? 1 : 0;
+    a += ((a + 1) * (a + 2) / 2 <= p) ? 1 : 0;
+    r1 = a;
+    r0 = p - a * (a + 1) / 2;
+}
+
+// With `lower`, only the tiles on or below the diagonal of a square tile grid (tiles_m x tiles_m),
+// taken row by row (the same XCD split of the sequence; no bands).
+__device__ inline bool tile_of(int pid, int tiles_m, int tiles_n, int& tm, int& tn, bool lower = false) {
+    if (lower) {
+        const int total = tiles_m * (tiles_m + 1) / 2;
+        const int chunk = (total + kXcds - 1) / kXcds;
+        const int t = (pid % kXcds) * chunk + pid / kXcds;
+        if (t >= total) return false;
+        tri_pair(t, tm, tn);
+        return true;
+    }
     const int total = tiles_m * tiles_n;
     const int chunk = (total + kXcds - 1) / kXcds;
     const int t = (pid % kXcds) * chunk + pid / kXcds;
@@ -56,6 +77,7 @@ struct KArgs {
     void* W;  // split-K partials [batch2 * batch * splits][M][N], accumulator type
     int vec_out;  // bf16-plane output whose aligned groups of 8 columns are 16-byte aligned and
                   // contiguous in every plane (the epilogue then stores 16 bytes per lane)
+    int sym, sym_tile, rdig, cdig;  // symmetric output (GemmOp::sym; FP64 kernel only), its tile size
 };
 
 // offset of batch element zb = z2 * batch + z1 in an operand with strides (bs, bs2)
@@ -93,6 +115,24 @@ __device__ inline void write_elem(const KArgs& p, int zb, int r, int c, double v
     put_out<OUT>(p.C, batch_off(p, zb, p.c_bs, p.c_bs2) + idx_off(p.rmap, r) + idx_off(p.cmap, c), p.c_ps, v, p.beta);
 }
 
+// write the output element of kernel row r (a packed row for sym = 2) and column c, and its mirror
+// image where the symmetric output has one that is not computed itself
+template <int OUT>
+__device__ inline void write_out(const KArgs& p, int zb, int r, int c, double v) {
+    if (p.sym == 2) {
+        int r1, r0;
+        tri_pair(r, r1, r0);
+        write_elem<OUT>(p, zb, r1 * p.rdig + r0, c, v);
+        if (r1 != r0) {
+            const int c1 = c / p.cdig, c0 = c - c1 * p.cdig;
+            write_elem<OUT>(p, zb, r0 * p.rdig + r1, c0 * p.cdig + c1, v);
+        }
+        return;
+    }
+    write_elem<OUT>(p, zb, r, c, v);
+    if (p.sym == 1 && r / p.sym_tile > c / p.sym_tile) write_elem<OUT>(p, zb, c, r, v);
+}
+
 
 
 // ------------------------------------------------------------------------------------------
@@ -128,6 +168,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_mfma4_kernel(KArgs p) {
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
     constexpr int PAD = 1;   // odd row stride: the transposing LDS stores of K-contiguous tiles spread over banks
+    constexpr bool SYM = sizeof(T) == 8;   // symmetric outputs: FP64 contractions only
     static_assert(AE >= 1 && BE >= 1, "tile too small");
     __shared__ T As[2][BK][BM + PAD];
     __shared__ T Bs[2][BK][BN + PAD];
@@ -136,13 +177,28 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_mfma4_kernel(KArgs p) {
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
     int tmi, tni;
-    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni)) return;
+    if (!tile_of(blockIdx.x, p.tiles_m, p.tiles_n, tmi, tni, p.sym == 1)) return;
     const int m0 = tmi * BM, n0 = tni * BN;
     const int zb = blockIdx.z / p.splits, zs = blockIdx.z % p.splits;
     const int kbeg = zs * p.k_chunk;
     const int kend = min(p.K, kbeg + p.k_chunk);
     const T* A = (const T*)p.A + batch_off(p, zb, p.a_bs, p.a_bs2);
     const T* B = (const T*)p.B + batch_off(p, zb, p.b_bs, p.b_bs2);
+    // the operand row each thread's A elements come from (-1 past the last row): the kernel row,
+    // or for sym = 2 the row its packed index stands for
+    int arow[AE];
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+        const int idx = tid + e * NT;
+        const int gm = m0 + (AKM ? idx % BM : idx / BK);
+        int r = gm < p.M ? gm : -1;
+        if (SYM && p.sym == 2 && r >= 0) {
+            int r1, r0;
+            tri_pair(gm, r1, r0);
+            r = r1 * p.rdig + r0;
+        }
+        arow[e] = r;
+    }
 
     acc_t acc[TM][TN];
 #pragma unroll
@@ -154,11 +210,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_mfma4_kernel(KArgs p) {
     auto load = [&](int k0) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
-            int m, k;
-            if (AKM) { int idx = tid + e * NT; k = idx / BM; m = idx % BM; }
-            else { int idx = tid + e * NT; m = idx / BK; k = idx % BK; }
-            int gm = m0 + m, gk = k0 + k;
-            ra[e] = (gm < p.M && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gm] : A[(i64)gm * p.lda + gk]) : T(0);
+            const int idx = tid + e * NT;
+            const int k = AKM ? idx / BM : idx % BK;
+            const int gr = arow[e], gk = k0 + k;
+            ra[e] = (gr >= 0 && gk < kend) ? (AKM ? A[(i64)gk * p.lda + gr] : A[(i64)gr * p.lda + gk]) : T(0);
         }
 #pragma unroll
         for (int e = 0; e < BE; ++e) {
@@ -227,15 +282,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_mfma4_kernel(KArgs p) {
         return;
     }
     constexpr int OUT = sizeof(TO) == 8 ? 0 : 1;
+    // a symmetric output: tiles below the diagonal (sym = 1) and packed rows with r1 > r0 (sym = 2)
+    // also write their mirror images
+    const bool mirror_tile = SYM && p.sym == 1 && tmi > tni;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int gm = m0 + wm0 + i * 16 + Mfma4<T>::row(lk, r), gn = n0 + wn0 + j * 16 + li;
-                if (gm < p.M && gn < p.N) write_elem<OUT>(p, zb, gm, gn, p.alpha * (double)acc[i][j][r]);
+        for (int r = 0; r < 4; ++r) {
+            const int gm = m0 + wm0 + i * 16 + Mfma4<T>::row(lk, r);
+            if (gm >= p.M) continue;
+            int orow = gm, mrow = -1;   // output row and mirrored row (sym = 2)
+            if (SYM && p.sym == 2) {
+                int r1, r0;
+                tri_pair(gm, r1, r0);
+                orow = r1 * p.rdig + r0;
+                if (r1 != r0) mrow = r0 * p.rdig + r1;
             }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int gn = n0 + wn0 + j * 16 + li;
+                if (gn >= p.N) continue;
+                const double v = p.alpha * (double)acc[i][j][r];
+                write_elem<OUT>(p, zb, orow, gn, v);
+                if (mirror_tile) write_elem<OUT>(p, zb, gn, gm, v);
+                if (SYM && mrow >= 0) {
+                    const int c1 = gn / p.cdig, c0 = gn - c1 * p.cdig;
+                    write_elem<OUT>(p, zb, mrow, c0 * p.cdig + c1, v);
+                }
+            }
+        }
 }
 
 template <class T, class TO, int BM, int BN, int BK, int TAG, int WGM, int WGN>

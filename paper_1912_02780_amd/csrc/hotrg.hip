@@ -210,10 +210,12 @@ void permute_op(dtrg_plan* P, Prec pr, const DevBuf<double>& in, const OpBuf& ou
     dtrg::permute_out(in.p, out.p(), out_code(pr), d, 1.0, scale_dev, P->S, s);
 }
 
-// A[a][b][j][k] = sum_{x,y} TA[(a,j)][(x,y)] TA[(b,k)][(x,y)]  (also B with TB)
+// A[a][b][j][k] = sum_{x,y} TA[(a,j)][(x,y)] TA[(b,k)][(x,y)]  (also B with TB): TA TA^T, so only
+// the tiles on or below its diagonal are computed and mirrored
 void half_env(Ctx& c, const DevBuf<double>& Tperm, DevBuf<double>& out, int X, int Y) {
     GemmOp g;
     g.M = g.N = X * Y; g.K = X * Y;
+    g.sym = 1;
     g.A = Tperm.p; g.lda = X * Y;
     g.B = Tperm.p; g.ldb = X * Y;
     g.C = out.p;
@@ -223,10 +225,14 @@ void half_env(Ctx& c, const DevBuf<double>& Tperm, DevBuf<double>& out, int X, i
     c.gemm(g);
 }
 
-// G[(a,c)][(b,d)] = sum_{(j,k)} A[(a,b),(j,k)] B[(c,d),(j,k)]
+// G[(a,c)][(b,d)] = sum_{(j,k)} A[(a,b),(j,k)] B[(c,d),(j,k)].  A and B are symmetric under
+// (a,j) <-> (b,k), so G[(b,d)][(a,c)] = G[(a,c)][(b,d)]: in the rows (a,b) and columns (c,d) of the
+// contraction, the element of row (b,a) and column (d,c) equals that of (a,b), (c,d).  Only the rows
+// with a >= b are computed; the others are written as their mirror images.
 void gram(Ctx& c, const DevBuf<double>& A, const DevBuf<double>& B, DevBuf<double>& G, int X, int Y) {
     GemmOp g;
-    g.M = g.N = X * X; g.K = Y * Y;
+    g.M = X * (X + 1) / 2; g.N = X * X; g.K = Y * Y;
+    g.sym = 2; g.rdig = X; g.cdig = X;
     g.A = A.p; g.lda = Y * Y;
     g.B = B.p; g.ldb = Y * Y;
     g.C = G.p;
@@ -1568,8 +1574,12 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         if (implicit_gram(P, st.sh)) {
             kron_gram_adjoint(c, st, Abar, Bbar);
         } else {
+            // G_bar and the half-environments are symmetric, so Abar' is symmetric under
+            // (a,j) <-> (b,k) and Bbar' under (c,j) <-> (d,k): only the rows (a,b) (and (c,d)) with
+            // a >= b are computed, the others are their mirror images
             GemmOp g;
-            g.M = X * X; g.N = Y * Y; g.K = X * X;
+            g.M = X * (X + 1) / 2; g.N = Y * Y; g.K = X * X;
+            g.sym = 2; g.rdig = X; g.cdig = Y;
             g.A = P->Gt.p; g.lda = X * X;
             g.B = P->B.p; g.ldb = Y * Y; g.b_kmajor = true;
             g.C = Abar.p;

@@ -31,8 +31,10 @@ typedef std::tuple<int, int, int, int, int, int, int, int, int, int> TuneKey;
 std::mutex g_mu;
 std::map<TuneKey, GemmCfg> g_table;
 
+// the precision field also carries a symmetric output's kind (prec + 16 sym): such an output
+// computes about half of its tiles, so it is tuned on its own
 TuneKey key_of(Prec prec, Out out, const GemmOp& op) {
-    return TuneKey((int)prec, (int)out, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
+    return TuneKey((int)prec + 16 * op.sym, (int)out, op.M, op.N, op.K, op.batch, op.batch2, op.a_kmajor ? 1 : 0,
                    op.b_kmajor ? 1 : 0, prec == Prec::F64 ? 0 : op.max_chain);
 }
 
@@ -61,7 +63,7 @@ int tuned_count() {
 
 // Persisted table: a text file, one shape per line, "dtrg-tune 1" first:
 //   prec out M N K batch batch2 a_kmajor b_kmajor max_chain tile splits
-// Loaded entries do not replace shapes the process has tuned already.
+// (prec + 16 sym for a symmetric output).  Loaded entries do not replace shapes the process has tuned already.
 int tune_load(const std::string& path) {
     FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return 0;
@@ -140,7 +142,8 @@ GemmCfg tuned_cfg(Prec prec, Out out, const GemmOp& op, bool allow_tune, hipStre
         if (tile == 3 && op.M < 256) continue;
         if (tile == 4 && op.N > 64) continue;
         const int BMt = tile_rows(tile), BNt = tile_cols(tile);
-        const i64 tiles = (i64)((op.M + BMt - 1) / BMt) * ((op.N + BNt - 1) / BNt) * nz;
+        const i64 tm = (op.M + BMt - 1) / BMt, tn = (op.N + BNt - 1) / BNt;
+        const i64 tiles = (op.sym == 1 ? tm * (tm + 1) / 2 : tm * tn) * nz;
         // the chain floor is always a candidate (the untuned path would take it too); larger
         // split counts only within the trial limits
         for (int sp : split_counts(minsp)) {

@@ -182,7 +182,8 @@ def test_gpu_forced_deep_tile_chi48_vs_golden(B, tmp_path):
     for ln in lines[1:]:
         v = [int(x) for x in ln.split()]
         prec, M, N, K, akm, bkm = v[0], v[2], v[3], v[4], v[7], v[8]
-        if prec >= 2 and not akm and not bkm and M >= 256 and N >= 256 and K % 16 == 0:
+        # prec 2 / 3: the bf16-plane formats (FP64 symmetric outputs carry prec + 16 sym)
+        if prec in (2, 3) and not akm and not bkm and M >= 256 and N >= 256 and K % 16 == 0:
             v[10] = tile
             forced += 1
         out_lines.append(" ".join(str(x) for x in v))
