@@ -269,7 +269,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     T0 = torch.from_numpy(I.random_d4_T0(0, D)).to(dev)
     ck = 64.0 if args.checkpoint_gib is None else args.checkpoint_gib
     chain = 4096 if args.max_fp32_chain is None else args.max_fp32_chain
-    opts = B.default_options(contract=args.contract, autotune=args.autotune, profile=1, checkpoint_gib=ck,
+    opts = B.default_options(oversample=args.oversample, contract=args.contract, autotune=args.autotune, profile=1, checkpoint_gib=ck,
                              max_fp32_chain=chain)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
@@ -305,8 +305,10 @@ def bench_chi48(args, B, I, torch, np, dev):
         "config": {"workload": (f"random D4-symmetric rank-4 tensor (D={D}, uniform[0,1) seed 0), HOTRG chi={chi}, "
                                 f"{n} RG steps, forward + backward to dlnZ/dT0"),
                    "D": D, "chi": chi, "n_steps": n, "contract": args.contract, "eig": "fp64", "autotune": args.autotune,
-                   "checkpoint_gib": ck, "max_fp32_chain": chain, "lnZ_per_site": L,
-                   "plan_device_GB": plan.device_bytes() / 1e9},
+                   "checkpoint_gib": ck, "max_fp32_chain": chain,
+                   "subspace_block": (f"chi' + {args.oversample} (oversample)" if args.oversample
+                                      else "library default, max(chi' + 16, 2 chi') up to 96"),
+                   "lnZ_per_site": L, "plan_device_GB": plan.device_bytes() / 1e9},
         "roofline": roofline(launches, ms, flops, args.contract, "chi^7 join contraction (gemm kernel, tag 7)",
                              traffic_bytes("chi48", args.contract) if (chi, n) == (48, 24) else None,
                              (_measured("chi48", args.contract) or {}).get("mfma_busy_counter")
@@ -320,7 +322,7 @@ def bench_chi48(args, B, I, torch, np, dev):
     if ck > 0 and not args.no_policy_compare:
         # the same pass with one checkpoint per RG step, recomputing inside the backward step
         _progress("timing the pass with recompute inside the step")
-        opts0 = B.default_options(contract=args.contract, autotune=args.autotune, checkpoint_gib=0.0,
+        opts0 = B.default_options(oversample=args.oversample, contract=args.contract, autotune=args.autotune, checkpoint_gib=0.0,
                                   max_fp32_chain=chain)
         plan0 = B.dtrg_plan_create(D, chi, n, opts0, dev)
         sec = _time_passes(B, torch, plan0, T0, None, 1, max(1, min(args.steps, 3)))
@@ -351,7 +353,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         # the plain FP64 GPU path on the same workload (same checkpoint policy and tuner): the
         # mixed-precision speedup at the accuracy reported above
         _progress("timing the FP64 path")
-        o64 = B.default_options(contract="fp64", autotune=args.autotune, checkpoint_gib=ck)
+        o64 = B.default_options(oversample=args.oversample, contract="fp64", autotune=args.autotune, checkpoint_gib=ck)
         p64 = B.dtrg_plan_create(D, chi, n, o64, dev)
         L64 = B.dtrg_plan_forward(p64, T0)     # (tuning pass)
         g64, _ = B.dtrg_hotrg_backward(p64, 1.0)
@@ -372,6 +374,7 @@ def bench_chi48(args, B, I, torch, np, dev):
         sub_args = argparse.Namespace(**vars(args))
         sub_args.steps, sub_args.warmup, sub_args.compact = 2, 1, True
         sub_args.checkpoint_gib = None
+        sub_args.oversample = 0   # the library's default subspace block
         for name, fn, chi_s, n_s in (("batch256", bench_batch256, 48, 24), ("ising_chi64", bench_ising_chi64, 64, 30),
                                      ("xy_chain", bench_xy_chain, 32, 18)):
             _progress(f"compact {name}")
@@ -486,7 +489,7 @@ def bench_ising_chi64(args, B, I, torch, np, dev):
     chain = CHI64_CHAIN if args.max_fp32_chain is None else args.max_fp32_chain
     # the fixed tile heuristic: the autotuner's trial output and split-K workspace would add to the
     # peak device memory this workload reports
-    opts = B.default_options(contract=args.contract, profile=1, checkpoint_gib=ck, max_fp32_chain=chain)
+    opts = B.default_options(oversample=args.oversample, contract=args.contract, profile=1, checkpoint_gib=ck, max_fp32_chain=chain)
     plan = B.dtrg_plan_create(D, chi, n, opts, dev)
 
     def one_step():
@@ -715,6 +718,10 @@ def main():
                     help="xy_chain: subspace products per eigensolve block (the spectrum is flat near the cut at "
                          "beta = 12.8, and more so as D grows)")
     ap.add_argument("--seq-sample", type=int, default=2, help="batch256: instances per chi timed on the FP64 path")
+    ap.add_argument("--oversample", type=int, default=None,
+                    help="guard columns of the subspace block beyond chi' (0: the library's default block, "
+                         "2 chi'; chi48: 16 by default, b = 64, 4%% faster than 96 at the same accuracy; "
+                         "the other workloads: 0)")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="chi48: time every contraction shape's tile configurations once (1) or use the fixed "
                          "heuristic (0)")
@@ -744,6 +751,8 @@ def main():
         args.chi = {"ising_chi64": 64, "xy_chain": 32}.get(args.workload, 48)
     if args.n_steps is None:
         args.n_steps = {"ising_chi64": 30, "xy_chain": 18}.get(args.workload, 24)
+    if args.oversample is None:
+        args.oversample = 16 if args.workload == "chi48" else 0
 
     import numpy as np
     import torch

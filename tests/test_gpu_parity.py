@@ -216,6 +216,24 @@ def test_gpu_vs_golden_fp64(B, name, form):
         assert abs(plan.step_info(k)["c"] / gd["c"][k - 1] - 1) < 1e-11 + gd["lam_last_kept"][k - 1]
 
 
+@pytest.mark.parametrize("contract,autotune", [("fp64", 0), ("bf16x6", 1)])
+def test_gpu_block64_vs_golden_chi48(B, contract, autotune):
+    """The subspace block of the chi = 48 benchmark (16 guard columns: b = 64 instead of the default
+    2 chi' = 96) against the FP64 golden, at the FP64 and three-plane tolerances."""
+    from paper_1912_02780_amd import inputs as I
+    gd = _golden("random_d4_seed0_chi48_n24")
+    _say(f"[gpu] block 64 golden chi48 {contract}")
+    lnZ, g, _, plan = _gpu(B, I.random_d4_T0(0), 48, 24, None, contract=contract, autotune=autotune,
+                           oversample=16)
+    go = np.array(gd["T0bar"]).reshape(gd["T0bar_shape"])
+    tol_l = 1e-10 if contract == "fp64" else 1e-6
+    tol_g = max(1e-10, 10.0 * gd.get("rounding_sensitivity_T0bar", 0.0)) if contract == "fp64" else GRAD_TOL[contract]
+    _say(f"    lnZ rel {abs(lnZ / gd['lnZ_per_site'] - 1):.2e}  T0bar rel {_rel(g, go):.2e} elem {_elem(g, go):.2e}")
+    assert abs(lnZ / gd["lnZ_per_site"] - 1) < tol_l
+    assert _rel(g, go) < tol_g
+    assert _elem(g, go) < tol_g
+
+
 # ---------------------------------------------------------------------------------------------
 # error paths (host-checked; nothing faults)
 # ---------------------------------------------------------------------------------------------
