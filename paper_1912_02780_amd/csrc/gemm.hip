@@ -9,11 +9,12 @@
 namespace dtrg {
 
 // Sum of split-K partials in a fixed order (q = 0, 1, ...), then the shared epilogue.  The
-// partials are loaded eight at a time before they are added, so that a thread waits for one
-// memory round trip per eight splits rather than per split.
+// partials are loaded sixteen at a time before they are added (the last group padded with zeros,
+// which leave the sum unchanged), so that a thread waits for one memory round trip per sixteen
+// splits rather than per split.
 template <class TA, int OUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     const i64 MN = (i64)p.M * p.N;
     const i64 total = MN * p.batch * p.batch2;
     for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
@@ -24,15 +25,13 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(KArgs p) {
         if (p.sym == 1 && r / p.sym_tile < c / p.sym_tile) continue;
         const TA* W = (const TA*)p.W + zb * p.splits * MN + rc;
         double s = 0.0;
-        int q = 0;
-        for (; q + U <= p.splits; q += U) {
+        for (int q = 0; q < p.splits; q += U) {
             TA v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = W[(i64)(q + u) * MN];
+            for (int u = 0; u < U; ++u) v[u] = q + u < p.splits ? W[(i64)(q + u) * MN] : TA(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) s += (double)v[u];
         }
-        for (; q < p.splits; ++q) s += (double)W[(i64)q * MN];
         write_out<OUT>(p, (int)zb, r, c, p.alpha * s);
     }
 }
