@@ -86,8 +86,8 @@ TRAFFIC_SOURCES = ["paper_1912_02780_amd/csrc/gemm_kernels.hpp", "paper_1912_027
                    "paper_1912_02780_amd/csrc/gemm_f32.hip", "paper_1912_02780_amd/csrc/gemm_split.hpp"]
 MEASURED_TRAFFIC = {
     # chi^7 join at chi = 48 (M = 110592, N = 2304, K = 2304), 20 launches of that size per pass
-    ("chi48", "bf16x6"): {"sources_sha256": "165121b6f3d6f950ecba3eb1e6ac11d8a9df5ce634406222a192b1cec94a6929",
-                          "fetch_kib": 5072505.0, "write_kib": 1698625.0,
+    ("chi48", "bf16x6"): {"sources_sha256": "f4c2d1a2e1974e045b55ba1313fcbba1746fca823d09f5783f5de7cfc34e60e6",
+                          "fetch_kib": 5216732.0, "write_kib": 1699305.0,
                           # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), same runs
                           "mfma_busy_counter": 0.576},
 }
