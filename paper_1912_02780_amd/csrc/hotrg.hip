@@ -1596,25 +1596,39 @@ void plan_backward(dtrg_plan* P, double gbar, bool with_dir, Mode mode) {
         // Tbar[a][x][y][j] += 2 sum_{(b,k)} Abar'[(a,j)][(b,k)] TA[(b,k)][(x,y)]   (the right
         // unfolding's tensor is the mirrored input: its gradient lands on Tbar[x][a][y][j])
         const i64 s1 = (i64)X * Y * Y, s0 = (i64)Y * Y;
-        {
+        // Tbar += 2 Hbar' T_H for one half-environment H (A with TA, B with TB): in FP64, or on the steps
+        // whose projections run in the plan's split-bf16 format, in that format (the two operands
+        // converted into the step's chi^5 work buffers, which are free at this point of the step),
+        // with FP64 accumulation into Tbar.  Like the projection contractions, this product comes
+        // after the eigensolve and its adjoint, which stay FP64.
+        const bool split_tbar = st.sh.mixed && !P->chain() && prec_planes(P->prec) > 1;
+        auto tbar_update = [&](const DevBuf<double>& Hbar, const DevBuf<double>& TH, IdxMap rmap, IdxMap cmap) {
             GemmOp g;
             g.M = X * Y; g.N = X * Y; g.K = X * Y;
-            g.A = Abar.p; g.lda = X * Y;
-            g.B = P->TA.p; g.ldb = X * Y; g.b_kmajor = true;
+            g.b_kmajor = true;
             g.C = P->Tbar2.p;
-            g.rmap = IdxMap::split(Y, right ? s0 : s1, 1);
-            g.cmap = IdxMap::split(Y, right ? s1 : s0, Y);
+            g.rmap = rmap;
+            g.cmap = cmap;
             g.alpha = 2.0; g.beta = 1.0;
-            set_bs(g, Abar.bs, P->TA.bs, P->Tbar2.bs);
-            c.gemm(g);
-            // Tbar[a][x][j][y] += 2 sum_{(b,k)} Bbar'[(a,j)][(b,k)] TB[(b,k)][(x,y)]   (right: Tbar[x][a][j][y])
-            g.A = Bbar.p;
-            g.B = P->TB.p;
-            g.rmap = IdxMap::split(Y, right ? s0 : s1, Y);
-            g.cmap = IdxMap::split(Y, right ? s1 : s0, 1);
-            set_bs(g, Bbar.bs, P->TB.bs, P->Tbar2.bs);
-            c.gemm(g);
-        }
+            if (split_tbar) {
+                const OpSet& o = P->ops[1];
+                const i64 ld = pad8((i64)X * Y);
+                // Hbar'[(a,j)][(b,k)] rows (a,j), K-contiguous; T_H[(b,k)][(x,y)] K-major rows (b,k)
+                permute_op(P, P->prec, Hbar, o.X1, pd4(X, Y, X, Y, 0, 1, 2, 3), 2, ld, nullptr, c.s);
+                permute_op(P, P->prec, TH, o.X2, pd4(X, Y, X, Y, 0, 1, 2, 3), 2, ld, nullptr, c.s);
+                set_ops(g, op_of(o.X1, ld), op_of(o.X2, ld));
+                g.c_bs2 = P->Tbar2.bs;
+                c.run(g, P->prec, Out::F64);
+            } else {
+                g.A = Hbar.p; g.lda = X * Y;
+                g.B = TH.p; g.ldb = X * Y;
+                set_bs(g, Hbar.bs, TH.bs, P->Tbar2.bs);
+                c.gemm(g);
+            }
+        };
+        tbar_update(Abar, P->TA, IdxMap::split(Y, right ? s0 : s1, 1), IdxMap::split(Y, right ? s1 : s0, Y));
+        // Tbar[a][x][j][y] += 2 sum_{(b,k)} Bbar'[(a,j)][(b,k)] TB[(b,k)][(x,y)]   (right: Tbar[x][a][j][y])
+        tbar_update(Bbar, P->TB, IdxMap::split(Y, right ? s0 : s1, Y), IdxMap::split(Y, right ? s1 : s0, 1));
         std::swap(P->Tbar, P->Tbar2);   // Tbar = gradient w.r.t. T_k
         if (c.adaptive()) check_flags(P, kFlagErrors, "backward step " + std::to_string(k));
     }
